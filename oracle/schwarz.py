@@ -1,0 +1,171 @@
+"""Oracle Schwarz iterations.  Test infrastructure only.
+
+Restricted additive Schwarz (Sec. 2.1, after Cai and Sarkis): every subdomain
+solves its local problem on its overlapping set, the values computed on
+overlap points are discarded and only the owned points are written back, so no
+weighting is needed and writes never collide.  Reading (the paper writes it in
+prose only), correction form with x^0 = 0:
+
+    r^k      = b - A x^k
+    hist[k]  = ||r^k||_2 / ||b||_2           (relative residual, Sec. 3.3.2)
+    stop when hist[k] < tau                   (global criterion, Sec. 3.3.2)
+    x^{k+1}  = x^k + sum_p  Rtilde_p^T S_p( R_p r^k )
+
+where R_p restricts to Omega_p and Rtilde_p^T writes back owned points only.
+The synchronous variant (Sec. 2.1, Sec. 3.4) applies all subdomain updates of
+a sweep from the same x^k.  Alg. 1's loop -- local solve, exchange, update,
+convergence check -- is one sweep here.
+
+The asynchronous variant (Sec. 2.1, Sec. 3.4) has no sweep barrier: each
+subdomain solves with whatever neighbour values it last received.  Two
+deterministic stand-ins are provided: restricted multiplicative Schwarz (one
+in-place x, subdomains visited in order -- the asynchronous iteration executed
+by a single worker in a fixed order) and a seeded event simulator with bounded
+staleness.  Convergence detection for the asynchronous variants follows
+Sec. 2.2 / Sec. 3.3.2: the local criterion ||r_p||^2 < tau^2 ||b_p||^2 over the
+overlapping set, a centralized detector that ends the iteration once every
+subdomain reports local convergence, then a verification of the global
+criterion after termination (resuming if it fails).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import scipy.sparse.linalg as spla
+
+from .local import LocalSolver, local_matrix
+from .overlap import subdomain_sets
+
+
+@dataclasses.dataclass
+class Subdomain:
+    owned: np.ndarray  # global ids, ascending
+    omega: np.ndarray  # global ids, ascending, superset of owned
+    ext: np.ndarray  # next layer out
+    pos: np.ndarray  # positions of `owned` inside `omega`
+    solver: LocalSolver
+
+
+class RAS:
+    """Setup of the Schwarz solver: subdomains, local matrices, local solvers."""
+
+    def __init__(self, A, owner: np.ndarray, gamma: int, local: str = "chol", storage: str = "fp64",
+                 cg_iters: int = 0):
+        self.A = A
+        self.M = A.scipy()
+        self.owner = np.asarray(owner, dtype=np.int32)
+        self.gamma = gamma
+        self.subs = []
+        for own, om, ext in subdomain_sets(A, self.owner, gamma):
+            Ap = local_matrix(A, om)
+            self.subs.append(Subdomain(own, om, ext, np.searchsorted(om, own), LocalSolver(Ap, local, storage, cg_iters)))
+
+    @property
+    def P(self) -> int:
+        return len(self.subs)
+
+    def residual(self, x: np.ndarray, b: np.ndarray) -> np.ndarray:
+        return b - self.M @ x
+
+    def local_residual(self, p: int, x: np.ndarray, b: np.ndarray) -> np.ndarray:
+        """R_p (b - A x): the rows of A on Omega_p read x on Omega_p and its external layer."""
+        om = self.subs[p].omega
+        return b[om] - self.M[om] @ x
+
+    # -- synchronous RAS -------------------------------------------------------------
+    def sync(self, b: np.ndarray, tol: float, max_sweeps: int, x0: np.ndarray | None = None):
+        """Returns (x, hist, sweeps): hist[k] = ||b - A x^k|| / ||b||, sweeps = updates applied."""
+        x = np.zeros_like(b) if x0 is None else x0.astype(np.float64).copy()
+        bn = np.linalg.norm(b)
+        hist = []
+        k = 0
+        while True:
+            r = self.residual(x, b)
+            hist.append(np.linalg.norm(r) / bn)
+            if hist[-1] < tol or k == max_sweeps:
+                return x, np.array(hist), k
+            x_next = x.copy()
+            for s in self.subs:
+                delta = s.solver(r[s.omega])
+                x_next[s.owned] += delta[s.pos]
+            x = x_next
+            k += 1
+
+    # -- restricted multiplicative Schwarz (ordered, in place) -------------------------
+    def ordered(self, b: np.ndarray, passes: int, x0: np.ndarray | None = None):
+        """`passes` full passes over p = 0..P-1, each local residual recomputed from the
+        current x.  Returns (x, hist) with hist[k] the relative residual before pass k."""
+        x = np.zeros_like(b) if x0 is None else x0.astype(np.float64).copy()
+        bn = np.linalg.norm(b)
+        hist = []
+        for _ in range(passes):
+            hist.append(np.linalg.norm(self.residual(x, b)) / bn)
+            for p, s in enumerate(self.subs):
+                delta = s.solver(self.local_residual(p, x, b))
+                x[s.owned] += delta[s.pos]
+        hist.append(np.linalg.norm(self.residual(x, b)) / bn)
+        return x, np.array(hist)
+
+    # -- seeded asynchronous simulator --------------------------------------------------
+    def async_sim(self, b: np.ndarray, tol: float, seed: int, staleness: int = 3, max_updates: int = 10**6,
+                  x0: np.ndarray | None = None, paused: set | None = None, pause_until: int = 0):
+        """Event-driven asynchronous RAS with bounded staleness.
+
+        Each event picks a subdomain at random; it reads every other subdomain's
+        owned values from one of that subdomain's last `staleness` published
+        versions (chosen at random), computes its local residual, records the local
+        criterion, solves and publishes its owned values.  Centralized detection:
+        once every subdomain's latest local criterion holds, the iteration stops and
+        the global criterion is verified on the current x; if it fails the iteration
+        resumes.  Subdomains in `paused` take no events before event `pause_until`
+        (forced staleness).  Returns (x, info dict)."""
+        rng = np.random.default_rng(seed)
+        x = np.zeros_like(b) if x0 is None else x0.astype(np.float64).copy()
+        bn2 = float(b @ b)
+        P = self.P
+        versions = [[x[s.owned].copy()] for s in self.subs]
+        conv = np.zeros(P, dtype=bool)
+        counts = np.zeros(P, dtype=np.int64)
+        verifications = 0
+        for ev in range(max_updates):
+            p = int(rng.integers(P))
+            if paused and p in paused and ev < pause_until:
+                continue
+            view = x.copy()
+            for q, sq in enumerate(self.subs):
+                if q == p:
+                    continue
+                hist_q = versions[q]
+                pick = hist_q[-1 - int(rng.integers(min(staleness, len(hist_q))))]
+                view[sq.owned] = pick
+            s = self.subs[p]
+            rp = b[s.omega] - self.M[s.omega] @ view
+            conv[p] = float(rp @ rp) < tol * tol * float(b[s.omega] @ b[s.omega])
+            delta = s.solver(rp)
+            x[s.owned] += delta[s.pos]
+            versions[p].append(x[s.owned].copy())
+            if len(versions[p]) > staleness:
+                versions[p].pop(0)
+            counts[p] += 1
+            if conv.all():
+                verifications += 1
+                r = self.residual(x, b)
+                if float(r @ r) < tol * tol * bn2:
+                    return x, dict(converged=True, events=ev + 1, local_solves=counts, verifications=verifications,
+                                   relres=np.sqrt(float(r @ r) / bn2))
+                conv[:] = False
+        r = self.residual(x, b)
+        return x, dict(converged=False, events=max_updates, local_solves=counts, verifications=verifications,
+                       relres=np.sqrt(float(r @ r) / bn2))
+
+
+def direct_solve(A, b: np.ndarray) -> np.ndarray:
+    """FP64 direct reference solution: dense LU for n <= 4096, sparse LU otherwise."""
+    if A.n <= 4096:
+        return np.linalg.solve(A.scipy().toarray(), b)
+    return spla.splu(A.scipy().tocsc()).solve(b)
+
+
+def relative_residual(A, x: np.ndarray, b: np.ndarray) -> float:
+    return float(np.linalg.norm(b - A.scipy() @ x) / np.linalg.norm(b))
