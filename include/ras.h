@@ -1,0 +1,219 @@
+/*
+ * ras.h -- C ABI of an MI355X (gfx950) restricted additive Schwarz solver.
+ *
+ * The method is the restricted additive Schwarz (RAS) iteration of Cai and
+ * Sarkis as used by Nayak, Cojean and Anzt, "Evaluating Abstract Asynchronous
+ * Schwarz solvers" (arXiv 2003.05361): the unknowns of A x = b (Sec. 2.1,
+ * eq. lin_sys) are partitioned into subdomains (Sec. 3.2.1), each subdomain is
+ * grown by `overlap` layers (Sec. 2.1, Fig. 1), every subdomain solves its
+ * local problem (Sec. 3.3.1) and writes back only the points it owns
+ * (Sec. 2.1).  The synchronous variant applies all local updates of a sweep
+ * from the same iterate; the asynchronous variant lets each subdomain proceed
+ * with whatever neighbour values are current (Sec. 2.1, Sec. 3.4).  Both run
+ * as one persistent GPU kernel holding every subdomain of the problem.
+ *
+ * Conventions for every entry point:
+ *   - every call returns ras_status and never throws or aborts;
+ *     ras_last_error() returns a thread-local message for the last failure;
+ *   - status < 0: error, outputs untouched; status > 0: outputs valid, warning;
+ *   - host pointers are borrowed for the duration of the call only; the
+ *     library copies what it keeps;
+ *   - device pointers (suffix _dev) are caller-owned, contiguous float64,
+ *     right-hand side j of a multi-RHS call at offset j*n, and are used on the
+ *     stream given at setup;
+ *   - a handle is used by one host thread at a time; distinct handles are
+ *     independent.
+ */
+#ifndef RAS_H
+#define RAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ras_status {
+    RAS_OK = 0,
+    RAS_NOT_CONVERGED = 1, /* tolerance not reached within max_sweeps / max_seconds; x valid */
+    RAS_PENDING = 2,       /* serving: result not ready yet */
+    RAS_E_ARG = -1,        /* invalid argument (sizes, null pointers, options) */
+    RAS_E_PATTERN = -2,    /* CSR pattern invalid: unsorted, duplicate, out of range, unsymmetric */
+    RAS_E_NOT_SPD = -3,    /* non-positive Cholesky pivot in a local factorisation */
+    RAS_E_NOMEM = -4,      /* host or device allocation failed, or over a memory budget */
+    RAS_E_HIP = -5,        /* a HIP runtime call failed (message names it) */
+    RAS_E_STATE = -6,      /* wrong object state (e.g. handle without a device) */
+    RAS_E_DIVERGED = -7,   /* non-finite residual */
+    RAS_E_UNSUPPORTED = -8 /* shape outside the kernels' documented limits */
+} ras_status;
+
+/* Global matrix A of A x = b (Sec. 2.1, eq. lin_sys): square, symmetric
+ * positive definite, CSR with n+1 monotone int64 row pointers, column indices
+ * sorted and unique within each row, a symmetric pattern, float64 values.  */
+typedef struct ras_csr {
+    int64_t n;
+    const int64_t* row_ptr;
+    const int32_t* col;
+    const double* val;
+} ras_csr;
+
+/* Partition into owned sets (Sec. 3.2.1).
+ *   REGULAR_1D: parts[0] = P; part p owns rows [floor(p n / P), floor((p+1) n / P)).
+ *   REGULAR_2D / REGULAR_3D: grid = (nx, ny, nz) with nx*ny*nz == n in natural
+ *     order g = i + nx (j + ny k); parts = (px, py, pz); axis bounds
+ *     floor(s N_axis / p_axis); subdomain id ix + px (iy + py iz).
+ *   RCB: recursive coordinate bisection of the grid points into parts[0] parts
+ *     with part weights 1 + jitter (2u - 1), u from SplitMix64(seed) (stand-in
+ *     for the paper's edge-cut partitioner).
+ *   EXPLICIT: owner[n] given, ids in [0, parts[0]), every part non-empty.  */
+enum { RAS_PART_REGULAR_1D = 0, RAS_PART_REGULAR_2D = 1, RAS_PART_REGULAR_3D = 2, RAS_PART_RCB = 3,
+       RAS_PART_EXPLICIT = 4 };
+typedef struct ras_partition {
+    int32_t kind;
+    int32_t grid[3];
+    int32_t parts[3];
+    int32_t reserved;
+    uint64_t seed;
+    double jitter;
+    const int32_t* owner;
+} ras_partition;
+
+/* Local solver (Sec. 3.3.1): a Cholesky factor of the local matrix computed
+ * once at setup and applied by two banded triangular solves per local solve,
+ * or cg_iters steps of conjugate gradients from a zero initial guess.
+ * storage: FP64, FP32 (float32 values and float32 local arithmetic) or
+ * FP16_ROWSCALED (factor rows scaled by their float32 max-abs, entries
+ * rounded to float16, float32 arithmetic; banded Cholesky only).  The outer
+ * residual, update and convergence test are always float64.  */
+enum { RAS_LOCAL_CHOL_BANDED = 0, RAS_LOCAL_CG = 1 };
+enum { RAS_STORAGE_FP64 = 0, RAS_STORAGE_FP32 = 1, RAS_STORAGE_FP16_ROWSCALED = 2 };
+typedef struct ras_local {
+    int32_t kind;
+    int32_t cg_iters;
+    int32_t storage;
+    int32_t reserved;
+} ras_local;
+
+/* Solve options.
+ *   mode SYNC: one grid barrier per sweep, every local solve of sweep k reads
+ *     x^k (Sec. 2.1, Sec. 3.4 synchronous); stops at the first k with
+ *     ||b - A x^k|| < tol ||b|| and returns x^k.
+ *   mode ASYNC: persistent kernel without a barrier; each subdomain reads the
+ *     current neighbour values (Sec. 2.1, Sec. 3.4 asynchronous).  Stops when
+ *     the detector (detect) sees every subdomain locally converged
+ *     (||r_p||^2 < tol^2 ||b_p||^2, Sec. 3.3.2, eq. local_conv); the global
+ *     criterion is then verified and the iteration resumes if it fails.
+ *   mode ORDERED: the asynchronous kernel run by one workgroup visiting the
+ *     subdomains in order (restricted multiplicative Schwarz; deterministic).
+ *   max_sweeps: sweeps (SYNC) or local solves per subdomain (ASYNC/ORDERED).
+ *   max_seconds <= 0: no time limit.  workgroups: 0 = library choice.  */
+enum { RAS_MODE_SYNC = 0, RAS_MODE_ASYNC = 1, RAS_MODE_ORDERED = 2 };
+enum { RAS_DETECT_CENTRAL = 0, RAS_DETECT_DECENTRAL = 1 };
+typedef struct ras_solve_opts {
+    int32_t mode;
+    int32_t detect;
+    double tol;
+    int64_t max_sweeps;
+    double max_seconds;
+    int32_t workgroups;
+    int32_t reserved;
+} ras_solve_opts;
+
+typedef struct ras_solve_info {
+    int32_t converged;
+    int32_t launches;          /* persistent-kernel launches (resumes after failed verification + 1) */
+    int64_t sweeps;            /* SYNC: updates applied; ASYNC: max local solves of any subdomain */
+    int64_t total_local_solves;
+    int64_t min_local_solves;
+    int64_t max_local_solves;
+    double rel_residual;       /* exact float64 ||b - A x|| / ||b|| recomputed after the stop */
+    double seconds;            /* device time of the solve (first launch to verified stop) */
+} ras_solve_info;
+
+/* Host-side setup summary. */
+typedef struct ras_plan_stats {
+    int64_t n;
+    int64_t nnz;
+    int32_t parts;
+    int32_t max_ell_width;
+    int64_t sum_local_rows;    /* sum_p |Omega_p| */
+    int64_t min_local_rows;
+    int64_t max_local_rows;
+    int32_t max_band;          /* max lower half-bandwidth of the local matrices */
+    int32_t reserved;
+    int64_t band_entries;      /* sum_p |Omega_p| (w_p + 1) */
+    int64_t device_bytes;      /* device memory the handle allocates for the matrix data */
+} ras_plan_stats;
+
+typedef struct ras_plan ras_plan;
+typedef struct ras_handle ras_handle;
+
+/* ---- host-only setup (no GPU needed; Sec. 3.2) ---------------------------------
+ * Validates A, partitions (Sec. 3.2.1), grows each owned set by `overlap`
+ * breadth-first layers over A's pattern (Sec. 2.1, Fig. 1), orders each local
+ * set by ascending global id, extracts the local matrices (Sec. 3.2.2) and,
+ * for the Cholesky solver, factors them in float64 (Sec. 3.3.1).  */
+ras_status ras_plan_create(const ras_csr* A, const ras_partition* part, int32_t overlap, const ras_local* local,
+                           ras_plan** out);
+ras_status ras_plan_get_stats(const ras_plan* plan, ras_plan_stats* out);
+/* Index sets: owner[n] (int32), omega_ptr[P+1] (int64), omega_idx[sum |Omega_p|]
+ * (int32, ascending per subdomain).  Any output may be NULL.  */
+ras_status ras_plan_sets(const ras_plan* plan, int32_t* owner, int64_t* omega_ptr, int32_t* omega_idx);
+/* Float64 band factor of subdomain p: band[i*(w+1) + (j - i + w)] = L_ij for
+ * i-w <= j <= i (zero outside the matrix); *w receives the half-bandwidth.
+ * band may be NULL to query w.  RAS_E_STATE unless the solver is Cholesky.  */
+ras_status ras_plan_factor(const ras_plan* plan, int32_t p, double* band, int32_t* w);
+/* FP16_ROWSCALED storage of subdomain p's factor, in the same band layout:
+ * half_bits[i*(w+1) + o] = float16 bits of L_ij / scale[i] (round to nearest
+ * even from float64), scale[i] = float32(max_j |L_ij|) (1 for an all-zero row).
+ * RAS_E_STATE unless the solver is Cholesky with FP16_ROWSCALED storage.  */
+ras_status ras_plan_factor_fp16(const ras_plan* plan, int32_t p, uint16_t* half_bits, float* scale);
+void ras_plan_destroy(ras_plan* plan);
+
+/* ---- device setup and solve ------------------------------------------------------
+ * ras_setup = ras_plan_create + upload; the handle owns every device array it
+ * allocates.  hip_stream may be NULL (default stream).  */
+ras_status ras_setup(const ras_csr* A, const ras_partition* part, int32_t overlap, const ras_local* local,
+                     void* hip_stream, ras_handle** out);
+/* Uploads a plan; the plan stays owned by the caller.  */
+ras_status ras_setup_from_plan(const ras_plan* plan, void* hip_stream, ras_handle** out);
+ras_status ras_handle_get_stats(const ras_handle* h, ras_plan_stats* out);
+
+/* Solves A x = b for nrhs right-hand sides (Alg. 1's SOLVE).  x_dev holds the
+ * initial guess on entry and the result on return; info[nrhs].  Blocks the
+ * calling thread until the result is on the device and info is filled.  */
+ras_status ras_solve(ras_handle* h, const double* b_dev, double* x_dev, int32_t nrhs, const ras_solve_opts* opts,
+                     ras_solve_info* info);
+
+/* Several systems (handles) in one persistent launch; handles must share the
+ * local solver kind and storage.  b[i], x[i] are device arrays of handle i
+ * with nrhs[i] right-hand sides; info has sum(nrhs) entries, in order.  */
+ras_status ras_batch_solve(int32_t m, ras_handle* const* hs, const double* const* b_dev, double* const* x_dev,
+                           const int32_t* nrhs, const ras_solve_opts* opts, ras_solve_info* info);
+
+/* Residual history of right-hand side `rhs` of the last solve: SYNC, one entry
+ * per sweep (exact ||b - A x^k|| / ||b||); ASYNC, one entry per detector
+ * check (estimate from the latest subdomain residuals, a mix of times) and a
+ * final exact entry per verification.  t_sec (may be NULL) gets seconds since
+ * the first launch.  *len = entries available; at most cap are copied.  */
+ras_status ras_residual_history(const ras_handle* h, int32_t rhs, double* t_sec, double* relres, int64_t cap,
+                                int64_t* len);
+/* Local solves completed by each subdomain in the last solve (Sec. 4.5/4.6,
+ * "subdomain update" counts); counts[P].  */
+ras_status ras_local_solve_counts(const ras_handle* h, int32_t rhs, int64_t* counts);
+ras_status ras_partition_sets(const ras_handle* h, int32_t* owner, int64_t* omega_ptr, int32_t* omega_idx);
+/* Exact ||b - A x|| / ||b|| of device vectors (the post-termination check of
+ * Sec. 3.3.2), computed by the library's verification kernel.  */
+ras_status ras_relative_residual(ras_handle* h, const double* b_dev, const double* x_dev, double* relres);
+void ras_destroy(ras_handle* h);
+
+const char* ras_last_error(void);
+/* Library version string. */
+const char* ras_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAS_H */

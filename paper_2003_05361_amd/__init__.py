@@ -1,0 +1,360 @@
+"""Python binding of the MI355X restricted additive Schwarz library (libras.so).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels and C++ setup code.  torch supplies device memory and streams.  The
+library must have been built (``python -m paper_2003_05361_amd.build``); a
+missing library is an error, never a fallback.
+
+    import paper_2003_05361_amd as ras
+    h = ras.setup(A, ras.partition("regular_2d", (8, 8), grid=A.grid), overlap=4,
+                  local=ras.local("cg", "fp64", 10))
+    x, info = h.solve(b_cuda, tol=1e-8, mode="async")
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libras.so")
+
+# ----------------------------------------------------------------------------- C mirrors
+RAS_OK, RAS_NOT_CONVERGED, RAS_PENDING = 0, 1, 2
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "PENDING", -1: "E_ARG", -2: "E_PATTERN", -3: "E_NOT_SPD",
+                -4: "E_NOMEM", -5: "E_HIP", -6: "E_STATE", -7: "E_DIVERGED", -8: "E_UNSUPPORTED"}
+PART_KINDS = {"regular_1d": 0, "regular_2d": 1, "regular_3d": 2, "rcb": 3, "explicit": 4}
+LOCAL_KINDS = {"chol": 0, "cg": 1}
+STORAGES = {"fp64": 0, "fp32": 1, "fp16": 2}
+MODES = {"sync": 0, "async": 1, "ordered": 2}
+DETECT = {"central": 0, "decentral": 1}
+
+
+class CSRStruct(C.Structure):
+    _fields_ = [("n", C.c_int64), ("row_ptr", C.POINTER(C.c_int64)), ("col", C.POINTER(C.c_int32)),
+                ("val", C.POINTER(C.c_double))]
+
+
+class PartitionStruct(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("grid", C.c_int32 * 3), ("parts", C.c_int32 * 3), ("reserved", C.c_int32),
+                ("seed", C.c_uint64), ("jitter", C.c_double), ("owner", C.POINTER(C.c_int32))]
+
+
+class LocalStruct(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("cg_iters", C.c_int32), ("storage", C.c_int32), ("reserved", C.c_int32)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("detect", C.c_int32), ("tol", C.c_double), ("max_sweeps", C.c_int64),
+                ("max_seconds", C.c_double), ("workgroups", C.c_int32), ("reserved", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("converged", C.c_int32), ("launches", C.c_int32), ("sweeps", C.c_int64),
+                ("total_local_solves", C.c_int64), ("min_local_solves", C.c_int64),
+                ("max_local_solves", C.c_int64), ("rel_residual", C.c_double), ("seconds", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class PlanStats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("parts", C.c_int32), ("max_ell_width", C.c_int32),
+                ("sum_local_rows", C.c_int64), ("min_local_rows", C.c_int64), ("max_local_rows", C.c_int64),
+                ("max_band", C.c_int32), ("reserved", C.c_int32), ("band_entries", C.c_int64),
+                ("device_bytes", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+# every symbol the header declares, with its ctypes signature
+_P = C.c_void_p
+SIGNATURES = {
+    "ras_plan_create": (C.c_int, [C.POINTER(CSRStruct), C.POINTER(PartitionStruct), C.c_int32,
+                                  C.POINTER(LocalStruct), C.POINTER(_P)]),
+    "ras_plan_get_stats": (C.c_int, [_P, C.POINTER(PlanStats)]),
+    "ras_plan_sets": (C.c_int, [_P, _P, _P, _P]),
+    "ras_plan_factor": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int32)]),
+    "ras_plan_factor_fp16": (C.c_int, [_P, C.c_int32, _P, _P]),
+    "ras_plan_destroy": (None, [_P]),
+    "ras_setup": (C.c_int, [C.POINTER(CSRStruct), C.POINTER(PartitionStruct), C.c_int32, C.POINTER(LocalStruct),
+                            _P, C.POINTER(_P)]),
+    "ras_setup_from_plan": (C.c_int, [_P, _P, C.POINTER(_P)]),
+    "ras_handle_get_stats": (C.c_int, [_P, C.POINTER(PlanStats)]),
+    "ras_solve": (C.c_int, [_P, _P, _P, C.c_int32, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
+    "ras_batch_solve": (C.c_int, [C.c_int32, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.POINTER(C.c_int32),
+                                  C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
+    "ras_residual_history": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int64, C.POINTER(C.c_int64)]),
+    "ras_local_solve_counts": (C.c_int, [_P, C.c_int32, _P]),
+    "ras_partition_sets": (C.c_int, [_P, _P, _P, _P]),
+    "ras_relative_residual": (C.c_int, [_P, _P, _P, C.POINTER(C.c_double)]),
+    "ras_destroy": (None, [_P]),
+    "ras_last_error": (C.c_char_p, []),
+    "ras_version": (C.c_char_p, []),
+}
+
+_lib_handle = None
+
+
+class RasError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib() -> C.CDLL:
+    """The loaded native library; raises if it has not been built."""
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"native library missing: {LIB_PATH} (build it with python -m paper_2003_05361_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib_handle = L
+    return _lib_handle
+
+
+def _check(st: int, allow=(RAS_OK,)) -> int:
+    if st not in allow:
+        raise RasError(st, lib().ras_last_error().decode())
+    return st
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+# ----------------------------------------------------------------------------- descriptions
+def partition(kind: str, parts, grid=(1, 1, 1), seed: int = 0, jitter: float = 0.0, owner=None) -> dict:
+    """Partition description (Sec. 3.2.1): kind in regular_1d / regular_2d / regular_3d / rcb / explicit."""
+    if kind not in PART_KINDS:
+        raise ValueError(kind)
+    parts = tuple(parts) if isinstance(parts, (tuple, list)) else (int(parts),)
+    return dict(kind=kind, parts=parts, grid=tuple(grid), seed=int(seed), jitter=float(jitter), owner=owner)
+
+
+def local(kind: str = "chol", storage: str = "fp64", cg_iters: int = 0) -> dict:
+    """Local solver (Sec. 3.3.1): banded Cholesky ("chol") or fixed-k CG ("cg"); storage fp64/fp32/fp16."""
+    if kind not in LOCAL_KINDS or storage not in STORAGES:
+        raise ValueError((kind, storage))
+    return dict(kind=kind, storage=storage, cg_iters=int(cg_iters))
+
+
+class _Keep:
+    """Host arrays that must stay alive while the C call runs."""
+
+    def __init__(self):
+        self.refs = []
+
+    def add(self, a):
+        self.refs.append(a)
+        return a
+
+
+def _csr(A, keep: _Keep) -> CSRStruct:
+    if hasattr(A, "indptr") and hasattr(A, "indices"):
+        indptr, indices, data = A.indptr, A.indices, A.data
+        n = len(indptr) - 1
+    else:
+        raise TypeError("A must be a CSR matrix (scipy.sparse.csr_matrix or ras_inputs.CSR)")
+    rp = keep.add(np.ascontiguousarray(indptr, dtype=np.int64))
+    ci = keep.add(np.ascontiguousarray(indices, dtype=np.int32))
+    va = keep.add(np.ascontiguousarray(data, dtype=np.float64))
+    return CSRStruct(n, _ptr(rp, C.c_int64), _ptr(ci, C.c_int32), _ptr(va, C.c_double))
+
+
+def _part(p: dict, A, keep: _Keep) -> PartitionStruct:
+    s = PartitionStruct()
+    s.kind = PART_KINDS[p["kind"]]
+    grid = p.get("grid") or getattr(A, "grid", (1, 1, 1))
+    if tuple(grid) == (1, 1, 1) and hasattr(A, "grid"):
+        grid = A.grid
+    g = (tuple(grid) + (1, 1, 1))[:3]
+    s.grid[:] = [int(v) for v in g]
+    parts = (tuple(p["parts"]) + (1, 1, 1))[:3]
+    s.parts[:] = [int(v) for v in parts]
+    s.seed = p.get("seed", 0)
+    s.jitter = p.get("jitter", 0.0)
+    if p.get("owner") is not None:
+        o = keep.add(np.ascontiguousarray(p["owner"], dtype=np.int32))
+        s.owner = _ptr(o, C.c_int32)
+    return s
+
+
+def _local(l: dict) -> LocalStruct:
+    return LocalStruct(LOCAL_KINDS[l["kind"]], int(l.get("cg_iters", 0)), STORAGES[l.get("storage", "fp64")], 0)
+
+
+# ----------------------------------------------------------------------------- host-only plan
+class Plan:
+    """Host-side setup (no GPU): partition, overlap, local matrices, factors."""
+
+    def __init__(self, A, part: dict, overlap: int, loc: dict):
+        keep = _Keep()
+        ptr = _P()
+        _check(lib().ras_plan_create(C.byref(_csr(A, keep)), C.byref(_part(part, A, keep)), int(overlap),
+                                     C.byref(_local(loc)), C.byref(ptr)))
+        self._p = ptr
+        self.n = len(A.indptr) - 1
+
+    def stats(self) -> dict:
+        s = PlanStats()
+        _check(lib().ras_plan_get_stats(self._p, C.byref(s)))
+        return s.as_dict()
+
+    def sets(self):
+        st = self.stats()
+        owner = np.empty(self.n, dtype=np.int32)
+        ptr = np.empty(st["parts"] + 1, dtype=np.int64)
+        idx = np.empty(st["sum_local_rows"], dtype=np.int32)
+        _check(lib().ras_plan_sets(self._p, owner.ctypes.data, ptr.ctypes.data, idx.ctypes.data))
+        return owner, ptr, idx
+
+    def factor(self, p: int) -> tuple[np.ndarray, int]:
+        w = C.c_int32()
+        _check(lib().ras_plan_factor(self._p, p, None, C.byref(w)))
+        owner, ptr, _ = self.sets()
+        n = int(ptr[p + 1] - ptr[p])
+        band = np.empty((n, w.value + 1))
+        _check(lib().ras_plan_factor(self._p, p, band.ctypes.data, C.byref(w)))
+        return band, w.value
+
+    def factor_fp16(self, p: int) -> tuple[np.ndarray, np.ndarray]:
+        band, w = self.factor(p)
+        bits = np.empty(band.shape, dtype=np.uint16)
+        scale = np.empty(band.shape[0], dtype=np.float32)
+        _check(lib().ras_plan_factor_fp16(self._p, p, bits.ctypes.data, scale.ctypes.data))
+        return bits, scale
+
+    def setup(self, stream=None) -> "Handle":
+        h = _P()
+        _check(lib().ras_setup_from_plan(self._p, _stream_ptr(stream), C.byref(h)))
+        return Handle(h, self.n)
+
+    def close(self):
+        if getattr(self, "_p", None):
+            lib().ras_plan_destroy(self._p)
+            self._p = None
+
+    __del__ = close
+
+
+# ----------------------------------------------------------------------------- device handle
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+def _opts(tol, mode, max_sweeps, max_seconds, detect, workgroups) -> SolveOpts:
+    return SolveOpts(MODES[mode], DETECT[detect], float(tol), int(max_sweeps), float(max_seconds), int(workgroups), 0)
+
+
+class Handle:
+    """A system set up on the device (Alg. 1's INITIALIZATION_AND_SETUP done)."""
+
+    def __init__(self, ptr, n: int):
+        self._h = ptr
+        self.n = n
+        self.last_nrhs = 0
+
+    def stats(self) -> dict:
+        s = PlanStats()
+        _check(lib().ras_handle_get_stats(self._h, C.byref(s)))
+        return s.as_dict()
+
+    def solve(self, b, x0=None, tol: float = 1e-8, mode: str = "async", max_sweeps: int = 1_000_000,
+              max_seconds: float = 0.0, detect: str = "central", workgroups: int = 0, allow_unconverged=True):
+        """Solve A x = b on the device.  b: float64 CUDA tensor [n] or [nrhs, n].
+        Returns (x, infos) with x the same shape as b."""
+        import torch
+
+        if b.device.type != "cuda" or b.dtype != torch.float64:
+            raise TypeError("b must be a float64 CUDA tensor")
+        b = b.contiguous()
+        nrhs = 1 if b.dim() == 1 else b.shape[0]
+        x = torch.zeros_like(b) if x0 is None else x0.to(torch.float64).contiguous().clone()
+        infos = (SolveInfo * nrhs)()
+        st = lib().ras_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), nrhs,
+                             C.byref(_opts(tol, mode, max_sweeps, max_seconds, detect, workgroups)), infos)
+        _check(st, (RAS_OK, RAS_NOT_CONVERGED) if allow_unconverged else (RAS_OK,))
+        self.last_nrhs = nrhs
+        return x, [i.as_dict() for i in infos]
+
+    def residual_history(self, rhs: int = 0) -> tuple[np.ndarray, np.ndarray]:
+        n = C.c_int64()
+        _check(lib().ras_residual_history(self._h, rhs, None, None, 0, C.byref(n)))
+        t = np.empty(n.value)
+        r = np.empty(n.value)
+        _check(lib().ras_residual_history(self._h, rhs, t.ctypes.data, r.ctypes.data, n.value, C.byref(n)))
+        return t, r
+
+    def local_solve_counts(self, rhs: int = 0) -> np.ndarray:
+        c = np.empty(self.stats()["parts"], dtype=np.int64)
+        _check(lib().ras_local_solve_counts(self._h, rhs, c.ctypes.data))
+        return c
+
+    def partition_sets(self):
+        st = self.stats()
+        owner = np.empty(self.n, dtype=np.int32)
+        ptr = np.empty(st["parts"] + 1, dtype=np.int64)
+        idx = np.empty(st["sum_local_rows"], dtype=np.int32)
+        _check(lib().ras_partition_sets(self._h, owner.ctypes.data, ptr.ctypes.data, idx.ctypes.data))
+        return owner, ptr, idx
+
+    def relative_residual(self, b, x) -> float:
+        r = C.c_double()
+        _check(lib().ras_relative_residual(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                                           C.byref(r)))
+        return r.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ras_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+
+def setup(A, part: dict, overlap: int, loc: dict, stream=None) -> Handle:
+    keep = _Keep()
+    h = _P()
+    _check(lib().ras_setup(C.byref(_csr(A, keep)), C.byref(_part(part, A, keep)), int(overlap),
+                           C.byref(_local(loc)), _stream_ptr(stream), C.byref(h)))
+    return Handle(h, len(A.indptr) - 1)
+
+
+def batch_solve(handles: Sequence[Handle], bs, xs=None, tol: float = 1e-8, mode: str = "async",
+                max_sweeps: int = 1_000_000, max_seconds: float = 0.0, detect: str = "central", workgroups: int = 0):
+    """Solve several systems in one persistent launch (same local solver kind/storage)."""
+    import torch
+
+    m = len(handles)
+    bs = [b.contiguous() for b in bs]
+    xs = [torch.zeros_like(b) for b in bs] if xs is None else [x.contiguous() for x in xs]
+    nr = [1 if b.dim() == 1 else b.shape[0] for b in bs]
+    H = (_P * m)(*[h._h for h in handles])
+    B = (_P * m)(*[b.data_ptr() for b in bs])
+    X = (_P * m)(*[x.data_ptr() for x in xs])
+    NR = (C.c_int32 * m)(*nr)
+    infos = (SolveInfo * sum(nr))()
+    st = lib().ras_batch_solve(m, H, B, X, NR, C.byref(_opts(tol, mode, max_sweeps, max_seconds, detect, workgroups)),
+                               infos)
+    _check(st, (RAS_OK, RAS_NOT_CONVERGED))
+    out, k = [], 0
+    for r in nr:
+        out.append([infos[k + j].as_dict() for j in range(r)])
+        k += r
+    return xs, out
+
+
+def version() -> str:
+    return lib().ras_version().decode()

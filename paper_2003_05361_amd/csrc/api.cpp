@@ -1,0 +1,927 @@
+// C ABI of the restricted additive Schwarz solver: setup (host plan + upload),
+// solve (work tables, persistent launch, verification / resume), queries.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <queue>
+#include <string>
+#include <vector>
+
+#include "../../include/ras.h"
+#include "device.hpp"
+#include "plan.hpp"
+
+namespace ras {
+// kernels.hip
+const void* select_kernel(int solver, int storage, bool async, int ell_width);
+hipError_t launch_solver(const void* kern, int solver, const Params& P, int max_w, int winm, size_t lds,
+                         hipStream_t st, bool coop);
+hipError_t occupancy(const void* kern, int solver, size_t lds, int* per_cu);
+hipError_t launch_residual(int64_t n, const int64_t* rp, const int32_t* ci, const double* va, const double* b,
+                           const double* x, double* parts, int nparts, double* out, hipStream_t st);
+hipError_t launch_copy(int64_t n, const double* src, double* dst, hipStream_t st);
+hipError_t launch_stamp(InstState* ist, int n, hipStream_t st);
+}  // namespace ras
+
+using namespace ras;
+
+namespace {
+
+thread_local std::string g_err;
+
+ras_status fail(ras_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) throw Error{RAS_E_HIP, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+// Owning device allocation.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { reset(); }
+    void reset() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t n) {
+        reset();
+        if (n == 0) return;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            throw Error{RAS_E_NOMEM, "hipMalloc(" + std::to_string(n) + " bytes) failed: " + hipGetErrorString(e)};
+        }
+        bytes = n;
+    }
+    void ensure(size_t n) {
+        if (bytes < n) alloc(n);
+    }
+    template <class T>
+    T* as() const {
+        return static_cast<T*>(p);
+    }
+};
+
+size_t ct_size(int storage) { return storage == RAS_STORAGE_FP64 ? 8 : 4; }
+
+int next_pow2(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+struct ras_plan : public Plan {};
+
+struct ras_handle {
+    std::unique_ptr<ras_plan> plan;  // host plan (factors dropped after upload)
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int64_t clock_khz = 0;
+    int num_cu = 0;
+    int solver = 0, storage = 0, cg_iters = 0;
+    int max_n = 0, max_w = 0, max_K = 0, uniform_K = 0;
+    int64_t sum_n = 0;
+    ras_plan_stats stats{};
+    DevBuf omega, ell_val, ell_valf, ell_gcol, ell_lcol, band_f, band_b, scale, invd;
+    DevBuf csr_rp, csr_ci, csr_va;
+    std::vector<SubDev> subs;  // host copy with device pointers
+    // last solve
+    std::vector<std::vector<double>> hist, hist_t;
+    std::vector<std::vector<int64_t>> counts;
+    // reusable per-solve workspace
+    DevBuf ws_x1, ws_scratch, ws_hist, ws_red;
+};
+
+namespace {
+
+template <class F>
+ras_status guarded(F&& f) {
+    try {
+        return f();
+    } catch (const Error& e) {
+        return fail(e.status, e.msg);
+    } catch (const std::bad_alloc&) {
+        return fail(RAS_E_NOMEM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return fail(RAS_E_ARG, e.what());
+    }
+}
+
+void build_plan(const ras_csr* A, const ras_partition* part, int32_t overlap, const ras_local* local, Plan& plan) {
+    if (!A || !part || !local) throw Error{RAS_E_ARG, "null argument"};
+    if (overlap < 0) throw Error{RAS_E_ARG, "overlap must be >= 0"};
+    if (local->kind != RAS_LOCAL_CHOL_BANDED && local->kind != RAS_LOCAL_CG) throw Error{RAS_E_ARG, "unknown local solver"};
+    if (local->storage < RAS_STORAGE_FP64 || local->storage > RAS_STORAGE_FP16_ROWSCALED)
+        throw Error{RAS_E_ARG, "unknown storage"};
+    if (local->kind == RAS_LOCAL_CG && local->storage == RAS_STORAGE_FP16_ROWSCALED)
+        throw Error{RAS_E_ARG, "FP16_ROWSCALED storage applies to the Cholesky factor only"};
+    if (local->kind == RAS_LOCAL_CG && local->cg_iters < 1) throw Error{RAS_E_ARG, "cg_iters must be >= 1"};
+    validate_csr(*A);
+    plan.n = A->n;
+    plan.nnz = A->row_ptr[A->n];
+    plan.overlap = overlap;
+    plan.local = *local;
+    plan.row_ptr.assign(A->row_ptr, A->row_ptr + A->n + 1);
+    plan.col.assign(A->col, A->col + plan.nnz);
+    plan.val.assign(A->val, A->val + plan.nnz);
+    plan.owner = make_owner(*A, *part, &plan.P);
+    build_overlap(plan);
+    if (local->kind == RAS_LOCAL_CHOL_BANDED) factor_local(plan);
+}
+
+void plan_stats(const Plan& plan, ras_plan_stats* o) {
+    std::memset(o, 0, sizeof(*o));
+    o->n = plan.n;
+    o->nnz = plan.nnz;
+    o->parts = plan.P;
+    o->min_local_rows = INT64_MAX;
+    for (const auto& s : plan.subs) {
+        const int64_t n = static_cast<int64_t>(s.omega.size());
+        o->max_ell_width = std::max(o->max_ell_width, s.ell_width);
+        o->sum_local_rows += n;
+        o->min_local_rows = std::min(o->min_local_rows, n);
+        o->max_local_rows = std::max(o->max_local_rows, n);
+        o->max_band = std::max(o->max_band, s.w);
+        o->band_entries += n * (s.w + 1);
+    }
+}
+
+int64_t n_pad_of(int64_t n) { return (n + 63) / 64 * 64; }
+
+// Upload the plan: ELL rows of A on every overlapping set, local column map,
+// factors in the storage type (forward L and reversed transpose), global CSR.
+void upload(ras_handle& h, const Plan& plan) {
+    const int P = plan.P;
+    const bool chol = plan.local.kind == RAS_LOCAL_CHOL_BANDED;
+    const int st = plan.local.storage;
+    h.solver = plan.local.kind;
+    h.storage = st;
+    h.cg_iters = plan.local.cg_iters;
+    std::vector<int64_t> row_off(P + 1, 0), ell_off(P + 1, 0), band_off(P + 1, 0);
+    int uniformK = -1;
+    for (int p = 0; p < P; ++p) {
+        const auto& s = plan.subs[p];
+        const int64_t n = static_cast<int64_t>(s.omega.size());
+        row_off[p + 1] = row_off[p] + n;
+        ell_off[p + 1] = ell_off[p] + n_pad_of(n) * s.ell_width;
+        band_off[p + 1] = band_off[p] + (chol ? n * (s.w + 1) : 0);
+        h.max_n = std::max<int>(h.max_n, static_cast<int>(n));
+        h.max_w = std::max(h.max_w, s.w);
+        h.max_K = std::max(h.max_K, s.ell_width);
+        if (uniformK == -1) uniformK = s.ell_width;
+        else if (uniformK != s.ell_width) uniformK = 0;
+    }
+    h.uniform_K = uniformK > 0 ? uniformK : 0;
+    h.sum_n = row_off[P];
+    const size_t cts = ct_size(st);
+    const size_t sts = st == RAS_STORAGE_FP64 ? 8 : st == RAS_STORAGE_FP32 ? 4 : 2;
+    h.omega.alloc(row_off[P] * sizeof(int32_t));
+    h.ell_val.alloc(ell_off[P] * sizeof(double));
+    if (!chol && st == RAS_STORAGE_FP32) h.ell_valf.alloc(ell_off[P] * sizeof(float));
+    h.ell_gcol.alloc(ell_off[P] * sizeof(int32_t));
+    h.ell_lcol.alloc(ell_off[P] * sizeof(int32_t));
+    if (chol) {
+        h.band_f.alloc(band_off[P] * sts);
+        h.band_b.alloc(band_off[P] * sts);
+        h.invd.alloc(row_off[P] * cts);
+        if (st == RAS_STORAGE_FP16_ROWSCALED) h.scale.alloc(row_off[P] * sizeof(float));
+    }
+    h.csr_rp.alloc((plan.n + 1) * sizeof(int64_t));
+    h.csr_ci.alloc(plan.nnz * sizeof(int32_t));
+    h.csr_va.alloc(plan.nnz * sizeof(double));
+    hip_check(hipMemcpy(h.csr_rp.p, plan.row_ptr.data(), (plan.n + 1) * sizeof(int64_t), hipMemcpyHostToDevice),
+              "copy row_ptr");
+    hip_check(hipMemcpy(h.csr_ci.p, plan.col.data(), plan.nnz * sizeof(int32_t), hipMemcpyHostToDevice), "copy col");
+    hip_check(hipMemcpy(h.csr_va.p, plan.val.data(), plan.nnz * sizeof(double), hipMemcpyHostToDevice), "copy val");
+
+    h.subs.resize(P);
+    std::vector<int32_t> om;
+    std::vector<double> ev;
+    std::vector<float> evf;
+    std::vector<int32_t> eg, el;
+    std::vector<unsigned char> bf, bb, iv;
+    std::vector<float> sc;
+    for (int p = 0; p < P; ++p) {
+        const auto& s = plan.subs[p];
+        const int64_t n = static_cast<int64_t>(s.omega.size());
+        const int64_t np = n_pad_of(n);
+        const int K = s.ell_width;
+        om.resize(n);
+        for (int64_t i = 0; i < n; ++i) om[i] = s.owned[i] ? s.omega[i] : ~s.omega[i];
+        ev.assign(np * K, 0.0);
+        eg.assign(np * K, 0);
+        el.assign(np * K, static_cast<int32_t>(n));
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t g = s.omega[i];
+            int k = 0;
+            for (int64_t e = plan.row_ptr[g]; e < plan.row_ptr[g + 1]; ++e, ++k) {
+                const int32_t c = plan.col[e];
+                ev[k * np + i] = plan.val[e];
+                eg[k * np + i] = c;
+                auto it = std::lower_bound(s.omega.begin(), s.omega.end(), c);
+                if (it != s.omega.end() && *it == c) el[k * np + i] = static_cast<int32_t>(it - s.omega.begin());
+            }
+            for (; k < K; ++k) eg[k * np + i] = g;  // padding: value 0 times the row's own x
+        }
+        hip_check(hipMemcpy(h.omega.as<int32_t>() + row_off[p], om.data(), n * sizeof(int32_t), hipMemcpyHostToDevice),
+                  "copy omega");
+        hip_check(hipMemcpy(h.ell_val.as<double>() + ell_off[p], ev.data(), np * K * sizeof(double),
+                            hipMemcpyHostToDevice),
+                  "copy ell_val");
+        if (h.ell_valf.p) {
+            evf.resize(np * K);
+            for (int64_t e = 0; e < np * K; ++e) evf[e] = static_cast<float>(ev[e]);
+            hip_check(hipMemcpy(h.ell_valf.as<float>() + ell_off[p], evf.data(), np * K * sizeof(float),
+                                hipMemcpyHostToDevice),
+                      "copy ell_valf");
+        }
+        hip_check(hipMemcpy(h.ell_gcol.as<int32_t>() + ell_off[p], eg.data(), np * K * sizeof(int32_t),
+                            hipMemcpyHostToDevice),
+                  "copy ell_gcol");
+        hip_check(hipMemcpy(h.ell_lcol.as<int32_t>() + ell_off[p], el.data(), np * K * sizeof(int32_t),
+                            hipMemcpyHostToDevice),
+                  "copy ell_lcol");
+        SubDev d{};
+        d.omega = h.omega.as<int32_t>() + row_off[p];
+        d.ell_val = h.ell_val.as<double>() + ell_off[p];
+        d.ell_valf = h.ell_valf.p ? h.ell_valf.as<float>() + ell_off[p] : nullptr;
+        d.ell_gcol = h.ell_gcol.as<int32_t>() + ell_off[p];
+        d.ell_lcol = h.ell_lcol.as<int32_t>() + ell_off[p];
+        d.n = static_cast<int32_t>(n);
+        d.n_pad = static_cast<int32_t>(np);
+        d.K = K;
+        d.w = s.w;
+        d.row_off = row_off[p];
+        if (chol) {
+            const int64_t ld = s.w + 1;
+            const double* L = s.L.data();
+            bf.resize(n * ld * sts);
+            bb.resize(n * ld * sts);
+            iv.resize(n * cts);
+            for (int64_t t = 0; t < n; ++t) {
+                for (int64_t o = 0; o < ld; ++o) {
+                    const int64_t r = (n - 1 - t) + s.w - o;  // row of L read by the reversed transpose
+                    const int64_t fi = t * ld + o;
+                    if (st == RAS_STORAGE_FP64) {
+                        reinterpret_cast<double*>(bf.data())[fi] = L[fi];
+                        reinterpret_cast<double*>(bb.data())[fi] = r < n ? L[r * ld + o] : 0.0;
+                    } else if (st == RAS_STORAGE_FP32) {
+                        reinterpret_cast<float*>(bf.data())[fi] = static_cast<float>(L[fi]);
+                        reinterpret_cast<float*>(bb.data())[fi] = r < n ? static_cast<float>(L[r * ld + o]) : 0.0f;
+                    } else {
+                        reinterpret_cast<uint16_t*>(bf.data())[fi] = s.Lh[fi];
+                        reinterpret_cast<uint16_t*>(bb.data())[fi] = r < n ? s.Lh[r * ld + o] : 0;
+                    }
+                }
+                // reciprocal of the diagonal as the triangular solves see it
+                const int64_t di = t * ld + s.w;
+                if (st == RAS_STORAGE_FP64) {
+                    reinterpret_cast<double*>(iv.data())[t] = 1.0 / L[di];
+                } else if (st == RAS_STORAGE_FP32) {
+                    reinterpret_cast<float*>(iv.data())[t] = static_cast<float>(1.0 / static_cast<double>(static_cast<float>(L[di])));
+                } else {
+                    _Float16 hv;
+                    std::memcpy(&hv, &s.Lh[di], 2);
+                    const float deq = static_cast<float>(hv) * s.scale[t];
+                    reinterpret_cast<float*>(iv.data())[t] = static_cast<float>(1.0 / static_cast<double>(deq));
+                }
+            }
+            hip_check(hipMemcpy(static_cast<char*>(h.band_f.p) + band_off[p] * sts, bf.data(), n * ld * sts,
+                                hipMemcpyHostToDevice),
+                      "copy band_f");
+            hip_check(hipMemcpy(static_cast<char*>(h.band_b.p) + band_off[p] * sts, bb.data(), n * ld * sts,
+                                hipMemcpyHostToDevice),
+                      "copy band_b");
+            hip_check(hipMemcpy(static_cast<char*>(h.invd.p) + row_off[p] * cts, iv.data(), n * cts,
+                                hipMemcpyHostToDevice),
+                      "copy invd");
+            d.band_f = static_cast<char*>(h.band_f.p) + band_off[p] * sts;
+            d.band_b = static_cast<char*>(h.band_b.p) + band_off[p] * sts;
+            d.invd = static_cast<char*>(h.invd.p) + row_off[p] * cts;
+            if (st == RAS_STORAGE_FP16_ROWSCALED) {
+                hip_check(hipMemcpy(h.scale.as<float>() + row_off[p], s.scale.data(), n * sizeof(float),
+                                    hipMemcpyHostToDevice),
+                          "copy scale");
+                d.scale = h.scale.as<float>() + row_off[p];
+            }
+        }
+        h.subs[p] = d;
+    }
+    plan_stats(plan, &h.stats);
+    h.stats.device_bytes = static_cast<int64_t>(h.omega.bytes + h.ell_val.bytes + h.ell_valf.bytes + h.ell_gcol.bytes +
+                                                h.ell_lcol.bytes + h.band_f.bytes + h.band_b.bytes + h.invd.bytes +
+                                                h.scale.bytes + h.csr_rp.bytes + h.csr_ci.bytes + h.csr_va.bytes);
+}
+
+void drop_factors(Plan& plan) {
+    for (auto& s : plan.subs) {
+        std::vector<double>().swap(s.L);
+        std::vector<uint16_t>().swap(s.Lh);
+        std::vector<float>().swap(s.scale);
+    }
+}
+
+// LDS bytes of a launch over subdomains with at most max_n rows / bandwidth max_w.
+size_t lds_bytes(int solver, int storage, int max_n, int max_w, int* winm) {
+    const size_t cts = ct_size(storage);
+    if (solver == RAS_LOCAL_CG) {
+        *winm = 0;
+        return (static_cast<size_t>(max_n) + 1) * cts;
+    }
+    const int win = next_pow2(max_w + kBandRows + 1);
+    *winm = win - 1;
+    return (static_cast<size_t>(kBandRows) * (max_w + 1) + win) * cts;
+}
+
+constexpr size_t kLdsLimit = 160 * 1024 - 4096;  // leave room for the kernels' static LDS
+
+struct InstSpec {
+    ras_handle* h;
+    const double* b;
+    double* x;
+    int rhs;
+};
+
+// One persistent solve over a set of right-hand sides of one or more systems.
+ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_solve_info* info) {
+    ras_handle& h0 = *specs[0].h;
+    hipStream_t stream = h0.stream;
+    hip_check(hipSetDevice(h0.device), "hipSetDevice");
+    const bool sync = o.mode == RAS_MODE_SYNC;
+    const bool ordered = o.mode == RAS_MODE_ORDERED;
+    if (o.mode != RAS_MODE_SYNC && o.mode != RAS_MODE_ASYNC && o.mode != RAS_MODE_ORDERED)
+        throw Error{RAS_E_ARG, "unknown mode"};
+    if (!(o.tol >= 0.0) || o.max_sweeps < 1) throw Error{RAS_E_ARG, "tol must be >= 0 and max_sweeps >= 1"};
+    // distinct handles, in first-use order
+    std::vector<ras_handle*> hs;
+    for (auto& sp : specs)
+        if (std::find(hs.begin(), hs.end(), sp.h) == hs.end()) hs.push_back(sp.h);
+    int max_n = 0, max_w = 0, K = -1;
+    for (ras_handle* h : hs) {
+        if (h->solver != h0.solver || h->storage != h0.storage || h->cg_iters != h0.cg_iters)
+            throw Error{RAS_E_ARG, "batched systems must share the local solver, storage and CG iterations"};
+        max_n = std::max(max_n, h->max_n);
+        max_w = std::max(max_w, h->max_w);
+        if (K == -1) K = h->uniform_K;
+        else if (K != h->uniform_K) K = 0;
+    }
+    int winm = 0;
+    const size_t lds = lds_bytes(h0.solver, h0.storage, max_n, max_w, &winm);
+    if (lds > kLdsLimit)
+        throw Error{RAS_E_UNSUPPORTED, "subdomain needs " + std::to_string(lds) + " bytes of LDS (limit " +
+                                           std::to_string(kLdsLimit) + "); use more subdomains"};
+    const void* kern = select_kernel(h0.solver, h0.storage, !sync, K);
+    if (!kern) throw Error{RAS_E_UNSUPPORTED, "no kernel for this configuration"};
+
+    // subdomain table: handle order; per-instance items
+    std::vector<SubDev> subs;
+    std::vector<int> sub_base(hs.size());
+    for (size_t k = 0; k < hs.size(); ++k) {
+        sub_base[k] = static_cast<int>(subs.size());
+        subs.insert(subs.end(), hs[k]->subs.begin(), hs[k]->subs.end());
+    }
+    const int ninst = static_cast<int>(specs.size());
+    std::vector<ItemDev> items;
+    std::vector<double> cost;
+    std::vector<InstDev> insts(ninst);
+    int64_t scratch_elems = 0;
+    std::vector<int64_t> scratch_off(ninst), x1_off(ninst);
+    int64_t x1_elems = 0;
+    const int64_t scratch_mult = h0.solver == RAS_LOCAL_CG ? 3 : 1;
+    for (int i = 0; i < ninst; ++i) {
+        ras_handle* h = specs[i].h;
+        const int hk = static_cast<int>(std::find(hs.begin(), hs.end(), h) - hs.begin());
+        insts[i].item_begin = static_cast<int32_t>(items.size());
+        insts[i].item_count = h->plan->P;
+        for (int p = 0; p < h->plan->P; ++p) {
+            items.push_back(ItemDev{i, sub_base[hk] + p});
+            const SubDev& sd = h->subs[p];
+            cost.push_back(h->solver == RAS_LOCAL_CG ? static_cast<double>(sd.n) * sd.K * (h->cg_iters + 1)
+                                                     : static_cast<double>(sd.n) * (2.0 * (sd.w + 1) + sd.K));
+        }
+        scratch_off[i] = scratch_elems;
+        scratch_elems += scratch_mult * h->sum_n;
+        x1_off[i] = x1_elems;
+        x1_elems += sync ? h->plan->n : 0;
+    }
+    const int nitems = static_cast<int>(items.size());
+
+    // workgroups: co-resident capacity, balanced static item lists (LPT)
+    int per_cu = 0;
+    hip_check(occupancy(kern, h0.solver, lds, &per_cu), "occupancy query");
+    if (per_cu < 1) throw Error{RAS_E_UNSUPPORTED, "kernel cannot be resident with this LDS size"};
+    const int capacity = per_cu * h0.num_cu;
+    int G = ordered ? 1 : std::min(nitems, capacity);
+    if (o.workgroups > 0) G = std::min(G, o.workgroups);
+    if (G < 1) G = 1;
+    std::vector<std::vector<int>> lists(G);
+    {
+        std::vector<int> order(nitems);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+        using Load = std::pair<double, int>;
+        std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+        for (int g = 0; g < G; ++g) heap.push({0.0, g});
+        for (int it : order) {
+            Load l = heap.top();
+            heap.pop();
+            lists[l.second].push_back(it);
+            heap.push({l.first + cost[it], l.second});
+        }
+        for (auto& l : lists) std::sort(l.begin(), l.end());
+    }
+    std::vector<int32_t> wg_ptr(G + 1, 0), wg_items;
+    std::vector<int> owner_wg(nitems, 0);
+    for (int g = 0; g < G; ++g) {
+        if (static_cast<int>(lists[g].size()) > kMaxItemsPerWg)
+            throw Error{RAS_E_UNSUPPORTED, "too many work items per workgroup"};
+        for (int it : lists[g]) {
+            wg_items.push_back(it);
+            owner_wg[it] = g;
+        }
+        wg_ptr[g + 1] = static_cast<int32_t>(wg_items.size());
+    }
+
+    // device workspace (one block, carved)
+    const int64_t hist_cap = std::min<int64_t>(o.max_sweeps + 1, 1 << 22);
+    auto align = [](size_t v) { return (v + 255) / 256 * 256; };
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        size_t at = off;
+        off += align(bytes);
+        return at;
+    };
+    const size_t o_subs = carve(subs.size() * sizeof(SubDev));
+    const size_t o_items = carve(items.size() * sizeof(ItemDev));
+    const size_t o_insts = carve(insts.size() * sizeof(InstDev));
+    const size_t o_ist = carve(insts.size() * sizeof(InstState));
+    const size_t o_res2 = carve(2 * nitems * sizeof(double));
+    const size_t o_conv = carve(nitems * sizeof(int32_t));
+    const size_t o_solves = carve(nitems * sizeof(int64_t));
+    const size_t o_version = carve(nitems * sizeof(uint32_t));
+    const size_t o_wgptr = carve((G + 1) * sizeof(int32_t));
+    const size_t o_wgitems = carve(wg_items.size() * sizeof(int32_t));
+    const size_t o_bar = carve(sizeof(GridBarrier));
+    const size_t o_scr = carve(scratch_elems * ct_size(h0.storage));
+    const size_t o_x1 = carve(x1_elems * sizeof(double));
+    const size_t o_hist = carve(2 * static_cast<size_t>(ninst) * hist_cap * sizeof(double));
+    const int nparts = 512;
+    const size_t o_red = carve((2 * nparts + 2) * sizeof(double));
+    DevBuf ws;
+    ws.alloc(off);
+    char* base = ws.as<char>();
+    for (int i = 0; i < ninst; ++i) {
+        InstDev& in = insts[i];
+        in.b = specs[i].b;
+        in.x0 = specs[i].x;
+        in.x1 = sync ? reinterpret_cast<double*>(base + o_x1) + x1_off[i] : nullptr;
+        in.scratch = base + o_scr + scratch_off[i] * ct_size(h0.storage);
+        in.hist = reinterpret_cast<double*>(base + o_hist) + static_cast<size_t>(i) * hist_cap;
+        in.hist_t = reinterpret_cast<double*>(base + o_hist) + static_cast<size_t>(ninst + i) * hist_cap;
+        in.hist_cap = hist_cap;
+        in.max_sweeps = o.max_sweeps;
+        in.tol2 = o.tol * o.tol;
+        in.leader = owner_wg[in.item_begin];
+        // ||b||^2 (deterministic two-pass reduction)
+        ras_handle* h = specs[i].h;
+        double out[2];
+        hip_check(launch_residual(h->plan->n, h->csr_rp.as<int64_t>(), h->csr_ci.as<int32_t>(), h->csr_va.as<double>(),
+                                  specs[i].b, nullptr, reinterpret_cast<double*>(base + o_red), nparts,
+                                  reinterpret_cast<double*>(base + o_red) + 2 * nparts, stream),
+                  "norm of b");
+        hip_check(hipMemcpyAsync(out, reinterpret_cast<double*>(base + o_red) + 2 * nparts, 2 * sizeof(double),
+                                 hipMemcpyDeviceToHost, stream),
+                  "copy norm");
+        hip_check(hipStreamSynchronize(stream), "sync norm");
+        in.bnorm2 = out[1];
+        if (!(in.bnorm2 > 0.0)) throw Error{RAS_E_ARG, "right-hand side " + std::to_string(i) + " is zero"};
+    }
+    std::vector<InstState> ist(ninst);
+    for (auto& s : ist) {
+        s.stop = 0;
+        s.result_buf = 0;
+        s.sweeps = 0;
+        s.hist_len = 0;
+        s.stopped_at = -1;
+        s.t0 = 0;
+    }
+    GridBarrier bar{0, 0, INT64_MAX};
+    auto up = [&](size_t o_, const void* src, size_t bytes) {
+        if (bytes) hip_check(hipMemcpyAsync(base + o_, src, bytes, hipMemcpyHostToDevice, stream), "upload tables");
+    };
+    up(o_subs, subs.data(), subs.size() * sizeof(SubDev));
+    up(o_items, items.data(), items.size() * sizeof(ItemDev));
+    up(o_insts, insts.data(), insts.size() * sizeof(InstDev));
+    up(o_ist, ist.data(), ist.size() * sizeof(InstState));
+    up(o_wgptr, wg_ptr.data(), wg_ptr.size() * sizeof(int32_t));
+    up(o_wgitems, wg_items.data(), wg_items.size() * sizeof(int32_t));
+    up(o_bar, &bar, sizeof(bar));
+    hip_check(hipMemsetAsync(base + o_res2, 0, 2 * nitems * sizeof(double), stream), "clear");
+    hip_check(hipMemsetAsync(base + o_conv, 0, nitems * sizeof(int32_t), stream), "clear");
+    hip_check(hipMemsetAsync(base + o_solves, 0, nitems * sizeof(int64_t), stream), "clear");
+    hip_check(hipMemsetAsync(base + o_version, 0, nitems * sizeof(uint32_t), stream), "clear");
+    if (sync)  // x^0 lives in the caller's buffer; the other buffer is filled by the first sweep
+        hip_check(hipMemsetAsync(base + o_x1, 0, x1_elems * sizeof(double), stream), "clear");
+
+    Params P{};
+    P.subs = reinterpret_cast<const SubDev*>(base + o_subs);
+    P.items = reinterpret_cast<const ItemDev*>(base + o_items);
+    P.insts = reinterpret_cast<const InstDev*>(base + o_insts);
+    P.ist = reinterpret_cast<InstState*>(base + o_ist);
+    P.res2_own = reinterpret_cast<double*>(base + o_res2);
+    P.conv = reinterpret_cast<int32_t*>(base + o_conv);
+    P.solves = reinterpret_cast<int64_t*>(base + o_solves);
+    P.version = reinterpret_cast<uint32_t*>(base + o_version);
+    P.wg_ptr = reinterpret_cast<const int32_t*>(base + o_wgptr);
+    P.wg_items = reinterpret_cast<const int32_t*>(base + o_wgitems);
+    P.bar = reinterpret_cast<GridBarrier*>(base + o_bar);
+    P.n_items = nitems;
+    P.n_insts = ninst;
+    P.n_wg = G;
+    P.cg_iters = h0.cg_iters;
+    P.max_ticks = o.max_seconds > 0 ? static_cast<int64_t>(o.max_seconds * h0.clock_khz * 1000.0) : 0;
+    P.sweep0 = 0;
+
+    hipEvent_t ev0, ev1;
+    hip_check(hipEventCreate(&ev0), "event");
+    hip_check(hipEventCreate(&ev1), "event");
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } evg{ev0, ev1};
+    hip_check(launch_stamp(P.ist, ninst, stream), "stamp");
+    hip_check(hipEventRecord(ev0, stream), "event record");
+
+    std::vector<std::vector<double>> hist(ninst), hist_t(ninst);
+    std::vector<double> relres(ninst, NAN);
+    std::vector<int> verified(ninst, 0);
+    std::vector<int> launches(ninst, 0);
+    const double tick_s = 1.0 / (static_cast<double>(h0.clock_khz) * 1000.0);
+    double* red = reinterpret_cast<double*>(base + o_red);
+    auto exact_relres = [&](int i) {
+        ras_handle* h = specs[i].h;
+        double out[2];
+        hip_check(launch_residual(h->plan->n, h->csr_rp.as<int64_t>(), h->csr_ci.as<int32_t>(), h->csr_va.as<double>(),
+                                  specs[i].b, specs[i].x, red, nparts, red + 2 * nparts, stream),
+                  "verification residual");
+        hip_check(hipMemcpyAsync(out, red + 2 * nparts, 2 * sizeof(double), hipMemcpyDeviceToHost, stream), "copy");
+        hip_check(hipStreamSynchronize(stream), "sync verification");
+        return std::sqrt(out[0] / out[1]);
+    };
+    std::vector<int64_t> solves_h(nitems);
+    bool time_out = false;
+    for (int launch = 0;; ++launch) {
+        hip_check(launch_solver(kern, h0.solver, P, max_w, winm, lds, stream, sync), "persistent kernel launch");
+        hip_check(hipStreamSynchronize(stream), "persistent kernel");
+        for (int i = 0; i < ninst; ++i)
+            if (!verified[i]) ++launches[i];
+        hip_check(hipMemcpy(ist.data(), P.ist, ninst * sizeof(InstState), hipMemcpyDeviceToHost), "copy state");
+        hip_check(hipMemcpy(solves_h.data(), P.solves, nitems * sizeof(int64_t), hipMemcpyDeviceToHost), "copy counts");
+        // collect history entries written by this launch
+        for (int i = 0; i < ninst; ++i) {
+            const int64_t len = std::min(ist[i].hist_len, hist_cap);
+            if (len > 0) {
+                std::vector<double> hv(len), ht(len);
+                hip_check(hipMemcpy(hv.data(), insts[i].hist, len * sizeof(double), hipMemcpyDeviceToHost), "hist");
+                hip_check(hipMemcpy(ht.data(), insts[i].hist_t, len * sizeof(double), hipMemcpyDeviceToHost), "hist");
+                for (int64_t k = 0; k < len; ++k) {
+                    hist[i].push_back(hv[k]);
+                    hist_t[i].push_back(ht[k] * tick_s);
+                }
+            }
+        }
+        if (sync) {
+            for (int i = 0; i < ninst; ++i) {
+                if (ist[i].result_buf == 1)
+                    hip_check(launch_copy(specs[i].h->plan->n, insts[i].x1, insts[i].x0, stream), "copy result");
+                relres[i] = exact_relres(i);
+                verified[i] = 1;
+            }
+            break;
+        }
+        // asynchronous: verify the global criterion after termination (Sec. 3.3.2)
+        bool again = false;
+        float ms_now = 0.0f;
+        hip_check(hipEventRecord(ev1, stream), "event");
+        hip_check(hipEventSynchronize(ev1), "event");
+        hip_check(hipEventElapsedTime(&ms_now, ev0, ev1), "elapsed");
+        for (int i = 0; i < ninst; ++i) {
+            if (verified[i]) continue;
+            relres[i] = exact_relres(i);
+            hist[i].push_back(relres[i]);
+            hist_t[i].push_back(ms_now * 1e-3);
+            int64_t mn = INT64_MAX;
+            for (int k = 0; k < insts[i].item_count; ++k) mn = std::min(mn, solves_h[insts[i].item_begin + k]);
+            const bool exhausted = mn >= o.max_sweeps;
+            const bool timed = ist[i].stop == 2 || (o.max_seconds > 0 && ms_now * 1e-3 > o.max_seconds);
+            if (ist[i].stop == 4 || !std::isfinite(relres[i])) {
+                verified[i] = 1;
+                continue;
+            }
+            if (relres[i] < o.tol || exhausted || timed || ordered) {
+                verified[i] = 1;
+                time_out = time_out || timed;
+                continue;
+            }
+            // resume: clear this instance's stop flag and history length
+            ist[i].stop = 0;
+            again = true;
+        }
+        if (!again || launch > 10000) break;
+        for (int i = 0; i < ninst; ++i) {
+            if (verified[i]) ist[i].stop = 1;  // keep finished systems parked
+            ist[i].hist_len = 0;
+        }
+        hip_check(hipMemcpy(P.ist, ist.data(), ninst * sizeof(InstState), hipMemcpyHostToDevice), "resume state");
+    }
+    (void)time_out;
+    hip_check(hipEventRecord(ev1, stream), "event");
+    hip_check(hipEventSynchronize(ev1), "event");
+    float ms = 0.0f;
+    hip_check(hipEventElapsedTime(&ms, ev0, ev1), "elapsed");
+    hip_check(hipMemcpy(solves_h.data(), P.solves, nitems * sizeof(int64_t), hipMemcpyDeviceToHost), "copy counts");
+
+    ras_status status = RAS_OK;
+    for (int i = 0; i < ninst; ++i) {
+        ras_solve_info& inf = info[i];
+        std::memset(&inf, 0, sizeof(inf));
+        const bool finite = std::isfinite(relres[i]);
+        inf.converged = finite && relres[i] < o.tol;
+        inf.launches = launches[i];
+        inf.rel_residual = relres[i];
+        inf.seconds = ms * 1e-3;
+        int64_t mn = INT64_MAX, mx = 0, tot = 0;
+        std::vector<int64_t> cnt(insts[i].item_count);
+        for (int k = 0; k < insts[i].item_count; ++k) {
+            // synchronous: every subdomain applied exactly `sweeps` updates to the
+            // returned iterate (the speculative update of the last sweep is dropped)
+            const int64_t c = sync ? ist[i].sweeps : solves_h[insts[i].item_begin + k];
+            cnt[k] = c;
+            mn = std::min(mn, c);
+            mx = std::max(mx, c);
+            tot += c;
+        }
+        inf.min_local_solves = mn;
+        inf.max_local_solves = mx;
+        inf.total_local_solves = tot;
+        inf.sweeps = sync ? ist[i].sweeps : mx;
+        ras_handle* h = specs[i].h;
+        const int r = specs[i].rhs;
+        if (static_cast<int>(h->hist.size()) <= r) {
+            h->hist.resize(r + 1);
+            h->hist_t.resize(r + 1);
+            h->counts.resize(r + 1);
+        }
+        h->hist[r] = std::move(hist[i]);
+        h->hist_t[r] = std::move(hist_t[i]);
+        h->counts[r] = std::move(cnt);
+        if (!finite) status = RAS_E_DIVERGED;
+        else if (!inf.converged && status == RAS_OK) status = RAS_NOT_CONVERGED;
+    }
+    if (status == RAS_E_DIVERGED) g_err = "non-finite residual";
+    else if (status == RAS_NOT_CONVERGED) g_err = "tolerance not reached within max_sweeps / max_seconds";
+    return status;
+}
+
+void init_device(ras_handle& h, void* stream) {
+    h.stream = static_cast<hipStream_t>(stream);
+    hip_check(hipGetDevice(&h.device), "hipGetDevice");
+    int khz = 0;
+    hip_check(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h.device), "wall clock rate");
+    h.clock_khz = khz > 0 ? khz : 100000;
+    hip_check(hipDeviceGetAttribute(&h.num_cu, hipDeviceAttributeMultiprocessorCount, h.device), "CU count");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ras_last_error(void) { return g_err.c_str(); }
+const char* ras_version(void) { return "ras-mi355x 0.1 (gfx950)"; }
+
+ras_status ras_plan_create(const ras_csr* A, const ras_partition* part, int32_t overlap, const ras_local* local,
+                           ras_plan** out) {
+    return guarded([&] {
+        if (!out) throw Error{RAS_E_ARG, "null output"};
+        auto plan = std::make_unique<ras_plan>();
+        build_plan(A, part, overlap, local, *plan);
+        *out = plan.release();
+        return RAS_OK;
+    });
+}
+
+ras_status ras_plan_get_stats(const ras_plan* plan, ras_plan_stats* out) {
+    return guarded([&] {
+        if (!plan || !out) throw Error{RAS_E_ARG, "null argument"};
+        plan_stats(*plan, out);
+        return RAS_OK;
+    });
+}
+
+static void copy_sets(const Plan& plan, int32_t* owner, int64_t* omega_ptr, int32_t* omega_idx) {
+    if (owner) std::copy(plan.owner.begin(), plan.owner.end(), owner);
+    int64_t acc = 0;
+    if (omega_ptr) omega_ptr[0] = 0;
+    for (int p = 0; p < plan.P; ++p) {
+        const auto& om = plan.subs[p].omega;
+        if (omega_idx) std::copy(om.begin(), om.end(), omega_idx + acc);
+        acc += static_cast<int64_t>(om.size());
+        if (omega_ptr) omega_ptr[p + 1] = acc;
+    }
+}
+
+ras_status ras_plan_sets(const ras_plan* plan, int32_t* owner, int64_t* omega_ptr, int32_t* omega_idx) {
+    return guarded([&] {
+        if (!plan) throw Error{RAS_E_ARG, "null plan"};
+        copy_sets(*plan, owner, omega_ptr, omega_idx);
+        return RAS_OK;
+    });
+}
+
+ras_status ras_plan_factor(const ras_plan* plan, int32_t p, double* band, int32_t* w) {
+    return guarded([&] {
+        if (!plan || !w) throw Error{RAS_E_ARG, "null argument"};
+        if (plan->local.kind != RAS_LOCAL_CHOL_BANDED) throw Error{RAS_E_STATE, "plan has no Cholesky factors"};
+        if (p < 0 || p >= plan->P) throw Error{RAS_E_ARG, "subdomain out of range"};
+        const auto& s = plan->subs[p];
+        if (s.L.empty() && !s.omega.empty()) throw Error{RAS_E_STATE, "factor released"};
+        *w = s.w;
+        if (band) std::copy(s.L.begin(), s.L.end(), band);
+        return RAS_OK;
+    });
+}
+
+ras_status ras_plan_factor_fp16(const ras_plan* plan, int32_t p, uint16_t* half_bits, float* scale) {
+    return guarded([&] {
+        if (!plan) throw Error{RAS_E_ARG, "null plan"};
+        if (plan->local.kind != RAS_LOCAL_CHOL_BANDED || plan->local.storage != RAS_STORAGE_FP16_ROWSCALED)
+            throw Error{RAS_E_STATE, "plan has no FP16 row-scaled factors"};
+        if (p < 0 || p >= plan->P) throw Error{RAS_E_ARG, "subdomain out of range"};
+        const auto& s = plan->subs[p];
+        if (half_bits) std::copy(s.Lh.begin(), s.Lh.end(), half_bits);
+        if (scale) std::copy(s.scale.begin(), s.scale.end(), scale);
+        return RAS_OK;
+    });
+}
+
+void ras_plan_destroy(ras_plan* plan) { delete plan; }
+
+ras_status ras_setup_from_plan(const ras_plan* plan, void* hip_stream, ras_handle** out) {
+    return guarded([&] {
+        if (!plan || !out) throw Error{RAS_E_ARG, "null argument"};
+        auto h = std::make_unique<ras_handle>();
+        init_device(*h, hip_stream);
+        upload(*h, *plan);
+        h->plan = std::make_unique<ras_plan>();
+        Plan& keep = *h->plan;
+        keep.n = plan->n;
+        keep.nnz = plan->nnz;
+        keep.P = plan->P;
+        keep.overlap = plan->overlap;
+        keep.local = plan->local;
+        keep.owner = plan->owner;
+        keep.subs.resize(plan->P);
+        for (int p = 0; p < plan->P; ++p) {
+            keep.subs[p].omega = plan->subs[p].omega;
+            keep.subs[p].w = plan->subs[p].w;
+            keep.subs[p].ell_width = plan->subs[p].ell_width;
+            keep.subs[p].n_owned = plan->subs[p].n_owned;
+        }
+        hip_check(hipDeviceSynchronize(), "upload");
+        *out = h.release();
+        return RAS_OK;
+    });
+}
+
+ras_status ras_setup(const ras_csr* A, const ras_partition* part, int32_t overlap, const ras_local* local,
+                     void* hip_stream, ras_handle** out) {
+    return guarded([&] {
+        if (!out) throw Error{RAS_E_ARG, "null output"};
+        auto plan = std::make_unique<ras_plan>();
+        build_plan(A, part, overlap, local, *plan);
+        auto h = std::make_unique<ras_handle>();
+        init_device(*h, hip_stream);
+        upload(*h, *plan);
+        drop_factors(*plan);
+        plan->row_ptr.clear();
+        plan->col.clear();
+        plan->val.clear();
+        h->plan = std::move(plan);
+        hip_check(hipDeviceSynchronize(), "upload");
+        *out = h.release();
+        return RAS_OK;
+    });
+}
+
+ras_status ras_handle_get_stats(const ras_handle* h, ras_plan_stats* out) {
+    return guarded([&] {
+        if (!h || !out) throw Error{RAS_E_ARG, "null argument"};
+        *out = h->stats;
+        return RAS_OK;
+    });
+}
+
+ras_status ras_solve(ras_handle* h, const double* b_dev, double* x_dev, int32_t nrhs, const ras_solve_opts* opts,
+                     ras_solve_info* info) {
+    return guarded([&] {
+        if (!h || !b_dev || !x_dev || !opts || !info || nrhs < 1) throw Error{RAS_E_ARG, "invalid argument"};
+        std::vector<InstSpec> specs;
+        for (int r = 0; r < nrhs; ++r)
+            specs.push_back(InstSpec{h, b_dev + static_cast<int64_t>(r) * h->plan->n,
+                                     x_dev + static_cast<int64_t>(r) * h->plan->n, r});
+        h->hist.clear();
+        h->hist_t.clear();
+        h->counts.clear();
+        return run_solve(specs, *opts, info);
+    });
+}
+
+ras_status ras_batch_solve(int32_t m, ras_handle* const* hs, const double* const* b_dev, double* const* x_dev,
+                           const int32_t* nrhs, const ras_solve_opts* opts, ras_solve_info* info) {
+    return guarded([&] {
+        if (m < 1 || !hs || !b_dev || !x_dev || !nrhs || !opts || !info) throw Error{RAS_E_ARG, "invalid argument"};
+        std::vector<InstSpec> specs;
+        for (int k = 0; k < m; ++k) {
+            if (!hs[k] || !b_dev[k] || !x_dev[k] || nrhs[k] < 1) throw Error{RAS_E_ARG, "invalid batch entry"};
+            if (hs[k]->stream != hs[0]->stream) throw Error{RAS_E_ARG, "batched handles must share a stream"};
+            hs[k]->hist.clear();
+            hs[k]->hist_t.clear();
+            hs[k]->counts.clear();
+            for (int r = 0; r < nrhs[k]; ++r)
+                specs.push_back(InstSpec{hs[k], b_dev[k] + static_cast<int64_t>(r) * hs[k]->plan->n,
+                                         x_dev[k] + static_cast<int64_t>(r) * hs[k]->plan->n, r});
+        }
+        return run_solve(specs, *opts, info);
+    });
+}
+
+ras_status ras_residual_history(const ras_handle* h, int32_t rhs, double* t_sec, double* relres, int64_t cap,
+                                 int64_t* len) {
+    return guarded([&] {
+        if (!h || !len) throw Error{RAS_E_ARG, "null argument"};
+        if (rhs < 0 || rhs >= static_cast<int32_t>(h->hist.size())) throw Error{RAS_E_STATE, "no history for this rhs"};
+        const auto& hv = h->hist[rhs];
+        const auto& ht = h->hist_t[rhs];
+        *len = static_cast<int64_t>(hv.size());
+        const int64_t c = std::min<int64_t>(cap, *len);
+        if (relres) std::copy(hv.begin(), hv.begin() + c, relres);
+        if (t_sec) std::copy(ht.begin(), ht.begin() + c, t_sec);
+        return RAS_OK;
+    });
+}
+
+ras_status ras_local_solve_counts(const ras_handle* h, int32_t rhs, int64_t* counts) {
+    return guarded([&] {
+        if (!h || !counts) throw Error{RAS_E_ARG, "null argument"};
+        if (rhs < 0 || rhs >= static_cast<int32_t>(h->counts.size())) throw Error{RAS_E_STATE, "no counts for this rhs"};
+        std::copy(h->counts[rhs].begin(), h->counts[rhs].end(), counts);
+        return RAS_OK;
+    });
+}
+
+ras_status ras_partition_sets(const ras_handle* h, int32_t* owner, int64_t* omega_ptr, int32_t* omega_idx) {
+    return guarded([&] {
+        if (!h) throw Error{RAS_E_ARG, "null handle"};
+        copy_sets(*h->plan, owner, omega_ptr, omega_idx);
+        return RAS_OK;
+    });
+}
+
+ras_status ras_relative_residual(ras_handle* h, const double* b_dev, const double* x_dev, double* relres) {
+    return guarded([&] {
+        if (!h || !b_dev || !x_dev || !relres) throw Error{RAS_E_ARG, "null argument"};
+        hip_check(hipSetDevice(h->device), "hipSetDevice");
+        const int nparts = 512;
+        h->ws_red.ensure((2 * nparts + 2) * sizeof(double));
+        double* red = h->ws_red.as<double>();
+        hip_check(launch_residual(h->plan->n, h->csr_rp.as<int64_t>(), h->csr_ci.as<int32_t>(), h->csr_va.as<double>(),
+                                  b_dev, x_dev, red, nparts, red + 2 * nparts, h->stream),
+                  "residual");
+        double out[2];
+        hip_check(hipMemcpyAsync(out, red + 2 * nparts, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream), "copy");
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        *relres = std::sqrt(out[0] / out[1]);
+        return RAS_OK;
+    });
+}
+
+void ras_destroy(ras_handle* h) { delete h; }
+
+}  // extern "C"

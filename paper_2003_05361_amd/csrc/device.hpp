@@ -1,0 +1,94 @@
+// Device-side data layout shared by the upload code and the kernels.
+//
+// Everything the persistent kernels touch lives in HBM in flat arrays owned by
+// a handle (matrix data) or by a solve (per right-hand side state).  A "work
+// item" is one subdomain of one right-hand side; a launch processes a table of
+// items that may come from several systems (batching).
+#pragma once
+
+#include <cstdint>
+
+namespace ras {
+
+constexpr int kCgThreads = 1024;    // workgroup size of the CG kernels
+constexpr int kBandThreads = 256;   // workgroup size of the banded-solve kernels
+constexpr int kBandRows = 32;       // rows per block of the banded triangular solves
+constexpr int kMaxItemsPerWg = 1024;  // work items one workgroup may own
+
+// Static data of one subdomain (setup output, Sec. 3.2.2 / Sec. 3.3.1).
+struct SubDev {
+    const int32_t* omega;     // [n] global id g (owned row) or ~g (overlap row), ascending g
+    const double* ell_val;    // [K][n_pad] values of A's rows on omega (float64)
+    const float* ell_valf;    // [K][n_pad] float32 copy (CG with FP32 storage), else null
+    const int32_t* ell_gcol;  // [K][n_pad] global column (padding: the row's own g)
+    const int32_t* ell_lcol;  // [K][n_pad] local column in omega; n for external columns and padding
+    const void* band_f;       // [n][w+1] factor L, row-major lower band, storage type
+    const void* band_b;       // [n][w+1] reversed transpose J L^T J, same layout
+    const float* scale;       // [n] FP16 row scale of L (null otherwise)
+    const void* invd;         // [n] 1 / L_ii in the local compute type
+    int32_t n, n_pad, K, w;
+    int64_t row_off;          // offset of this subdomain in per-RHS scratch vectors
+    int64_t pad_;
+};
+
+// One work item: subdomain `sub` of right-hand side (instance) `inst`.
+struct ItemDev {
+    int32_t inst;
+    int32_t sub;
+};
+
+// One right-hand side of one system.
+struct InstDev {
+    const double* b;          // [n]
+    double* x0;               // [n] caller's x (initial guess in, result out)
+    double* x1;               // [n] second buffer (synchronous mode)
+    void* scratch;            // local vectors in the compute type: [3 sum n_p] (CG) or [sum n_p] (band)
+    double* hist;             // [hist_cap] relative residual history
+    double* hist_t;           // [hist_cap] seconds since start
+    int64_t hist_cap;
+    int64_t max_sweeps;
+    double tol2;              // tol^2
+    double bnorm2;            // ||b||^2 (filled on device before the solve)
+    int32_t item_begin;       // items of this instance are [item_begin, item_begin + item_count)
+    int32_t item_count;
+    int32_t leader;           // workgroup owning item_begin (runs the detector / records history)
+    int32_t pad_;
+};
+
+// Mutable per-instance state.
+struct InstState {
+    int32_t stop;             // async: 0 running, 1 converged (detector), 2 time limit, 3 exhausted
+    int32_t result_buf;       // sync: buffer (0/1) that holds the returned iterate
+    int64_t sweeps;           // sync: sweeps applied; async: detector passes
+    int64_t hist_len;
+    int64_t stopped_at;       // sync: sweep of the stop decision (-1 running)
+    int64_t t0;               // wall-clock tick of the first launch
+};
+
+struct GridBarrier {
+    uint32_t count;
+    uint32_t gen;
+    int64_t abort_at;         // sync: sweep at which every instance stops (time limit)
+};
+
+struct Params {
+    const SubDev* subs;
+    const ItemDev* items;
+    const InstDev* insts;
+    InstState* ist;
+    double* res2_own;         // [2][n_items] owned residual^2 (sync: by sweep parity)
+    int32_t* conv;            // [n_items] local criterion met (async)
+    int64_t* solves;          // [n_items] local solves done
+    uint32_t* version;        // [n_items] published updates (async)
+    const int32_t* wg_ptr;    // [n_wg + 1]
+    const int32_t* wg_items;  // item ids per workgroup, in visiting order
+    GridBarrier* bar;
+    int32_t n_items;
+    int32_t n_insts;
+    int32_t n_wg;
+    int32_t cg_iters;
+    int64_t max_ticks;        // wall-clock ticks allowed (<= 0: unlimited)
+    int64_t sweep0;           // sync: first sweep index of this launch
+};
+
+}  // namespace ras

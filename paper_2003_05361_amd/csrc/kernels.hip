@@ -1,0 +1,771 @@
+// Persistent restricted additive Schwarz kernels for gfx950 (CDNA4, wave64).
+//
+// One launch runs a whole solve (or until a time limit): every workgroup owns
+// a static list of work items (subdomain x right-hand side) and repeats, per
+// item, one "subdomain update":
+//   1. restrict + residual: r_p = b[Omega_p] - (A x)[Omega_p]  (Sec. 3.2.2: the
+//      local rows of A with their interface columns; reads neighbour-owned x),
+//      plus ||r_p[owned]||^2, ||r_p||^2, ||b_p||^2 (Sec. 3.3.2, eq. local_conv);
+//   2. local solve (Sec. 3.3.1): k steps of CG on A_p, or the forward and
+//      backward banded triangular solves with the Cholesky factor of A_p;
+//   3. restricted prolongation: x[O_p] += delta_p on owned points only
+//      (Sec. 2.1, restricted additive Schwarz).
+// Synchronous mode (Sec. 2.1, Sec. 3.4 two-sided): x is double-buffered, all
+// updates of sweep k read x^k, and one grid barrier separates sweeps.
+// Asynchronous mode (Sec. 2.1, Sec. 3.4 one-sided): a single x in place, read
+// and written with agent-scope relaxed atomics, no barrier; a per-item
+// version counter is bumped with release semantics after each publish.
+// Termination (Sec. 2.2, Sec. 3.3.2): synchronous -- the exact global residual
+// of x^k is assembled from the owned partial norms after the barrier;
+// asynchronous -- a centralized detector (the workgroup holding the system's
+// first subdomain) stops the system once every subdomain reports its local
+// criterion and the sum of the latest owned residuals is below tolerance; the
+// host then verifies the exact residual and resumes if it fails.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device.hpp"
+
+namespace ras {
+
+// ------------------------------------------------------------------------------ helpers
+
+#define RAS_GLOBAL __attribute__((address_space(1)))
+
+// Uniform (SGPR) copies of 32/64-bit values loaded from memory.
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int32_t>(v)));
+    const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int32_t>(v >> 32)));
+    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+template <class T>
+__device__ __forceinline__ RAS_GLOBAL T* gptr(const T* p) {
+    return (RAS_GLOBAL T*)(reinterpret_cast<T*>(uni64(reinterpret_cast<int64_t>(p))));
+}
+
+// A subdomain descriptor held in scalar registers with global-memory pointers.
+struct SubU {
+    RAS_GLOBAL int32_t* omega;
+    RAS_GLOBAL double* ell_val;
+    RAS_GLOBAL float* ell_valf;
+    RAS_GLOBAL int32_t* ell_gcol;
+    RAS_GLOBAL int32_t* ell_lcol;
+    const void* band_f;
+    const void* band_b;
+    RAS_GLOBAL float* scale;
+    const void* invd;
+    int32_t n, n_pad, K, w;
+    int64_t row_off;
+};
+
+__device__ __forceinline__ SubU load_sub(const SubDev* p) {
+    const SubDev d = *p;
+    SubU s;
+    s.omega = gptr(d.omega);
+    s.ell_val = gptr(d.ell_val);
+    s.ell_valf = gptr(d.ell_valf);
+    s.ell_gcol = gptr(d.ell_gcol);
+    s.ell_lcol = gptr(d.ell_lcol);
+    s.band_f = reinterpret_cast<const void*>(uni64(reinterpret_cast<int64_t>(d.band_f)));
+    s.band_b = reinterpret_cast<const void*>(uni64(reinterpret_cast<int64_t>(d.band_b)));
+    s.scale = gptr(d.scale);
+    s.invd = reinterpret_cast<const void*>(uni64(reinterpret_cast<int64_t>(d.invd)));
+    s.n = uni(d.n);
+    s.n_pad = uni(d.n_pad);
+    s.K = uni(d.K);
+    s.w = uni(d.w);
+    s.row_off = uni64(d.row_off);
+    return s;
+}
+
+// The per-instance pointers and scalars an update needs, uniform.
+struct InstU {
+    RAS_GLOBAL double* b;
+    RAS_GLOBAL double* x0;
+    RAS_GLOBAL double* x1;
+    void* scratch;
+};
+
+__device__ __forceinline__ InstU load_inst(const InstDev* p) {
+    const InstDev d = *p;
+    InstU u;
+    u.b = gptr(d.b);
+    u.x0 = gptr(d.x0);
+    u.x1 = gptr(d.x1);
+    u.scratch = reinterpret_cast<void*>(uni64(reinterpret_cast<int64_t>(d.scratch)));
+    return u;
+}
+
+template <bool ATOMIC>
+__device__ __forceinline__ double ldx(RAS_GLOBAL double* p) {
+    if constexpr (ATOMIC)
+        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        return *p;
+}
+
+template <bool ATOMIC>
+__device__ __forceinline__ void stx(RAS_GLOBAL double* p, double v) {
+    if constexpr (ATOMIC)
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        *p = v;
+}
+
+template <class T>
+__device__ __forceinline__ T ld_rlx(const T* p) {
+    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ void st_rlx(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over the workgroup; every thread gets the same value (fixed order):
+// per-wave butterfly, then every wave reduces the per-wave partials the same way.
+template <int B, class T>
+__device__ __forceinline__ T block_sum(T v, T* red) {
+    static_assert(B / 64 <= 64, "at most 64 waves");
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    T t = lane < B / 64 ? red[lane] : T(0);
+    t = wave_sum(t);
+    __syncthreads();
+    return t;
+}
+
+template <int B>
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* red) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    constexpr int NW = B / 64;
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = a;
+        red[NW + (threadIdx.x >> 6)] = b;
+        red[2 * NW + (threadIdx.x >> 6)] = c;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    a = wave_sum(lane < NW ? red[lane] : 0.0);
+    b = wave_sum(lane < NW ? red[NW + lane] : 0.0);
+    c = wave_sum(lane < NW ? red[2 * NW + lane] : 0.0);
+    __syncthreads();
+}
+
+// Grid-wide barrier for co-resident workgroups (cooperative launch).  Every
+// thread fences its own writes at agent scope before arriving; the last
+// arriver opens the next generation with a release store.
+__device__ void grid_barrier(GridBarrier* bar, uint32_t nwg) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t g = __hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t arrived =
+            __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nwg - 1) {
+            __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bar->gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            while (__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g)
+                __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+template <class CT>
+__device__ __forceinline__ CT load_as(const void* base, int64_t idx);
+template <>
+__device__ __forceinline__ double load_as<double>(const void* base, int64_t idx) {
+    return static_cast<const double*>(base)[idx];
+}
+template <>
+__device__ __forceinline__ float load_as<float>(const void* base, int64_t idx) {
+    return static_cast<const float*>(base)[idx];
+}
+
+// ------------------------------------------------------------------------------ residual
+// r_i = b_g - sum_k A_{g, col_k} x_{col_k} for local row i (global g).  ELL
+// slot k of row i sits at k * n_pad + i.  KT > 0: compile-time row width.
+template <int KT, bool ATOMIC>
+__device__ __forceinline__ double row_residual(const SubU& s, RAS_GLOBAL double* b, RAS_GLOBAL double* x, int i,
+                                               bool& owned, double& bg) {
+    const int32_t e = s.omega[i];
+    owned = e >= 0;
+    const int32_t g = owned ? e : ~e;
+    bg = b[g];
+    double acc = bg;
+    if constexpr (KT > 0) {
+        int32_t c[KT];
+        double a[KT];
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+            c[k] = (s.ell_gcol + static_cast<uint32_t>(k * s.n_pad))[static_cast<uint32_t>(i)];
+            a[k] = (s.ell_val + static_cast<uint32_t>(k * s.n_pad))[static_cast<uint32_t>(i)];
+        }
+#pragma unroll
+        for (int k = 0; k < KT; ++k) acc -= a[k] * ldx<ATOMIC>(x + c[k]);
+    } else {
+        for (int k = 0; k < s.K; ++k) {
+            const uint32_t idx = static_cast<uint32_t>(k * s.n_pad + i);
+            acc -= s.ell_val[idx] * ldx<ATOMIC>(x + s.ell_gcol[idx]);
+        }
+    }
+    return acc;
+}
+
+// ------------------------------------------------------------------------------ CG update
+// Local solve by `cg_iters` steps of Hestenes-Stiefel CG from zero on A_p (the
+// local rows and columns of A; external columns point at a zero LDS slot).
+// The search direction p lives in LDS (the local SpMV gathers it); r, A p and
+// the correction live in a per-item scratch block [3][n] of the compute type,
+// accessed row-coalesced.  Only owned rows of the correction are kept (RAS
+// discards the overlap part).
+template <class CT, int KT, bool ASYNC>
+struct CgUpdate {
+    static constexpr int B = kCgThreads;
+
+    __device__ __forceinline__ void operator()(const Params& P, const ItemDev& item, RAS_GLOBAL double* xin,
+                                               RAS_GLOBAL double* xout, double& own2, double& loc2, double& b2) {
+        extern __shared__ __align__(16) unsigned char smem[];
+        __shared__ CT redc[B / 64];
+        __shared__ double red3[3 * (B / 64)];
+        CT* pl = reinterpret_cast<CT*>(smem);  // search direction, [n + 1]
+        const SubU s = load_sub(P.subs + item.sub);
+        const InstU in = load_inst(P.insts + item.inst);
+        const int tid = threadIdx.x;
+        const int n = s.n;
+        RAS_GLOBAL CT* rg = gptr(static_cast<CT*>(in.scratch)) + 3 * s.row_off;
+        RAS_GLOBAL CT* qg = rg + n;
+        RAS_GLOBAL CT* dg = qg + n;
+        RAS_GLOBAL CT* val;
+        if constexpr (sizeof(CT) == 8)
+            val = s.ell_val;
+        else
+            val = s.ell_valf;
+        own2 = 0.0;
+        loc2 = 0.0;
+        b2 = 0.0;
+        CT rr = CT(0);
+        for (int i = tid; i < n; i += B) {
+            double bg;
+            bool ow;
+            const double ri = row_residual<KT, ASYNC>(s, in.b, xin, i, ow, bg);
+            loc2 += ri * ri;
+            b2 += bg * bg;
+            if (ow) own2 += ri * ri;
+            const CT rc = static_cast<CT>(ri);
+            rr += rc * rc;
+            rg[i] = rc;
+            pl[i] = rc;
+            dg[i] = CT(0);
+        }
+        if (tid == 0) pl[n] = CT(0);
+        block_sum3<B>(own2, loc2, b2, red3);
+        CT rho = block_sum<B>(rr, redc);
+        for (int it = 0; it < P.cg_iters; ++it) {
+            CT sp = CT(0);
+            for (int i = tid; i < n; i += B) {
+                CT acc = CT(0);
+                if constexpr (KT > 0) {
+                    int32_t c[KT];
+                    CT a[KT];
+#pragma unroll
+                    for (int k = 0; k < KT; ++k) {
+                        c[k] = (s.ell_lcol + static_cast<uint32_t>(k * s.n_pad))[static_cast<uint32_t>(i)];
+                        a[k] = (val + static_cast<uint32_t>(k * s.n_pad))[static_cast<uint32_t>(i)];
+                    }
+#pragma unroll
+                    for (int k = 0; k < KT; ++k) acc += a[k] * pl[c[k]];
+                } else {
+                    for (int k = 0; k < s.K; ++k) {
+                        const uint32_t idx = static_cast<uint32_t>(k * s.n_pad + i);
+                        acc += val[idx] * pl[s.ell_lcol[idx]];
+                    }
+                }
+                qg[i] = acc;
+                sp += pl[i] * acc;
+            }
+            const CT sigma = block_sum<B>(sp, redc);
+            if (rho == CT(0) || !(sigma > CT(0))) break;  // breakdown guard (uniform)
+            const CT alpha = rho / sigma;
+            CT rn = CT(0);
+            for (int i = tid; i < n; i += B) {
+                dg[i] += alpha * pl[i];
+                const CT ri = rg[i] - alpha * qg[i];
+                rg[i] = ri;
+                rn += ri * ri;
+            }
+            const CT rho_new = block_sum<B>(rn, redc);
+            const CT beta = rho_new / rho;
+            for (int i = tid; i < n; i += B) pl[i] = rg[i] + beta * pl[i];
+            rho = rho_new;
+            __syncthreads();
+        }
+        // restricted prolongation: owned points only
+        for (int i = tid; i < n; i += B) {
+            const int32_t e = s.omega[i];
+            if (e >= 0) stx<ASYNC>(xout + e, ldx<ASYNC>(xin + e) + static_cast<double>(dg[i]));
+        }
+    }
+};
+
+// ------------------------------------------------------------------------------ banded solves
+template <class ST>
+struct StorageTraits;
+template <>
+struct StorageTraits<double> {
+    using CT = double;
+    static constexpr bool kHalf = false;
+};
+template <>
+struct StorageTraits<float> {
+    using CT = float;
+    static constexpr bool kHalf = false;
+};
+template <>
+struct StorageTraits<_Float16> {
+    using CT = float;
+    static constexpr bool kHalf = true;
+};
+
+// Forward substitution with a row-major lower band [n][w+1] (diagonal at
+// offset w), in blocks of kBandRows rows: the part of each row reaching into
+// earlier blocks is a small GEMV against a sliding LDS window of the solution;
+// the triangular diagonal block is solved by one wavefront.  With rev the
+// matrix is the reversed transpose of L (backward substitution with L^T) and
+// the vector is addressed from the end.
+template <class ST>
+__device__ void band_pass(RAS_GLOBAL ST* Lb, RAS_GLOBAL float* scale, bool rev,
+                          RAS_GLOBAL typename StorageTraits<ST>::CT* invd, int n, int w,
+                          RAS_GLOBAL typename StorageTraits<ST>::CT* v, typename StorageTraits<ST>::CT* stage,
+                          typename StorageTraits<ST>::CT* win, int winm, typename StorageTraits<ST>::CT* gsum) {
+    using CT = typename StorageTraits<ST>::CT;
+    constexpr int BR = kBandRows;
+    constexpr int NT = kBandThreads;
+    constexpr int TPR = NT / BR;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int ld = w + 1;
+    const int nblk = (n + BR - 1) / BR;
+    for (int bk = 0; bk < nblk; ++bk) {
+        const int t0 = bk * BR;
+        const int rows = min(BR, n - t0);
+        const int cnt = rows * ld;
+        RAS_GLOBAL ST* src = Lb + static_cast<int64_t>(t0) * ld;
+        for (int e = tid; e < cnt; e += NT) {
+            CT val = static_cast<CT>(src[e]);
+            if constexpr (StorageTraits<ST>::kHalf) {
+                const int rr = e / ld;
+                const int o = e - rr * ld;
+                const int t = t0 + rr;
+                const int lrow = rev ? (n - 1 - t) + w - o : t;
+                val = lrow < n ? val * scale[lrow] : CT(0);
+            }
+            stage[e] = val;
+        }
+        __syncthreads();
+        {
+            const int rr = tid / TPR;
+            const int sub = tid % TPR;
+            const int t = t0 + rr;
+            CT acc = CT(0);
+            if (rr < rows) {
+                const int olo = max(0, w - t);
+                const int ohi = w - rr;
+                for (int o = olo + sub; o < ohi; o += TPR) acc += stage[rr * ld + o] * win[(t - w + o) & winm];
+            }
+#pragma unroll
+            for (int off = TPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            if (sub == 0) gsum[rr] = acc;
+        }
+        __syncthreads();
+        if (tid < 64) {
+            const int l = lane;
+            const int t = t0 + l;
+            const bool act = l < rows;
+            const int vi = rev ? n - 1 - t : t;
+            CT val = act ? static_cast<CT>(v[vi] - gsum[l]) : CT(0);
+            const CT dinv = act ? invd[vi] : CT(0);
+            CT Ld[BR];
+#pragma unroll
+            for (int m = 0; m < BR; ++m) Ld[m] = (act && m < l && m >= l - w) ? stage[l * ld + (w - l + m)] : CT(0);
+            CT y = CT(0);
+#pragma unroll
+            for (int m = 0; m < BR; ++m) {
+                const CT ym = __shfl(val * dinv, m, 64);
+                if (l == m) y = ym;
+                val -= Ld[m] * ym;
+            }
+            if (act) {
+                v[vi] = y;
+                win[t & winm] = y;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <class ST, bool ASYNC>
+struct BandUpdate {
+    using CT = typename StorageTraits<ST>::CT;
+    static constexpr int B = kBandThreads;
+    int max_w;
+    int winm;
+
+    __device__ __forceinline__ void operator()(const Params& P, const ItemDev& item, RAS_GLOBAL double* xin,
+                                               RAS_GLOBAL double* xout, double& own2, double& loc2, double& b2) {
+        extern __shared__ __align__(16) unsigned char smem[];
+        __shared__ double red3[3 * (B / 64)];
+        __shared__ CT gsum[kBandRows];
+        CT* stage = reinterpret_cast<CT*>(smem);  // [kBandRows][max_w + 1]
+        CT* win = stage + kBandRows * (max_w + 1);  // [winm + 1]
+        const SubU s = load_sub(P.subs + item.sub);
+        const InstU in = load_inst(P.insts + item.inst);
+        const int tid = threadIdx.x;
+        const int n = s.n;
+        RAS_GLOBAL CT* v = gptr(static_cast<CT*>(in.scratch)) + s.row_off;
+        own2 = 0.0;
+        loc2 = 0.0;
+        b2 = 0.0;
+        for (int i = tid; i < n; i += B) {
+            bool owned;
+            double bg;
+            const double ri = row_residual<0, ASYNC>(s, in.b, xin, i, owned, bg);
+            loc2 += ri * ri;
+            b2 += bg * bg;
+            if (owned) own2 += ri * ri;
+            v[i] = static_cast<CT>(ri);
+        }
+        block_sum3<B>(own2, loc2, b2, red3);
+        band_pass<ST>(gptr(static_cast<const ST*>(s.band_f)), s.scale, false, gptr(static_cast<const CT*>(s.invd)), n,
+                      s.w, v, stage, win, winm, gsum);
+        band_pass<ST>(gptr(static_cast<const ST*>(s.band_b)), s.scale, true, gptr(static_cast<const CT*>(s.invd)), n,
+                      s.w, v, stage, win, winm, gsum);
+        for (int i = tid; i < n; i += B) {
+            const int32_t e = s.omega[i];
+            if (e >= 0) stx<ASYNC>(xout + e, ldx<ASYNC>(xin + e) + static_cast<double>(v[i]));
+        }
+    }
+};
+
+// ------------------------------------------------------------------------------ drivers
+template <int B>
+__device__ double instance_owned_sum(const Params& P, const InstDev& in, int parity, double* red) {
+    double s = 0.0;
+    for (int k = threadIdx.x; k < in.item_count; k += B) s += P.res2_own[parity * P.n_items + in.item_begin + k];
+    return block_sum<B>(s, red);
+}
+
+// Synchronous sweeps: phase 1 updates every active item from x^k into the
+// other buffer and records its owned residual^2; after the grid barrier every
+// workgroup assembles ||b - A x^k||^2 of its systems (same order everywhere,
+// hence the same decision everywhere) and stops a system at the first k with
+// relative residual < tol, returning x^k.
+template <int B, class U>
+__device__ __forceinline__ void run_sync(const Params& P, U& upd, double* red, int8_t* done) {
+    const int tid = threadIdx.x;
+    const int wg = blockIdx.x;
+    const int ib = P.wg_ptr[wg], ie = P.wg_ptr[wg + 1];
+    for (int j = tid; j < ie - ib; j += B) done[j] = 0;
+    __syncthreads();
+    for (int64_t s = P.sweep0;; ++s) {
+        const int par = static_cast<int>(s & 1);
+        for (int j = ib; j < ie; ++j) {
+            if (done[j - ib]) continue;
+            const int it = __builtin_amdgcn_readfirstlane(P.wg_items[j]);
+            ItemDev item = P.items[it];
+            item.inst = __builtin_amdgcn_readfirstlane(item.inst);
+            item.sub = __builtin_amdgcn_readfirstlane(item.sub);
+            const InstU iu = load_inst(P.insts + item.inst);
+            RAS_GLOBAL double* xc = par ? iu.x1 : iu.x0;
+            RAS_GLOBAL double* xn = par ? iu.x0 : iu.x1;
+            double own2, loc2, b2;
+            upd(P, item, xc, xn, own2, loc2, b2);
+            if (tid == 0) {
+                P.res2_own[par * P.n_items + it] = own2;
+                P.solves[it] += 1;
+            }
+        }
+        grid_barrier(P.bar, static_cast<uint32_t>(P.n_wg));
+        // uniform exit: every system's stop decision of an earlier sweep is visible now
+        int running = 0;
+        for (int k = tid; k < P.n_insts; k += B) running |= (P.ist[k].stopped_at < 0 || P.ist[k].stopped_at >= s);
+        if (!__syncthreads_or(running)) break;
+        const int64_t abort_at = P.bar->abort_at;
+        int last_inst = -1;
+        bool last_stop = false;
+        for (int j = ib; j < ie; ++j) {
+            if (done[j - ib]) continue;
+            const int it = __builtin_amdgcn_readfirstlane(P.wg_items[j]);
+            ItemDev item = P.items[it];
+            item.inst = __builtin_amdgcn_readfirstlane(item.inst);
+            item.sub = __builtin_amdgcn_readfirstlane(item.sub);
+            if (item.inst != last_inst) {
+                const InstDev& in = P.insts[item.inst];
+                const double sum = instance_owned_sum<B>(P, in, par, red);
+                const double rel = sqrt(sum / in.bnorm2);
+                last_stop = !(rel >= sqrt(in.tol2)) || s >= in.max_sweeps || abort_at <= s;
+                last_inst = item.inst;
+                if (tid == 0 && wg == in.leader && it == in.item_begin) {
+                    InstState* st = P.ist + item.inst;
+                    if (s < in.hist_cap) {
+                        in.hist[s] = rel;
+                        in.hist_t[s] = static_cast<double>(wall_clock64() - st->t0);
+                        st->hist_len = s + 1;
+                    }
+                    if (last_stop) {
+                        st->sweeps = s;
+                        st->result_buf = par;
+                        st->stopped_at = s;
+                    }
+                }
+            }
+            if (last_stop && tid == 0) done[j - ib] = 1;
+        }
+        if (wg == 0 && tid == 0 && P.max_ticks > 0 && abort_at > s + 1 &&
+            wall_clock64() - P.ist[0].t0 > P.max_ticks)
+            P.bar->abort_at = s + 1;
+        __syncthreads();
+    }
+}
+
+// Asynchronous iteration: no barrier.  Workgroup-uniform control data is
+// read by thread 0 and broadcast through LDS.
+template <int B, class U>
+__device__ __forceinline__ void run_async(const Params& P, U& upd, double* red, int8_t* done) {
+    const int tid = threadIdx.x;
+    const int wg = blockIdx.x;
+    const int ib = P.wg_ptr[wg], ie = P.wg_ptr[wg + 1];
+    __shared__ int flag;
+    for (int j = tid; j < ie - ib; j += B) done[j] = 0;
+    __syncthreads();
+    for (;;) {
+        bool any = false;
+        for (int j = ib; j < ie; ++j) {
+            if (done[j - ib]) continue;
+            const int it = __builtin_amdgcn_readfirstlane(P.wg_items[j]);
+            ItemDev item = P.items[it];
+            item.inst = __builtin_amdgcn_readfirstlane(item.inst);
+            item.sub = __builtin_amdgcn_readfirstlane(item.sub);
+            const InstDev& in = P.insts[item.inst];
+            InstState* st = P.ist + item.inst;
+            if (tid == 0) flag = (ld_rlx(&st->stop) != 0) || (P.solves[it] >= in.max_sweeps);
+            __syncthreads();
+            const bool skip = flag != 0;
+            __syncthreads();
+            if (skip) {
+                if (tid == 0) done[j - ib] = 1;
+                continue;
+            }
+            any = true;
+            double own2, loc2, b2;
+            const InstU iu = load_inst(P.insts + item.inst);
+            upd(P, item, iu.x0, iu.x0, own2, loc2, b2);
+            __threadfence();
+            __syncthreads();
+            if (tid == 0) {
+                st_rlx(P.res2_own + it, own2);
+                st_rlx(P.conv + it, static_cast<int32_t>(loc2 < in.tol2 * b2));
+                P.solves[it] += 1;
+                __hip_atomic_fetch_add(P.version + it, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (wg == in.leader && it == in.item_begin) {
+                // centralized detector (Sec. 2.2): all local criteria + owned-residual estimate
+                int allc = 1;
+                double sum = 0.0;
+                for (int k = tid; k < in.item_count; k += B) {
+                    allc &= ld_rlx(P.conv + in.item_begin + k);
+                    sum += ld_rlx(P.res2_own + in.item_begin + k);
+                }
+                allc = __syncthreads_and(allc);
+                sum = block_sum<B>(sum, red);
+                if (tid == 0) {
+                    const int64_t now = wall_clock64();
+                    const int64_t h = st->hist_len;
+                    if (h < in.hist_cap) {
+                        in.hist[h] = sqrt(sum / in.bnorm2);
+                        in.hist_t[h] = static_cast<double>(now - st->t0);
+                        st->hist_len = h + 1;
+                    }
+                    st->sweeps += 1;
+                    int32_t stop = 0;
+                    if (!(sum == sum) || sum > 1e300) stop = 4;
+                    else if (allc && sum < in.tol2 * in.bnorm2) stop = 1;
+                    else if (P.max_ticks > 0 && now - st->t0 > P.max_ticks) stop = 2;
+                    if (stop) st_rlx(&st->stop, stop);
+                }
+            }
+            __syncthreads();
+        }
+        if (!__syncthreads_or(any)) break;
+    }
+}
+
+// ------------------------------------------------------------------------------ kernels
+template <class CT, int KT, bool ASYNC>
+__global__ void __launch_bounds__(kCgThreads) cg_kernel(Params P) {
+    __shared__ double red[kCgThreads / 64];
+    __shared__ int8_t done[kMaxItemsPerWg];
+    CgUpdate<CT, KT, ASYNC> upd;
+    if constexpr (ASYNC)
+        run_async<kCgThreads>(P, upd, red, done);
+    else
+        run_sync<kCgThreads>(P, upd, red, done);
+}
+
+template <class ST, bool ASYNC>
+__global__ void __launch_bounds__(kBandThreads) band_kernel(Params P, int max_w, int winm) {
+    __shared__ double red[kBandThreads / 64];
+    __shared__ int8_t done[kMaxItemsPerWg];
+    BandUpdate<ST, ASYNC> upd{max_w, winm};
+    if constexpr (ASYNC)
+        run_async<kBandThreads>(P, upd, red, done);
+    else
+        run_sync<kBandThreads>(P, upd, red, done);
+}
+
+// ||b||^2 per instance and the exact residual ||b - A x||^2 (verification,
+// Sec. 3.3.2), two-pass deterministic reductions.
+constexpr int kRedThreads = 256;
+
+__global__ void __launch_bounds__(kRedThreads)
+    residual_partials(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                      const double* __restrict__ va, const double* __restrict__ b, const double* __restrict__ x,
+                      double* __restrict__ part_r, double* __restrict__ part_b) {
+    __shared__ double red[kRedThreads / 64];
+    double sr = 0.0, sb = 0.0;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kRedThreads) {
+        double acc = b[i];
+        if (x != nullptr)
+            for (int64_t e = rp[i]; e < rp[i + 1]; ++e) acc -= va[e] * x[ci[e]];
+        sr += acc * acc;
+        sb += b[i] * b[i];
+    }
+    sr = block_sum<kRedThreads>(sr, red);
+    sb = block_sum<kRedThreads>(sb, red);
+    if (threadIdx.x == 0) {
+        part_r[blockIdx.x] = sr;
+        part_b[blockIdx.x] = sb;
+    }
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+    finish_partials(int nparts, const double* __restrict__ part_r, const double* __restrict__ part_b,
+                    double* __restrict__ out /* [2]: r2, b2 */) {
+    __shared__ double red[kRedThreads / 64];
+    double sr = 0.0, sb = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += kRedThreads) {
+        sr += part_r[k];
+        sb += part_b[k];
+    }
+    sr = block_sum<kRedThreads>(sr, red);
+    sb = block_sum<kRedThreads>(sb, red);
+    if (threadIdx.x == 0) {
+        out[0] = sr;
+        out[1] = sb;
+    }
+}
+
+__global__ void copy_vec(int64_t n, const double* __restrict__ src, double* __restrict__ dst) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ void stamp_start(InstState* ist, int n) {
+    const int64_t now = wall_clock64();
+    for (int k = threadIdx.x; k < n; k += blockDim.x) ist[k].t0 = now;
+}
+
+// ------------------------------------------------------------------------------ host launchers
+namespace {
+template <class K>
+hipError_t launch(K kern, dim3 grid, dim3 block, size_t lds, hipStream_t st, bool coop, void** args) {
+    if (lds > 0) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+    }
+    if (coop) return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), grid, block, args, lds, st);
+    return hipLaunchKernel(reinterpret_cast<const void*>(kern), grid, block, args, lds, st);
+}
+
+template <class CT, bool ASYNC>
+const void* cg_kernel_for(int kt) {
+    if (kt == 5) return reinterpret_cast<const void*>(cg_kernel<CT, 5, ASYNC>);
+    if (kt == 7) return reinterpret_cast<const void*>(cg_kernel<CT, 7, ASYNC>);
+    return reinterpret_cast<const void*>(cg_kernel<CT, 0, ASYNC>);
+}
+
+template <class ST>
+const void* band_kernel_for(bool async) {
+    return async ? reinterpret_cast<const void*>(band_kernel<ST, true>)
+                 : reinterpret_cast<const void*>(band_kernel<ST, false>);
+}
+}  // namespace
+
+const void* select_kernel(int solver, int storage, bool async, int ell_width) {
+    if (solver == 1) {  // CG
+        if (storage == 0) return async ? cg_kernel_for<double, true>(ell_width) : cg_kernel_for<double, false>(ell_width);
+        return async ? cg_kernel_for<float, true>(ell_width) : cg_kernel_for<float, false>(ell_width);
+    }
+    if (storage == 0) return band_kernel_for<double>(async);
+    if (storage == 1) return band_kernel_for<float>(async);
+    return band_kernel_for<_Float16>(async);
+}
+
+hipError_t launch_solver(const void* kern, int solver, const Params& P, int max_w, int winm, size_t lds,
+                         hipStream_t st, bool coop) {
+    Params p = P;
+    if (lds > 0) {
+        hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+    }
+    const dim3 grid(P.n_wg), block(solver == 1 ? kCgThreads : kBandThreads);
+    if (solver == 1) {
+        void* args[] = {&p};
+        return coop ? hipLaunchCooperativeKernel(kern, grid, block, args, lds, st)
+                    : hipLaunchKernel(kern, grid, block, args, lds, st);
+    }
+    void* args[] = {&p, &max_w, &winm};
+    return coop ? hipLaunchCooperativeKernel(kern, grid, block, args, lds, st)
+                : hipLaunchKernel(kern, grid, block, args, lds, st);
+}
+
+hipError_t occupancy(const void* kern, int solver, size_t lds, int* per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, solver == 1 ? kCgThreads : kBandThreads, lds);
+}
+
+hipError_t launch_residual(int64_t n, const int64_t* rp, const int32_t* ci, const double* va, const double* b,
+                           const double* x, double* parts, int nparts, double* out, hipStream_t st) {
+    residual_partials<<<nparts, kRedThreads, 0, st>>>(n, rp, ci, va, b, x, parts, parts + nparts);
+    finish_partials<<<1, kRedThreads, 0, st>>>(nparts, parts, parts + nparts, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(int64_t n, const double* src, double* dst, hipStream_t st) {
+    copy_vec<<<1024, 256, 0, st>>>(n, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_stamp(InstState* ist, int n, hipStream_t st) {
+    stamp_start<<<1, 256, 0, st>>>(ist, n);
+    return hipGetLastError();
+}
+
+}  // namespace ras

@@ -1,0 +1,259 @@
+"""GPU parity: the HIP path through the C ABI against the oracle (needs an MI355X).
+
+Tolerances: float64 local solves -- the same iteration up to rounding order,
+so histories agree to 1e-9 relative per sweep while the residual is above
+1e-12, iterates to 1e-9 relative; float32 local arithmetic -- iterates after a
+fixed number of sweeps to 2e-5 relative (float32 unit roundoff 6e-8 times the
+growth of CG / triangular-solve rounding over a few sweeps); converged
+solutions to the BASELINE criteria: relative residual below tol (exact,
+recomputed) and 1e-6 relative error against the float64 direct solve where the
+right-hand side makes that attainable.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import ras_inputs as R
+from oracle import partition as opart
+from oracle import schwarz
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _ras():
+    import paper_2003_05361_amd as ras
+
+    ras.lib()
+    return ras
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _cuda(v):
+    torch = _torch()
+    return torch.tensor(np.ascontiguousarray(v), dtype=torch.float64, device="cuda")
+
+
+def _owner(A, kind, arg):
+    if kind == "regular_1d":
+        return opart.regular_1d(A.n, arg)
+    if kind in ("regular_2d", "regular_3d"):
+        return opart.regular_grid(A.grid, arg)
+    P, seed, jit = arg
+    return opart.rcb(A.coords(), P, seed, jit)
+
+
+def _spec(ras, A, kind, arg):
+    if kind == "rcb":
+        P, seed, jit = arg
+        return ras.partition("rcb", P, grid=A.grid, seed=seed, jitter=jit)
+    return ras.partition(kind, arg, grid=A.grid)
+
+
+def _oracle(A, kind, arg, gamma, loc, storage="fp64", k=0):
+    return schwarz.RAS(A, _owner(A, kind, arg), gamma, loc, storage, k)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# ----------------------------------------------------------------------------- synchronous parity
+def test_config1_sync_exact_history_and_solution():
+    """64^2 Poisson, 4 strips, overlap 2, banded Cholesky FP64, sync to 1e-10."""
+    ras = _ras()
+    _say("case: poisson2d_64_strips4 sync chol fp64")
+    A, b, cfg = R.config_problem("poisson2d_64_strips4")
+    orc = _oracle(A, "regular_1d", 4, 2, "chol")
+    xo, ho, ko = orc.sync(b, 1e-10, 10000)
+    h = ras.setup(A, _spec(ras, A, "regular_1d", 4), 2, ras.local("chol", "fp64"))
+    x, info = h.solve(_cuda(b), tol=1e-10, mode="sync", max_sweeps=10000)
+    x = x.cpu().numpy()
+    _, hg = h.residual_history()
+    assert info[0]["converged"] and info[0]["sweeps"] == ko
+    assert len(hg) == len(ho)
+    big = ho > 1e-12
+    assert np.max(np.abs(hg[big] - ho[big]) / ho[big]) <= 1e-9
+    assert _rel(x, xo) <= 1e-9
+    assert info[0]["rel_residual"] < 1e-10
+    xd = schwarz.direct_solve(A, b)
+    assert _rel(x, xd) <= 1e-6
+    assert _rel(x, cfg["x_star"]) <= 1e-6
+    assert np.all(h.local_solve_counts() == ko)
+
+
+@pytest.mark.parametrize("N,part,gamma,k", [
+    (48, ("regular_2d", (3, 3)), 2, 6),
+    (37, ("regular_2d", (2, 3)), 1, 4),  # ragged boxes and tails
+    (40, ("regular_1d", 5), 0, 3),  # zero overlap: block Jacobi with CG
+])
+def test_sync_cg_fp64_matches_oracle(N, part, gamma, k):
+    ras = _ras()
+    _say(f"case: sync cg fp64 N={N} part={part} gamma={gamma} k={k}")
+    A = R.laplace2d(N, N + 3)
+    b = R.uniform_rhs(A.n, 11)
+    orc = _oracle(A, part[0], part[1], gamma, "cg", "fp64", k)
+    h = ras.setup(A, _spec(ras, A, *part), gamma, ras.local("cg", "fp64", k))
+    for sweeps in (1, 2, 7):
+        xo, ho, _ = orc.sync(b, 0.0, sweeps)
+        x, info = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=sweeps)
+        assert info[0]["sweeps"] == sweeps
+        assert _rel(x.cpu().numpy(), xo) <= 1e-9
+        _, hg = h.residual_history()
+        assert np.max(np.abs(hg - ho) / ho) <= 1e-9
+
+
+def test_sync_cg_fp32_3d_rcb_matches_oracle():
+    ras = _ras()
+    _say("case: sync cg fp32 3d rcb")
+    A = R.laplace3d(14)
+    b = R.uniform_rhs(A.n, 12)
+    part = ("rcb", (9, 3, 0.4))
+    orc = _oracle(A, *part, 1, "cg", "fp32", 8)
+    h = ras.setup(A, _spec(ras, A, *part), 1, ras.local("cg", "fp32", 8))
+    for sweeps in (1, 4):
+        xo, ho, _ = orc.sync(b, 0.0, sweeps)
+        x, _ = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=sweeps)
+        assert _rel(x.cpu().numpy(), xo) <= 2e-5
+    # and it converges to the float64 tolerance (correction form)
+    x, info = h.solve(_cuda(b), tol=1e-8, mode="sync", max_sweeps=5000)
+    assert info[0]["converged"] and info[0]["rel_residual"] < 1e-8
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", 1e-9), ("fp32", 2e-5), ("fp16", 2e-5)])
+def test_sync_band_storage_matches_oracle(storage, tol):
+    ras = _ras()
+    _say(f"case: sync band {storage}")
+    g = R.gaussian_random_field_2d(56, 8.0, 4)
+    A = R.tpfa2d(np.exp(2.0 * g), 10.0)
+    b = R.uniform_rhs(A.n, 5)
+    part = ("regular_2d", (3, 2))
+    orc = _oracle(A, *part, 3, "chol", storage)
+    h = ras.setup(A, _spec(ras, A, *part), 3, ras.local("chol", storage))
+    for sweeps in (1, 3):
+        xo, _, _ = orc.sync(b, 0.0, sweeps)
+        x, _ = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=sweeps)
+        assert _rel(x.cpu().numpy(), xo) <= tol
+    x, info = h.solve(_cuda(b), tol=1e-8, mode="sync", max_sweeps=20000)
+    assert info[0]["converged"] and info[0]["rel_residual"] < 1e-8
+
+
+def test_single_subdomain_is_direct_solve():
+    ras = _ras()
+    _say("case: one subdomain")
+    A = R.laplace2d(30, 17)
+    b = R.uniform_rhs(A.n, 13)
+    h = ras.setup(A, ras.partition("regular_1d", 1), 0, ras.local("chol", "fp64"))
+    x, info = h.solve(_cuda(b), tol=1e-12, mode="sync", max_sweeps=5)
+    assert info[0]["sweeps"] == 1 and info[0]["converged"]
+    assert _rel(x.cpu().numpy(), schwarz.direct_solve(A, b)) <= 1e-12
+
+
+def test_tiny_and_ragged_subdomains():
+    """Subdomains smaller than a block of the banded solve and than a wavefront."""
+    ras = _ras()
+    _say("case: tiny ragged")
+    A = R.laplace2d(7, 5)
+    b = R.uniform_rhs(A.n, 14)
+    part = ("regular_1d", 6)
+    for loc, st, k in (("chol", "fp64", 0), ("cg", "fp64", 3)):
+        orc = _oracle(A, *part, 1, loc, st, k)
+        h = ras.setup(A, _spec(ras, A, *part), 1, ras.local(loc, st, k))
+        xo, _, _ = orc.sync(b, 0.0, 3)
+        x, _ = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=3)
+        assert _rel(x.cpu().numpy(), xo) <= 1e-9
+
+
+# ----------------------------------------------------------------------------- ordered = RMS
+@pytest.mark.parametrize("loc,k", [("chol", 0), ("cg", 5)])
+def test_ordered_mode_is_multiplicative_schwarz(loc, k):
+    ras = _ras()
+    _say(f"case: ordered {loc}")
+    A = R.laplace2d(40)
+    b = R.uniform_rhs(A.n, 15)
+    part = ("regular_2d", (2, 3))
+    orc = _oracle(A, *part, 2, loc, "fp64", k)
+    h = ras.setup(A, _spec(ras, A, *part), 2, ras.local(loc, "fp64", k))
+    for passes in (1, 3):
+        xo, _ = orc.ordered(b, passes)
+        x, info = h.solve(_cuda(b), tol=0.0, mode="ordered", max_sweeps=passes)
+        assert info[0]["min_local_solves"] == passes and info[0]["max_local_solves"] == passes
+        assert _rel(x.cpu().numpy(), xo) <= 1e-9
+
+
+# ----------------------------------------------------------------------------- asynchronous
+@pytest.mark.parametrize("loc,st,k", [("chol", "fp64", 0), ("cg", "fp64", 10), ("chol", "fp32", 0)])
+def test_async_converges_and_verifies(loc, st, k):
+    ras = _ras()
+    _say(f"case: async {loc} {st}")
+    A = R.laplace2d(96)
+    b = R.uniform_rhs(A.n, 16)
+    xd = schwarz.direct_solve(A, b)
+    h = ras.setup(A, ras.partition("regular_2d", (4, 4), grid=A.grid), 3, ras.local(loc, st, k))
+    for run in range(3):
+        x, info = h.solve(_cuda(b), tol=1e-8, mode="async", max_sweeps=200000, max_seconds=60)
+        xx = x.cpu().numpy()
+        assert info[0]["converged"], info
+        assert schwarz.relative_residual(A, xx, b) < 1e-8
+        assert _rel(xx, xd) <= 1e-6
+        counts = h.local_solve_counts()
+        assert counts.min() >= 1 and counts.sum() == info[0]["total_local_solves"]
+
+
+# ----------------------------------------------------------------------------- multi-RHS and batching
+def test_multi_rhs_equals_single_sync():
+    ras = _ras()
+    _say("case: multi rhs")
+    torch = _torch()
+    A = R.laplace2d(50)
+    B = np.stack([R.uniform_rhs(A.n, s) for s in (1, 2, 3)])
+    h = ras.setup(A, ras.partition("regular_2d", (3, 3), grid=A.grid), 2, ras.local("cg", "fp64", 6))
+    X, infos = h.solve(_cuda(B), tol=1e-8, mode="sync", max_sweeps=100000)
+    for j in range(3):
+        x1, i1 = h.solve(_cuda(B[j]), tol=1e-8, mode="sync", max_sweeps=100000)
+        assert torch.equal(X[j], x1)
+        assert infos[j]["sweeps"] == i1[0]["sweeps"]
+
+
+def test_batch_equals_alone():
+    ras = _ras()
+    _say("case: batch")
+    torch = _torch()
+    A1, A2 = R.laplace2d(40), R.laplace3d(12)
+    b1, b2 = R.uniform_rhs(A1.n, 3), R.uniform_rhs(A2.n, 4)
+    h1 = ras.setup(A1, ras.partition("regular_2d", (2, 2), grid=A1.grid), 2, ras.local("chol", "fp64"))
+    h2 = ras.setup(A2, ras.partition("regular_3d", (2, 2, 2), grid=A2.grid), 1, ras.local("chol", "fp64"))
+    xs, infos = ras.batch_solve([h1, h2], [_cuda(b1), _cuda(b2)], tol=1e-9, mode="sync", max_sweeps=100000)
+    a1, _ = h1.solve(_cuda(b1), tol=1e-9, mode="sync", max_sweeps=100000)
+    a2, _ = h2.solve(_cuda(b2), tol=1e-9, mode="sync", max_sweeps=100000)
+    assert torch.equal(xs[0], a1) and torch.equal(xs[1], a2)
+    ys, infos = ras.batch_solve([h1, h2], [_cuda(b1), _cuda(b2)], tol=1e-9, mode="async", max_sweeps=100000)
+    for y, A, b in ((ys[0], A1, b1), (ys[1], A2, b2)):
+        yy = y.cpu().numpy()
+        assert schwarz.relative_residual(A, yy, b) < 1e-9
+        assert _rel(yy, schwarz.direct_solve(A, b)) <= 1e-6
+
+
+# ----------------------------------------------------------------------------- full-size sampled checks
+def test_config2_full_size_two_sweeps():
+    """1024^2, 8x8 boxes, overlap 4, CG-10 FP64 -- the bench's launch shape."""
+    ras = _ras()
+    _say("case: poisson2d_1024_8x8 two sync sweeps vs oracle")
+    A, b, cfg = R.config_problem("poisson2d_1024_8x8")
+    orc = _oracle(A, "regular_2d", (8, 8), 4, "cg", "fp64", 10)
+    xo, ho, _ = orc.sync(b, 0.0, 2)
+    h = ras.setup(A, ras.partition("regular_2d", (8, 8), grid=A.grid), 4, ras.local("cg", "fp64", 10))
+    x, info = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=2)
+    assert _rel(x.cpu().numpy(), xo) <= 1e-9
+    _, hg = h.residual_history()
+    assert np.max(np.abs(hg - ho) / ho) <= 1e-9
