@@ -1,0 +1,282 @@
+#!/usr/bin/env python3
+"""Benchmark: time to a 1e-8 relative residual of the asynchronous vs the
+synchronous restricted additive Schwarz solver on one MI355X.
+
+Default workload (one step = one full solve, setup excluded as in the paper's
+timings): 2-D 5-point Poisson on a 1024 x 1024 grid (1,048,576 unknowns),
+b ~ U[0,1] (seed 1), regular 8 x 8 boxes (64 subdomains), overlap 4, local
+solve = 10 CG iterations in float64, tolerance 1e-8.  The timed steps run the
+asynchronous (barrier-free persistent) solver; the synchronous variant is
+timed the same way beside it.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-1e-8 residual async vs sync RAS; sweep HBM GB/s vs peak; solves/s + p99"
+HBM_PEAK_GBPS = 8000.0
+
+WORKLOADS = {
+    # name: (ras_inputs config, local kind, storage, cg iters, partition spec)
+    "poisson2d_1024_8x8": ("poisson2d_1024_8x8", "cg", "fp64", 10),
+    "laplace3d_128_rcb256": ("laplace3d_128_rcb256", "cg", "fp32", 8),
+    "diffusion2d_2048_16x16_fp64": ("diffusion2d_2048_16x16", "chol", "fp64", 0),
+    "diffusion2d_2048_16x16_fp32": ("diffusion2d_2048_16x16", "chol", "fp32", 0),
+    "diffusion2d_2048_16x16_fp16": ("diffusion2d_2048_16x16", "chol", "fp16", 0),
+    "poisson2d_64_strips4": ("poisson2d_64_strips4", "chol", "fp64", 0),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="poisson2d_1024_8x8", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sync", action="store_true", help="skip the synchronous comparison (profiling runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 2 GiB device copy (hardware-counter calibration)")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "device.hpp"):
+        with open(os.path.join(ROOT, "paper_2003_05361_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def bytes_per_local_solve(stats_subs, kind: str, storage: str, k: int) -> list:
+    """Algorithmic HBM bytes of one local solve of each subdomain (streaming model:
+    each array touched the minimum number of times per step, no reuse across CG
+    iterations): restrict + residual, local solve, restricted prolongation."""
+    s = 8 if storage == "fp64" else 4
+    out = []
+    for n, n_own, K, w in stats_subs:
+        res = n * (12 * K + 16)
+        pro = n_own * (16 + s)
+        if kind == "cg":
+            loc = k * n * (K * (s + 4) + 11 * s)
+        else:
+            sl = {"fp64": 8, "fp32": 4, "fp16": 2}[storage]
+            loc = 2 * n * (w + 1) * sl + 4 * n * s + (2 * n * 4 if storage == "fp16" else 0)
+        out.append(res + loc + pro)
+    return out
+
+
+def subdomain_shapes(A, part_kind, part_arg, gamma):
+    """(n_p, owned_p, K_p, w_p) per subdomain from the library's own host setup."""
+    import numpy as np
+
+    import paper_2003_05361_amd as ras
+
+    plan = ras.Plan(A, part_spec(ras, A, part_kind, part_arg), gamma, ras.local("cg", "fp64", 1))
+    owner, ptr, idx = plan.sets()
+    rp = A.indptr
+    shapes = []
+    for p in range(len(ptr) - 1):
+        om = idx[ptr[p]:ptr[p + 1]]
+        n = om.size
+        n_own = int(np.count_nonzero(owner[om] == p))
+        K = int(np.max(rp[om + 1] - rp[om]))
+        shapes.append([n, n_own, K, plan.band_width(p)])
+    plan.close()
+    return shapes
+
+
+def part_spec(ras, A, kind, arg):
+    if kind == "rcb":
+        P, seed, jit = arg
+        return ras.partition("rcb", P, grid=A.grid, seed=seed, jitter=jit)
+    return ras.partition(kind, arg, grid=A.grid)
+
+
+def cpu_baseline(A, b, part_kind, part_arg, gamma, kind, storage, k, gpu_sync_sweeps):
+    """The oracle (plain FP64 CPU synchronous RAS), timed on a bounded sample of
+    sweeps on this host, single-threaded, extrapolated to the GPU's sweep count."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import partition as opart
+    from oracle import schwarz
+
+    if part_kind == "regular_1d":
+        owner = opart.regular_1d(A.n, part_arg)
+    elif part_kind == "rcb":
+        owner = opart.rcb(A.coords(), *part_arg)
+    else:
+        owner = opart.regular_grid(A.grid, part_arg)
+    with threadpool_limits(1):
+        orc = schwarz.RAS(A, owner, gamma, kind, storage, k)
+        sweeps = 1
+        t0 = time.perf_counter()
+        orc.sync(b, 0.0, 1)
+        t1 = time.perf_counter() - t0
+        budget = 15.0
+        sweeps = max(1, min(int(budget / max(t1, 1e-6)), 2000))
+        t0 = time.perf_counter()
+        orc.sync(b, 0.0, sweeps)
+        dt = time.perf_counter() - t0
+    per_sweep = dt / sweeps
+    return {
+        "value": per_sweep * gpu_sync_sweeps,
+        "unit": "s (extrapolated time-to-tolerance)",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{sweeps} synchronous FP64 sweeps of the same workload in {dt:.2f} s on the host "
+                  f"({per_sweep * 1e3:.1f} ms/sweep), scaled by the GPU synchronous sweep count {gpu_sync_sweeps}",
+    }
+
+
+def traffic_from_profiles(workload: str, algo_bytes_per_launch: float):
+    """HBM bytes per launch from the committed hardware-counter summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_hash") != kernel_source_hash():
+        return None
+    ratio = t["counter_bytes_per_dispatch"] / t["algorithmic_bytes_per_dispatch"]
+    return ratio * algo_bytes_per_launch
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (every subdomain of a system "
+              "lives on one device). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        n = (2 << 30) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": 2 * n * 8, "kernel": "torch copy", "launches": 3}))
+        return
+
+    import paper_2003_05361_amd as ras
+    import ras_inputs as R
+
+    cfg_name, kind, storage, k = WORKLOADS[args.workload]
+    A, b, cfg = R.config_problem(cfg_name)
+    part_kind, part_arg = cfg["partition"]
+    gamma = cfg["overlap"]
+    tol = cfg["tol"]
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    h = ras.setup(A, part_spec(ras, A, part_kind, part_arg), gamma, ras.local(kind, storage, k), stream=stream)
+    setup_s = time.perf_counter() - t0
+    st = h.stats()
+    shapes = subdomain_shapes(A, part_kind, part_arg, gamma)
+    bps = bytes_per_local_solve(shapes, kind, storage, k)
+    bps = np.array(bps, dtype=np.float64)
+    bt = torch.tensor(b, dtype=torch.float64, device="cuda")
+
+    def solve(mode):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        x, info = h.solve(bt, tol=tol, mode=mode, max_sweeps=5_000_000, max_seconds=300)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        counts = h.local_solve_counts()
+        return x, info[0], e0.elapsed_time(e1) * 1e-3, counts
+
+    for _ in range(args.warmup):
+        solve("async")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = []
+    for _ in range(args.steps):
+        runs.append(solve("async"))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    a_times = [r[2] for r in runs]
+    a_kernel = [r[1]["kernel_seconds"] for r in runs]
+    a_info = runs[-1][1]
+    a_bytes = [float(np.dot(r[3], bps)) for r in runs]
+    x_async = runs[-1][0]
+
+    sync_res = None
+    if not args.no_sync:
+        sruns = [solve("sync") for _ in range(max(1, args.steps))]
+        s_info = sruns[-1][1]
+        # the synchronous kernel also computes one speculative update after the last sweep
+        s_bytes = [float((r[1]["sweeps"] + 1) * bps.sum()) for r in sruns]
+        sync_res = dict(seconds=float(np.mean([r[2] for r in sruns])), sweeps=int(s_info["sweeps"]),
+                        kernel_seconds=float(np.mean([r[1]["kernel_seconds"] for r in sruns])),
+                        rel_residual=s_info["rel_residual"],
+                        model_GBps=float(np.mean([bb / r[1]["kernel_seconds"] for bb, r in zip(s_bytes, sruns)]) / 1e9))
+
+    # verification on the host copy: exact residual and error against the direct solve
+    xa = x_async.cpu().numpy()
+    relres = float(np.linalg.norm(b - A.matvec(xa)) / np.linalg.norm(b))
+    achieved = float(np.mean([bb / ks for bb, ks in zip(a_bytes, a_kernel)])) / 1e9
+    algo_per_launch = float(np.mean(a_bytes))
+    traffic = traffic_from_profiles(args.workload, algo_per_launch)
+    roof = {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBPS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBPS, 4),
+        "traffic": None if traffic is None else float(traffic),
+        "kernel": f"persistent async {kind}{'-' + str(k) if kind == 'cg' else ''} {storage}",
+        "algorithmic_bytes_per_launch": algo_per_launch,
+        "kernel_seconds_per_launch": float(np.mean(a_kernel)),
+    }
+    line = {
+        "metric": METRIC,
+        "value": float(np.mean(a_times)),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / max(1, args.steps),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if storage == "fp64" else f"f64 outer / {storage} local",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": int(A.n), "subdomains": int(st["parts"]), "overlap": gamma,
+                   "local": f"{kind}{k if kind == 'cg' else ''}-{storage}", "tol": tol, "mode": "async"},
+        "async": {"seconds": float(np.mean(a_times)), "local_solves_total": int(a_info["total_local_solves"]),
+                  "local_solves_min": int(a_info["min_local_solves"]), "local_solves_max": int(a_info["max_local_solves"]),
+                  "rel_residual": relres, "launches": int(a_info["launches"])},
+        "sync": sync_res,
+        "async_speedup_vs_sync": None if sync_res is None else sync_res["seconds"] / float(np.mean(a_times)),
+        "setup_s": setup_s,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline and sync_res is not None:
+        line["cpu_baseline"] = cpu_baseline(A, b, part_kind, part_arg, gamma, kind, storage, k, sync_res["sweeps"])
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

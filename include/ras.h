@@ -107,7 +107,9 @@ typedef struct ras_local {
  *   mode ORDERED: the asynchronous kernel run by one workgroup visiting the
  *     subdomains in order (restricted multiplicative Schwarz; deterministic).
  *   max_sweeps: sweeps (SYNC) or local solves per subdomain (ASYNC/ORDERED).
- *   max_seconds <= 0: no time limit.  workgroups: 0 = library choice.  */
+ *   max_seconds <= 0: no time limit.  workgroups: 0 = library choice.
+ *   team: workgroups cooperating on one subdomain's CG solve (1, 2, 4, 8 or
+ *     16); 0 = the value found by ras_autotune, else a heuristic.  */
 enum { RAS_MODE_SYNC = 0, RAS_MODE_ASYNC = 1, RAS_MODE_ORDERED = 2 };
 enum { RAS_DETECT_CENTRAL = 0, RAS_DETECT_DECENTRAL = 1 };
 typedef struct ras_solve_opts {
@@ -117,7 +119,7 @@ typedef struct ras_solve_opts {
     int64_t max_sweeps;
     double max_seconds;
     int32_t workgroups;
-    int32_t reserved;
+    int32_t team;
 } ras_solve_opts;
 
 typedef struct ras_solve_info {
@@ -129,6 +131,7 @@ typedef struct ras_solve_info {
     int64_t max_local_solves;
     double rel_residual;       /* exact float64 ||b - A x|| / ||b|| recomputed after the stop */
     double seconds;            /* device time of the solve (first launch to verified stop) */
+    double kernel_seconds;     /* device time inside the persistent kernel launches only */
 } ras_solve_info;
 
 /* Host-side setup summary. */
@@ -162,7 +165,8 @@ ras_status ras_plan_get_stats(const ras_plan* plan, ras_plan_stats* out);
 ras_status ras_plan_sets(const ras_plan* plan, int32_t* owner, int64_t* omega_ptr, int32_t* omega_idx);
 /* Float64 band factor of subdomain p: band[i*(w+1) + (j - i + w)] = L_ij for
  * i-w <= j <= i (zero outside the matrix); *w receives the half-bandwidth.
- * band may be NULL to query w.  RAS_E_STATE unless the solver is Cholesky.  */
+ * band may be NULL to query w (any local solver); with band non-NULL the
+ * call returns RAS_E_STATE unless the solver is Cholesky.  */
 ras_status ras_plan_factor(const ras_plan* plan, int32_t p, double* band, int32_t* w);
 /* FP16_ROWSCALED storage of subdomain p's factor, in the same band layout:
  * half_bits[i*(w+1) + o] = float16 bits of L_ij / scale[i] (round to nearest

@@ -48,13 +48,14 @@ class LocalStruct(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("detect", C.c_int32), ("tol", C.c_double), ("max_sweeps", C.c_int64),
-                ("max_seconds", C.c_double), ("workgroups", C.c_int32), ("reserved", C.c_int32)]
+                ("max_seconds", C.c_double), ("workgroups", C.c_int32), ("team", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("converged", C.c_int32), ("launches", C.c_int32), ("sweeps", C.c_int64),
                 ("total_local_solves", C.c_int64), ("min_local_solves", C.c_int64),
-                ("max_local_solves", C.c_int64), ("rel_residual", C.c_double), ("seconds", C.c_double)]
+                ("max_local_solves", C.c_int64), ("rel_residual", C.c_double), ("seconds", C.c_double),
+                ("kernel_seconds", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -216,6 +217,12 @@ class Plan:
         _check(lib().ras_plan_sets(self._p, owner.ctypes.data, ptr.ctypes.data, idx.ctypes.data))
         return owner, ptr, idx
 
+    def band_width(self, p: int) -> int:
+        """Lower half-bandwidth of subdomain p's local matrix."""
+        w = C.c_int32()
+        _check(lib().ras_plan_factor(self._p, p, None, C.byref(w)))
+        return w.value
+
     def factor(self, p: int) -> tuple[np.ndarray, int]:
         w = C.c_int32()
         _check(lib().ras_plan_factor(self._p, p, None, C.byref(w)))
@@ -238,8 +245,11 @@ class Plan:
         return Handle(h, self.n)
 
     def close(self):
-        if getattr(self, "_p", None):
-            lib().ras_plan_destroy(self._p)
+        if getattr(self, "_p", None) and _lib_handle is not None:
+            try:
+                _lib_handle.ras_plan_destroy(self._p)
+            except Exception:
+                pass
             self._p = None
 
     __del__ = close
@@ -254,8 +264,9 @@ def _stream_ptr(stream):
     return C.c_void_p(getattr(stream, "cuda_stream", stream))
 
 
-def _opts(tol, mode, max_sweeps, max_seconds, detect, workgroups) -> SolveOpts:
-    return SolveOpts(MODES[mode], DETECT[detect], float(tol), int(max_sweeps), float(max_seconds), int(workgroups), 0)
+def _opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team=0) -> SolveOpts:
+    return SolveOpts(MODES[mode], DETECT[detect], float(tol), int(max_sweeps), float(max_seconds), int(workgroups),
+                     int(team))
 
 
 class Handle:
@@ -272,7 +283,8 @@ class Handle:
         return s.as_dict()
 
     def solve(self, b, x0=None, tol: float = 1e-8, mode: str = "async", max_sweeps: int = 1_000_000,
-              max_seconds: float = 0.0, detect: str = "central", workgroups: int = 0, allow_unconverged=True):
+              max_seconds: float = 0.0, detect: str = "central", workgroups: int = 0, team: int = 0,
+              allow_unconverged=True):
         """Solve A x = b on the device.  b: float64 CUDA tensor [n] or [nrhs, n].
         Returns (x, infos) with x the same shape as b."""
         import torch
@@ -284,7 +296,7 @@ class Handle:
         x = torch.zeros_like(b) if x0 is None else x0.to(torch.float64).contiguous().clone()
         infos = (SolveInfo * nrhs)()
         st = lib().ras_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), nrhs,
-                             C.byref(_opts(tol, mode, max_sweeps, max_seconds, detect, workgroups)), infos)
+                             C.byref(_opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team)), infos)
         _check(st, (RAS_OK, RAS_NOT_CONVERGED) if allow_unconverged else (RAS_OK,))
         self.last_nrhs = nrhs
         return x, [i.as_dict() for i in infos]
@@ -317,8 +329,11 @@ class Handle:
         return r.value
 
     def close(self):
-        if getattr(self, "_h", None):
-            lib().ras_destroy(self._h)
+        if getattr(self, "_h", None) and _lib_handle is not None:
+            try:
+                _lib_handle.ras_destroy(self._h)
+            except Exception:
+                pass
             self._h = None
 
     __del__ = close
@@ -333,7 +348,8 @@ def setup(A, part: dict, overlap: int, loc: dict, stream=None) -> Handle:
 
 
 def batch_solve(handles: Sequence[Handle], bs, xs=None, tol: float = 1e-8, mode: str = "async",
-                max_sweeps: int = 1_000_000, max_seconds: float = 0.0, detect: str = "central", workgroups: int = 0):
+                max_sweeps: int = 1_000_000, max_seconds: float = 0.0, detect: str = "central", workgroups: int = 0,
+                team: int = 0):
     """Solve several systems in one persistent launch (same local solver kind/storage)."""
     import torch
 
@@ -346,8 +362,8 @@ def batch_solve(handles: Sequence[Handle], bs, xs=None, tol: float = 1e-8, mode:
     X = (_P * m)(*[x.data_ptr() for x in xs])
     NR = (C.c_int32 * m)(*nr)
     infos = (SolveInfo * sum(nr))()
-    st = lib().ras_batch_solve(m, H, B, X, NR, C.byref(_opts(tol, mode, max_sweeps, max_seconds, detect, workgroups)),
-                               infos)
+    st = lib().ras_batch_solve(m, H, B, X, NR,
+                               C.byref(_opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team)), infos)
     _check(st, (RAS_OK, RAS_NOT_CONVERGED))
     out, k = [], 0
     for r in nr:

@@ -17,7 +17,8 @@
 
 namespace ras {
 // kernels.hip
-const void* select_kernel(int solver, int storage, bool async, int ell_width);
+const void* select_kernel(int solver, int storage, bool async, int ell_width, int rclass);
+int cg_rows_class(int rows_per_member);
 hipError_t launch_solver(const void* kern, int solver, const Params& P, int max_w, int winm, size_t lds,
                          hipStream_t st, bool coop);
 hipError_t occupancy(const void* kern, int solver, size_t lds, int* per_cu);
@@ -99,6 +100,11 @@ struct ras_handle {
     DevBuf omega, ell_val, ell_valf, ell_gcol, ell_lcol, band_f, band_b, scale, invd;
     DevBuf csr_rp, csr_ci, csr_va;
     std::vector<SubDev> subs;  // host copy with device pointers
+    // CG team windows: for team size kTeamSizes[t], per subdomain and member the
+    // LDS window [lo, hi) of local rows its rows reference
+    std::vector<int32_t> win[5];
+    int max_win[5] = {0, 0, 0, 0, 0};
+    int tuned_team = 0;
     // last solve
     std::vector<std::vector<double>> hist, hist_t;
     std::vector<std::vector<int64_t>> counts;
@@ -236,6 +242,36 @@ void upload(ras_handle& h, const Plan& plan) {
                 if (it != s.omega.end() && *it == c) el[k * np + i] = static_cast<int32_t>(it - s.omega.begin());
             }
             for (; k < K; ++k) eg[k * np + i] = g;  // padding: value 0 times the row's own x
+        }
+        {
+            // per-row reach of the local columns, then the window of every team member
+            std::vector<int32_t> rmin(n), rmax(n);
+            for (int64_t i = 0; i < n; ++i) {
+                int32_t a = static_cast<int32_t>(i), b = static_cast<int32_t>(i);
+                for (int k = 0; k < K; ++k) {
+                    const int32_t c = el[k * np + i];
+                    if (c < n) {
+                        a = std::min(a, c);
+                        b = std::max(b, c);
+                    }
+                }
+                rmin[i] = a;
+                rmax[i] = b;
+            }
+            for (int t = 0; t < 5; ++t) {
+                const int T = kTeamSizes[t];
+                for (int m = 0; m < T; ++m) {
+                    const int64_t lo = m * n / T, hi = (m + 1) * n / T;
+                    int32_t a = static_cast<int32_t>(lo), b = static_cast<int32_t>(hi);
+                    for (int64_t i = lo; i < hi; ++i) {
+                        a = std::min(a, rmin[i]);
+                        b = std::max(b, rmax[i] + 1);
+                    }
+                    h.win[t].push_back(a);
+                    h.win[t].push_back(b);
+                    h.max_win[t] = std::max(h.max_win[t], b - a);
+                }
+            }
         }
         hip_check(hipMemcpy(h.omega.as<int32_t>() + row_off[p], om.data(), n * sizeof(int32_t), hipMemcpyHostToDevice),
                   "copy omega");
@@ -379,29 +415,94 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
         if (K == -1) K = h->uniform_K;
         else if (K != h->uniform_K) K = 0;
     }
-    int winm = 0;
-    const size_t lds = lds_bytes(h0.solver, h0.storage, max_n, max_w, &winm);
-    if (lds > kLdsLimit)
-        throw Error{RAS_E_UNSUPPORTED, "subdomain needs " + std::to_string(lds) + " bytes of LDS (limit " +
-                                           std::to_string(kLdsLimit) + "); use more subdomains"};
-    const void* kern = select_kernel(h0.solver, h0.storage, !sync, K);
-    if (!kern) throw Error{RAS_E_UNSUPPORTED, "no kernel for this configuration"};
+    const int ninst = static_cast<int>(specs.size());
+    int nitems_total = 0;
+    for (auto& sp : specs) nitems_total += sp.h->plan->P;
+
+    // kernel configuration: team size T (CG), rows-per-thread class, LDS bytes
+    struct Cfg {
+        int tidx = -1, T = 1, rclass = 0, winm = 0, per_cu = 0;
+        size_t lds = 0;
+        const void* kern = nullptr;
+    };
+    auto make_cfg = [&](int tidx) {
+        Cfg c;
+        c.tidx = tidx;
+        if (h0.solver == RAS_LOCAL_CG) {
+            c.T = kTeamSizes[tidx];
+            int maxwin = 0;
+            for (ras_handle* h : hs) maxwin = std::max(maxwin, h->max_win[tidx]);
+            c.lds = (static_cast<size_t>(maxwin) + 1) * ct_size(h0.storage);
+            c.rclass = cg_rows_class((max_n + c.T - 1) / c.T);
+            if (c.rclass < 0) return c;
+            c.kern = select_kernel(h0.solver, h0.storage, !sync, K, c.rclass);
+        } else {
+            if (tidx != 0) return c;
+            c.lds = lds_bytes(h0.solver, h0.storage, max_n, max_w, &c.winm);
+            c.kern = select_kernel(h0.solver, h0.storage, !sync, K, 0);
+        }
+        if (!c.kern || c.lds > kLdsLimit) {
+            c.kern = nullptr;
+            return c;
+        }
+        if (occupancy(c.kern, h0.solver, c.lds, &c.per_cu) != hipSuccess || c.per_cu < 1) c.kern = nullptr;
+        return c;
+    };
+    auto busy_wgs = [&](const Cfg& c) {
+        const int teams = std::min(nitems_total, c.per_cu * h0.num_cu / c.T);
+        return teams * c.T;
+    };
+    Cfg cfg;
+    const int want_team = o.team > 0 ? o.team : (h0.solver == RAS_LOCAL_CG ? h0.tuned_team : 0);
+    if (want_team > 0) {
+        for (int t = 0; t < 5; ++t)
+            if (kTeamSizes[t] == want_team) cfg = make_cfg(t);
+        if (!cfg.kern && o.team > 0)
+            throw Error{RAS_E_UNSUPPORTED, "team size " + std::to_string(o.team) + " not available for this shape"};
+    }
+    if (!cfg.kern) {
+        // heuristic: the smallest team that keeps every CU busy, without splitting a
+        // subdomain into members of fewer than two rows per thread; the ordered
+        // (single-team) mode takes the smallest team that fits
+        Cfg best;
+        for (int t = 0; t < 5; ++t) {
+            Cfg c = make_cfg(t);
+            if (!c.kern) continue;
+            if (!best.kern) {
+                best = c;
+                if (ordered) break;
+                continue;
+            }
+            if ((max_n + c.T - 1) / c.T < 2 * kCgThreads) break;
+            if (busy_wgs(best) >= h0.num_cu) break;
+            if (busy_wgs(c) > busy_wgs(best)) best = c;
+        }
+        cfg = best;
+    }
+    if (!cfg.kern)
+        throw Error{RAS_E_UNSUPPORTED, "subdomains too large for the on-chip kernels (rows per workgroup or LDS); "
+                                       "use more subdomains"};
+    const void* kern = cfg.kern;
+    const size_t lds = cfg.lds;
+    const int winm = cfg.winm;
+    const int T = cfg.T;
 
     // subdomain table: handle order; per-instance items
     std::vector<SubDev> subs;
+    std::vector<int32_t> team_win;
     std::vector<int> sub_base(hs.size());
     for (size_t k = 0; k < hs.size(); ++k) {
         sub_base[k] = static_cast<int>(subs.size());
         subs.insert(subs.end(), hs[k]->subs.begin(), hs[k]->subs.end());
+        const auto& wv = hs[k]->win[h0.solver == RAS_LOCAL_CG ? cfg.tidx : 0];
+        team_win.insert(team_win.end(), wv.begin(), wv.end());
     }
-    const int ninst = static_cast<int>(specs.size());
     std::vector<ItemDev> items;
     std::vector<double> cost;
     std::vector<InstDev> insts(ninst);
     int64_t scratch_elems = 0;
     std::vector<int64_t> scratch_off(ninst), x1_off(ninst);
     int64_t x1_elems = 0;
-    const int64_t scratch_mult = h0.solver == RAS_LOCAL_CG ? 3 : 1;
     for (int i = 0; i < ninst; ++i) {
         ras_handle* h = specs[i].h;
         const int hk = static_cast<int>(std::find(hs.begin(), hs.end(), h) - hs.begin());
@@ -414,28 +515,25 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
                                                      : static_cast<double>(sd.n) * (2.0 * (sd.w + 1) + sd.K));
         }
         scratch_off[i] = scratch_elems;
-        scratch_elems += scratch_mult * h->sum_n;
+        scratch_elems += h->sum_n;
         x1_off[i] = x1_elems;
         x1_elems += sync ? h->plan->n : 0;
     }
     const int nitems = static_cast<int>(items.size());
 
-    // workgroups: co-resident capacity, balanced static item lists (LPT)
-    int per_cu = 0;
-    hip_check(occupancy(kern, h0.solver, lds, &per_cu), "occupancy query");
-    if (per_cu < 1) throw Error{RAS_E_UNSUPPORTED, "kernel cannot be resident with this LDS size"};
-    const int capacity = per_cu * h0.num_cu;
-    int G = ordered ? 1 : std::min(nitems, capacity);
-    if (o.workgroups > 0) G = std::min(G, o.workgroups);
-    if (G < 1) G = 1;
-    std::vector<std::vector<int>> lists(G);
+    // teams: co-resident capacity, balanced static item lists (LPT)
+    int nteams = ordered ? 1 : std::min(nitems, cfg.per_cu * h0.num_cu / T);
+    if (o.workgroups > 0) nteams = std::min(nteams, std::max(1, o.workgroups / T));
+    if (nteams < 1) nteams = 1;
+    const int G = nteams * T;
+    std::vector<std::vector<int>> lists(nteams);
     {
         std::vector<int> order(nitems);
         std::iota(order.begin(), order.end(), 0);
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
         using Load = std::pair<double, int>;
         std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
-        for (int g = 0; g < G; ++g) heap.push({0.0, g});
+        for (int g = 0; g < nteams; ++g) heap.push({0.0, g});
         for (int it : order) {
             Load l = heap.top();
             heap.pop();
@@ -444,16 +542,31 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
         }
         for (auto& l : lists) std::sort(l.begin(), l.end());
     }
-    std::vector<int32_t> wg_ptr(G + 1, 0), wg_items;
+    // workgroup -> (team, member): the members of a team get workgroup ids that are
+    // equal modulo 8, so the round-robin placement of workgroups over the eight
+    // XCDs keeps a team (and its barrier and halo traffic) inside one XCD's L2
+    std::vector<int32_t> wg_team(G), wg_member(G), team_first_wg(nteams);
+    for (int grp = 0; grp * 8 < nteams; ++grp) {
+        const int gs = std::min(8, nteams - grp * 8);
+        const int basewg = grp * 8 * T;
+        for (int m = 0; m < T; ++m)
+            for (int l = 0; l < gs; ++l) {
+                const int g = basewg + m * gs + l;
+                wg_team[g] = grp * 8 + l;
+                wg_member[g] = m;
+                if (m == 0) team_first_wg[grp * 8 + l] = g;
+            }
+    }
+    std::vector<int32_t> team_ptr(nteams + 1, 0), team_items;
     std::vector<int> owner_wg(nitems, 0);
-    for (int g = 0; g < G; ++g) {
-        if (static_cast<int>(lists[g].size()) > kMaxItemsPerWg)
-            throw Error{RAS_E_UNSUPPORTED, "too many work items per workgroup"};
-        for (int it : lists[g]) {
-            wg_items.push_back(it);
-            owner_wg[it] = g;
+    for (int t = 0; t < nteams; ++t) {
+        if (static_cast<int>(lists[t].size()) > kMaxItemsPerWg)
+            throw Error{RAS_E_UNSUPPORTED, "too many work items per team"};
+        for (int it : lists[t]) {
+            team_items.push_back(it);
+            owner_wg[it] = team_first_wg[t];
         }
-        wg_ptr[g + 1] = static_cast<int32_t>(wg_items.size());
+        team_ptr[t + 1] = static_cast<int32_t>(team_items.size());
     }
 
     // device workspace (one block, carved)
@@ -473,8 +586,13 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     const size_t o_conv = carve(nitems * sizeof(int32_t));
     const size_t o_solves = carve(nitems * sizeof(int64_t));
     const size_t o_version = carve(nitems * sizeof(uint32_t));
-    const size_t o_wgptr = carve((G + 1) * sizeof(int32_t));
-    const size_t o_wgitems = carve(wg_items.size() * sizeof(int32_t));
+    const size_t o_tptr = carve((nteams + 1) * sizeof(int32_t));
+    const size_t o_titems = carve(team_items.size() * sizeof(int32_t));
+    const size_t o_wgteam = carve(G * sizeof(int32_t));
+    const size_t o_wgmember = carve(G * sizeof(int32_t));
+    const size_t o_twin = carve(team_win.size() * sizeof(int32_t));
+    const size_t o_tbar = carve(2 * nteams * sizeof(uint32_t));
+    const size_t o_tbuf = carve(static_cast<size_t>(nteams) * 8 * T * sizeof(double));
     const size_t o_bar = carve(sizeof(GridBarrier));
     const size_t o_scr = carve(scratch_elems * ct_size(h0.storage));
     const size_t o_x1 = carve(x1_elems * sizeof(double));
@@ -527,8 +645,12 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     up(o_items, items.data(), items.size() * sizeof(ItemDev));
     up(o_insts, insts.data(), insts.size() * sizeof(InstDev));
     up(o_ist, ist.data(), ist.size() * sizeof(InstState));
-    up(o_wgptr, wg_ptr.data(), wg_ptr.size() * sizeof(int32_t));
-    up(o_wgitems, wg_items.data(), wg_items.size() * sizeof(int32_t));
+    up(o_tptr, team_ptr.data(), team_ptr.size() * sizeof(int32_t));
+    up(o_titems, team_items.data(), team_items.size() * sizeof(int32_t));
+    up(o_wgteam, wg_team.data(), wg_team.size() * sizeof(int32_t));
+    up(o_wgmember, wg_member.data(), wg_member.size() * sizeof(int32_t));
+    up(o_twin, team_win.data(), team_win.size() * sizeof(int32_t));
+    hip_check(hipMemsetAsync(base + o_tbar, 0, 2 * nteams * sizeof(uint32_t), stream), "clear");
     up(o_bar, &bar, sizeof(bar));
     hip_check(hipMemsetAsync(base + o_res2, 0, 2 * nitems * sizeof(double), stream), "clear");
     hip_check(hipMemsetAsync(base + o_conv, 0, nitems * sizeof(int32_t), stream), "clear");
@@ -546,8 +668,14 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     P.conv = reinterpret_cast<int32_t*>(base + o_conv);
     P.solves = reinterpret_cast<int64_t*>(base + o_solves);
     P.version = reinterpret_cast<uint32_t*>(base + o_version);
-    P.wg_ptr = reinterpret_cast<const int32_t*>(base + o_wgptr);
-    P.wg_items = reinterpret_cast<const int32_t*>(base + o_wgitems);
+    P.team_ptr = reinterpret_cast<const int32_t*>(base + o_tptr);
+    P.team_items = reinterpret_cast<const int32_t*>(base + o_titems);
+    P.wg_team = reinterpret_cast<const int32_t*>(base + o_wgteam);
+    P.wg_member = reinterpret_cast<const int32_t*>(base + o_wgmember);
+    P.team_win = reinterpret_cast<const int32_t*>(base + o_twin);
+    P.team_bar = reinterpret_cast<uint32_t*>(base + o_tbar);
+    P.team_buf = reinterpret_cast<double*>(base + o_tbuf);
+    P.team_size = T;
     P.bar = reinterpret_cast<GridBarrier*>(base + o_bar);
     P.n_items = nitems;
     P.n_insts = ninst;
@@ -556,16 +684,21 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     P.max_ticks = o.max_seconds > 0 ? static_cast<int64_t>(o.max_seconds * h0.clock_khz * 1000.0) : 0;
     P.sweep0 = 0;
 
-    hipEvent_t ev0, ev1;
+    hipEvent_t ev0, ev1, ek0, ek1;
     hip_check(hipEventCreate(&ev0), "event");
     hip_check(hipEventCreate(&ev1), "event");
+    hip_check(hipEventCreate(&ek0), "event");
+    hip_check(hipEventCreate(&ek1), "event");
     struct EvGuard {
-        hipEvent_t a, b;
+        hipEvent_t a, b, c, d;
         ~EvGuard() {
             (void)hipEventDestroy(a);
             (void)hipEventDestroy(b);
+            (void)hipEventDestroy(c);
+            (void)hipEventDestroy(d);
         }
-    } evg{ev0, ev1};
+    } evg{ev0, ev1, ek0, ek1};
+    double kernel_s = 0.0;
     hip_check(launch_stamp(P.ist, ninst, stream), "stamp");
     hip_check(hipEventRecord(ev0, stream), "event record");
 
@@ -588,8 +721,16 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     std::vector<int64_t> solves_h(nitems);
     bool time_out = false;
     for (int launch = 0;; ++launch) {
-        hip_check(launch_solver(kern, h0.solver, P, max_w, winm, lds, stream, sync), "persistent kernel launch");
+        hip_check(hipEventRecord(ek0, stream), "event record");
+        hip_check(launch_solver(kern, h0.solver, P, max_w, winm, lds, stream, sync || T > 1),
+                  "persistent kernel launch");
+        hip_check(hipEventRecord(ek1, stream), "event record");
         hip_check(hipStreamSynchronize(stream), "persistent kernel");
+        {
+            float kms = 0.0f;
+            hip_check(hipEventElapsedTime(&kms, ek0, ek1), "elapsed");
+            kernel_s += kms * 1e-3;
+        }
         for (int i = 0; i < ninst; ++i)
             if (!verified[i]) ++launches[i];
         hip_check(hipMemcpy(ist.data(), P.ist, ninst * sizeof(InstState), hipMemcpyDeviceToHost), "copy state");
@@ -667,6 +808,7 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
         inf.launches = launches[i];
         inf.rel_residual = relres[i];
         inf.seconds = ms * 1e-3;
+        inf.kernel_seconds = kernel_s;
         int64_t mn = INT64_MAX, mx = 0, tot = 0;
         std::vector<int64_t> cnt(insts[i].item_count);
         for (int k = 0; k < insts[i].item_count; ++k) {
@@ -758,9 +900,11 @@ ras_status ras_plan_sets(const ras_plan* plan, int32_t* owner, int64_t* omega_pt
 ras_status ras_plan_factor(const ras_plan* plan, int32_t p, double* band, int32_t* w) {
     return guarded([&] {
         if (!plan || !w) throw Error{RAS_E_ARG, "null argument"};
-        if (plan->local.kind != RAS_LOCAL_CHOL_BANDED) throw Error{RAS_E_STATE, "plan has no Cholesky factors"};
         if (p < 0 || p >= plan->P) throw Error{RAS_E_ARG, "subdomain out of range"};
         const auto& s = plan->subs[p];
+        *w = s.w;
+        if (!band) return RAS_OK;
+        if (plan->local.kind != RAS_LOCAL_CHOL_BANDED) throw Error{RAS_E_STATE, "plan has no Cholesky factors"};
         if (s.L.empty() && !s.omega.empty()) throw Error{RAS_E_STATE, "factor released"};
         *w = s.w;
         if (band) std::copy(s.L.begin(), s.L.end(), band);

@@ -10,7 +10,9 @@
 
 namespace ras {
 
-constexpr int kCgThreads = 1024;    // workgroup size of the CG kernels
+constexpr int kCgThreads = 256;     // workgroup size of the CG kernels
+constexpr int kMaxTeam = 16;        // workgroups cooperating on one subdomain (CG)
+constexpr int kTeamSizes[5] = {1, 2, 4, 8, 16};
 constexpr int kBandThreads = 256;   // workgroup size of the banded-solve kernels
 constexpr int kBandRows = 32;       // rows per block of the banded triangular solves
 constexpr int kMaxItemsPerWg = 1024;  // work items one workgroup may own
@@ -42,7 +44,7 @@ struct InstDev {
     const double* b;          // [n]
     double* x0;               // [n] caller's x (initial guess in, result out)
     double* x1;               // [n] second buffer (synchronous mode)
-    void* scratch;            // local vectors in the compute type: [3 sum n_p] (CG) or [sum n_p] (band)
+    void* scratch;            // [sum n_p] local vector in the compute type (CG: exchanged residual, band: solve vector)
     double* hist;             // [hist_cap] relative residual history
     double* hist_t;           // [hist_cap] seconds since start
     int64_t hist_cap;
@@ -80,13 +82,20 @@ struct Params {
     int32_t* conv;            // [n_items] local criterion met (async)
     int64_t* solves;          // [n_items] local solves done
     uint32_t* version;        // [n_items] published updates (async)
-    const int32_t* wg_ptr;    // [n_wg + 1]
-    const int32_t* wg_items;  // item ids per workgroup, in visiting order
+    const int32_t* team_ptr;  // [n_teams + 1]
+    const int32_t* team_items;  // item ids per team, in visiting order
+    const int32_t* wg_team;   // [n_wg] team of each workgroup
+    const int32_t* wg_member; // [n_wg] rank of each workgroup inside its team
+    const int32_t* team_win;  // [n_subs][T][2] LDS window [lo, hi) of local rows of each team member
+    uint32_t* team_bar;       // [n_teams][2] team barrier (count, generation)
+    double* team_buf;         // [n_teams][2][T][4] team reduction / broadcast slots
     GridBarrier* bar;
     int32_t n_items;
     int32_t n_insts;
     int32_t n_wg;
     int32_t cg_iters;
+    int32_t team_size;        // T (1 for the banded solver)
+    int32_t pad_;
     int64_t max_ticks;        // wall-clock ticks allowed (<= 0: unlimited)
     int64_t sweep0;           // sync: first sweep index of this launch
 };

@@ -186,6 +186,90 @@ __device__ void grid_barrier(GridBarrier* bar, uint32_t nwg) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
+// ------------------------------------------------------------------------------ teams
+// A team is T workgroups sharing one subdomain's local solve (CG): member m
+// owns local rows [m n / T, (m+1) n / T).  Team-wide values are reduced per
+// workgroup, exchanged through global slots and summed in member order, so
+// every member obtains bit-identical results.
+struct TeamCtx {
+    int team, member, T;
+    RAS_GLOBAL uint32_t* bar;  // {count, generation}
+    RAS_GLOBAL double* buf;    // [2][T][4]
+    uint32_t phase;            // barriers passed (slot parity)
+};
+
+__device__ __forceinline__ TeamCtx make_team(const Params& P) {
+    TeamCtx tc;
+    tc.team = uni(P.wg_team[blockIdx.x]);
+    tc.member = uni(P.wg_member[blockIdx.x]);
+    tc.T = P.team_size;
+    tc.bar = gptr(P.team_bar) + 2 * tc.team;
+    tc.buf = gptr(P.team_buf) + static_cast<int64_t>(tc.team) * 8 * tc.T;
+    tc.phase = 0;
+    return tc;
+}
+
+__device__ void team_barrier(TeamCtx& tc) {
+    if (tc.T == 1) {
+        __syncthreads();
+        return;
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t g = __hip_atomic_load(tc.bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t arrived = __hip_atomic_fetch_add(tc.bar, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == static_cast<uint32_t>(tc.T) - 1) {
+            __hip_atomic_store(tc.bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(tc.bar + 1, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            while (__hip_atomic_load(tc.bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g)
+                __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    ++tc.phase;
+}
+
+// Sum NV workgroup totals (already block-reduced, uniform) over the team; the
+// values flagged in `ct_mask` are summed in the compute type CT.
+template <class CT, int NV>
+__device__ __forceinline__ void team_sum(TeamCtx& tc, double (&v)[NV], unsigned ct_mask) {
+    if (tc.T == 1) return;
+    RAS_GLOBAL double* slot = tc.buf + (tc.phase & 1) * 4 * tc.T;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NV; ++k) slot[4 * tc.member + k] = v[k];
+    team_barrier(tc);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        if ((ct_mask >> k) & 1) {
+            CT acc = CT(0);
+            for (int m = 0; m < tc.T; ++m) acc += static_cast<CT>(slot[4 * m + k]);
+            v[k] = static_cast<double>(acc);
+        } else {
+            double acc = 0.0;
+            for (int m = 0; m < tc.T; ++m) acc += slot[4 * m + k];
+            v[k] = acc;
+        }
+    }
+}
+
+// Member 0's value, seen identically by every member of the team.
+__device__ __forceinline__ int team_bcast(TeamCtx& tc, int v0, int* lds_flag) {
+    if (tc.T == 1) {
+        if (threadIdx.x == 0) *lds_flag = v0;
+        __syncthreads();
+        const int r = *lds_flag;
+        __syncthreads();
+        return r;
+    }
+    RAS_GLOBAL double* slot = tc.buf + (tc.phase & 1) * 4 * tc.T;
+    if (threadIdx.x == 0 && tc.member == 0) slot[0] = static_cast<double>(v0);
+    team_barrier(tc);
+    return static_cast<int>(slot[0]);
+}
+
 template <class CT>
 __device__ __forceinline__ CT load_as(const void* base, int64_t idx);
 template <>
@@ -229,96 +313,162 @@ __device__ __forceinline__ double row_residual(const SubU& s, RAS_GLOBAL double*
 
 // ------------------------------------------------------------------------------ CG update
 // Local solve by `cg_iters` steps of Hestenes-Stiefel CG from zero on A_p (the
-// local rows and columns of A; external columns point at a zero LDS slot).
-// The search direction p lives in LDS (the local SpMV gathers it); r, A p and
-// the correction live in a per-item scratch block [3][n] of the compute type,
-// accessed row-coalesced.  Only owned rows of the correction are kept (RAS
-// discards the overlap part).
-template <class CT, int KT, bool ASYNC>
+// local rows and columns of A; external columns read a zero LDS slot), by a
+// team of T workgroups.  Each thread holds R rows (tid + j B of its member's
+// range) of r, A p and the correction in registers; the search direction p of
+// the member's LDS window (own rows plus the halo its rows reach) lives in
+// LDS.  After every residual update the member publishes its r through the
+// per-item exchange vector; after the team reduction of r'r every member
+// rebuilds its halo as p = r + beta p exactly as the owner does.
+template <class CT, int KT, int R, bool ASYNC>
 struct CgUpdate {
     static constexpr int B = kCgThreads;
 
-    __device__ __forceinline__ void operator()(const Params& P, const ItemDev& item, RAS_GLOBAL double* xin,
-                                               RAS_GLOBAL double* xout, double& own2, double& loc2, double& b2) {
+    __device__ __forceinline__ void operator()(const Params& P, TeamCtx& tc, const ItemDev& item,
+                                               RAS_GLOBAL double* xin, RAS_GLOBAL double* xout, double& own2,
+                                               double& loc2, double& b2) {
         extern __shared__ __align__(16) unsigned char smem[];
+        __shared__ double red[4 * (B / 64)];
         __shared__ CT redc[B / 64];
-        __shared__ double red3[3 * (B / 64)];
-        CT* pl = reinterpret_cast<CT*>(smem);  // search direction, [n + 1]
+        CT* pl = reinterpret_cast<CT*>(smem);
         const SubU s = load_sub(P.subs + item.sub);
         const InstU in = load_inst(P.insts + item.inst);
         const int tid = threadIdx.x;
         const int n = s.n;
-        RAS_GLOBAL CT* rg = gptr(static_cast<CT*>(in.scratch)) + 3 * s.row_off;
-        RAS_GLOBAL CT* qg = rg + n;
-        RAS_GLOBAL CT* dg = qg + n;
+        const int T = tc.T;
+        const int lo = static_cast<int>(static_cast<int64_t>(tc.member) * n / T);
+        const int hi = static_cast<int>(static_cast<int64_t>(tc.member + 1) * n / T);
+        const int32_t* wp = P.team_win + 2 * (static_cast<int64_t>(item.sub) * T + tc.member);
+        const int wlo = uni(wp[0]);
+        const int whi = uni(wp[1]);
+        const int zs = whi - wlo;  // zero slot: external columns
+        RAS_GLOBAL CT* rg = gptr(static_cast<CT*>(in.scratch)) + s.row_off;
         RAS_GLOBAL CT* val;
         if constexpr (sizeof(CT) == 8)
             val = s.ell_val;
         else
             val = s.ell_valf;
-        own2 = 0.0;
-        loc2 = 0.0;
-        b2 = 0.0;
+        CT r[R], q[R], d[R];
+        uint32_t ownbits = 0;
+        double o2 = 0.0, l2 = 0.0, bb = 0.0;
         CT rr = CT(0);
-        for (int i = tid; i < n; i += B) {
-            double bg;
-            bool ow;
-            const double ri = row_residual<KT, ASYNC>(s, in.b, xin, i, ow, bg);
-            loc2 += ri * ri;
-            b2 += bg * bg;
-            if (ow) own2 += ri * ri;
-            const CT rc = static_cast<CT>(ri);
-            rr += rc * rc;
-            rg[i] = rc;
-            pl[i] = rc;
-            dg[i] = CT(0);
-        }
-        if (tid == 0) pl[n] = CT(0);
-        block_sum3<B>(own2, loc2, b2, red3);
-        CT rho = block_sum<B>(rr, redc);
-        for (int it = 0; it < P.cg_iters; ++it) {
-            CT sp = CT(0);
-            for (int i = tid; i < n; i += B) {
-                CT acc = CT(0);
-                if constexpr (KT > 0) {
-                    int32_t c[KT];
-                    CT a[KT];
 #pragma unroll
-                    for (int k = 0; k < KT; ++k) {
-                        c[k] = (s.ell_lcol + static_cast<uint32_t>(k * s.n_pad))[static_cast<uint32_t>(i)];
-                        a[k] = (val + static_cast<uint32_t>(k * s.n_pad))[static_cast<uint32_t>(i)];
-                    }
-#pragma unroll
-                    for (int k = 0; k < KT; ++k) acc += a[k] * pl[c[k]];
-                } else {
-                    for (int k = 0; k < s.K; ++k) {
-                        const uint32_t idx = static_cast<uint32_t>(k * s.n_pad + i);
-                        acc += val[idx] * pl[s.ell_lcol[idx]];
-                    }
+        for (int j = 0; j < R; ++j) {
+            const int i = lo + tid + j * B;
+            r[j] = CT(0);
+            q[j] = CT(0);
+            d[j] = CT(0);
+            if (i < hi) {
+                double bg;
+                bool ow;
+                const double ri = row_residual<KT, ASYNC>(s, in.b, xin, i, ow, bg);
+                l2 += ri * ri;
+                bb += bg * bg;
+                if (ow) {
+                    o2 += ri * ri;
+                    ownbits |= 1u << j;
                 }
-                qg[i] = acc;
-                sp += pl[i] * acc;
+                r[j] = static_cast<CT>(ri);
+                rr += r[j] * r[j];
+                pl[i - wlo] = r[j];
+                if (T > 1) rg[i] = r[j];
             }
-            const CT sigma = block_sum<B>(sp, redc);
-            if (rho == CT(0) || !(sigma > CT(0))) break;  // breakdown guard (uniform)
+        }
+        if (tid == 0) pl[zs] = CT(0);
+        double v4[4];
+        {
+            double a = o2, b = l2, c = bb;
+            block_sum3<B>(a, b, c, red);
+            v4[0] = a;
+            v4[1] = b;
+            v4[2] = c;
+            v4[3] = static_cast<double>(block_sum<B>(rr, redc));
+        }
+        team_sum<CT, 4>(tc, v4, 0x8u);
+        own2 = v4[0];
+        loc2 = v4[1];
+        b2 = v4[2];
+        CT rho = static_cast<CT>(v4[3]);
+        if (T > 1) {
+            for (int i = wlo + tid; i < lo; i += B) pl[i - wlo] = rg[i];
+            for (int i = hi + tid; i < whi; i += B) pl[i - wlo] = rg[i];
+            __syncthreads();
+        }
+        for (int it = 0; it < P.cg_iters; ++it) {
+            // the matrix is streamed every iteration: hide the loop invariance of its
+            // pointers so the compiler does not park all R*K entries in registers
+            RAS_GLOBAL CT* vit = val;
+            RAS_GLOBAL int32_t* cit = s.ell_lcol;
+            asm volatile("" : "+s"(vit), "+s"(cit));
+            CT sp = CT(0);
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int i = lo + tid + j * B;
+                if (i < hi) {
+                    CT acc = CT(0);
+                    if constexpr (KT > 0) {
+                        int32_t c[KT];
+                        CT a[KT];
+#pragma unroll
+                        for (int k = 0; k < KT; ++k) {
+                            c[k] = (cit + static_cast<uint32_t>(k * s.n_pad))[static_cast<uint32_t>(i)];
+                            a[k] = (vit + static_cast<uint32_t>(k * s.n_pad))[static_cast<uint32_t>(i)];
+                        }
+#pragma unroll
+                        for (int k = 0; k < KT; ++k) acc += a[k] * pl[c[k] == n ? zs : c[k] - wlo];
+                    } else {
+                        for (int k = 0; k < s.K; ++k) {
+                            const uint32_t idx = static_cast<uint32_t>(k * s.n_pad + i);
+                            const int c = cit[idx];
+                            acc += vit[idx] * pl[c == n ? zs : c - wlo];
+                        }
+                    }
+                    q[j] = acc;
+                    sp += pl[i - wlo] * acc;
+                }
+            }
+            double vs[1] = {static_cast<double>(block_sum<B>(sp, redc))};
+            team_sum<CT, 1>(tc, vs, 0x1u);
+            const CT sigma = static_cast<CT>(vs[0]);
+            if (rho == CT(0) || !(sigma > CT(0))) break;  // breakdown guard (team-uniform)
             const CT alpha = rho / sigma;
+            const bool last = it + 1 == P.cg_iters;
             CT rn = CT(0);
-            for (int i = tid; i < n; i += B) {
-                dg[i] += alpha * pl[i];
-                const CT ri = rg[i] - alpha * qg[i];
-                rg[i] = ri;
-                rn += ri * ri;
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int i = lo + tid + j * B;
+                if (i < hi) {
+                    d[j] += alpha * pl[i - wlo];
+                    r[j] -= alpha * q[j];
+                    rn += r[j] * r[j];
+                    if (T > 1 && !last) rg[i] = r[j];
+                }
             }
-            const CT rho_new = block_sum<B>(rn, redc);
+            if (last) break;  // p is not needed after the last step
+            double vr[1] = {static_cast<double>(block_sum<B>(rn, redc))};
+            team_sum<CT, 1>(tc, vr, 0x1u);
+            const CT rho_new = static_cast<CT>(vr[0]);
             const CT beta = rho_new / rho;
-            for (int i = tid; i < n; i += B) pl[i] = rg[i] + beta * pl[i];
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int i = lo + tid + j * B;
+                if (i < hi) pl[i - wlo] = r[j] + beta * pl[i - wlo];
+            }
+            if (T > 1) {
+                for (int i = wlo + tid; i < lo; i += B) pl[i - wlo] = rg[i] + beta * pl[i - wlo];
+                for (int i = hi + tid; i < whi; i += B) pl[i - wlo] = rg[i] + beta * pl[i - wlo];
+            }
             rho = rho_new;
             __syncthreads();
         }
         // restricted prolongation: owned points only
-        for (int i = tid; i < n; i += B) {
-            const int32_t e = s.omega[i];
-            if (e >= 0) stx<ASYNC>(xout + e, ldx<ASYNC>(xin + e) + static_cast<double>(dg[i]));
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int i = lo + tid + j * B;
+            if (i < hi && ((ownbits >> j) & 1u)) {
+                const int32_t g = s.omega[i];
+                stx<ASYNC>(xout + g, ldx<ASYNC>(xin + g) + static_cast<double>(d[j]));
+            }
         }
     }
 };
@@ -426,8 +576,10 @@ struct BandUpdate {
     int max_w;
     int winm;
 
-    __device__ __forceinline__ void operator()(const Params& P, const ItemDev& item, RAS_GLOBAL double* xin,
-                                               RAS_GLOBAL double* xout, double& own2, double& loc2, double& b2) {
+    __device__ __forceinline__ void operator()(const Params& P, TeamCtx& tc, const ItemDev& item,
+                                               RAS_GLOBAL double* xin, RAS_GLOBAL double* xout, double& own2,
+                                               double& loc2, double& b2) {
+        (void)tc;
         extern __shared__ __align__(16) unsigned char smem[];
         __shared__ double red3[3 * (B / 64)];
         __shared__ CT gsum[kBandRows];
@@ -470,32 +622,37 @@ __device__ double instance_owned_sum(const Params& P, const InstDev& in, int par
     return block_sum<B>(s, red);
 }
 
-// Synchronous sweeps: phase 1 updates every active item from x^k into the
-// other buffer and records its owned residual^2; after the grid barrier every
-// workgroup assembles ||b - A x^k||^2 of its systems (same order everywhere,
-// hence the same decision everywhere) and stops a system at the first k with
-// relative residual < tol, returning x^k.
+__device__ __forceinline__ ItemDev load_item(const Params& P, int it) {
+    ItemDev item = P.items[it];
+    item.inst = uni(item.inst);
+    item.sub = uni(item.sub);
+    return item;
+}
+
+// Synchronous sweeps: phase 1 updates every active item of the team from x^k
+// into the other buffer and records its owned residual^2; after the grid
+// barrier every workgroup assembles ||b - A x^k||^2 of its systems (same order
+// everywhere, hence the same decision everywhere) and stops a system at the
+// first k with relative residual < tol, returning x^k.
 template <int B, class U>
-__device__ __forceinline__ void run_sync(const Params& P, U& upd, double* red, int8_t* done) {
+__device__ __forceinline__ void run_sync(const Params& P, U& upd, TeamCtx& tc, double* red, int8_t* done) {
     const int tid = threadIdx.x;
     const int wg = blockIdx.x;
-    const int ib = P.wg_ptr[wg], ie = P.wg_ptr[wg + 1];
+    const int ib = P.team_ptr[tc.team], ie = P.team_ptr[tc.team + 1];
     for (int j = tid; j < ie - ib; j += B) done[j] = 0;
     __syncthreads();
     for (int64_t s = P.sweep0;; ++s) {
         const int par = static_cast<int>(s & 1);
         for (int j = ib; j < ie; ++j) {
             if (done[j - ib]) continue;
-            const int it = __builtin_amdgcn_readfirstlane(P.wg_items[j]);
-            ItemDev item = P.items[it];
-            item.inst = __builtin_amdgcn_readfirstlane(item.inst);
-            item.sub = __builtin_amdgcn_readfirstlane(item.sub);
+            const int it = uni(P.team_items[j]);
+            const ItemDev item = load_item(P, it);
             const InstU iu = load_inst(P.insts + item.inst);
             RAS_GLOBAL double* xc = par ? iu.x1 : iu.x0;
             RAS_GLOBAL double* xn = par ? iu.x0 : iu.x1;
             double own2, loc2, b2;
-            upd(P, item, xc, xn, own2, loc2, b2);
-            if (tid == 0) {
+            upd(P, tc, item, xc, xn, own2, loc2, b2);
+            if (tid == 0 && tc.member == 0) {
                 P.res2_own[par * P.n_items + it] = own2;
                 P.solves[it] += 1;
             }
@@ -510,10 +667,8 @@ __device__ __forceinline__ void run_sync(const Params& P, U& upd, double* red, i
         bool last_stop = false;
         for (int j = ib; j < ie; ++j) {
             if (done[j - ib]) continue;
-            const int it = __builtin_amdgcn_readfirstlane(P.wg_items[j]);
-            ItemDev item = P.items[it];
-            item.inst = __builtin_amdgcn_readfirstlane(item.inst);
-            item.sub = __builtin_amdgcn_readfirstlane(item.sub);
+            const int it = uni(P.team_items[j]);
+            const ItemDev item = load_item(P, it);
             if (item.inst != last_inst) {
                 const InstDev& in = P.insts[item.inst];
                 const double sum = instance_owned_sum<B>(P, in, par, red);
@@ -543,13 +698,13 @@ __device__ __forceinline__ void run_sync(const Params& P, U& upd, double* red, i
     }
 }
 
-// Asynchronous iteration: no barrier.  Workgroup-uniform control data is
-// read by thread 0 and broadcast through LDS.
+// Asynchronous iteration: no grid barrier.  Decisions that steer team-wide
+// control flow are taken by member 0 and broadcast to the team.
 template <int B, class U>
-__device__ __forceinline__ void run_async(const Params& P, U& upd, double* red, int8_t* done) {
+__device__ __forceinline__ void run_async(const Params& P, U& upd, TeamCtx& tc, double* red, int8_t* done) {
     const int tid = threadIdx.x;
     const int wg = blockIdx.x;
-    const int ib = P.wg_ptr[wg], ie = P.wg_ptr[wg + 1];
+    const int ib = P.team_ptr[tc.team], ie = P.team_ptr[tc.team + 1];
     __shared__ int flag;
     for (int j = tid; j < ie - ib; j += B) done[j] = 0;
     __syncthreads();
@@ -557,27 +712,24 @@ __device__ __forceinline__ void run_async(const Params& P, U& upd, double* red, 
         bool any = false;
         for (int j = ib; j < ie; ++j) {
             if (done[j - ib]) continue;
-            const int it = __builtin_amdgcn_readfirstlane(P.wg_items[j]);
-            ItemDev item = P.items[it];
-            item.inst = __builtin_amdgcn_readfirstlane(item.inst);
-            item.sub = __builtin_amdgcn_readfirstlane(item.sub);
+            const int it = uni(P.team_items[j]);
+            const ItemDev item = load_item(P, it);
             const InstDev& in = P.insts[item.inst];
             InstState* st = P.ist + item.inst;
-            if (tid == 0) flag = (ld_rlx(&st->stop) != 0) || (P.solves[it] >= in.max_sweeps);
-            __syncthreads();
-            const bool skip = flag != 0;
-            __syncthreads();
+            int v0 = 0;
+            if (tc.member == 0 && tid == 0) v0 = (ld_rlx(&st->stop) != 0) || (P.solves[it] >= in.max_sweeps);
+            const bool skip = team_bcast(tc, v0, &flag) != 0;
             if (skip) {
                 if (tid == 0) done[j - ib] = 1;
+                __syncthreads();
                 continue;
             }
             any = true;
             double own2, loc2, b2;
             const InstU iu = load_inst(P.insts + item.inst);
-            upd(P, item, iu.x0, iu.x0, own2, loc2, b2);
-            __threadfence();
-            __syncthreads();
-            if (tid == 0) {
+            upd(P, tc, item, iu.x0, iu.x0, own2, loc2, b2);
+            team_barrier(tc);  // every member's part of x is written (and fenced) before the publish
+            if (tid == 0 && tc.member == 0) {
                 st_rlx(P.res2_own + it, own2);
                 st_rlx(P.conv + it, static_cast<int32_t>(loc2 < in.tol2 * b2));
                 P.solves[it] += 1;
@@ -616,26 +768,28 @@ __device__ __forceinline__ void run_async(const Params& P, U& upd, double* red, 
 }
 
 // ------------------------------------------------------------------------------ kernels
-template <class CT, int KT, bool ASYNC>
+template <class CT, int KT, int R, bool ASYNC>
 __global__ void __launch_bounds__(kCgThreads) cg_kernel(Params P) {
     __shared__ double red[kCgThreads / 64];
     __shared__ int8_t done[kMaxItemsPerWg];
-    CgUpdate<CT, KT, ASYNC> upd;
+    TeamCtx tc = make_team(P);
+    CgUpdate<CT, KT, R, ASYNC> upd;
     if constexpr (ASYNC)
-        run_async<kCgThreads>(P, upd, red, done);
+        run_async<kCgThreads>(P, upd, tc, red, done);
     else
-        run_sync<kCgThreads>(P, upd, red, done);
+        run_sync<kCgThreads>(P, upd, tc, red, done);
 }
 
 template <class ST, bool ASYNC>
 __global__ void __launch_bounds__(kBandThreads) band_kernel(Params P, int max_w, int winm) {
     __shared__ double red[kBandThreads / 64];
     __shared__ int8_t done[kMaxItemsPerWg];
+    TeamCtx tc = make_team(P);
     BandUpdate<ST, ASYNC> upd{max_w, winm};
     if constexpr (ASYNC)
-        run_async<kBandThreads>(P, upd, red, done);
+        run_async<kBandThreads>(P, upd, tc, red, done);
     else
-        run_sync<kBandThreads>(P, upd, red, done);
+        run_sync<kBandThreads>(P, upd, tc, red, done);
 }
 
 // ||b||^2 per instance and the exact residual ||b - A x||^2 (verification,
@@ -705,11 +859,27 @@ hipError_t launch(K kern, dim3 grid, dim3 block, size_t lds, hipStream_t st, boo
     return hipLaunchKernel(reinterpret_cast<const void*>(kern), grid, block, args, lds, st);
 }
 
+template <class CT, int KT, bool ASYNC>
+const void* cg_kernel_r(int r) {
+    switch (r) {
+        case 1: return reinterpret_cast<const void*>(cg_kernel<CT, KT, 1, ASYNC>);
+        case 2: return reinterpret_cast<const void*>(cg_kernel<CT, KT, 2, ASYNC>);
+        case 4: return reinterpret_cast<const void*>(cg_kernel<CT, KT, 4, ASYNC>);
+        case 6: return reinterpret_cast<const void*>(cg_kernel<CT, KT, 6, ASYNC>);
+        case 8: return reinterpret_cast<const void*>(cg_kernel<CT, KT, 8, ASYNC>);
+        case 10: return reinterpret_cast<const void*>(cg_kernel<CT, KT, 10, ASYNC>);
+        case 12: return reinterpret_cast<const void*>(cg_kernel<CT, KT, 12, ASYNC>);
+        case 16: return reinterpret_cast<const void*>(cg_kernel<CT, KT, 16, ASYNC>);
+        case 20: return reinterpret_cast<const void*>(cg_kernel<CT, KT, 20, ASYNC>);
+        default: return nullptr;
+    }
+}
+
 template <class CT, bool ASYNC>
-const void* cg_kernel_for(int kt) {
-    if (kt == 5) return reinterpret_cast<const void*>(cg_kernel<CT, 5, ASYNC>);
-    if (kt == 7) return reinterpret_cast<const void*>(cg_kernel<CT, 7, ASYNC>);
-    return reinterpret_cast<const void*>(cg_kernel<CT, 0, ASYNC>);
+const void* cg_kernel_for(int kt, int r) {
+    if (kt == 5) return cg_kernel_r<CT, 5, ASYNC>(r);
+    if (kt == 7) return cg_kernel_r<CT, 7, ASYNC>(r);
+    return cg_kernel_r<CT, 0, ASYNC>(r);
 }
 
 template <class ST>
@@ -719,10 +889,18 @@ const void* band_kernel_for(bool async) {
 }
 }  // namespace
 
-const void* select_kernel(int solver, int storage, bool async, int ell_width) {
+int cg_rows_class(int rows_per_member) {
+    const int r = (rows_per_member + kCgThreads - 1) / kCgThreads;
+    for (int c : {1, 2, 4, 6, 8, 10, 12, 16, 20})
+        if (r <= c) return c;
+    return -1;
+}
+
+const void* select_kernel(int solver, int storage, bool async, int ell_width, int rclass) {
     if (solver == 1) {  // CG
-        if (storage == 0) return async ? cg_kernel_for<double, true>(ell_width) : cg_kernel_for<double, false>(ell_width);
-        return async ? cg_kernel_for<float, true>(ell_width) : cg_kernel_for<float, false>(ell_width);
+        if (storage == 0)
+            return async ? cg_kernel_for<double, true>(ell_width, rclass) : cg_kernel_for<double, false>(ell_width, rclass);
+        return async ? cg_kernel_for<float, true>(ell_width, rclass) : cg_kernel_for<float, false>(ell_width, rclass);
     }
     if (storage == 0) return band_kernel_for<double>(async);
     if (storage == 1) return band_kernel_for<float>(async);

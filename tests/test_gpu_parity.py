@@ -1,8 +1,10 @@
 """GPU parity: the HIP path through the C ABI against the oracle (needs an MI355X).
 
 Tolerances: float64 local solves -- the same iteration up to rounding order,
-so histories agree to 1e-9 relative per sweep while the residual is above
-1e-12, iterates to 1e-9 relative; float32 local arithmetic -- iterates after a
+so histories agree to 1e-9 relative per sweep plus an absolute 1e-13 (the
+relative residual of an iterate near convergence is itself computed with
+about 1e-16 ||A|| ||x|| / ||b|| of cancellation error), iterates to 1e-9
+relative; float32 local arithmetic -- iterates after a
 fixed number of sweeps to 2e-5 relative (float32 unit roundoff 6e-8 times the
 growth of CG / triangular-solve rounding over a few sweeps); converged
 solutions to the BASELINE criteria: relative residual below tol (exact,
@@ -82,8 +84,7 @@ def test_config1_sync_exact_history_and_solution():
     _, hg = h.residual_history()
     assert info[0]["converged"] and info[0]["sweeps"] == ko
     assert len(hg) == len(ho)
-    big = ho > 1e-12
-    assert np.max(np.abs(hg[big] - ho[big]) / ho[big]) <= 1e-9
+    assert np.all(np.abs(hg - ho) <= 1e-9 * ho + 1e-13)
     assert _rel(x, xo) <= 1e-9
     assert info[0]["rel_residual"] < 1e-10
     xd = schwarz.direct_solve(A, b)
@@ -110,7 +111,42 @@ def test_sync_cg_fp64_matches_oracle(N, part, gamma, k):
         assert info[0]["sweeps"] == sweeps
         assert _rel(x.cpu().numpy(), xo) <= 1e-9
         _, hg = h.residual_history()
-        assert np.max(np.abs(hg - ho) / ho) <= 1e-9
+        assert np.all(np.abs(hg - ho) <= 1e-9 * ho + 1e-13)
+
+
+@pytest.mark.parametrize("team", [1, 2, 4, 8, 16])
+def test_sync_cg_team_sizes_match_oracle(team):
+    """Several workgroups per subdomain (halo exchange + team reductions) give the
+    same iteration as the oracle, for every team size."""
+    ras = _ras()
+    _say(f"case: sync cg fp64 team={team}")
+    A = R.laplace2d(70, 61)
+    b = R.uniform_rhs(A.n, 21)
+    part = ("regular_2d", (2, 2))
+    orc = _oracle(A, *part, 3, "cg", "fp64", 7)
+    h = ras.setup(A, _spec(ras, A, *part), 3, ras.local("cg", "fp64", 7))
+    for sweeps in (1, 4):
+        xo, ho, _ = orc.sync(b, 0.0, sweeps)
+        x, info = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=sweeps, team=team)
+        assert _rel(x.cpu().numpy(), xo) <= 1e-9
+        _, hg = h.residual_history()
+        assert np.all(np.abs(hg - ho) <= 1e-9 * ho + 1e-13)
+    xa, info = h.solve(_cuda(b), tol=1e-8, mode="async", max_sweeps=100000, max_seconds=60, team=team)
+    assert info[0]["converged"] and schwarz.relative_residual(A, xa.cpu().numpy(), b) < 1e-8
+
+
+@pytest.mark.parametrize("team", [1, 4])
+def test_ordered_cg_team_is_multiplicative_schwarz(team):
+    ras = _ras()
+    _say(f"case: ordered cg team={team}")
+    A = R.laplace2d(40)
+    b = R.uniform_rhs(A.n, 15)
+    part = ("regular_2d", (2, 3))
+    orc = _oracle(A, *part, 2, "cg", "fp64", 5)
+    h = ras.setup(A, _spec(ras, A, *part), 2, ras.local("cg", "fp64", 5))
+    xo, _ = orc.ordered(b, 3)
+    x, _ = h.solve(_cuda(b), tol=0.0, mode="ordered", max_sweeps=3, team=team)
+    assert _rel(x.cpu().numpy(), xo) <= 1e-9
 
 
 def test_sync_cg_fp32_3d_rcb_matches_oracle():
@@ -256,4 +292,4 @@ def test_config2_full_size_two_sweeps():
     x, info = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=2)
     assert _rel(x.cpu().numpy(), xo) <= 1e-9
     _, hg = h.residual_history()
-    assert np.max(np.abs(hg - ho) / ho) <= 1e-9
+    assert np.all(np.abs(hg - ho) <= 1e-9 * ho + 1e-13)
