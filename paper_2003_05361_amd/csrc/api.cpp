@@ -19,7 +19,7 @@ namespace ras {
 // kernels.hip
 const void* select_kernel(int solver, int storage, bool async, int ell_width, int rclass);
 int cg_rows_class(int rows_per_member);
-hipError_t launch_solver(const void* kern, int solver, const Params& P, int max_w, int winm, size_t lds,
+hipError_t launch_solver(const void* kern, int solver, const Params& P, const int* band_args, size_t lds,
                          hipStream_t st, bool coop);
 hipError_t occupancy(const void* kern, int solver, size_t lds, int* per_cu);
 hipError_t launch_residual(int64_t n, const int64_t* rp, const int32_t* ci, const double* va, const double* b,
@@ -184,7 +184,8 @@ void upload(ras_handle& h, const Plan& plan) {
         const int64_t n = static_cast<int64_t>(s.omega.size());
         row_off[p + 1] = row_off[p] + n;
         ell_off[p + 1] = ell_off[p] + n_pad_of(n) * s.ell_width;
-        band_off[p + 1] = band_off[p] + (chol ? n * (s.w + 1) : 0);
+        // 64-element aligned starts (16-byte aligned rows blocks for the direct LDS loads)
+        band_off[p + 1] = band_off[p] + (chol ? (n * (s.w + 1) + 63) / 64 * 64 : 0);
         h.max_n = std::max<int>(h.max_n, static_cast<int>(n));
         h.max_w = std::max(h.max_w, s.w);
         h.max_K = std::max(h.max_K, s.ell_width);
@@ -201,8 +202,9 @@ void upload(ras_handle& h, const Plan& plan) {
     h.ell_gcol.alloc(ell_off[P] * sizeof(int32_t));
     h.ell_lcol.alloc(ell_off[P] * sizeof(int32_t));
     if (chol) {
-        h.band_f.alloc(band_off[P] * sts);
-        h.band_b.alloc(band_off[P] * sts);
+        // 1 KB tail: block loads move whole 1 KB pieces and may read past a factor's end
+        h.band_f.alloc(band_off[P] * sts + 1024);
+        h.band_b.alloc(band_off[P] * sts + 1024);
         h.invd.alloc(row_off[P] * cts);
         if (st == RAS_STORAGE_FP16_ROWSCALED) h.scale.alloc(row_off[P] * sizeof(float));
     }
@@ -422,6 +424,7 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     // kernel configuration: team size T (CG), rows-per-thread class, LDS bytes
     struct Cfg {
         int tidx = -1, T = 1, rclass = 0, winm = 0, per_cu = 0;
+        int band_args[5] = {0, 0, 0, 0, 0};
         size_t lds = 0;
         const void* kern = nullptr;
     };
@@ -438,8 +441,38 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
             c.kern = select_kernel(h0.solver, h0.storage, !sync, K, c.rclass);
         } else {
             if (tidx != 0) return c;
-            c.lds = lds_bytes(h0.solver, h0.storage, max_n, max_w, &c.winm);
-            c.kern = select_kernel(h0.solver, h0.storage, !sync, K, 0);
+            // pipelined banded solve: three LDS stages of BR rows (+ FP16 scale windows)
+            // and the solution window; BR = 64 if it fits, else 32, else the
+            // unpipelined pass with one stage
+            const size_t sts = h0.storage == RAS_STORAGE_FP64 ? 8 : h0.storage == RAS_STORAGE_FP32 ? 4 : 2;
+            const size_t cts = ct_size(h0.storage);
+            c.rclass = 0;
+            for (int br : {64, 32}) {
+                if (br == 64 && h0.storage != RAS_STORAGE_FP32) continue;
+                const size_t stage = (static_cast<size_t>(br) * (max_w + 1) * sts + 1023) / 1024 * 1024;
+                const size_t scw = h0.storage == RAS_STORAGE_FP16_ROWSCALED ? (br + max_w + 63) / 64 * 64 : 0;
+                const int win = next_pow2(max_w + br + 1);
+                const size_t bytes = 3 * stage + 3 * scw * sizeof(float) + static_cast<size_t>(win) * cts;
+                if (bytes <= kLdsLimit) {
+                    c.rclass = br;
+                    c.lds = bytes;
+                    c.winm = win - 1;
+                    c.band_args[2] = 1;
+                    c.band_args[3] = static_cast<int>(stage);
+                    c.band_args[4] = static_cast<int>(scw);
+                    break;
+                }
+            }
+            if (c.rclass == 0) {
+                c.rclass = 32;
+                c.lds = lds_bytes(h0.solver, h0.storage, max_n, max_w, &c.winm);
+                c.band_args[2] = 0;
+                c.band_args[3] = 0;
+                c.band_args[4] = 0;
+            }
+            c.band_args[0] = max_w;
+            c.band_args[1] = c.winm;
+            c.kern = select_kernel(h0.solver, h0.storage, !sync, K, c.rclass);
         }
         if (!c.kern || c.lds > kLdsLimit) {
             c.kern = nullptr;
@@ -484,7 +517,6 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
                                        "use more subdomains"};
     const void* kern = cfg.kern;
     const size_t lds = cfg.lds;
-    const int winm = cfg.winm;
     const int T = cfg.T;
 
     // subdomain table: handle order; per-instance items
@@ -722,7 +754,7 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     bool time_out = false;
     for (int launch = 0;; ++launch) {
         hip_check(hipEventRecord(ek0, stream), "event record");
-        hip_check(launch_solver(kern, h0.solver, P, max_w, winm, lds, stream, sync || T > 1),
+        hip_check(launch_solver(kern, h0.solver, P, cfg.band_args, lds, stream, sync || T > 1),
                   "persistent kernel launch");
         hip_check(hipEventRecord(ek1, stream), "event record");
         hip_check(hipStreamSynchronize(stream), "persistent kernel");

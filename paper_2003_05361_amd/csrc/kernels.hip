@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "device.hpp"
 
@@ -569,12 +570,137 @@ __device__ void band_pass(RAS_GLOBAL ST* Lb, RAS_GLOBAL float* scale, bool rev,
     }
 }
 
-template <class ST, bool ASYNC>
+// Pipelined variant of band_pass.  Waves 1..3 are loaders: loader k owns LDS
+// stage k-1 and streams the blocks b = k-1 (mod 3) of the factor into it with
+// direct global-to-LDS loads (global_load_lds_dwordx4, 1 KB per wave
+// instruction, no registers), then hands the stage over through an LDS flag.
+// Wave 0 consumes the blocks in order: per row (one lane per row) the GEMV
+// against the LDS solution window, then the BR x BR diagonal triangle with
+// register-held entries and lane broadcasts.  Factor streaming thus overlaps
+// the sequential chain.  FP16 entries are dequantised on use with the row
+// scale of L (forward: the lane's row; backward: the L row of each entry, from
+// a per-stage scale window loaded with the block).
+template <class ST>
+struct Deq;
+template <>
+struct Deq<double> {
+    __device__ __forceinline__ static double get(const unsigned char* st, int idx) {
+        return reinterpret_cast<const double*>(st)[idx];
+    }
+};
+template <>
+struct Deq<float> {
+    __device__ __forceinline__ static float get(const unsigned char* st, int idx) {
+        return reinterpret_cast<const float*>(st)[idx];
+    }
+};
+template <>
+struct Deq<_Float16> {
+    __device__ __forceinline__ static float get(const unsigned char* st, int idx) {
+        return static_cast<float>(reinterpret_cast<const _Float16*>(st)[idx]);
+    }
+};
+
+template <class ST, int BR>
+__device__ void band_pass_dma(RAS_GLOBAL ST* Lb, RAS_GLOBAL float* scale, bool rev,
+                              RAS_GLOBAL typename StorageTraits<ST>::CT* invd, int n, int w,
+                              RAS_GLOBAL typename StorageTraits<ST>::CT* v, unsigned char* stages, int stage_bytes,
+                              float* scw, int scw_stride, typename StorageTraits<ST>::CT* win, int winm, int* flags) {
+    using CT = typename StorageTraits<ST>::CT;
+    constexpr bool kHalf = StorageTraits<ST>::kHalf;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int ld = w + 1;
+    const int nblk = (n + BR - 1) / BR;
+    if (tid < 3) flags[tid] = 0;
+    __syncthreads();
+    if (wave > 0) {
+        const int s = wave - 1;
+        unsigned char* dst = stages + s * stage_bytes;
+        for (int b = s; b < nblk; b += 3) {
+            while (__hip_atomic_load(flags + s, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != 0)
+                __builtin_amdgcn_s_sleep(1);
+            const int t0 = b * BR;
+            const int rows = min(BR, n - t0);
+            const int bytes = rows * ld * static_cast<int>(sizeof(ST));
+            const RAS_GLOBAL unsigned char* src =
+                reinterpret_cast<const RAS_GLOBAL unsigned char*>(Lb + static_cast<int64_t>(t0) * ld);
+            for (int q = 0; q * 1024 < bytes; ++q)
+                __builtin_amdgcn_global_load_lds(src + q * 1024 + lane * 16,
+                                                 (__attribute__((address_space(3))) void*)(dst + q * 1024), 16, 0, 0);
+            if constexpr (kHalf) {
+                if (rev) {  // scales of L rows n - t0 - BR + k, k in [0, BR + w)
+                    const int rlo = n - t0 - BR;
+                    float* sw = scw + s * scw_stride;
+                    for (int q = 0; q * 64 < BR + w; ++q) {
+                        const int r = min(max(rlo + q * 64 + lane, 0), n - 1);
+                        __builtin_amdgcn_global_load_lds(scale + r, (__attribute__((address_space(3))) void*)(sw + q * 64),
+                                                         4, 0, 0);
+                    }
+                }
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __hip_atomic_store(flags + s, b + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    } else {
+        for (int b = 0; b < nblk; ++b) {
+            const int s = b % 3;
+            while (__hip_atomic_load(flags + s, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != b + 1)
+                __builtin_amdgcn_s_sleep(1);
+            const unsigned char* L = stages + s * stage_bytes;
+            const float* sw = scw + s * scw_stride;
+            const int t0 = b * BR;
+            const int rows = min(BR, n - t0);
+            const int l = lane;
+            const int t = t0 + l;
+            const bool act = l < BR && l < rows;
+            CT rs = CT(1);
+            if constexpr (kHalf)
+                if (!rev && act) rs = scale[t];
+            auto entry = [&](int o) -> CT {
+                CT e = static_cast<CT>(Deq<ST>::get(L, l * ld + o));
+                if constexpr (kHalf) e *= rev ? static_cast<CT>(sw[BR - 1 - l + w - o]) : rs;
+                return e;
+            };
+            CT acc = CT(0);
+            if (act) {
+                const int olo = max(0, w - t);
+                const int ohi = w - l;
+                for (int o = olo; o < ohi; ++o) acc += entry(o) * win[(t - w + o) & winm];
+            }
+            const int vi = rev ? n - 1 - t : t;
+            CT val = act ? static_cast<CT>(v[vi] - acc) : CT(0);
+            const CT dinv = act ? invd[vi] : CT(0);
+            CT Ld[BR];
+#pragma unroll
+            for (int m = 0; m < BR; ++m) Ld[m] = (act && m < l && m >= l - w) ? entry(w - l + m) : CT(0);
+            CT y = CT(0);
+#pragma unroll
+            for (int m = 0; m < BR; ++m) {
+                const CT ym = __shfl(val * dinv, m, 64);
+                if (l == m) y = ym;
+                val -= Ld[m] * ym;
+            }
+            if (act) {
+                v[vi] = y;
+                win[t & winm] = y;
+            }
+            __hip_atomic_store(flags + s, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+    __syncthreads();
+}
+
+template <class ST, int BR, bool ASYNC>
 struct BandUpdate {
     using CT = typename StorageTraits<ST>::CT;
     static constexpr int B = kBandThreads;
     int max_w;
     int winm;
+    int pipelined;    // 1: band_pass_dma (three LDS stages of BR rows), 0: band_pass
+    int stage_bytes;  // bytes per LDS stage (pipelined)
+    int scw_stride;   // floats per scale-window stage (pipelined FP16)
 
     __device__ __forceinline__ void operator()(const Params& P, TeamCtx& tc, const ItemDev& item,
                                                RAS_GLOBAL double* xin, RAS_GLOBAL double* xout, double& own2,
@@ -583,8 +709,7 @@ struct BandUpdate {
         extern __shared__ __align__(16) unsigned char smem[];
         __shared__ double red3[3 * (B / 64)];
         __shared__ CT gsum[kBandRows];
-        CT* stage = reinterpret_cast<CT*>(smem);  // [kBandRows][max_w + 1]
-        CT* win = stage + kBandRows * (max_w + 1);  // [winm + 1]
+        __shared__ int flags[4];
         const SubU s = load_sub(P.subs + item.sub);
         const InstU in = load_inst(P.insts + item.inst);
         const int tid = threadIdx.x;
@@ -603,10 +728,23 @@ struct BandUpdate {
             v[i] = static_cast<CT>(ri);
         }
         block_sum3<B>(own2, loc2, b2, red3);
-        band_pass<ST>(gptr(static_cast<const ST*>(s.band_f)), s.scale, false, gptr(static_cast<const CT*>(s.invd)), n,
-                      s.w, v, stage, win, winm, gsum);
-        band_pass<ST>(gptr(static_cast<const ST*>(s.band_b)), s.scale, true, gptr(static_cast<const CT*>(s.invd)), n,
-                      s.w, v, stage, win, winm, gsum);
+        RAS_GLOBAL ST* Lf = gptr(static_cast<const ST*>(s.band_f));
+        RAS_GLOBAL ST* Lr = gptr(static_cast<const ST*>(s.band_b));
+        RAS_GLOBAL CT* iv = gptr(static_cast<const CT*>(s.invd));
+        if (pipelined) {
+            unsigned char* stages = smem;
+            float* scw = reinterpret_cast<float*>(smem + 3 * stage_bytes);
+            CT* win = reinterpret_cast<CT*>(smem + 3 * stage_bytes + 3 * scw_stride * sizeof(float));
+            band_pass_dma<ST, BR>(Lf, s.scale, false, iv, n, s.w, v, stages, stage_bytes, scw, scw_stride, win, winm,
+                                  flags);
+            band_pass_dma<ST, BR>(Lr, s.scale, true, iv, n, s.w, v, stages, stage_bytes, scw, scw_stride, win, winm,
+                                  flags);
+        } else {
+            CT* stage = reinterpret_cast<CT*>(smem);   // [kBandRows][max_w + 1]
+            CT* win = stage + kBandRows * (max_w + 1);  // [winm + 1]
+            band_pass<ST>(Lf, s.scale, false, iv, n, s.w, v, stage, win, winm, gsum);
+            band_pass<ST>(Lr, s.scale, true, iv, n, s.w, v, stage, win, winm, gsum);
+        }
         for (int i = tid; i < n; i += B) {
             const int32_t e = s.omega[i];
             if (e >= 0) stx<ASYNC>(xout + e, ldx<ASYNC>(xin + e) + static_cast<double>(v[i]));
@@ -780,12 +918,13 @@ __global__ void __launch_bounds__(kCgThreads) cg_kernel(Params P) {
         run_sync<kCgThreads>(P, upd, tc, red, done);
 }
 
-template <class ST, bool ASYNC>
-__global__ void __launch_bounds__(kBandThreads) band_kernel(Params P, int max_w, int winm) {
+template <class ST, int BR, bool ASYNC>
+__global__ void __launch_bounds__(kBandThreads)
+    band_kernel(Params P, int max_w, int winm, int pipelined, int stage_bytes, int scw_stride) {
     __shared__ double red[kBandThreads / 64];
     __shared__ int8_t done[kMaxItemsPerWg];
     TeamCtx tc = make_team(P);
-    BandUpdate<ST, ASYNC> upd{max_w, winm};
+    BandUpdate<ST, BR, ASYNC> upd{max_w, winm, pipelined, stage_bytes, scw_stride};
     if constexpr (ASYNC)
         run_async<kBandThreads>(P, upd, tc, red, done);
     else
@@ -882,10 +1021,18 @@ const void* cg_kernel_for(int kt, int r) {
     return cg_kernel_r<CT, 0, ASYNC>(r);
 }
 
+// 64-row blocks only for float32 storage: with float64 entries or float16
+// dequantisation the 64-entry diagonal row no longer fits in registers
 template <class ST>
-const void* band_kernel_for(bool async) {
-    return async ? reinterpret_cast<const void*>(band_kernel<ST, true>)
-                 : reinterpret_cast<const void*>(band_kernel<ST, false>);
+const void* band_kernel_for(bool async, int br) {
+    if constexpr (std::is_same<ST, float>::value) {
+        if (br == 64)
+            return async ? reinterpret_cast<const void*>(band_kernel<ST, 64, true>)
+                         : reinterpret_cast<const void*>(band_kernel<ST, 64, false>);
+    }
+    if (br != 32) return nullptr;
+    return async ? reinterpret_cast<const void*>(band_kernel<ST, 32, true>)
+                 : reinterpret_cast<const void*>(band_kernel<ST, 32, false>);
 }
 }  // namespace
 
@@ -902,12 +1049,12 @@ const void* select_kernel(int solver, int storage, bool async, int ell_width, in
             return async ? cg_kernel_for<double, true>(ell_width, rclass) : cg_kernel_for<double, false>(ell_width, rclass);
         return async ? cg_kernel_for<float, true>(ell_width, rclass) : cg_kernel_for<float, false>(ell_width, rclass);
     }
-    if (storage == 0) return band_kernel_for<double>(async);
-    if (storage == 1) return band_kernel_for<float>(async);
-    return band_kernel_for<_Float16>(async);
+    if (storage == 0) return band_kernel_for<double>(async, rclass);
+    if (storage == 1) return band_kernel_for<float>(async, rclass);
+    return band_kernel_for<_Float16>(async, rclass);
 }
 
-hipError_t launch_solver(const void* kern, int solver, const Params& P, int max_w, int winm, size_t lds,
+hipError_t launch_solver(const void* kern, int solver, const Params& P, const int* band_args, size_t lds,
                          hipStream_t st, bool coop) {
     Params p = P;
     if (lds > 0) {
@@ -920,7 +1067,8 @@ hipError_t launch_solver(const void* kern, int solver, const Params& P, int max_
         return coop ? hipLaunchCooperativeKernel(kern, grid, block, args, lds, st)
                     : hipLaunchKernel(kern, grid, block, args, lds, st);
     }
-    void* args[] = {&p, &max_w, &winm};
+    int a0 = band_args[0], a1 = band_args[1], a2 = band_args[2], a3 = band_args[3], a4 = band_args[4];
+    void* args[] = {&p, &a0, &a1, &a2, &a3, &a4};
     return coop ? hipLaunchCooperativeKernel(kern, grid, block, args, lds, st)
                 : hipLaunchKernel(kern, grid, block, args, lds, st);
 }
