@@ -212,6 +212,46 @@ ras_status ras_partition_sets(const ras_handle* h, int32_t* owner, int64_t* omeg
 ras_status ras_relative_residual(ras_handle* h, const double* b_dev, const double* x_dev, double* relres);
 void ras_destroy(ras_handle* h);
 
+/* ---- serving: continuous batching ----------------------------------------------
+ * A server admits submitted systems while the device memory they need fits in
+ * hbm_budget bytes, sets them up (host planning on its own thread, so setup of
+ * newcomers overlaps device work), and advances every admitted system together
+ * in time-sliced batched asynchronous launches of slice_seconds each; systems
+ * that arrive while others run join at the next slice.  A system retires as soon
+ * as its verified relative residual is below its tolerance; its device memory
+ * is released at once and its result waits for ras_server_poll.  A system
+ * larger than the whole budget is rejected (RAS_E_NOMEM) at submission.
+ * Local solver, partition and overlap are per system; systems with the same
+ * local solver share one launch per slice.  All calls are thread-safe.  */
+typedef struct ras_server ras_server;
+typedef struct ras_server_stats {
+    int64_t submitted;
+    int64_t completed;
+    int64_t queued;            /* submitted, not yet admitted */
+    int64_t active;            /* admitted, not yet retired */
+    int64_t slices;            /* batched launches issued */
+    int64_t in_use_bytes;      /* device memory held by admitted systems */
+    int64_t peak_in_use_bytes;
+    int64_t budget_bytes;
+    double device_seconds;     /* time inside slices */
+} ras_server_stats;
+
+ras_status ras_server_create(int64_t hbm_budget, double slice_seconds, void* hip_stream, ras_server** out);
+/* Copies A, the partition and b_host[nrhs * n]; returns a ticket at once.  */
+ras_status ras_server_submit(ras_server* srv, const ras_csr* A, const ras_partition* part, int32_t overlap,
+                             const ras_local* local, const double* b_host, int32_t nrhs, double tol,
+                             uint64_t* ticket);
+/* RAS_PENDING until the system has retired; then copies x_host[nrhs * n] and
+ * info[nrhs] (either may be NULL), the latency from submission to retirement,
+ * and releases the result.  An error during setup or solve is returned here.  */
+ras_status ras_server_poll(ras_server* srv, uint64_t ticket, double* x_host, ras_solve_info* info,
+                           double* latency_seconds);
+/* Blocks until the ticket has retired (RAS_OK) or timeout_seconds elapse (RAS_PENDING).  */
+ras_status ras_server_wait(ras_server* srv, uint64_t ticket, double timeout_seconds);
+ras_status ras_server_get_stats(ras_server* srv, ras_server_stats* out);
+/* Stops the server: pending systems are dropped, threads joined, memory freed.  */
+void ras_server_destroy(ras_server* srv);
+
 const char* ras_last_error(void);
 /* Library version string. */
 const char* ras_version(void);

@@ -93,6 +93,13 @@ SIGNATURES = {
     "ras_partition_sets": (C.c_int, [_P, _P, _P, _P]),
     "ras_relative_residual": (C.c_int, [_P, _P, _P, C.POINTER(C.c_double)]),
     "ras_destroy": (None, [_P]),
+    "ras_server_create": (C.c_int, [C.c_int64, C.c_double, _P, C.POINTER(_P)]),
+    "ras_server_submit": (C.c_int, [_P, C.POINTER(CSRStruct), C.POINTER(PartitionStruct), C.c_int32,
+                                    C.POINTER(LocalStruct), _P, C.c_int32, C.c_double, C.POINTER(C.c_uint64)]),
+    "ras_server_poll": (C.c_int, [_P, C.c_uint64, _P, _P, C.POINTER(C.c_double)]),
+    "ras_server_wait": (C.c_int, [_P, C.c_uint64, C.c_double]),
+    "ras_server_get_stats": (C.c_int, [_P, _P]),
+    "ras_server_destroy": (None, [_P]),
     "ras_last_error": (C.c_char_p, []),
     "ras_version": (C.c_char_p, []),
 }
@@ -370,6 +377,66 @@ def batch_solve(handles: Sequence[Handle], bs, xs=None, tol: float = 1e-8, mode:
         out.append([infos[k + j].as_dict() for j in range(r)])
         k += r
     return xs, out
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("queued", C.c_int64), ("active", C.c_int64),
+                ("slices", C.c_int64), ("in_use_bytes", C.c_int64), ("peak_in_use_bytes", C.c_int64),
+                ("budget_bytes", C.c_int64), ("device_seconds", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Server:
+    """Continuous-batching solver service (the library's native server): systems
+    are admitted while their device memory fits the budget and advanced together
+    in time-sliced batched asynchronous launches."""
+
+    def __init__(self, hbm_budget_bytes: int, slice_seconds: float = 0.02, stream=None):
+        p = _P()
+        st = None if stream is None else _stream_ptr(stream)
+        _check(lib().ras_server_create(int(hbm_budget_bytes), float(slice_seconds), st, C.byref(p)))
+        self._s = p
+
+    def submit(self, A, part: dict, overlap: int, loc: dict, B, tol: float = 1e-8) -> int:
+        """Queue a system; B is a host array [n] or [nrhs, n].  Returns a ticket."""
+        keep = _Keep()
+        Bh = keep.add(np.ascontiguousarray(B, dtype=np.float64))
+        nrhs = 1 if Bh.ndim == 1 else Bh.shape[0]
+        t = C.c_uint64()
+        _check(lib().ras_server_submit(self._s, C.byref(_csr(A, keep)), C.byref(_part(part, A, keep)), int(overlap),
+                                       C.byref(_local(loc)), Bh.ctypes.data, nrhs, float(tol), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, n: int, nrhs: int = 1):
+        """(done, x[nrhs, n] or None, infos, latency_s); raises on a failed system."""
+        x = np.empty((nrhs, n))
+        infos = (SolveInfo * nrhs)()
+        lat = C.c_double()
+        st = lib().ras_server_poll(self._s, int(ticket), x.ctypes.data, infos, C.byref(lat))
+        if st == RAS_PENDING:
+            return False, None, None, None
+        _check(st)
+        return True, x, [i.as_dict() for i in infos], lat.value
+
+    def wait(self, ticket: int, timeout: float = 60.0) -> bool:
+        return lib().ras_server_wait(self._s, int(ticket), float(timeout)) == RAS_OK
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(lib().ras_server_get_stats(self._s, C.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "_s", None) and _lib_handle is not None:
+            try:
+                _lib_handle.ras_server_destroy(self._s)
+            except Exception:
+                pass
+            self._s = None
+
+    __del__ = close
 
 
 def version() -> str:

@@ -3,12 +3,19 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <queue>
 #include <string>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/ras.h"
@@ -392,6 +399,7 @@ struct InstSpec {
     const double* b;
     double* x;
     int rhs;
+    double tol = -1.0;  // per-system tolerance (< 0: the solve options' tol)
 };
 
 // One persistent solve over a set of right-hand sides of one or more systems.
@@ -418,6 +426,8 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
         else if (K != h->uniform_K) K = 0;
     }
     const int ninst = static_cast<int>(specs.size());
+    std::vector<double> tol_v(ninst);
+    for (int i = 0; i < ninst; ++i) tol_v[i] = specs[i].tol >= 0.0 ? specs[i].tol : o.tol;
     int nitems_total = 0;
     for (auto& sp : specs) nitems_total += sp.h->plan->P;
 
@@ -602,7 +612,8 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     }
 
     // device workspace (one block, carved)
-    const int64_t hist_cap = std::min<int64_t>(o.max_sweeps + 1, 1 << 22);
+    // synchronous history: one entry per sweep; asynchronous: one per detector check
+    const int64_t hist_cap = std::min<int64_t>(o.max_sweeps + 1, sync ? (1 << 20) : (1 << 16));
     auto align = [](size_t v) { return (v + 255) / 256 * 256; };
     size_t off = 0;
     auto carve = [&](size_t bytes) {
@@ -644,7 +655,7 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
         in.hist_t = reinterpret_cast<double*>(base + o_hist) + static_cast<size_t>(ninst + i) * hist_cap;
         in.hist_cap = hist_cap;
         in.max_sweeps = o.max_sweeps;
-        in.tol2 = o.tol * o.tol;
+        in.tol2 = tol_v[i] * tol_v[i];
         in.leader = owner_wg[in.item_begin];
         // ||b||^2 (deterministic two-pass reduction)
         ras_handle* h = specs[i].h;
@@ -808,7 +819,7 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
                 verified[i] = 1;
                 continue;
             }
-            if (relres[i] < o.tol || exhausted || timed || ordered) {
+            if (relres[i] < tol_v[i] || exhausted || timed || ordered) {
                 verified[i] = 1;
                 time_out = time_out || timed;
                 continue;
@@ -836,7 +847,7 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
         ras_solve_info& inf = info[i];
         std::memset(&inf, 0, sizeof(inf));
         const bool finite = std::isfinite(relres[i]);
-        inf.converged = finite && relres[i] < o.tol;
+        inf.converged = finite && relres[i] < tol_v[i];
         inf.launches = launches[i];
         inf.rel_residual = relres[i];
         inf.seconds = ms * 1e-3;
@@ -883,6 +894,293 @@ void init_device(ras_handle& h, void* stream) {
     hip_check(hipDeviceGetAttribute(&h.num_cu, hipDeviceAttributeMultiprocessorCount, h.device), "CU count");
 }
 
+
+// ------------------------------------------------------------------------------ serving
+// Device bytes a system will hold while admitted: its handle (matrix data,
+// factors, global CSR) plus per right-hand side b, x, the local vector and the
+// history of the batched solve.
+int64_t estimate_device_bytes(const Plan& plan, int nrhs) {
+    const bool chol = plan.local.kind == RAS_LOCAL_CHOL_BANDED;
+    const int64_t cts = ct_size(plan.local.storage);
+    const int64_t sts = plan.local.storage == RAS_STORAGE_FP64 ? 8 : plan.local.storage == RAS_STORAGE_FP32 ? 4 : 2;
+    int64_t bytes = (plan.n + 1) * 8 + plan.nnz * 12 + 2048;
+    int64_t sum_n = 0;
+    for (const auto& sd : plan.subs) {
+        const int64_t n = static_cast<int64_t>(sd.omega.size());
+        sum_n += n;
+        const int64_t ell = n_pad_of(n) * sd.ell_width;
+        bytes += 4 * n + ell * (8 + 4 + 4 + (!chol && plan.local.storage == RAS_STORAGE_FP32 ? 4 : 0)) + 512;
+        if (chol) bytes += 2 * ((n * (sd.w + 1) + 63) / 64 * 64) * sts + n * cts + (plan.local.storage == 2 ? 4 * n : 0);
+    }
+    if (chol) bytes += 2048;
+    bytes += nrhs * (16 * plan.n + sum_n * cts + 2 * 8 * 65536 + 64 * plan.P);
+    return bytes;
+}
+
+struct SrvRequest {
+    uint64_t ticket = 0;
+    std::vector<int64_t> rp;
+    std::vector<int32_t> ci;
+    std::vector<double> va;
+    std::vector<int32_t> owner;
+    ras_partition part{};
+    int32_t overlap = 0;
+    ras_local local{};
+    std::vector<double> b;
+    int nrhs = 1;
+    double tol = 1e-8;
+    std::chrono::steady_clock::time_point t_submit;
+    std::unique_ptr<ras_plan> plan;
+    int64_t bytes = 0;
+};
+
+struct SrvSystem {
+    uint64_t ticket = 0;
+    ras_handle* h = nullptr;
+    DevBuf b, x;
+    int nrhs = 1;
+    int64_t n = 0;
+    double tol = 1e-8;
+    int64_t bytes = 0;
+    std::chrono::steady_clock::time_point t_submit;
+    std::vector<ras_solve_info> acc;  // accumulated over slices
+    ~SrvSystem() {
+        if (h) delete h;
+    }
+};
+
+struct SrvResult {
+    ras_status status = RAS_OK;
+    std::string msg;
+    std::vector<double> x;
+    std::vector<ras_solve_info> info;
+    double latency = 0.0;
+};
+
+}  // namespace
+
+struct ras_server {
+    int64_t budget = 0;
+    double slice = 0.02;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv_plan, cv_admit, cv_done;
+    std::deque<std::unique_ptr<SrvRequest>> submitted, planned;
+    std::vector<std::unique_ptr<SrvSystem>> active;
+    std::unordered_map<uint64_t, SrvResult> results;
+    std::unordered_map<uint64_t, int> state;  // 0 queued, 1 planned, 2 active, 3 done
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    int64_t in_use = 0, peak = 0, slices = 0, submitted_n = 0, completed_n = 0;
+    double device_seconds = 0.0;
+    std::thread planner, driver;
+
+    void finish(uint64_t ticket, SrvResult&& r) {
+        results[ticket] = std::move(r);
+        state[ticket] = 3;
+        ++completed_n;
+        cv_done.notify_all();
+    }
+
+    void plan_loop() {
+        for (;;) {
+            std::unique_ptr<SrvRequest> rq;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_plan.wait(lk, [&] { return stop || !submitted.empty(); });
+                if (stop) return;
+                rq = std::move(submitted.front());
+                submitted.pop_front();
+            }
+            SrvResult err;
+            try {
+                ras_csr A{static_cast<int64_t>(rq->rp.size()) - 1, rq->rp.data(), rq->ci.data(), rq->va.data()};
+                if (!rq->owner.empty()) rq->part.owner = rq->owner.data();
+                rq->plan = std::make_unique<ras_plan>();
+                build_plan(&A, &rq->part, rq->overlap, &rq->local, *rq->plan);
+                rq->bytes = estimate_device_bytes(*rq->plan, rq->nrhs);
+                std::vector<int64_t>().swap(rq->rp);
+                std::vector<int32_t>().swap(rq->ci);
+                std::vector<double>().swap(rq->va);
+            } catch (const Error& e) {
+                err.status = e.status;
+                err.msg = e.msg;
+            } catch (const std::bad_alloc&) {
+                err.status = RAS_E_NOMEM;
+                err.msg = "host allocation failed";
+            }
+            std::lock_guard<std::mutex> lk(mu);
+            if (err.status != RAS_OK) {
+                finish(rq->ticket, std::move(err));
+                continue;
+            }
+            if (rq->bytes > budget) {
+                SrvResult r;
+                r.status = RAS_E_NOMEM;
+                r.msg = "system needs " + std::to_string(rq->bytes) + " device bytes, above the server budget";
+                finish(rq->ticket, std::move(r));
+                continue;
+            }
+            state[rq->ticket] = 1;
+            planned.push_back(std::move(rq));
+            cv_admit.notify_all();
+        }
+    }
+
+    // Upload one planned request (outside the lock).
+    std::unique_ptr<SrvSystem> admit(SrvRequest& rq) {
+        auto sys = std::make_unique<SrvSystem>();
+        sys->ticket = rq.ticket;
+        sys->nrhs = rq.nrhs;
+        sys->n = rq.plan->n;
+        sys->tol = rq.tol;
+        sys->bytes = rq.bytes;
+        sys->t_submit = rq.t_submit;
+        auto h = std::make_unique<ras_handle>();
+        init_device(*h, stream);
+        upload(*h, *rq.plan);
+        drop_factors(*rq.plan);
+        rq.plan->row_ptr.clear();
+        rq.plan->col.clear();
+        rq.plan->val.clear();
+        h->plan = std::move(rq.plan);
+        const size_t vb = static_cast<size_t>(sys->nrhs) * sys->n * sizeof(double);
+        sys->b.alloc(vb);
+        sys->x.alloc(vb);
+        hip_check(hipMemcpyAsync(sys->b.p, rq.b.data(), vb, hipMemcpyHostToDevice, stream), "upload b");
+        hip_check(hipMemsetAsync(sys->x.p, 0, vb, stream), "clear x");
+        hip_check(hipStreamSynchronize(stream), "admit");
+        sys->h = h.release();
+        sys->acc.assign(sys->nrhs, ras_solve_info{});
+        return sys;
+    }
+
+    void retire(SrvSystem& sys, ras_status st, const std::string& msg) {
+        SrvResult r;
+        r.status = st;
+        r.msg = msg;
+        if (st >= 0) {
+            r.x.resize(static_cast<size_t>(sys.nrhs) * sys.n);
+            if (hipMemcpy(r.x.data(), sys.x.p, r.x.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+                r.status = RAS_E_HIP;
+                r.msg = "copy result";
+            }
+        }
+        r.info = sys.acc;
+        r.latency = std::chrono::duration<double>(std::chrono::steady_clock::now() - sys.t_submit).count();
+        finish(sys.ticket, std::move(r));
+    }
+
+    void drive_loop() {
+        if (hipSetDevice(device) != hipSuccess) return;
+        for (;;) {
+            // admission by budget: the oldest planned systems that fit
+            for (;;) {
+                std::unique_ptr<SrvRequest> rq;
+                {
+                    std::unique_lock<std::mutex> lk(mu);
+                    if (stop) return;
+                    if (active.empty() && planned.empty()) {
+                        cv_admit.wait(lk, [&] { return stop || !planned.empty(); });
+                        if (stop) return;
+                    }
+                    if (planned.empty() || (!active.empty() && in_use + planned.front()->bytes > budget)) break;
+                    rq = std::move(planned.front());
+                    planned.pop_front();
+                    in_use += rq->bytes;
+                    peak = std::max(peak, in_use);
+                    state[rq->ticket] = 2;
+                }
+                try {
+                    auto sys = admit(*rq);
+                    std::lock_guard<std::mutex> lk(mu);
+                    active.push_back(std::move(sys));
+                } catch (const Error& e) {
+                    std::lock_guard<std::mutex> lk(mu);
+                    in_use -= rq->bytes;
+                    SrvResult r;
+                    r.status = e.status;
+                    r.msg = e.msg;
+                    finish(rq->ticket, std::move(r));
+                }
+            }
+            // one slice: every admitted system, grouped by local solver
+            std::map<std::tuple<int, int, int>, std::vector<SrvSystem*>> groups;
+            for (auto& sp : active)
+                groups[{sp->h->solver, sp->h->storage, sp->h->cg_iters}].push_back(sp.get());
+            const auto t0 = std::chrono::steady_clock::now();
+            std::vector<std::pair<SrvSystem*, std::pair<ras_status, std::string>>> done;
+            for (auto& kv : groups) {
+                std::vector<InstSpec> specs;
+                for (SrvSystem* sy : kv.second)
+                    for (int r = 0; r < sy->nrhs; ++r)
+                        specs.push_back(InstSpec{sy->h, sy->b.as<double>() + r * sy->n, sy->x.as<double>() + r * sy->n,
+                                                 r, sy->tol});
+                ras_solve_opts o{};
+                o.mode = RAS_MODE_ASYNC;
+                o.tol = kv.second.front()->tol;
+                o.max_sweeps = INT64_MAX / 4;
+                o.max_seconds = slice;
+                std::vector<ras_solve_info> infos(specs.size());
+                ras_status st = RAS_OK;
+                std::string msg;
+                try {
+                    st = run_solve(specs, o, infos.data());
+                } catch (const Error& e) {
+                    st = e.status;
+                    msg = e.msg;
+                }
+                size_t k = 0;
+                for (SrvSystem* sy : kv.second) {
+                    bool all = true;
+                    for (int r = 0; r < sy->nrhs; ++r, ++k) {
+                        if (st < 0 && st != RAS_E_DIVERGED) {
+                            all = false;
+                            continue;
+                        }
+                        ras_solve_info& a = sy->acc[r];
+                        const ras_solve_info& f = infos[k];
+                        a.converged = f.converged;
+                        a.launches += f.launches;
+                        a.sweeps += f.sweeps;
+                        a.total_local_solves += f.total_local_solves;
+                        a.min_local_solves += f.min_local_solves;
+                        a.max_local_solves += f.max_local_solves;
+                        a.rel_residual = f.rel_residual;
+                        a.seconds += f.seconds;
+                        a.kernel_seconds += f.kernel_seconds;
+                        all = all && f.converged;
+                    }
+                    if (st < 0 && st != RAS_E_DIVERGED) done.push_back({sy, {st, msg}});
+                    else if (all) done.push_back({sy, {RAS_OK, std::string()}});
+                    else
+                        for (int r = 0; r < sy->nrhs; ++r)
+                            if (!std::isfinite(sy->acc[r].rel_residual)) {
+                                done.push_back({sy, {RAS_E_DIVERGED, "non-finite residual"}});
+                                break;
+                            }
+                }
+            }
+            const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            std::lock_guard<std::mutex> lk(mu);
+            ++slices;
+            device_seconds += dt;
+            for (auto& d : done) {
+                retire(*d.first, d.second.first, d.second.second);
+                in_use -= d.first->bytes;
+                for (size_t i = 0; i < active.size(); ++i)
+                    if (active[i].get() == d.first) {
+                        active.erase(active.begin() + static_cast<long>(i));
+                        break;
+                    }
+            }
+        }
+    }
+};
+
+namespace {
 }  // namespace
 
 extern "C" {
@@ -1099,5 +1397,128 @@ ras_status ras_relative_residual(ras_handle* h, const double* b_dev, const doubl
 }
 
 void ras_destroy(ras_handle* h) { delete h; }
+
+ras_status ras_server_create(int64_t hbm_budget, double slice_seconds, void* hip_stream, ras_server** out) {
+    return guarded([&] {
+        if (!out || hbm_budget <= 0 || !(slice_seconds > 0.0)) throw Error{RAS_E_ARG, "invalid server arguments"};
+        auto srv = std::make_unique<ras_server>();
+        srv->budget = hbm_budget;
+        srv->slice = slice_seconds;
+        hip_check(hipGetDevice(&srv->device), "hipGetDevice");
+        if (hip_stream) {
+            srv->stream = static_cast<hipStream_t>(hip_stream);
+        } else {
+            hip_check(hipStreamCreate(&srv->stream), "hipStreamCreate");
+            srv->own_stream = true;
+        }
+        ras_server* p = srv.get();
+        p->planner = std::thread([p] { p->plan_loop(); });
+        p->driver = std::thread([p] { p->drive_loop(); });
+        *out = srv.release();
+        return RAS_OK;
+    });
+}
+
+ras_status ras_server_submit(ras_server* srv, const ras_csr* A, const ras_partition* part, int32_t overlap,
+                             const ras_local* local, const double* b_host, int32_t nrhs, double tol,
+                             uint64_t* ticket) {
+    return guarded([&] {
+        if (!srv || !A || !part || !local || !b_host || nrhs < 1 || !ticket || !(tol >= 0.0) || A->n < 1 ||
+            !A->row_ptr || !A->col || !A->val)
+            throw Error{RAS_E_ARG, "invalid submission"};
+        auto rq = std::make_unique<SrvRequest>();
+        const int64_t n = A->n, nnz = A->row_ptr[n];
+        if (nnz < 0) throw Error{RAS_E_PATTERN, "row_ptr[n] < 0"};
+        rq->rp.assign(A->row_ptr, A->row_ptr + n + 1);
+        rq->ci.assign(A->col, A->col + nnz);
+        rq->va.assign(A->val, A->val + nnz);
+        rq->part = *part;
+        if (part->kind == RAS_PART_EXPLICIT && part->owner) rq->owner.assign(part->owner, part->owner + n);
+        rq->part.owner = nullptr;
+        rq->overlap = overlap;
+        rq->local = *local;
+        rq->b.assign(b_host, b_host + n * nrhs);
+        rq->nrhs = nrhs;
+        rq->tol = tol;
+        rq->t_submit = std::chrono::steady_clock::now();
+        std::lock_guard<std::mutex> lk(srv->mu);
+        rq->ticket = srv->next_ticket++;
+        *ticket = rq->ticket;
+        srv->state[rq->ticket] = 0;
+        ++srv->submitted_n;
+        srv->submitted.push_back(std::move(rq));
+        srv->cv_plan.notify_one();
+        return RAS_OK;
+    });
+}
+
+ras_status ras_server_poll(ras_server* srv, uint64_t ticket, double* x_host, ras_solve_info* info,
+                           double* latency_seconds) {
+    return guarded([&] {
+        if (!srv) throw Error{RAS_E_ARG, "null server"};
+        std::lock_guard<std::mutex> lk(srv->mu);
+        auto st = srv->state.find(ticket);
+        if (st == srv->state.end()) throw Error{RAS_E_ARG, "unknown ticket"};
+        if (st->second != 3) return RAS_PENDING;
+        SrvResult& r = srv->results[ticket];
+        const ras_status status = r.status;
+        if (status < 0) {
+            g_err = r.msg;
+        } else {
+            if (x_host) std::copy(r.x.begin(), r.x.end(), x_host);
+            if (info) std::copy(r.info.begin(), r.info.end(), info);
+        }
+        if (latency_seconds) *latency_seconds = r.latency;
+        srv->results.erase(ticket);
+        srv->state.erase(st);
+        return status;
+    });
+}
+
+ras_status ras_server_wait(ras_server* srv, uint64_t ticket, double timeout_seconds) {
+    return guarded([&] {
+        if (!srv) throw Error{RAS_E_ARG, "null server"};
+        std::unique_lock<std::mutex> lk(srv->mu);
+        auto ready = [&] {
+            auto st = srv->state.find(ticket);
+            return st == srv->state.end() || st->second == 3;
+        };
+        const bool ok = srv->cv_done.wait_for(lk, std::chrono::duration<double>(std::max(0.0, timeout_seconds)), ready);
+        return ok ? RAS_OK : RAS_PENDING;
+    });
+}
+
+ras_status ras_server_get_stats(ras_server* srv, ras_server_stats* out) {
+    return guarded([&] {
+        if (!srv || !out) throw Error{RAS_E_ARG, "null argument"};
+        std::lock_guard<std::mutex> lk(srv->mu);
+        out->submitted = srv->submitted_n;
+        out->completed = srv->completed_n;
+        out->queued = static_cast<int64_t>(srv->submitted.size() + srv->planned.size());
+        out->active = static_cast<int64_t>(srv->active.size());
+        out->slices = srv->slices;
+        out->in_use_bytes = srv->in_use;
+        out->peak_in_use_bytes = srv->peak;
+        out->budget_bytes = srv->budget;
+        out->device_seconds = srv->device_seconds;
+        return RAS_OK;
+    });
+}
+
+void ras_server_destroy(ras_server* srv) {
+    if (!srv) return;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+    }
+    srv->cv_plan.notify_all();
+    srv->cv_admit.notify_all();
+    if (srv->planner.joinable()) srv->planner.join();
+    if (srv->driver.joinable()) srv->driver.join();
+    srv->active.clear();
+    if (srv->own_stream) (void)hipStreamDestroy(srv->stream);
+    delete srv;
+}
+
 
 }  // extern "C"

@@ -87,7 +87,7 @@ struct Params {
     const int32_t* wg_team;   // [n_wg] team of each workgroup
     const int32_t* wg_member; // [n_wg] rank of each workgroup inside its team
     const int32_t* team_win;  // [n_subs][T][2] LDS window [lo, hi) of local rows of each team member
-    uint32_t* team_bar;       // [n_teams][2] team barrier (count, generation)
+    uint32_t* team_bar;       // [n_teams][2] team barrier ticket counter (64-bit)
     double* team_buf;         // [n_teams][2][T][4] team reduction / broadcast slots
     GridBarrier* bar;
     int32_t n_items;

@@ -210,27 +210,41 @@ __device__ __forceinline__ TeamCtx make_team(const Params& P) {
     return tc;
 }
 
+// Team barrier without cache-wide fences.  Every value that crosses workgroups
+// inside a team (exchanged residual rows, reduction slots) is written and read
+// with device-scope relaxed atomics, which go to the device-coherent level and
+// never sit in (or are served from) an XCD-private cache line.  Each wave
+// drains its memory counters before the workgroup arrives, so those stores
+// have completed when the arrival is counted; arrivals increment a 64-bit
+// ticket counter and a member leaves barrier k once the counter reaches
+// (k + 1) T.  No cache write-back or invalidation is needed, which keeps the
+// two barriers of every CG step cheap.
 __device__ void team_barrier(TeamCtx& tc) {
     if (tc.T == 1) {
         __syncthreads();
         return;
     }
-    __threadfence();
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint32_t g = __hip_atomic_load(tc.bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t arrived = __hip_atomic_fetch_add(tc.bar, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == static_cast<uint32_t>(tc.T) - 1) {
-            __hip_atomic_store(tc.bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(tc.bar + 1, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            while (__hip_atomic_load(tc.bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g)
-                __builtin_amdgcn_s_sleep(1);
-        }
+        RAS_GLOBAL unsigned long long* ctr = (RAS_GLOBAL unsigned long long*)(tc.bar);
+        const unsigned long long ticket =
+            __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long target = (ticket / tc.T + 1) * tc.T;
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
+            __builtin_amdgcn_s_sleep(1);
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     ++tc.phase;
+}
+
+template <class T>
+__device__ __forceinline__ T ldg_dev(RAS_GLOBAL T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ void stg_dev(RAS_GLOBAL T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Sum NV workgroup totals (already block-reduced, uniform) over the team; the
@@ -240,17 +254,17 @@ __device__ __forceinline__ void team_sum(TeamCtx& tc, double (&v)[NV], unsigned 
     if (tc.T == 1) return;
     RAS_GLOBAL double* slot = tc.buf + (tc.phase & 1) * 4 * tc.T;
     if (threadIdx.x == 0)
-        for (int k = 0; k < NV; ++k) slot[4 * tc.member + k] = v[k];
+        for (int k = 0; k < NV; ++k) stg_dev(slot + 4 * tc.member + k, v[k]);
     team_barrier(tc);
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         if ((ct_mask >> k) & 1) {
             CT acc = CT(0);
-            for (int m = 0; m < tc.T; ++m) acc += static_cast<CT>(slot[4 * m + k]);
+            for (int m = 0; m < tc.T; ++m) acc += static_cast<CT>(ldg_dev(slot + 4 * m + k));
             v[k] = static_cast<double>(acc);
         } else {
             double acc = 0.0;
-            for (int m = 0; m < tc.T; ++m) acc += slot[4 * m + k];
+            for (int m = 0; m < tc.T; ++m) acc += ldg_dev(slot + 4 * m + k);
             v[k] = acc;
         }
     }
@@ -266,9 +280,9 @@ __device__ __forceinline__ int team_bcast(TeamCtx& tc, int v0, int* lds_flag) {
         return r;
     }
     RAS_GLOBAL double* slot = tc.buf + (tc.phase & 1) * 4 * tc.T;
-    if (threadIdx.x == 0 && tc.member == 0) slot[0] = static_cast<double>(v0);
+    if (threadIdx.x == 0 && tc.member == 0) stg_dev(slot, static_cast<double>(v0));
     team_barrier(tc);
-    return static_cast<int>(slot[0]);
+    return static_cast<int>(ldg_dev(slot));
 }
 
 template <class CT>
@@ -372,7 +386,7 @@ struct CgUpdate {
                 r[j] = static_cast<CT>(ri);
                 rr += r[j] * r[j];
                 pl[i - wlo] = r[j];
-                if (T > 1) rg[i] = r[j];
+                if (T > 1) stg_dev(rg + i, r[j]);
             }
         }
         if (tid == 0) pl[zs] = CT(0);
@@ -391,8 +405,8 @@ struct CgUpdate {
         b2 = v4[2];
         CT rho = static_cast<CT>(v4[3]);
         if (T > 1) {
-            for (int i = wlo + tid; i < lo; i += B) pl[i - wlo] = rg[i];
-            for (int i = hi + tid; i < whi; i += B) pl[i - wlo] = rg[i];
+            for (int i = wlo + tid; i < lo; i += B) pl[i - wlo] = ldg_dev(rg + i);
+            for (int i = hi + tid; i < whi; i += B) pl[i - wlo] = ldg_dev(rg + i);
             __syncthreads();
         }
         for (int it = 0; it < P.cg_iters; ++it) {
@@ -442,7 +456,7 @@ struct CgUpdate {
                     d[j] += alpha * pl[i - wlo];
                     r[j] -= alpha * q[j];
                     rn += r[j] * r[j];
-                    if (T > 1 && !last) rg[i] = r[j];
+                    if (T > 1 && !last) stg_dev(rg + i, r[j]);
                 }
             }
             if (last) break;  // p is not needed after the last step
@@ -456,8 +470,8 @@ struct CgUpdate {
                 if (i < hi) pl[i - wlo] = r[j] + beta * pl[i - wlo];
             }
             if (T > 1) {
-                for (int i = wlo + tid; i < lo; i += B) pl[i - wlo] = rg[i] + beta * pl[i - wlo];
-                for (int i = hi + tid; i < whi; i += B) pl[i - wlo] = rg[i] + beta * pl[i - wlo];
+                for (int i = wlo + tid; i < lo; i += B) pl[i - wlo] = ldg_dev(rg + i) + beta * pl[i - wlo];
+                for (int i = hi + tid; i < whi; i += B) pl[i - wlo] = ldg_dev(rg + i) + beta * pl[i - wlo];
             }
             rho = rho_new;
             __syncthreads();
