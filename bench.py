@@ -34,6 +34,7 @@ WORKLOADS = {
     "diffusion2d_2048_16x16_fp32": ("diffusion2d_2048_16x16", "chol", "fp32", 0),
     "diffusion2d_2048_16x16_fp16": ("diffusion2d_2048_16x16", "chol", "fp16", 0),
     "poisson2d_64_strips4": ("poisson2d_64_strips4", "chol", "fp64", 0),
+    "serving": (None, None, None, 0),
 }
 
 
@@ -47,6 +48,8 @@ def parse():
     ap.add_argument("--no-sync", action="store_true", help="skip the synchronous comparison (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 2 GiB device copy (hardware-counter calibration)")
+    ap.add_argument("--serve-count", type=int, default=200, help="systems in the serving stream")
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     return ap.parse_args()
 
 
@@ -153,6 +156,82 @@ def traffic_from_profiles(workload: str, algo_bytes_per_launch: float):
     return ratio * algo_bytes_per_launch
 
 
+
+def serving_bench(args):
+    """Continuous-batching service: a stream of independent SPD systems (half 2-D
+    five-point, half 3-D seven-point finite volumes, log-normal coefficients,
+    log-uniform sizes, 1-8 right-hand sides) with Poisson arrivals, admitted by
+    device-memory budget.  A closed-loop pass over the first systems measures the
+    saturated rate; the timed open-loop pass arrives at 0.7 x that rate."""
+    import numpy as np
+
+    import paper_2003_05361_amd as ras
+    import ras_inputs as R
+
+    specs = list(R.serving_stream(count=args.serve_count, rate=1.0))
+    systems = []
+    for sp in specs:
+        A, B, parts = R.serving_system(sp)
+        if sp["dims"] == 2:
+            part, loc = ras.partition("regular_2d", parts, grid=A.grid), ras.local("chol", "fp32")
+        else:
+            part, loc = ras.partition("regular_3d", parts, grid=A.grid), ras.local("cg", "fp32", 8)
+        systems.append((A, part, loc, B))
+    budget = int(args.serve_budget_gib * (1 << 30))
+
+    def run(subset, arrivals):
+        srv = ras.Server(budget, slice_seconds=0.02)
+        t0 = time.perf_counter()
+        tickets = []
+        for (A, part, loc, B), ta in zip(subset, arrivals):
+            delay = ta - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(srv.submit(A, part, 2, loc, B, 1e-8))
+        lat, rhs, bad = [], 0, 0
+        for (A, part, loc, B), tk in zip(subset, tickets):
+            srv.wait(tk, 600.0)
+            done, x, infos, l = srv.poll(tk, A.n, B.shape[0])
+            lat.append(l)
+            rhs += B.shape[0]
+            bad += sum(1 for i in infos if not i["converged"])
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return wall, np.array(lat), rhs, bad, st
+
+    warm = systems[: min(40, len(systems))]
+    wall0, _, _, _, _ = run(warm, [0.0] * len(warm))
+    sat_rate = len(warm) / wall0
+    rate = 0.7 * sat_rate
+    arr = np.cumsum(np.random.default_rng(7).exponential(1.0 / rate, len(systems)))
+    arr -= arr[0]
+    wall, lat, rhs, bad, st = run(systems, list(arr))
+    line = {
+        "metric": METRIC,
+        "value": rhs / wall,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": wall * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 outer / f32 local",
+        "data": "synthetic",
+        "config": {"workload": "serving", "systems": len(systems), "rhs": int(rhs),
+                   "arrival_rate_per_s": rate, "saturated_rate_per_s": sat_rate,
+                   "budget_bytes": budget, "tol": 1e-8},
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "max": float(lat.max())},
+        "unconverged_rhs": int(bad),
+        "server": st,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -175,6 +254,10 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": 2 * n * 8, "kernel": "torch copy", "launches": 3}))
+        return
+
+    if args.workload == "serving":
+        serving_bench(args)
         return
 
     import paper_2003_05361_amd as ras

@@ -108,8 +108,19 @@ class RAS:
         return x, np.array(hist)
 
     # -- seeded asynchronous simulator --------------------------------------------------
+    def neighbours(self) -> list[np.ndarray]:
+        """Subdomains owning a point that subdomain p's local rows read (Omega_p and
+        its external layer), excluding p."""
+        out = []
+        for p, s in enumerate(self.subs):
+            cols = self.M[s.omega].indices
+            q = np.unique(self.owner[cols])
+            out.append(q[q != p])
+        return out
+
     def async_sim(self, b: np.ndarray, tol: float, seed: int, staleness: int = 3, max_updates: int = 10**6,
-                  x0: np.ndarray | None = None, paused: set | None = None, pause_until: int = 0):
+                  x0: np.ndarray | None = None, paused: set | None = None, pause_until: int = 0,
+                  detect: str = "central"):
         """Event-driven asynchronous RAS with bounded staleness.
 
         Each event picks a subdomain at random; it reads every other subdomain's
@@ -118,19 +129,28 @@ class RAS:
         criterion, solves and publishes its owned values.  Centralized detection:
         once every subdomain's latest local criterion holds, the iteration stops and
         the global criterion is verified on the current x; if it fails the iteration
-        resumes.  Subdomains in `paused` take no events before event `pause_until`
-        (forced staleness).  Returns (x, info dict)."""
+        resumes.  Decentralized detection (Sec. 2.2, after Bahi et al.): a subdomain
+        raises its global flag when it and all its neighbours report local
+        convergence, or when a neighbour's flag is up (flooding), and then stops
+        updating; once every flag is up the global criterion is verified, and on
+        failure all flags are cleared and the iteration resumes.  Subdomains in
+        `paused` take no events before event `pause_until` (forced staleness).
+        Returns (x, info dict)."""
         rng = np.random.default_rng(seed)
         x = np.zeros_like(b) if x0 is None else x0.astype(np.float64).copy()
         bn2 = float(b @ b)
         P = self.P
         versions = [[x[s.owned].copy()] for s in self.subs]
         conv = np.zeros(P, dtype=bool)
+        gflag = np.zeros(P, dtype=bool)
+        nbrs = self.neighbours() if detect == "decentral" else None
         counts = np.zeros(P, dtype=np.int64)
         verifications = 0
         for ev in range(max_updates):
             p = int(rng.integers(P))
             if paused and p in paused and ev < pause_until:
+                continue
+            if gflag[p]:
                 continue
             view = x.copy()
             for q, sq in enumerate(self.subs):
@@ -148,6 +168,20 @@ class RAS:
             if len(versions[p]) > staleness:
                 versions[p].pop(0)
             counts[p] += 1
+            if detect == "decentral":
+                nb = nbrs[p]
+                if (conv[p] and conv[nb].all()) or gflag[nb].any():
+                    gflag[p] = True
+                if not gflag.all():
+                    continue
+                verifications += 1
+                r = self.residual(x, b)
+                if float(r @ r) < tol * tol * bn2:
+                    return x, dict(converged=True, events=ev + 1, local_solves=counts, verifications=verifications,
+                                   relres=np.sqrt(float(r @ r) / bn2))
+                gflag[:] = False
+                conv[:] = False
+                continue
             if conv.all():
                 verifications += 1
                 r = self.residual(x, b)

@@ -105,7 +105,7 @@ struct ras_handle {
     int64_t sum_n = 0;
     ras_plan_stats stats{};
     DevBuf omega, ell_val, ell_valf, ell_gcol, ell_lcol, band_f, band_b, scale, invd;
-    DevBuf csr_rp, csr_ci, csr_va;
+    DevBuf csr_rp, csr_ci, csr_va, nbr;
     std::vector<SubDev> subs;  // host copy with device pointers
     // CG team windows: for team size kTeamSizes[t], per subdomain and member the
     // LDS window [lo, hi) of local rows its rows reference
@@ -365,6 +365,30 @@ void upload(ras_handle& h, const Plan& plan) {
             }
         }
         h.subs[p] = d;
+    }
+    // neighbours: subdomains owning a column read by a row of Omega_p (the
+    // residual's interface columns included); used by decentralized detection
+    {
+        std::vector<int32_t> all, ptr(P + 1, 0), mark(P, -1);
+        for (int p = 0; p < P; ++p) {
+            for (int32_t g : plan.subs[p].omega)
+                for (int64_t e = plan.row_ptr[g]; e < plan.row_ptr[g + 1]; ++e) {
+                    const int32_t q = plan.owner[plan.col[e]];
+                    if (q != p && mark[q] != p) {
+                        mark[q] = p;
+                        all.push_back(q);
+                    }
+                }
+            std::sort(all.begin() + ptr[p], all.end());
+            ptr[p + 1] = static_cast<int32_t>(all.size());
+        }
+        h.nbr.alloc(std::max<size_t>(1, all.size()) * sizeof(int32_t));
+        if (!all.empty())
+            hip_check(hipMemcpy(h.nbr.p, all.data(), all.size() * sizeof(int32_t), hipMemcpyHostToDevice), "copy nbr");
+        for (int p = 0; p < P; ++p) {
+            h.subs[p].nbr = h.nbr.as<int32_t>() + ptr[p];
+            h.subs[p].n_nbr = ptr[p + 1] - ptr[p];
+        }
     }
     plan_stats(plan, &h.stats);
     h.stats.device_bytes = static_cast<int64_t>(h.omega.bytes + h.ell_val.bytes + h.ell_valf.bytes + h.ell_gcol.bytes +
@@ -627,6 +651,7 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     const size_t o_ist = carve(insts.size() * sizeof(InstState));
     const size_t o_res2 = carve(2 * nitems * sizeof(double));
     const size_t o_conv = carve(nitems * sizeof(int32_t));
+    const size_t o_gflag = carve(nitems * sizeof(int32_t));
     const size_t o_solves = carve(nitems * sizeof(int64_t));
     const size_t o_version = carve(nitems * sizeof(uint32_t));
     const size_t o_tptr = carve((nteams + 1) * sizeof(int32_t));
@@ -697,6 +722,7 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     up(o_bar, &bar, sizeof(bar));
     hip_check(hipMemsetAsync(base + o_res2, 0, 2 * nitems * sizeof(double), stream), "clear");
     hip_check(hipMemsetAsync(base + o_conv, 0, nitems * sizeof(int32_t), stream), "clear");
+    hip_check(hipMemsetAsync(base + o_gflag, 0, nitems * sizeof(int32_t), stream), "clear");
     hip_check(hipMemsetAsync(base + o_solves, 0, nitems * sizeof(int64_t), stream), "clear");
     hip_check(hipMemsetAsync(base + o_version, 0, nitems * sizeof(uint32_t), stream), "clear");
     if (sync)  // x^0 lives in the caller's buffer; the other buffer is filled by the first sweep
@@ -709,6 +735,9 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     P.ist = reinterpret_cast<InstState*>(base + o_ist);
     P.res2_own = reinterpret_cast<double*>(base + o_res2);
     P.conv = reinterpret_cast<int32_t*>(base + o_conv);
+    P.gflag = reinterpret_cast<int32_t*>(base + o_gflag);
+    if (o.detect != RAS_DETECT_CENTRAL && o.detect != RAS_DETECT_DECENTRAL) throw Error{RAS_E_ARG, "unknown detector"};
+    P.detect = o.detect;
     P.solves = reinterpret_cast<int64_t*>(base + o_solves);
     P.version = reinterpret_cast<uint32_t*>(base + o_version);
     P.team_ptr = reinterpret_cast<const int32_t*>(base + o_tptr);
@@ -824,8 +853,12 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
                 time_out = time_out || timed;
                 continue;
             }
-            // resume: clear this instance's stop flag and history length
+            // resume: clear this instance's stop flag and its detection flags
             ist[i].stop = 0;
+            hip_check(hipMemsetAsync(P.gflag + insts[i].item_begin, 0, insts[i].item_count * sizeof(int32_t), stream),
+                      "clear flags");
+            hip_check(hipMemsetAsync(P.conv + insts[i].item_begin, 0, insts[i].item_count * sizeof(int32_t), stream),
+                      "clear flags");
             again = true;
         }
         if (!again || launch > 10000) break;

@@ -30,7 +30,9 @@ struct SubDev {
     const void* invd;         // [n] 1 / L_ii in the local compute type
     int32_t n, n_pad, K, w;
     int64_t row_off;          // offset of this subdomain in per-RHS scratch vectors
-    int64_t pad_;
+    const int32_t* nbr;       // [n_nbr] subdomains (of the same system) owning a point this one reads
+    int32_t n_nbr;
+    int32_t pad_;
 };
 
 // One work item: subdomain `sub` of right-hand side (instance) `inst`.
@@ -80,6 +82,7 @@ struct Params {
     InstState* ist;
     double* res2_own;         // [2][n_items] owned residual^2 (sync: by sweep parity)
     int32_t* conv;            // [n_items] local criterion met (async)
+    int32_t* gflag;           // [n_items] global-convergence flag (decentralized detection)
     int64_t* solves;          // [n_items] local solves done
     uint32_t* version;        // [n_items] published updates (async)
     const int32_t* team_ptr;  // [n_teams + 1]
@@ -95,7 +98,7 @@ struct Params {
     int32_t n_wg;
     int32_t cg_iters;
     int32_t team_size;        // T (1 for the banded solver)
-    int32_t pad_;
+    int32_t detect;           // 0 centralized, 1 decentralized (asynchronous mode)
     int64_t max_ticks;        // wall-clock ticks allowed (<= 0: unlimited)
     int64_t sweep0;           // sync: first sweep index of this launch
 };

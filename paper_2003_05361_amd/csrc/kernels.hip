@@ -869,7 +869,9 @@ __device__ __forceinline__ void run_async(const Params& P, U& upd, TeamCtx& tc, 
             const InstDev& in = P.insts[item.inst];
             InstState* st = P.ist + item.inst;
             int v0 = 0;
-            if (tc.member == 0 && tid == 0) v0 = (ld_rlx(&st->stop) != 0) || (P.solves[it] >= in.max_sweeps);
+            if (tc.member == 0 && tid == 0)
+                v0 = (ld_rlx(&st->stop) != 0) || (P.solves[it] >= in.max_sweeps) ||
+                     (P.detect == 1 && ld_rlx(P.gflag + it) != 0);
             const bool skip = team_bcast(tc, v0, &flag) != 0;
             if (skip) {
                 if (tid == 0) done[j - ib] = 1;
@@ -886,6 +888,24 @@ __device__ __forceinline__ void run_async(const Params& P, U& upd, TeamCtx& tc, 
                 st_rlx(P.conv + it, static_cast<int32_t>(loc2 < in.tol2 * b2));
                 P.solves[it] += 1;
                 __hip_atomic_fetch_add(P.version + it, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (P.detect == 1 && tc.member == 0) {
+                // decentralized detection (Sec. 2.2, Sec. 3.3.2, after Bahi et al.): a
+                // subdomain raises its global flag once it and every neighbour report
+                // local convergence, or as soon as a neighbour's flag is up (flooding);
+                // a flagged subdomain stops updating.
+                const SubDev* sd = P.subs + item.sub;
+                const int nn = uni(sd->n_nbr);
+                const int32_t* nb = sd->nbr;
+                int ok = 1, anyg = 0;
+                for (int k = tid; k < nn; k += B) {
+                    const int q = in.item_begin + nb[k];
+                    ok &= ld_rlx(P.conv + q) != 0;
+                    anyg |= ld_rlx(P.gflag + q) != 0;
+                }
+                ok = __syncthreads_and(ok);
+                anyg = __syncthreads_or(anyg);
+                if (tid == 0 && ((ok && loc2 < in.tol2 * b2) || anyg)) st_rlx(P.gflag + it, 1);
             }
             if (wg == in.leader && it == in.item_begin) {
                 // centralized detector (Sec. 2.2): all local criteria + owned-residual estimate
@@ -908,7 +928,7 @@ __device__ __forceinline__ void run_async(const Params& P, U& upd, TeamCtx& tc, 
                     st->sweeps += 1;
                     int32_t stop = 0;
                     if (!(sum == sum) || sum > 1e300) stop = 4;
-                    else if (allc && sum < in.tol2 * in.bnorm2) stop = 1;
+                    else if (P.detect == 0 && allc && sum < in.tol2 * in.bnorm2) stop = 1;
                     else if (P.max_ticks > 0 && now - st->t0 > P.max_ticks) stop = 2;
                     if (stop) st_rlx(&st->stop, stop);
                 }

@@ -246,6 +246,23 @@ def test_async_converges_and_verifies(loc, st, k):
         assert counts.min() >= 1 and counts.sum() == info[0]["total_local_solves"]
 
 
+@pytest.mark.parametrize("loc,st,k,team", [("chol", "fp64", 0, 0), ("cg", "fp64", 10, 4), ("cg", "fp32", 6, 1)])
+def test_async_decentralized_detection(loc, st, k, team):
+    ras = _ras()
+    _say(f"case: async decentral {loc} {st} team={team}")
+    A = R.laplace2d(96)
+    b = R.uniform_rhs(A.n, 17)
+    xd = schwarz.direct_solve(A, b)
+    h = ras.setup(A, ras.partition("regular_2d", (4, 4), grid=A.grid), 3, ras.local(loc, st, k))
+    for run in range(2):
+        x, info = h.solve(_cuda(b), tol=1e-8, mode="async", detect="decentral", max_sweeps=200000, max_seconds=60,
+                          team=team)
+        xx = x.cpu().numpy()
+        assert info[0]["converged"], info
+        assert schwarz.relative_residual(A, xx, b) < 1e-8
+        assert _rel(xx, xd) <= 1e-6
+
+
 # ----------------------------------------------------------------------------- multi-RHS and batching
 def test_multi_rhs_equals_single_sync():
     ras = _ras()

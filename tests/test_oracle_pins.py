@@ -365,6 +365,19 @@ def test_async_simulator_converges_and_verifies():
         assert np.linalg.norm(x - xd) <= 1e-6 * np.linalg.norm(xd)
 
 
+def test_async_simulator_decentralized_detection():
+    A = R.laplace2d(24)
+    b = R.uniform_rhs(A.n, 10)
+    xd = schwarz.direct_solve(A, b)
+    ras = schwarz.RAS(A, partition.regular_grid(A.grid, (3, 3)), 2, "chol")
+    nb = ras.neighbours()
+    assert sorted(nb[4].tolist()) == [0, 1, 2, 3, 5, 6, 7, 8]  # centre box reads its corners through overlap 2
+    assert sorted(nb[0].tolist()) == [1, 3, 4]
+    x, info = ras.async_sim(b, 1e-8, seed=3, staleness=2, max_updates=200000, detect="decentral")
+    assert info["converged"] and schwarz.relative_residual(A, x, b) < 1e-8
+    assert np.linalg.norm(x - xd) <= 1e-6 * np.linalg.norm(xd)
+
+
 def test_async_simulator_waits_for_paused_subdomain():
     A = R.laplace2d(16)
     b = R.uniform_rhs(A.n, 9)
