@@ -207,6 +207,14 @@ ras_status ras_residual_history(const ras_handle* h, int32_t rhs, double* t_sec,
  * "subdomain update" counts); counts[P].  */
 ras_status ras_local_solve_counts(const ras_handle* h, int32_t rhs, int64_t* counts);
 ras_status ras_partition_sets(const ras_handle* h, int32_t* owner, int64_t* omega_ptr, int32_t* omega_idx);
+/* Autotuner: times `sweeps` synchronous sweeps from x = 0 for every feasible CG
+ * team size (workgroups per subdomain) and keeps the fastest in the handle (used
+ * when ras_solve_opts.team is 0) and in a process-wide cache keyed by the
+ * problem shape, so later handles of the same shape start tuned.  x_dev is
+ * overwritten (work space).  best_team / best_ms_per_sweep may be NULL.  The
+ * banded solver has one configuration: it returns team 1.  */
+ras_status ras_autotune(ras_handle* h, const double* b_dev, double* x_dev, int32_t sweeps, int32_t* best_team,
+                        double* best_ms_per_sweep);
 /* Exact ||b - A x|| / ||b|| of device vectors (the post-termination check of
  * Sec. 3.3.2), computed by the library's verification kernel.  */
 ras_status ras_relative_residual(ras_handle* h, const double* b_dev, const double* x_dev, double* relres);

@@ -92,6 +92,7 @@ SIGNATURES = {
     "ras_local_solve_counts": (C.c_int, [_P, C.c_int32, _P]),
     "ras_partition_sets": (C.c_int, [_P, _P, _P, _P]),
     "ras_relative_residual": (C.c_int, [_P, _P, _P, C.POINTER(C.c_double)]),
+    "ras_autotune": (C.c_int, [_P, _P, _P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "ras_destroy": (None, [_P]),
     "ras_server_create": (C.c_int, [C.c_int64, C.c_double, _P, C.POINTER(_P)]),
     "ras_server_submit": (C.c_int, [_P, C.POINTER(CSRStruct), C.POINTER(PartitionStruct), C.c_int32,
@@ -328,6 +329,18 @@ class Handle:
         idx = np.empty(st["sum_local_rows"], dtype=np.int32)
         _check(lib().ras_partition_sets(self._h, owner.ctypes.data, ptr.ctypes.data, idx.ctypes.data))
         return owner, ptr, idx
+
+    def autotune(self, b, sweeps: int = 20) -> tuple[int, float]:
+        """Time `sweeps` synchronous sweeps for every feasible team size; keep the best.
+        Returns (team, ms per sweep)."""
+        import torch
+
+        x = torch.zeros_like(b)
+        t = C.c_int32()
+        ms = C.c_double()
+        _check(lib().ras_autotune(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), int(sweeps),
+                                  C.byref(t), C.byref(ms)))
+        return t.value, ms.value
 
     def relative_residual(self, b, x) -> float:
         r = C.c_double()

@@ -94,6 +94,12 @@ int next_pow2(int v) {
 
 struct ras_plan : public Plan {};
 
+namespace {
+// Shape key -> best CG team size found by ras_autotune (process-wide).
+std::mutex g_tune_mu;
+std::map<std::tuple<int64_t, int32_t, int32_t, int32_t, int32_t, int32_t>, int> g_tune;
+}  // namespace
+
 struct ras_handle {
     std::unique_ptr<ras_plan> plan;  // host plan (factors dropped after upload)
     hipStream_t stream = nullptr;
@@ -520,7 +526,12 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
         return teams * c.T;
     };
     Cfg cfg;
-    const int want_team = o.team > 0 ? o.team : (h0.solver == RAS_LOCAL_CG ? h0.tuned_team : 0);
+    int want_team = o.team > 0 ? o.team : (h0.solver == RAS_LOCAL_CG ? h0.tuned_team : 0);
+    if (want_team == 0 && h0.solver == RAS_LOCAL_CG && hs.size() == 1) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find({h0.plan->n, h0.plan->P, h0.max_n, h0.uniform_K, h0.storage, h0.cg_iters});
+        if (it != g_tune.end()) want_team = it->second;
+    }
     if (want_team > 0) {
         for (int t = 0; t < 5; ++t)
             if (kTeamSizes[t] == want_team) cfg = make_cfg(t);
@@ -1430,6 +1441,60 @@ ras_status ras_relative_residual(ras_handle* h, const double* b_dev, const doubl
 }
 
 void ras_destroy(ras_handle* h) { delete h; }
+
+ras_status ras_autotune(ras_handle* h, const double* b_dev, double* x_dev, int32_t sweeps, int32_t* best_team,
+                        double* best_ms_per_sweep) {
+    return guarded([&] {
+        if (!h || !b_dev || !x_dev || sweeps < 1) throw Error{RAS_E_ARG, "invalid argument"};
+        hip_check(hipSetDevice(h->device), "hipSetDevice");
+        int best = 1;
+        double best_ms = INFINITY;
+        if (h->solver == RAS_LOCAL_CG) {
+            for (int t = 0; t < 5; ++t) {
+                const int T = kTeamSizes[t];
+                ras_solve_opts o{};
+                o.mode = RAS_MODE_SYNC;
+                o.tol = 0.0;
+                o.max_sweeps = sweeps;
+                o.team = T;
+                hip_check(hipMemsetAsync(x_dev, 0, h->plan->n * sizeof(double), h->stream), "clear x");
+                std::vector<InstSpec> specs{InstSpec{h, b_dev, x_dev, 0}};
+                ras_solve_info info{};
+                try {
+                    run_solve(specs, o, &info);
+                } catch (const Error& e) {
+                    if (e.status == RAS_E_UNSUPPORTED) continue;  // infeasible team size for this shape
+                    throw;
+                }
+                const double ms = 1e3 * info.kernel_seconds / (sweeps + 1);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = T;
+                }
+            }
+            h->tuned_team = best;
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune[{h->plan->n, h->plan->P, h->max_n, h->uniform_K, h->storage, h->cg_iters}] = best;
+        } else {
+            ras_solve_opts o{};
+            o.mode = RAS_MODE_SYNC;
+            o.tol = 0.0;
+            o.max_sweeps = sweeps;
+            hip_check(hipMemsetAsync(x_dev, 0, h->plan->n * sizeof(double), h->stream), "clear x");
+            std::vector<InstSpec> specs{InstSpec{h, b_dev, x_dev, 0}};
+            ras_solve_info info{};
+            run_solve(specs, o, &info);
+            best_ms = 1e3 * info.kernel_seconds / (sweeps + 1);
+        }
+        h->hist.clear();
+        h->hist_t.clear();
+        h->counts.clear();
+        if (best_team) *best_team = best;
+        if (best_ms_per_sweep) *best_ms_per_sweep = best_ms;
+        return RAS_OK;
+    });
+}
+
 
 ras_status ras_server_create(int64_t hbm_budget, double slice_seconds, void* hip_stream, ras_server** out) {
     return guarded([&] {
