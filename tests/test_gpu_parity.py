@@ -297,6 +297,20 @@ def test_batch_equals_alone():
         assert _rel(yy, schwarz.direct_solve(A, b)) <= 1e-6
 
 
+def test_autotune_picks_a_feasible_team_and_keeps_parity():
+    ras = _ras()
+    _say("case: autotune")
+    A = R.laplace2d(90)
+    b = R.uniform_rhs(A.n, 23)
+    h = ras.setup(A, ras.partition("regular_2d", (2, 2), grid=A.grid), 3, ras.local("cg", "fp64", 6))
+    team, ms = h.autotune(_cuda(b), 5)
+    assert team in (1, 2, 4, 8, 16) and ms > 0
+    orc = _oracle(A, "regular_2d", (2, 2), 3, "cg", "fp64", 6)
+    xo, _, _ = orc.sync(b, 0.0, 3)
+    x, _ = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=3)  # team 0 -> the tuned one
+    assert _rel(x.cpu().numpy(), xo) <= 1e-9
+
+
 # ----------------------------------------------------------------------------- full-size sampled checks
 def test_config2_full_size_two_sweeps():
     """1024^2, 8x8 boxes, overlap 4, CG-10 FP64 -- the bench's launch shape."""
