@@ -108,9 +108,12 @@ struct ras_handle {
     int num_cu = 0;
     int solver = 0, storage = 0, cg_iters = 0;
     int max_n = 0, max_w = 0, max_K = 0, uniform_K = 0;
+    int max_w_rowmajor = -1;  // widest band kept row-major (w > kSlabMaxW), -1 if none
+    bool any_slab = false;
     int64_t sum_n = 0;
+    int64_t sum_snap = 0;  // sum over subdomains of n + n_ext (asynchronous snapshot size per right-hand side)
     ras_plan_stats stats{};
-    DevBuf omega, ell_val, ell_valf, ell_gcol, ell_lcol, band_f, band_b, scale, invd;
+    DevBuf omega, ell_val, ell_valf, ell_gcol, ell_lcol, band_f, band_b, scale, invd, ext;
     DevBuf csr_rp, csr_ci, csr_va, nbr;
     std::vector<SubDev> subs;  // host copy with device pointers
     // CG team windows: for team size kTeamSizes[t], per subdomain and member the
@@ -181,6 +184,14 @@ void plan_stats(const Plan& plan, ras_plan_stats* o) {
 
 int64_t n_pad_of(int64_t n) { return (n + 63) / 64 * 64; }
 
+// entries of one stored factor: slab layout (whole blocks of kBandRows rows,
+// w entries per row) for w <= kSlabMaxW, else row-major [n][w + 1]
+int64_t band_elems(int64_t n, int w) {
+    if (w <= kSlabMaxW) return (n + kBandRows - 1) / kBandRows * kBandRows * w;
+    return n * (w + 1);
+}
+constexpr int64_t kSlabTailBytes = 4096;
+
 // Upload the plan: ELL rows of A on every overlapping set, local column map,
 // factors in the storage type (forward L and reversed transpose), global CSR.
 void upload(ras_handle& h, const Plan& plan) {
@@ -197,8 +208,10 @@ void upload(ras_handle& h, const Plan& plan) {
         const int64_t n = static_cast<int64_t>(s.omega.size());
         row_off[p + 1] = row_off[p] + n;
         ell_off[p + 1] = ell_off[p] + n_pad_of(n) * s.ell_width;
-        // 64-element aligned starts (16-byte aligned rows blocks for the direct LDS loads)
-        band_off[p + 1] = band_off[p] + (chol ? (n * (s.w + 1) + 63) / 64 * 64 : 0);
+        // 64-element aligned starts (16-byte aligned blocks for the 16-byte loads)
+        band_off[p + 1] = band_off[p] + (chol ? (band_elems(n, s.w) + 63) / 64 * 64 : 0);
+        if (chol && s.w <= kSlabMaxW) h.any_slab = true;
+        if (chol && s.w > kSlabMaxW) h.max_w_rowmajor = std::max(h.max_w_rowmajor, s.w);
         h.max_n = std::max<int>(h.max_n, static_cast<int>(n));
         h.max_w = std::max(h.max_w, s.w);
         h.max_K = std::max(h.max_K, s.ell_width);
@@ -215,9 +228,9 @@ void upload(ras_handle& h, const Plan& plan) {
     h.ell_gcol.alloc(ell_off[P] * sizeof(int32_t));
     h.ell_lcol.alloc(ell_off[P] * sizeof(int32_t));
     if (chol) {
-        // 1 KB tail: block loads move whole 1 KB pieces and may read past a factor's end
-        h.band_f.alloc(band_off[P] * sts + 1024);
-        h.band_b.alloc(band_off[P] * sts + 1024);
+        // tail: the last load round of a slab block may read up to one round past its end
+        h.band_f.alloc(band_off[P] * sts + kSlabTailBytes);
+        h.band_b.alloc(band_off[P] * sts + kSlabTailBytes);
         h.invd.alloc(row_off[P] * cts);
         if (st == RAS_STORAGE_FP16_ROWSCALED) h.scale.alloc(row_off[P] * sizeof(float));
     }
@@ -233,7 +246,8 @@ void upload(ras_handle& h, const Plan& plan) {
     std::vector<int32_t> om;
     std::vector<double> ev;
     std::vector<float> evf;
-    std::vector<int32_t> eg, el;
+    std::vector<int32_t> eg, el, xe, ext_all;
+    std::vector<int64_t> ext_off{0};
     std::vector<unsigned char> bf, bb, iv;
     std::vector<float> sc;
     for (int p = 0; p < P; ++p) {
@@ -245,7 +259,18 @@ void upload(ras_handle& h, const Plan& plan) {
         for (int64_t i = 0; i < n; ++i) om[i] = s.owned[i] ? s.omega[i] : ~s.omega[i];
         ev.assign(np * K, 0.0);
         eg.assign(np * K, 0);
-        el.assign(np * K, static_cast<int32_t>(n));
+        el.assign(np * K, 0);
+        // external columns: read by omega's rows, outside omega (sorted, unique)
+        xe.clear();
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t g = s.omega[i];
+            for (int64_t e = plan.row_ptr[g]; e < plan.row_ptr[g + 1]; ++e) {
+                const int32_t c = plan.col[e];
+                if (!std::binary_search(s.omega.begin(), s.omega.end(), c)) xe.push_back(c);
+            }
+        }
+        std::sort(xe.begin(), xe.end());
+        xe.erase(std::unique(xe.begin(), xe.end()), xe.end());
         for (int64_t i = 0; i < n; ++i) {
             const int32_t g = s.omega[i];
             int k = 0;
@@ -254,10 +279,18 @@ void upload(ras_handle& h, const Plan& plan) {
                 ev[k * np + i] = plan.val[e];
                 eg[k * np + i] = c;
                 auto it = std::lower_bound(s.omega.begin(), s.omega.end(), c);
-                if (it != s.omega.end() && *it == c) el[k * np + i] = static_cast<int32_t>(it - s.omega.begin());
+                if (it != s.omega.end() && *it == c)
+                    el[k * np + i] = static_cast<int32_t>(it - s.omega.begin());
+                else
+                    el[k * np + i] = static_cast<int32_t>(n + (std::lower_bound(xe.begin(), xe.end(), c) - xe.begin()));
             }
-            for (; k < K; ++k) eg[k * np + i] = g;  // padding: value 0 times the row's own x
+            for (; k < K; ++k) {  // padding: value 0 times the row's own x
+                eg[k * np + i] = g;
+                el[k * np + i] = static_cast<int32_t>(i);
+            }
         }
+        ext_all.insert(ext_all.end(), xe.begin(), xe.end());
+        ext_off.push_back(static_cast<int64_t>(ext_all.size()));
         {
             // per-row reach of the local columns, then the window of every team member
             std::vector<int32_t> rmin(n), rmax(n);
@@ -319,23 +352,35 @@ void upload(ras_handle& h, const Plan& plan) {
         d.row_off = row_off[p];
         if (chol) {
             const int64_t ld = s.w + 1;
+            const int w = s.w;
             const double* L = s.L.data();
-            bf.resize(n * ld * sts);
-            bb.resize(n * ld * sts);
+            const bool slab = w <= kSlabMaxW;
+            const int64_t elems = band_elems(n, w);
+            bf.assign(elems * sts, 0);
+            bb.assign(elems * sts, 0);
             iv.resize(n * cts);
+            // destination index of entry (t, o): row-major [t][o], or slab block
+            // t / BR stored [o][t % BR] (diagonal not stored in the slab)
+            auto dst = [&](int64_t t, int64_t o) -> int64_t {
+                if (!slab) return t * ld + o;
+                const int64_t j = t / kBandRows, r = t % kBandRows;
+                return (j * w + o) * kBandRows + r;
+            };
+            const int64_t olim = slab ? w : ld;
             for (int64_t t = 0; t < n; ++t) {
-                for (int64_t o = 0; o < ld; ++o) {
-                    const int64_t r = (n - 1 - t) + s.w - o;  // row of L read by the reversed transpose
+                for (int64_t o = 0; o < olim; ++o) {
+                    const int64_t r = (n - 1 - t) + w - o;  // row of L read by the reversed transpose
                     const int64_t fi = t * ld + o;
+                    const int64_t di = dst(t, o);
                     if (st == RAS_STORAGE_FP64) {
-                        reinterpret_cast<double*>(bf.data())[fi] = L[fi];
-                        reinterpret_cast<double*>(bb.data())[fi] = r < n ? L[r * ld + o] : 0.0;
+                        reinterpret_cast<double*>(bf.data())[di] = L[fi];
+                        reinterpret_cast<double*>(bb.data())[di] = r < n ? L[r * ld + o] : 0.0;
                     } else if (st == RAS_STORAGE_FP32) {
-                        reinterpret_cast<float*>(bf.data())[fi] = static_cast<float>(L[fi]);
-                        reinterpret_cast<float*>(bb.data())[fi] = r < n ? static_cast<float>(L[r * ld + o]) : 0.0f;
+                        reinterpret_cast<float*>(bf.data())[di] = static_cast<float>(L[fi]);
+                        reinterpret_cast<float*>(bb.data())[di] = r < n ? static_cast<float>(L[r * ld + o]) : 0.0f;
                     } else {
-                        reinterpret_cast<uint16_t*>(bf.data())[fi] = s.Lh[fi];
-                        reinterpret_cast<uint16_t*>(bb.data())[fi] = r < n ? s.Lh[r * ld + o] : 0;
+                        reinterpret_cast<uint16_t*>(bf.data())[di] = s.Lh[fi];
+                        reinterpret_cast<uint16_t*>(bb.data())[di] = r < n ? s.Lh[r * ld + o] : 0;
                     }
                 }
                 // reciprocal of the diagonal as the triangular solves see it
@@ -351,10 +396,11 @@ void upload(ras_handle& h, const Plan& plan) {
                     reinterpret_cast<float*>(iv.data())[t] = static_cast<float>(1.0 / static_cast<double>(deq));
                 }
             }
-            hip_check(hipMemcpy(static_cast<char*>(h.band_f.p) + band_off[p] * sts, bf.data(), n * ld * sts,
+            d.slab = slab ? 1 : 0;
+            hip_check(hipMemcpy(static_cast<char*>(h.band_f.p) + band_off[p] * sts, bf.data(), elems * sts,
                                 hipMemcpyHostToDevice),
                       "copy band_f");
-            hip_check(hipMemcpy(static_cast<char*>(h.band_b.p) + band_off[p] * sts, bb.data(), n * ld * sts,
+            hip_check(hipMemcpy(static_cast<char*>(h.band_b.p) + band_off[p] * sts, bb.data(), elems * sts,
                                 hipMemcpyHostToDevice),
                       "copy band_b");
             hip_check(hipMemcpy(static_cast<char*>(h.invd.p) + row_off[p] * cts, iv.data(), n * cts,
@@ -396,10 +442,26 @@ void upload(ras_handle& h, const Plan& plan) {
             h.subs[p].n_nbr = ptr[p + 1] - ptr[p];
         }
     }
+    // external columns of every subdomain, and the snapshot offsets (n + n_ext per subdomain)
+    {
+        h.ext.alloc(std::max<size_t>(1, ext_all.size()) * sizeof(int32_t));
+        if (!ext_all.empty())
+            hip_check(hipMemcpy(h.ext.p, ext_all.data(), ext_all.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+                      "copy ext");
+        int64_t so = 0;
+        for (int p = 0; p < P; ++p) {
+            h.subs[p].ext = h.ext.as<int32_t>() + ext_off[p];
+            h.subs[p].n_ext = static_cast<int32_t>(ext_off[p + 1] - ext_off[p]);
+            h.subs[p].snap_off = so;
+            so += h.subs[p].n + h.subs[p].n_ext;
+        }
+        h.sum_snap = so;
+    }
     plan_stats(plan, &h.stats);
     h.stats.device_bytes = static_cast<int64_t>(h.omega.bytes + h.ell_val.bytes + h.ell_valf.bytes + h.ell_gcol.bytes +
                                                 h.ell_lcol.bytes + h.band_f.bytes + h.band_b.bytes + h.invd.bytes +
-                                                h.scale.bytes + h.csr_rp.bytes + h.csr_ci.bytes + h.csr_va.bytes);
+                                                h.scale.bytes + h.csr_rp.bytes + h.csr_ci.bytes + h.csr_va.bytes +
+                                                h.ext.bytes);
 }
 
 void drop_factors(Plan& plan) {
@@ -408,18 +470,6 @@ void drop_factors(Plan& plan) {
         std::vector<uint16_t>().swap(s.Lh);
         std::vector<float>().swap(s.scale);
     }
-}
-
-// LDS bytes of a launch over subdomains with at most max_n rows / bandwidth max_w.
-size_t lds_bytes(int solver, int storage, int max_n, int max_w, int* winm) {
-    const size_t cts = ct_size(storage);
-    if (solver == RAS_LOCAL_CG) {
-        *winm = 0;
-        return (static_cast<size_t>(max_n) + 1) * cts;
-    }
-    const int win = next_pow2(max_w + kBandRows + 1);
-    *winm = win - 1;
-    return (static_cast<size_t>(kBandRows) * (max_w + 1) + win) * cts;
 }
 
 constexpr size_t kLdsLimit = 160 * 1024 - 4096;  // leave room for the kernels' static LDS
@@ -464,7 +514,7 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     // kernel configuration: team size T (CG), rows-per-thread class, LDS bytes
     struct Cfg {
         int tidx = -1, T = 1, rclass = 0, winm = 0, per_cu = 0;
-        int band_args[5] = {0, 0, 0, 0, 0};
+        int band_args[3] = {0, 0, 0};
         size_t lds = 0;
         const void* kern = nullptr;
     };
@@ -481,37 +531,25 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
             c.kern = select_kernel(h0.solver, h0.storage, !sync, K, c.rclass);
         } else {
             if (tidx != 0) return c;
-            // pipelined banded solve: three LDS stages of BR rows (+ FP16 scale windows)
-            // and the solution window; BR = 64 if it fits, else 32, else the
-            // unpipelined pass with one stage
-            const size_t sts = h0.storage == RAS_STORAGE_FP64 ? 8 : h0.storage == RAS_STORAGE_FP32 ? 4 : 2;
+            // LDS: slab stages + solution window (2w + 2 blocks, a power of two)
+            // + partial sums, and / or the window + stage of the row-major pass
             const size_t cts = ct_size(h0.storage);
-            c.rclass = 0;
-            for (int br : {64, 32}) {
-                if (br == 64 && h0.storage != RAS_STORAGE_FP32) continue;
-                const size_t stage = (static_cast<size_t>(br) * (max_w + 1) * sts + 1023) / 1024 * 1024;
-                const size_t scw = h0.storage == RAS_STORAGE_FP16_ROWSCALED ? (br + max_w + 63) / 64 * 64 : 0;
-                const int win = next_pow2(max_w + br + 1);
-                const size_t bytes = 3 * stage + 3 * scw * sizeof(float) + static_cast<size_t>(win) * cts;
-                if (bytes <= kLdsLimit) {
-                    c.rclass = br;
-                    c.lds = bytes;
-                    c.winm = win - 1;
-                    c.band_args[2] = 1;
-                    c.band_args[3] = static_cast<int>(stage);
-                    c.band_args[4] = static_cast<int>(scw);
-                    break;
-                }
+            const int sts = h0.storage == RAS_STORAGE_FP64 ? 8 : h0.storage == RAS_STORAGE_FP32 ? 4 : 2;
+            int wrm = -1, wslab = -1;
+            for (ras_handle* h : hs) {
+                wrm = std::max(wrm, h->max_w_rowmajor);
+                if (h->any_slab) wslab = std::max(wslab, std::min(h->max_w, kSlabMaxW));
             }
-            if (c.rclass == 0) {
-                c.rclass = 32;
-                c.lds = lds_bytes(h0.solver, h0.storage, max_n, max_w, &c.winm);
-                c.band_args[2] = 0;
-                c.band_args[3] = 0;
-                c.band_args[4] = 0;
-            }
-            c.band_args[0] = max_w;
+            const int win = next_pow2(2 * max_w + 2 * kBandRows);
+            size_t bytes = 0;
+            if (wslab >= 0) bytes = std::max(bytes, slab_lds_bytes(sts, static_cast<int>(cts), wslab, win));
+            if (wrm >= 0) bytes = std::max(bytes, (static_cast<size_t>(win) + static_cast<size_t>(kBandRows) * (wrm + 1)) * cts);
+            c.rclass = kBandRows;
+            c.winm = win - 1;
+            c.lds = bytes;
+            c.band_args[0] = std::max(wrm, 0);
             c.band_args[1] = c.winm;
+            c.band_args[2] = wslab >= 0 ? static_cast<int>(slab_stage_bytes(sts, wslab)) : 0;
             c.kern = select_kernel(h0.solver, h0.storage, !sync, K, c.rclass);
         }
         if (!c.kern || c.lds > kLdsLimit) {
@@ -578,8 +616,8 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     std::vector<double> cost;
     std::vector<InstDev> insts(ninst);
     int64_t scratch_elems = 0;
-    std::vector<int64_t> scratch_off(ninst), x1_off(ninst);
-    int64_t x1_elems = 0;
+    std::vector<int64_t> scratch_off(ninst), x1_off(ninst), snap_off(ninst);
+    int64_t x1_elems = 0, snap_elems = 0;
     for (int i = 0; i < ninst; ++i) {
         ras_handle* h = specs[i].h;
         const int hk = static_cast<int>(std::find(hs.begin(), hs.end(), h) - hs.begin());
@@ -595,6 +633,8 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
         scratch_elems += h->sum_n;
         x1_off[i] = x1_elems;
         x1_elems += sync ? h->plan->n : 0;
+        snap_off[i] = snap_elems;
+        snap_elems += sync ? 0 : h->sum_snap;
     }
     const int nitems = static_cast<int>(items.size());
 
@@ -675,6 +715,7 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     const size_t o_bar = carve(sizeof(GridBarrier));
     const size_t o_scr = carve(scratch_elems * ct_size(h0.storage));
     const size_t o_x1 = carve(x1_elems * sizeof(double));
+    const size_t o_snap = carve(snap_elems * sizeof(double));
     const size_t o_hist = carve(2 * static_cast<size_t>(ninst) * hist_cap * sizeof(double));
     const int nparts = 512;
     const size_t o_red = carve((2 * nparts + 2) * sizeof(double));
@@ -687,6 +728,7 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
         in.x0 = specs[i].x;
         in.x1 = sync ? reinterpret_cast<double*>(base + o_x1) + x1_off[i] : nullptr;
         in.scratch = base + o_scr + scratch_off[i] * ct_size(h0.storage);
+        in.snap = sync ? nullptr : reinterpret_cast<double*>(base + o_snap) + snap_off[i];
         in.hist = reinterpret_cast<double*>(base + o_hist) + static_cast<size_t>(i) * hist_cap;
         in.hist_t = reinterpret_cast<double*>(base + o_hist) + static_cast<size_t>(ninst + i) * hist_cap;
         in.hist_cap = hist_cap;
@@ -953,11 +995,13 @@ int64_t estimate_device_bytes(const Plan& plan, int nrhs) {
         const int64_t n = static_cast<int64_t>(sd.omega.size());
         sum_n += n;
         const int64_t ell = n_pad_of(n) * sd.ell_width;
-        bytes += 4 * n + ell * (8 + 4 + 4 + (!chol && plan.local.storage == RAS_STORAGE_FP32 ? 4 : 0)) + 512;
-        if (chol) bytes += 2 * ((n * (sd.w + 1) + 63) / 64 * 64) * sts + n * cts + (plan.local.storage == 2 ? 4 * n : 0);
+        bytes += 8 * n + ell * (8 + 4 + 4 + (!chol && plan.local.storage == RAS_STORAGE_FP32 ? 4 : 0)) + 512;
+        if (chol) bytes += 2 * ((band_elems(n, sd.w) + 63) / 64 * 64) * sts + n * cts + (plan.local.storage == 2 ? 4 * n : 0);
     }
-    if (chol) bytes += 2048;
-    bytes += nrhs * (16 * plan.n + sum_n * cts + 2 * 8 * 65536 + 64 * plan.P);
+    if (chol) bytes += 2 * kSlabTailBytes;
+    // per right-hand side: b, x, local vector, x snapshot (omega plus an external layer,
+    // bounded by 2 n_p), history
+    bytes += nrhs * (16 * plan.n + sum_n * cts + 2 * 8 * sum_n + 2 * 8 * 65536 + 64 * plan.P);
     return bytes;
 }
 

@@ -6,6 +6,7 @@
 // items that may come from several systems (batching).
 #pragma once
 
+#include <cstddef>
 #include <cstdint>
 
 namespace ras {
@@ -13,8 +14,35 @@ namespace ras {
 constexpr int kCgThreads = 256;     // workgroup size of the CG kernels
 constexpr int kMaxTeam = 16;        // workgroups cooperating on one subdomain (CG)
 constexpr int kTeamSizes[5] = {1, 2, 4, 8, 16};
-constexpr int kBandThreads = 256;   // workgroup size of the banded-solve kernels
+constexpr int kBandThreads = 512;   // workgroup size of the banded-solve kernels
 constexpr int kBandRows = 32;       // rows per block of the banded triangular solves
+// Block-transposed ("slab") factor layout, used for half-bandwidths up to
+// kSlabMaxW: the factor is cut into blocks of kBandRows rows and block j is
+// stored as the dense array S_j[o][r] = L[j*kBandRows + r][o] (o < w: the w
+// sub-diagonal offsets of the row, r < kBandRows: the row in the block), zero
+// for rows past n; the diagonal is kept apart as its reciprocal.  One block
+// is w * kBandRows contiguous entries, so a wavefront reading a fixed o for
+// consecutive r touches consecutive addresses.
+constexpr int kSlabMaxW = 144;
+constexpr int kSlabFarWaves = 4;    // waves of the off-diagonal sums
+constexpr int kSlabLead[3] = {2, 3, 4};  // blocks in flight: FP64, FP32, FP16 storage
+constexpr int kSlabWinTail = 16;    // mirrored slots after the solution window
+// row stride (compute-type entries) of the near + triangle buffer: 2 blocks
+// of columns plus padding that keeps 16-byte rows aligned and spreads the
+// rows of a wavefront over the LDS banks
+constexpr int slab_nt_stride(int compute_bytes) { return 2 * kBandRows + (compute_bytes == 8 ? 2 : 4); }
+// LDS bytes of the slab pass: stages of (factor block + 512 bytes of row
+// data), solution window + mirrored tail, near + triangle entries [2][rows][stride], row
+// data [2][3][rows], far partial sums [2][waves][rows], results [2][rows]
+inline size_t slab_stage_bytes(int storage_bytes, int max_w) {
+    return (static_cast<size_t>(kBandRows) * max_w * storage_bytes + 1023) / 1024 * 1024;
+}
+inline size_t slab_lds_bytes(int storage_bytes, int compute_bytes, int max_w, int win) {
+    const int lead = kSlabLead[storage_bytes == 8 ? 0 : storage_bytes == 4 ? 1 : 2];
+    const size_t elems = static_cast<size_t>(win) + kSlabWinTail + 2 * kBandRows * slab_nt_stride(compute_bytes) + 2 * 3 * kBandRows +
+                         2 * kSlabFarWaves * kBandRows + 2 * kBandRows;
+    return (lead + 1) * (slab_stage_bytes(storage_bytes, max_w) + 512) + elems * compute_bytes;
+}
 constexpr int kMaxItemsPerWg = 1024;  // work items one workgroup may own
 
 // Static data of one subdomain (setup output, Sec. 3.2.2 / Sec. 3.3.1).
@@ -23,16 +51,21 @@ struct SubDev {
     const double* ell_val;    // [K][n_pad] values of A's rows on omega (float64)
     const float* ell_valf;    // [K][n_pad] float32 copy (CG with FP32 storage), else null
     const int32_t* ell_gcol;  // [K][n_pad] global column (padding: the row's own g)
-    const int32_t* ell_lcol;  // [K][n_pad] local column in omega; n for external columns and padding
-    const void* band_f;       // [n][w+1] factor L, row-major lower band, storage type
-    const void* band_b;       // [n][w+1] reversed transpose J L^T J, same layout
+    const int32_t* ell_lcol;  // [K][n_pad] slot of the column: local index in omega (< n), or
+                              // n + position in ext for an external column; padding: the row itself
+    const void* band_f;       // factor L: slab layout if slab, else [n][w+1] row-major lower band
+    const void* band_b;       // reversed transpose J L^T J, same layout as band_f
     const float* scale;       // [n] FP16 row scale of L (null otherwise)
     const void* invd;         // [n] 1 / L_ii in the local compute type
     int32_t n, n_pad, K, w;
     int64_t row_off;          // offset of this subdomain in per-RHS scratch vectors
     const int32_t* nbr;       // [n_nbr] subdomains (of the same system) owning a point this one reads
     int32_t n_nbr;
-    int32_t pad_;
+    int32_t slab;             // 1: band_f / band_b in the slab layout (w <= kSlabMaxW)
+    const int32_t* ext;       // [n_ext] global ids of the columns outside omega that omega's rows read
+    int32_t n_ext;
+    int32_t pad2_;
+    int64_t snap_off;         // offset of this subdomain's x snapshot (n + n_ext values) per right-hand side
 };
 
 // One work item: subdomain `sub` of right-hand side (instance) `inst`.
@@ -47,6 +80,8 @@ struct InstDev {
     double* x0;               // [n] caller's x (initial guess in, result out)
     double* x1;               // [n] second buffer (synchronous mode)
     void* scratch;            // [sum n_p] local vector in the compute type (CG: exchanged residual, band: solve vector)
+    double* snap;             // asynchronous: [sum (n_p + n_ext_p)] x on omega and its external layer, as one
+                              // update read it (every row and the prolongation use these values); else null
     double* hist;             // [hist_cap] relative residual history
     double* hist_t;           // [hist_cap] seconds since start
     int64_t hist_cap;

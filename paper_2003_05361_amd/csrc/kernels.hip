@@ -33,6 +33,7 @@ namespace ras {
 // ------------------------------------------------------------------------------ helpers
 
 #define RAS_GLOBAL __attribute__((address_space(1)))
+#define RAS_LDS __attribute__((address_space(3)))
 
 // Uniform (SGPR) copies of 32/64-bit values loaded from memory.
 __device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -59,6 +60,9 @@ struct SubU {
     const void* invd;
     int32_t n, n_pad, K, w;
     int64_t row_off;
+    RAS_GLOBAL int32_t* ext;
+    int32_t n_ext;
+    int64_t snap_off;
 };
 
 __device__ __forceinline__ SubU load_sub(const SubDev* p) {
@@ -78,6 +82,9 @@ __device__ __forceinline__ SubU load_sub(const SubDev* p) {
     s.K = uni(d.K);
     s.w = uni(d.w);
     s.row_off = uni64(d.row_off);
+    s.ext = gptr(d.ext);
+    s.n_ext = uni(d.n_ext);
+    s.snap_off = uni64(d.snap_off);
     return s;
 }
 
@@ -87,6 +94,7 @@ struct InstU {
     RAS_GLOBAL double* x0;
     RAS_GLOBAL double* x1;
     void* scratch;
+    RAS_GLOBAL double* snap;
 };
 
 __device__ __forceinline__ InstU load_inst(const InstDev* p) {
@@ -96,6 +104,7 @@ __device__ __forceinline__ InstU load_inst(const InstDev* p) {
     u.x0 = gptr(d.x0);
     u.x1 = gptr(d.x1);
     u.scratch = reinterpret_cast<void*>(uni64(reinterpret_cast<int64_t>(d.scratch)));
+    u.snap = gptr(d.snap);
     return u;
 }
 
@@ -326,6 +335,58 @@ __device__ __forceinline__ double row_residual(const SubU& s, RAS_GLOBAL double*
     return acc;
 }
 
+// Asynchronous updates read x once.  A residual row reads a neighbour-owned
+// value of x that other rows read too; should those reads see different
+// versions (the owner updates meanwhile), the exact cancellation in the local
+// solve no longer holds and the iteration can diverge, while one version per
+// value (any version) keeps it convergent (Sec. 2.1: each subdomain works on
+// a local copy of the values it receives).  So an update first copies x on
+// omega and its external layer into a snapshot (slots: omega's local order,
+// then the external columns), and the residual and the prolongation read
+// only the snapshot.  Team members fill disjoint slices with device-scope
+// stores; everything reads the snapshot with device-scope loads.
+__device__ __forceinline__ void take_snapshot(const SubU& s, RAS_GLOBAL double* x, RAS_GLOBAL double* xs, int lo,
+                                              int hi, int nthreads) {
+    for (int k = lo + static_cast<int>(threadIdx.x); k < hi; k += nthreads) {
+        int32_t g;
+        if (k < s.n) {
+            const int32_t e = s.omega[k];
+            g = e >= 0 ? e : ~e;
+        } else {
+            g = s.ext[k - s.n];
+        }
+        stg_dev(xs + k, ldx<true>(x + g));
+    }
+}
+
+// b - A x for local row i, x from the snapshot
+template <int KT>
+__device__ __forceinline__ double row_residual_snap(const SubU& s, RAS_GLOBAL double* b, RAS_GLOBAL double* xs,
+                                                    int i, bool& owned, double& bg) {
+    const int32_t e = s.omega[i];
+    owned = e >= 0;
+    const int32_t g = owned ? e : ~e;
+    bg = b[g];
+    double acc = bg;
+    if constexpr (KT > 0) {
+        int32_t c[KT];
+        double a[KT];
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+            c[k] = (s.ell_lcol + static_cast<uint32_t>(k * s.n_pad))[static_cast<uint32_t>(i)];
+            a[k] = (s.ell_val + static_cast<uint32_t>(k * s.n_pad))[static_cast<uint32_t>(i)];
+        }
+#pragma unroll
+        for (int k = 0; k < KT; ++k) acc -= a[k] * ldg_dev(xs + c[k]);
+    } else {
+        for (int k = 0; k < s.K; ++k) {
+            const uint32_t idx = static_cast<uint32_t>(k * s.n_pad + i);
+            acc -= s.ell_val[idx] * ldg_dev(xs + s.ell_lcol[idx]);
+        }
+    }
+    return acc;
+}
+
 // ------------------------------------------------------------------------------ CG update
 // Local solve by `cg_iters` steps of Hestenes-Stiefel CG from zero on A_p (the
 // local rows and columns of A; external columns read a zero LDS slot), by a
@@ -367,6 +428,15 @@ struct CgUpdate {
         uint32_t ownbits = 0;
         double o2 = 0.0, l2 = 0.0, bb = 0.0;
         CT rr = CT(0);
+        RAS_GLOBAL double* xs = nullptr;
+        if constexpr (ASYNC) {
+            xs = in.snap + s.snap_off;
+            const int m = n + s.n_ext;
+            take_snapshot(s, xin, xs, static_cast<int>(static_cast<int64_t>(tc.member) * m / T),
+                          static_cast<int>(static_cast<int64_t>(tc.member + 1) * m / T), B);
+            __builtin_amdgcn_s_waitcnt(0);
+            team_barrier(tc);
+        }
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int i = lo + tid + j * B;
@@ -376,7 +446,11 @@ struct CgUpdate {
             if (i < hi) {
                 double bg;
                 bool ow;
-                const double ri = row_residual<KT, ASYNC>(s, in.b, xin, i, ow, bg);
+                double ri;
+                if constexpr (ASYNC)
+                    ri = row_residual_snap<KT>(s, in.b, xs, i, ow, bg);
+                else
+                    ri = row_residual<KT, false>(s, in.b, xin, i, ow, bg);
                 l2 += ri * ri;
                 bb += bg * bg;
                 if (ow) {
@@ -430,12 +504,12 @@ struct CgUpdate {
                             a[k] = (vit + static_cast<uint32_t>(k * s.n_pad))[static_cast<uint32_t>(i)];
                         }
 #pragma unroll
-                        for (int k = 0; k < KT; ++k) acc += a[k] * pl[c[k] == n ? zs : c[k] - wlo];
+                        for (int k = 0; k < KT; ++k) acc += a[k] * pl[c[k] >= n ? zs : c[k] - wlo];
                     } else {
                         for (int k = 0; k < s.K; ++k) {
                             const uint32_t idx = static_cast<uint32_t>(k * s.n_pad + i);
                             const int c = cit[idx];
-                            acc += vit[idx] * pl[c == n ? zs : c - wlo];
+                            acc += vit[idx] * pl[c >= n ? zs : c - wlo];
                         }
                     }
                     q[j] = acc;
@@ -482,7 +556,10 @@ struct CgUpdate {
             const int i = lo + tid + j * B;
             if (i < hi && ((ownbits >> j) & 1u)) {
                 const int32_t g = s.omega[i];
-                stx<ASYNC>(xout + g, ldx<ASYNC>(xin + g) + static_cast<double>(d[j]));
+                if constexpr (ASYNC)
+                    stx<true>(xout + g, ldg_dev(xs + i) + static_cast<double>(d[j]));
+                else
+                    stx<false>(xout + g, xin[g] + static_cast<double>(d[j]));
             }
         }
     }
@@ -584,137 +661,416 @@ __device__ void band_pass(RAS_GLOBAL ST* Lb, RAS_GLOBAL float* scale, bool rev,
     }
 }
 
-// Pipelined variant of band_pass.  Waves 1..3 are loaders: loader k owns LDS
-// stage k-1 and streams the blocks b = k-1 (mod 3) of the factor into it with
-// direct global-to-LDS loads (global_load_lds_dwordx4, 1 KB per wave
-// instruction, no registers), then hands the stage over through an LDS flag.
-// Wave 0 consumes the blocks in order: per row (one lane per row) the GEMV
-// against the LDS solution window, then the BR x BR diagonal triangle with
-// register-held entries and lane broadcasts.  Factor streaming thus overlaps
-// the sequential chain.  FP16 entries are dequantised on use with the row
-// scale of L (forward: the lane's row; backward: the L row of each entry, from
-// a per-stage scale window loaded with the block).
+// ---- banded solves in the slab layout ---------------------------------------------
+// Row t of a block (t = t0 + r) needs sum_o L[t][o] y[t - w + o] over its w
+// sub-diagonal entries.  Split by column: "far" columns lie at least two
+// blocks back, "near" columns in the previous block, "triangle" columns in
+// the block itself.  Far sums of block j only need blocks <= j - 2, so they
+// are computed one step ahead of the solver.  Per step (one workgroup
+// barrier) the eight waves of the workgroup do:
+//   wave 0          solver: near GEMV (a lane per row) and the sequential
+//                   triangle of block j - 1, lane broadcasts by readlane;
+//   waves 1,2,3,5   block j: far sums from its LDS stage, and a copy of its
+//                   near + triangle entries (zero outside the band) and row
+//                   data into a row-major buffer the solver reads in 16-byte
+//                   pieces without masks;
+//   waves 4,6       loaders: block j + D of the factor and its row data
+//                   (right-hand side, 1/diagonal, FP16 scale) streamed from
+//                   HBM straight into an LDS stage (global_load_lds, no
+//                   registers), then a wait for the block due next step;
+//   wave 7          store: results of block j - 2 to the local vector.
+// Only loaders and the store wave touch global memory, so the LDS reads of
+// the other waves never wait for memory; the loaders read no LDS, so their
+// in-flight blocks are never drained by a wait the compiler places before
+// an LDS access (the store wave reads LDS through an opaque instruction).
+// Synchronisation inside a pass is a plain s_barrier after the LDS counter
+// drains: no memory fence.
 template <class ST>
-struct Deq;
-template <>
-struct Deq<double> {
-    __device__ __forceinline__ static double get(const unsigned char* st, int idx) {
-        return reinterpret_cast<const double*>(st)[idx];
-    }
-};
-template <>
-struct Deq<float> {
-    __device__ __forceinline__ static float get(const unsigned char* st, int idx) {
-        return reinterpret_cast<const float*>(st)[idx];
-    }
-};
-template <>
-struct Deq<_Float16> {
-    __device__ __forceinline__ static float get(const unsigned char* st, int idx) {
-        return static_cast<float>(reinterpret_cast<const _Float16*>(st)[idx]);
-    }
+struct SlabCfg {
+    using CT = typename StorageTraits<ST>::CT;
+    static constexpr int BR = kBandRows;
+    static constexpr int SZ = static_cast<int>(sizeof(ST));
+    static constexpr int E = 16 / SZ;                             // entries per 16-byte read
+    static constexpr int RT = BR / E;                             // lanes covering one o of a block
+    static constexpr int FT = kSlabFarWaves * 64;                 // far threads
+    static constexpr int OPC = FT * E / BR;                       // o values per far round
+    static constexpr int D = kSlabLead[SZ == 8 ? 0 : SZ == 4 ? 1 : 2];  // blocks in flight
+    static constexpr int S = D + 1;                               // LDS stages
+    static constexpr int QMAX = (kSlabMaxW * BR * SZ + 1023) / 1024;   // 1 KB pieces of a block
+    static constexpr int QH = (QMAX + 1) / 2;                     // pieces per loader wave
+    static constexpr int QW = QH + 1;                             // + one row-data load
+    static constexpr int NTS = slab_nt_stride(static_cast<int>(sizeof(CT)));  // near/triangle row stride
+    static constexpr int CV = 16 / static_cast<int>(sizeof(CT));  // compute-type entries per 16 bytes
+    static constexpr int KF = (kSlabMaxW - BR + 7) / 8;           // far columns per thread, widest band
+    static_assert(KF <= kSlabWinTail, "mirrored window tail");
+    static_assert((D - 1) * QW <= 63, "vmcnt range");
+    static_assert(FT == BR * 8, "one far thread per 8 near/triangle entries");
 };
 
-template <class ST, int BR>
-__device__ void band_pass_dma(RAS_GLOBAL ST* Lb, RAS_GLOBAL float* scale, bool rev,
-                              RAS_GLOBAL typename StorageTraits<ST>::CT* invd, int n, int w,
-                              RAS_GLOBAL typename StorageTraits<ST>::CT* v, unsigned char* stages, int stage_bytes,
-                              float* scw, int scw_stride, typename StorageTraits<ST>::CT* win, int winm, int* flags) {
-    using CT = typename StorageTraits<ST>::CT;
-    constexpr bool kHalf = StorageTraits<ST>::kHalf;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int ld = w + 1;
-    const int nblk = (n + BR - 1) / BR;
-    if (tid < 3) flags[tid] = 0;
-    __syncthreads();
-    if (wave > 0) {
-        const int s = wave - 1;
-        unsigned char* dst = stages + s * stage_bytes;
-        for (int b = s; b < nblk; b += 3) {
-            while (__hip_atomic_load(flags + s, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != 0)
-                __builtin_amdgcn_s_sleep(1);
-            const int t0 = b * BR;
-            const int rows = min(BR, n - t0);
-            const int bytes = rows * ld * static_cast<int>(sizeof(ST));
-            const RAS_GLOBAL unsigned char* src =
-                reinterpret_cast<const RAS_GLOBAL unsigned char*>(Lb + static_cast<int64_t>(t0) * ld);
-            for (int q = 0; q * 1024 < bytes; ++q)
-                __builtin_amdgcn_global_load_lds(src + q * 1024 + lane * 16,
-                                                 (__attribute__((address_space(3))) void*)(dst + q * 1024), 16, 0, 0);
-            if constexpr (kHalf) {
-                if (rev) {  // scales of L rows n - t0 - BR + k, k in [0, BR + w)
-                    const int rlo = n - t0 - BR;
-                    float* sw = scw + s * scw_stride;
-                    for (int q = 0; q * 64 < BR + w; ++q) {
-                        const int r = min(max(rlo + q * 64 + lane, 0), n - 1);
-                        __builtin_amdgcn_global_load_lds(scale + r, (__attribute__((address_space(3))) void*)(sw + q * 64),
-                                                         4, 0, 0);
-                    }
-                }
-            }
-            __builtin_amdgcn_s_waitcnt(0);
-            __hip_atomic_store(flags + s, b + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-    } else {
-        for (int b = 0; b < nblk; ++b) {
-            const int s = b % 3;
-            while (__hip_atomic_load(flags + s, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != b + 1)
-                __builtin_amdgcn_s_sleep(1);
-            const unsigned char* L = stages + s * stage_bytes;
-            const float* sw = scw + s * scw_stride;
-            const int t0 = b * BR;
-            const int rows = min(BR, n - t0);
-            const int l = lane;
-            const int t = t0 + l;
-            const bool act = l < BR && l < rows;
-            CT rs = CT(1);
-            if constexpr (kHalf)
-                if (!rev && act) rs = scale[t];
-            auto entry = [&](int o) -> CT {
-                CT e = static_cast<CT>(Deq<ST>::get(L, l * ld + o));
-                if constexpr (kHalf) e *= rev ? static_cast<CT>(sw[BR - 1 - l + w - o]) : rs;
-                return e;
-            };
-            CT acc = CT(0);
-            if (act) {
-                const int olo = max(0, w - t);
-                const int ohi = w - l;
-                for (int o = olo; o < ohi; ++o) acc += entry(o) * win[(t - w + o) & winm];
-            }
-            const int vi = rev ? n - 1 - t : t;
-            CT val = act ? static_cast<CT>(v[vi] - acc) : CT(0);
-            const CT dinv = act ? invd[vi] : CT(0);
-            CT Ld[BR];
-#pragma unroll
-            for (int m = 0; m < BR; ++m) Ld[m] = (act && m < l && m >= l - w) ? entry(w - l + m) : CT(0);
-            CT y = CT(0);
-#pragma unroll
-            for (int m = 0; m < BR; ++m) {
-                const CT ym = __shfl(val * dinv, m, 64);
-                if (l == m) y = ym;
-                val -= Ld[m] * ym;
-            }
-            if (act) {
-                v[vi] = y;
-                win[t & winm] = y;
-            }
-            __hip_atomic_store(flags + s, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-    }
-    __syncthreads();
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// wait until at most N vector-memory operations of this wave are outstanding
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N <= 63, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-template <class ST, int BR, bool ASYNC>
+// LDS reads the compiler does not see as such (no memory wait is placed in front)
+__device__ __forceinline__ double lds_opaque(const RAS_LDS double* p) {
+    double r;
+    asm volatile("ds_read_b64 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(r) : "v"(p) : "memory");
+    return r;
+}
+__device__ __forceinline__ float lds_opaque(const RAS_LDS float* p) {
+    float r;
+    asm volatile("ds_read_b32 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(r) : "v"(p) : "memory");
+    return r;
+}
+
+template <class ST>
+__device__ __forceinline__ typename StorageTraits<ST>::CT lds_entry(const RAS_LDS unsigned char* p) {
+    if constexpr (sizeof(ST) == 2)
+        return static_cast<float>(*reinterpret_cast<const RAS_LDS _Float16*>(p));
+    else
+        return *reinterpret_cast<const RAS_LDS ST*>(p);
+}
+
+// the 16 / sizeof(ST) entries of one 16-byte read, in the compute type
+template <class ST>
+__device__ __forceinline__ void unpack(const u32x4& q, typename StorageTraits<ST>::CT* e) {
+    const uint32_t wv[4] = {q[0], q[1], q[2], q[3]};
+#pragma unroll
+    for (int u = 0; u < 16 / static_cast<int>(sizeof(ST)); ++u) {
+        if constexpr (sizeof(ST) == 8) {
+            e[u] = __builtin_bit_cast(double, (static_cast<uint64_t>(wv[2 * u + 1]) << 32) | wv[2 * u]);
+        } else if constexpr (sizeof(ST) == 4) {
+            e[u] = __builtin_bit_cast(float, wv[u]);
+        } else {
+            const uint16_t hb = static_cast<uint16_t>(wv[u / 2] >> (16 * (u & 1)));
+            e[u] = static_cast<float>(__builtin_bit_cast(_Float16, hb));
+        }
+    }
+}
+
+// 16 bytes of compute-type entries from LDS
+__device__ __forceinline__ void lds_vec(const RAS_LDS double* p, double* out) {
+    const f64x2 q = *reinterpret_cast<const RAS_LDS f64x2*>(p);
+    out[0] = q[0];
+    out[1] = q[1];
+}
+__device__ __forceinline__ void lds_vec(const RAS_LDS float* p, float* out) {
+    const f32x4 q = *reinterpret_cast<const RAS_LDS f32x4*>(p);
+    out[0] = q[0];
+    out[1] = q[1];
+    out[2] = q[2];
+    out[3] = q[3];
+}
+
+__device__ __forceinline__ float lane_value(float v, int m) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), m));
+}
+__device__ __forceinline__ double lane_value(double v, int m) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(b), m));
+    const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(b >> 32), m));
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// One triangular pass (forward with L, or backward with the reversed
+// transpose when rev) over a factor in the slab layout.  LDS:
+//   stages [S][stage_bytes + 512]: factor block, then row data (FP64: rhs
+//     [BR], 1/diag [BR]; otherwise rhs [BR], 1/diag [BR], scale [BR]);
+//   solution window [winm + 1];
+//   near + triangle entries [2][BR][NTS] (row r: near columns c < BR of the
+//     previous block, then triangle columns BR + m, zero outside the band);
+//   row data [2][3][BR]; far partial sums [2][waves][BR]; results [2][BR].
+template <class ST>
+struct SlabPass {
+    using C = SlabCfg<ST>;
+    using CT = typename C::CT;
+    static constexpr int BR = C::BR, E = C::E, RT = C::RT, OPC = C::OPC, S = C::S, D = C::D, NTS = C::NTS,
+                         CV = C::CV;
+    static constexpr bool kHalf = StorageTraits<ST>::kHalf;
+    static constexpr int kRowBytes = 512;
+
+    RAS_GLOBAL const unsigned char* slab;
+    RAS_GLOBAL CT* invd;
+    RAS_GLOBAL float* scale;
+    RAS_GLOBAL CT* v;
+    RAS_LDS unsigned char* stages;
+    RAS_LDS CT* win;
+    RAS_LDS CT* nt;
+    RAS_LDS CT* rowd;
+    RAS_LDS CT* part;
+    RAS_LDS CT* yout;
+    int stage_bytes, n, w, winm, nblk, qlast;
+    bool rev;
+    int lane, wave;
+
+    __device__ __forceinline__ RAS_LDS unsigned char* stage(int j) const {
+        return stages + (j % S) * (stage_bytes + kRowBytes);
+    }
+    __device__ __forceinline__ int row_index(int t) const { return rev ? n - 1 - t : t; }
+
+    // loader k (0 or 1): its pieces of block j (clamped into the factor) and one row-data load
+    __device__ __forceinline__ void load_block(int k, int j) {
+        const int jj = min(j, nblk - 1);
+        RAS_LDS unsigned char* st = stage(j);
+        RAS_GLOBAL const unsigned char* src = slab + static_cast<int64_t>(jj) * w * BR * C::SZ + lane * 16;
+#pragma unroll
+        for (int i = 0; i < C::QH; ++i) {
+            const int q = min(2 * i + k, qlast);
+            __builtin_amdgcn_global_load_lds(src + q * 1024, (RAS_LDS void*)(st + q * 1024), 16, 0, 0);
+        }
+        RAS_LDS unsigned char* rw = st + stage_bytes;
+        if constexpr (sizeof(CT) == 8) {
+            // two dwords per row: lane l carries half l & 1 of row l >> 1
+            const int t = min(jj * BR + (lane >> 1), n - 1);
+            const RAS_GLOBAL unsigned char* a =
+                reinterpret_cast<const RAS_GLOBAL unsigned char*>(k == 0 ? v + row_index(t) : invd + row_index(t));
+            __builtin_amdgcn_global_load_lds(a + 4 * (lane & 1), (RAS_LDS void*)(rw + k * 256), 4, 0, 0);
+        } else {
+            const int t = min(jj * BR + (lane & (BR - 1)), n - 1);
+            const int i = row_index(t);
+            const RAS_GLOBAL void* a;
+            if (k == 0 || !kHalf)
+                a = lane < BR ? static_cast<const RAS_GLOBAL void*>(v + i) : static_cast<const RAS_GLOBAL void*>(invd + i);
+            else
+                a = scale + i;
+            __builtin_amdgcn_global_load_lds(a, (RAS_LDS void*)(rw + (k == 0 || !kHalf ? 0 : 256)), 4, 0, 0);
+        }
+    }
+
+    // far thread f of 4 * 64: far sums, near + triangle entries and row data
+    // of block j.  Every LDS read is issued before the first write, so the
+    // reads are in flight together.
+    __device__ __forceinline__ void far_work(int f, int j) {
+        const RAS_LDS unsigned char* st = stage(j);
+        const int t0 = j * BR;
+        // far sums: thread (row r = f % BR, part p = f / BR) takes the columns
+        // o in [p K, p K + K) of row r that lie two or more blocks back
+        // (o < w - BR - r).  Consecutive o are one stage row apart and read
+        // consecutive window slots (the window has a mirrored tail, so a run
+        // of K slots never wraps).
+        const int fr = f % BR;
+        const int fp = f / BR;
+        const int fw = w - BR;
+        const int K = (max(fw, 0) + 7) / 8;
+        const int ob = fp * K;
+        const RAS_LDS unsigned char* sp = st + (min(ob, w - 1) * BR + fr) * C::SZ;
+        const RAS_LDS CT* wp = win + ((t0 + fr - w + ob) & winm);
+        CT fe[C::KF], fy[C::KF];
+#pragma unroll
+        for (int k = 0; k < C::KF; ++k) {
+            if (k < K) {
+                fe[k] = lds_entry<ST>(sp + k * BR * C::SZ);
+                fy[k] = wp[k];
+            }
+        }
+        // near + triangle entries: thread (r = f % BR, d = f / BR) copies the
+        // entries at o = w - 2 BR + 1 + d + 8 k (k < 8), i.e. column
+        // c = o - (w - BR) + r of row r; a fixed o over consecutive r is a
+        // contiguous stage row.  Columns c < 0 belong to the far sums; the
+        // slots c >= BR + r (diagonal and above) stay zero from the pass start.
+        const int rr = f % BR;
+        const int d = f / BR;
+        CT ntv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int o = w - 2 * BR + 1 + d + 8 * k;
+            ntv[k] = lds_entry<ST>(st + (max(min(o, w - 1), 0) * BR + rr) * C::SZ);
+        }
+        CT rdv[3];
+        if (f < BR) {
+            const RAS_LDS unsigned char* rw = st + stage_bytes;
+            if constexpr (sizeof(CT) == 8) {
+                rdv[0] = reinterpret_cast<const RAS_LDS CT*>(rw)[f];
+                rdv[1] = reinterpret_cast<const RAS_LDS CT*>(rw + 256)[f];
+                rdv[2] = CT(1);
+            } else {
+                rdv[0] = reinterpret_cast<const RAS_LDS CT*>(rw)[f];
+                rdv[1] = reinterpret_cast<const RAS_LDS CT*>(rw)[BR + f];
+                rdv[2] = kHalf ? reinterpret_cast<const RAS_LDS CT*>(rw + 256)[f] : CT(1);
+            }
+        }
+        CT acc0 = CT(0), acc1 = CT(0);
+#pragma unroll
+        for (int k = 0; k < C::KF; k += 2) {
+            if (k < K) acc0 += (ob + k < fw - fr ? fe[k] : CT(0)) * fy[k];
+            if (k + 1 < C::KF && k + 1 < K) acc1 += (ob + k + 1 < fw - fr ? fe[k + 1] : CT(0)) * fy[k + 1];
+        }
+        CT acc = acc0 + acc1;
+        RAS_LDS CT* dst = nt + (j & 1) * BR * NTS + rr * NTS;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int o = w - 2 * BR + 1 + d + 8 * k;
+            const int c = o - (w - BR) + rr;
+            if (c >= 0 && o < w) dst[c] = o >= 0 ? ntv[k] : CT(0);
+        }
+        if (f < BR) {
+            RAS_LDS CT* rd = rowd + (j & 1) * 3 * BR + f;
+            rd[0] = rdv[0];
+            rd[BR] = rdv[1];
+            rd[2 * BR] = rdv[2];
+        }
+        acc += __shfl_xor(acc, 32, 64);  // the two parts of row fr in this wave
+        if (lane < BR) part[((j & 1) * kSlabFarWaves + f / 64) * BR + fr] = acc;
+    }
+
+    __device__ __forceinline__ void solve_block(int j) {
+        if (lane >= BR) return;
+        const int t0 = j * BR;
+        const int r = lane;
+        const RAS_LDS CT* rd = rowd + (j & 1) * 3 * BR + r;
+        const CT vin = rd[0], dinv = rd[BR], sc = rd[2 * BR];
+        const RAS_LDS CT* pb = part + (j & 1) * kSlabFarWaves * BR + r;
+        CT fsum = pb[0];
+#pragma unroll
+        for (int k = 1; k < kSlabFarWaves; ++k) fsum += pb[k * BR];
+        const RAS_LDS CT* ntr = nt + (j & 1) * BR * NTS + r * NTS;
+        // near columns: entries of row r times the previous block's results
+        // (the window slots t0 - BR .. t0 - 1 are contiguous and aligned)
+        const RAS_LDS CT* yp = win + ((t0 - BR) & winm);
+        // all reads first (the triangle entries too), so they are in flight together
+        CT e[BR], yb[BR], tri[BR];
+#pragma unroll
+        for (int c = 0; c < BR; c += CV) {
+            lds_vec(ntr + c, e + c);
+            lds_vec(yp + c, yb + c);
+        }
+#pragma unroll
+        for (int m = 0; m < BR; m += CV) lds_vec(ntr + BR + m, tri + m);
+        asm volatile("" ::: "memory");
+        CT a[4] = {CT(0), CT(0), CT(0), CT(0)};
+#pragma unroll
+        for (int c = 0; c < BR; ++c) a[c & 3] += e[c] * yb[c];
+        const CT nsum = (a[0] + a[1]) + (a[2] + a[3]);
+        CT u, g;
+        if constexpr (kHalf) {
+            if (!rev) {
+                g = sc * dinv;
+                u = (vin - sc * (fsum + nsum)) * dinv;
+            } else {
+                g = dinv * sc;
+                u = (vin - (fsum + nsum)) * g;
+            }
+        } else {
+            g = dinv;
+            u = (vin - (fsum + nsum)) * g;
+        }
+        CT Ld[BR];
+#pragma unroll
+        for (int m = 0; m < BR; ++m) Ld[m] = tri[m] * g;
+        // lane m's value is final once steps 0 .. m - 1 are done; entries
+        // with m >= r are zero, so later steps leave it unchanged
+#pragma unroll
+        for (int m = 0; m < BR - 1; ++m) u -= Ld[m] * lane_value(u, m);
+        const int t = t0 + r;
+        CT y = u;
+        if constexpr (kHalf)
+            if (rev) y = u / sc;
+        yout[(j & 1) * BR + r] = y;
+        const int slot = t & winm;
+        const CT wv = t < n ? u : CT(0);
+        win[slot] = wv;
+        if (slot < C::KF) win[winm + 1 + slot] = wv;  // mirrored tail
+    }
+
+    __device__ __forceinline__ void store_block(int j) {
+        const int t = j * BR + lane;
+        if (lane < BR && t < n) v[row_index(t)] = lds_opaque(yout + (j & 1) * BR + lane);
+    }
+
+    __device__ __forceinline__ void run() {
+        const int tid = threadIdx.x;
+        for (int i = tid; i <= winm + kSlabWinTail; i += kBandThreads) win[i] = CT(0);
+        for (int i = tid; i < 2 * BR * NTS; i += kBandThreads) nt[i] = CT(0);
+        __syncthreads();
+        const bool loader = wave == 4 || wave == 6;
+        const int lk = wave == 4 ? 0 : 1;
+        const int far = wave >= 1 && wave <= 3 ? wave - 1 : wave == 5 ? 3 : -1;
+        if (loader) {
+            for (int j = 0; j < D; ++j) load_block(lk, j);
+            wait_vm<(D - 1) * C::QW>();  // block 0 has landed
+        }
+        lds_barrier();
+        // step j: solver on block j - 1, far work on block j, loads of block
+        // j + D (into the stage block j - 1 used), stores of block j - 2
+        for (int j = 0; j <= nblk + 1; ++j) {
+            if (wave == 0) {
+                if (j >= 1 && j <= nblk) solve_block(j - 1);
+            } else if (far >= 0) {
+                if (j < nblk) far_work(far * 64 + lane, j);
+            } else if (loader) {
+                load_block(lk, j + D);
+                wait_vm<(D - 1) * C::QW>();  // block j + 1 has landed
+            } else {
+                if (j >= 2) store_block(j - 2);
+            }
+            lds_barrier();
+        }
+        if (loader || wave == 7) wait_vm<0>();
+        __syncthreads();
+    }
+};
+
+// One pass, out of line: one copy serves both passes, and the pass state is
+// a local here (registers), its pressure separate from the update around it.
+template <class ST>
+__device__ __attribute__((noinline)) void slab_run(RAS_GLOBAL const unsigned char* slab,
+                                                   RAS_GLOBAL typename StorageTraits<ST>::CT* invd,
+                                                   RAS_GLOBAL float* scale, RAS_GLOBAL typename StorageTraits<ST>::CT* v,
+                                                   RAS_LDS unsigned char* lds, int stage_bytes, int n, int w, int winm,
+                                                   bool rev) {
+    using C = SlabCfg<ST>;
+    using CT = typename C::CT;
+    SlabPass<ST> ps;
+    ps.slab = slab;
+    ps.invd = invd;
+    ps.scale = scale;
+    ps.v = v;
+    ps.stages = lds;
+    ps.win = (RAS_LDS CT*)(lds + C::S * (stage_bytes + SlabPass<ST>::kRowBytes));
+    ps.nt = ps.win + (winm + 1 + kSlabWinTail);
+    ps.rowd = ps.nt + 2 * C::BR * C::NTS;
+    ps.part = ps.rowd + 2 * 3 * C::BR;
+    ps.yout = ps.part + 2 * kSlabFarWaves * C::BR;
+    ps.stage_bytes = stage_bytes;
+    ps.n = n;
+    ps.w = w;
+    ps.winm = winm;
+    ps.nblk = (n + C::BR - 1) / C::BR;
+    ps.qlast = max((w * C::BR * C::SZ + 1023) / 1024 - 1, 0);  // last 1 KB piece of a block
+    ps.rev = rev;
+    ps.lane = threadIdx.x & 63;
+    ps.wave = uni(static_cast<int>(threadIdx.x >> 6));
+    ps.run();
+}
+
+template <class ST>
+__device__ __forceinline__ void slab_solve(const SubU& s, RAS_GLOBAL typename StorageTraits<ST>::CT* v,
+                                           unsigned char* lds, int winm, int stage_bytes) {
+    using CT = typename StorageTraits<ST>::CT;
+    RAS_GLOBAL CT* invd = gptr(static_cast<const CT*>(s.invd));
+    RAS_LDS unsigned char* l = (RAS_LDS unsigned char*)(lds);
+    slab_run<ST>(gptr(static_cast<const unsigned char*>(s.band_f)), invd, s.scale, v, l, stage_bytes, s.n, s.w, winm,
+                 false);
+    slab_run<ST>(gptr(static_cast<const unsigned char*>(s.band_b)), invd, s.scale, v, l, stage_bytes, s.n, s.w, winm,
+                 true);
+}
+
+template <class ST, bool ASYNC>
 struct BandUpdate {
     using CT = typename StorageTraits<ST>::CT;
     static constexpr int B = kBandThreads;
-    int max_w;
-    int winm;
-    int pipelined;    // 1: band_pass_dma (three LDS stages of BR rows), 0: band_pass
-    int stage_bytes;  // bytes per LDS stage (pipelined)
-    int scw_stride;   // floats per scale-window stage (pipelined FP16)
+    int max_w;        // widest row-major band of the launch (unpipelined pass stage)
+    int winm;         // solution window size - 1
+    int stage_bytes;  // slab pass: bytes of one factor block stage
 
     __device__ __forceinline__ void operator()(const Params& P, TeamCtx& tc, const ItemDev& item,
                                                RAS_GLOBAL double* xin, RAS_GLOBAL double* xout, double& own2,
@@ -723,8 +1079,8 @@ struct BandUpdate {
         extern __shared__ __align__(16) unsigned char smem[];
         __shared__ double red3[3 * (B / 64)];
         __shared__ CT gsum[kBandRows];
-        __shared__ int flags[4];
         const SubU s = load_sub(P.subs + item.sub);
+        const int slab = uni(P.subs[item.sub].slab);
         const InstU in = load_inst(P.insts + item.inst);
         const int tid = threadIdx.x;
         const int n = s.n;
@@ -732,36 +1088,48 @@ struct BandUpdate {
         own2 = 0.0;
         loc2 = 0.0;
         b2 = 0.0;
+        RAS_GLOBAL double* xs = nullptr;
+        if constexpr (ASYNC) {
+            xs = in.snap + s.snap_off;
+            take_snapshot(s, xin, xs, 0, n + s.n_ext, B);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        }
         for (int i = tid; i < n; i += B) {
             bool owned;
             double bg;
-            const double ri = row_residual<0, ASYNC>(s, in.b, xin, i, owned, bg);
+            double ri;
+            if constexpr (ASYNC)
+                ri = row_residual_snap<0>(s, in.b, xs, i, owned, bg);
+            else
+                ri = row_residual<0, false>(s, in.b, xin, i, owned, bg);
             loc2 += ri * ri;
             b2 += bg * bg;
             if (owned) own2 += ri * ri;
             v[i] = static_cast<CT>(ri);
         }
+        // the loaders read v back through global-to-LDS loads
+        __builtin_amdgcn_s_waitcnt(0);
         block_sum3<B>(own2, loc2, b2, red3);
-        RAS_GLOBAL ST* Lf = gptr(static_cast<const ST*>(s.band_f));
-        RAS_GLOBAL ST* Lr = gptr(static_cast<const ST*>(s.band_b));
-        RAS_GLOBAL CT* iv = gptr(static_cast<const CT*>(s.invd));
-        if (pipelined) {
-            unsigned char* stages = smem;
-            float* scw = reinterpret_cast<float*>(smem + 3 * stage_bytes);
-            CT* win = reinterpret_cast<CT*>(smem + 3 * stage_bytes + 3 * scw_stride * sizeof(float));
-            band_pass_dma<ST, BR>(Lf, s.scale, false, iv, n, s.w, v, stages, stage_bytes, scw, scw_stride, win, winm,
-                                  flags);
-            band_pass_dma<ST, BR>(Lr, s.scale, true, iv, n, s.w, v, stages, stage_bytes, scw, scw_stride, win, winm,
-                                  flags);
+        if (slab) {
+            slab_solve<ST>(s, v, smem, winm, stage_bytes);
         } else {
-            CT* stage = reinterpret_cast<CT*>(smem);   // [kBandRows][max_w + 1]
-            CT* win = stage + kBandRows * (max_w + 1);  // [winm + 1]
+            RAS_GLOBAL ST* Lf = gptr(static_cast<const ST*>(s.band_f));
+            RAS_GLOBAL ST* Lr = gptr(static_cast<const ST*>(s.band_b));
+            RAS_GLOBAL CT* iv = gptr(static_cast<const CT*>(s.invd));
+            CT* win = reinterpret_cast<CT*>(smem);   // [winm + 1]
+            CT* stage = win + (winm + 1);             // [kBandRows][max_w + 1]
             band_pass<ST>(Lf, s.scale, false, iv, n, s.w, v, stage, win, winm, gsum);
             band_pass<ST>(Lr, s.scale, true, iv, n, s.w, v, stage, win, winm, gsum);
         }
         for (int i = tid; i < n; i += B) {
             const int32_t e = s.omega[i];
-            if (e >= 0) stx<ASYNC>(xout + e, ldx<ASYNC>(xin + e) + static_cast<double>(v[i]));
+            if (e >= 0) {
+                if constexpr (ASYNC)
+                    stx<true>(xout + e, ldg_dev(xs + i) + static_cast<double>(v[i]));
+                else
+                    stx<false>(xout + e, xin[e] + static_cast<double>(v[i]));
+            }
         }
     }
 };
@@ -882,6 +1250,13 @@ __device__ __forceinline__ void run_async(const Params& P, U& upd, TeamCtx& tc, 
             double own2, loc2, b2;
             const InstU iu = load_inst(P.insts + item.inst);
             upd(P, tc, item, iu.x0, iu.x0, own2, loc2, b2);
+            // The update wrote x[owned] = x[owned] + delta, delta computed from the
+            // owned values this workgroup read in its residual.  The next residual
+            // must read these stores, not older values still in flight (a
+            // workgroup barrier does not wait for outstanding stores), or the
+            // next correction would be added to a newer value than it was
+            // computed from, i.e. counted twice.
+            __builtin_amdgcn_s_waitcnt(0);
             team_barrier(tc);  // every member's part of x is written (and fenced) before the publish
             if (tid == 0 && tc.member == 0) {
                 st_rlx(P.res2_own + it, own2);
@@ -952,13 +1327,12 @@ __global__ void __launch_bounds__(kCgThreads) cg_kernel(Params P) {
         run_sync<kCgThreads>(P, upd, tc, red, done);
 }
 
-template <class ST, int BR, bool ASYNC>
-__global__ void __launch_bounds__(kBandThreads)
-    band_kernel(Params P, int max_w, int winm, int pipelined, int stage_bytes, int scw_stride) {
+template <class ST, bool ASYNC>
+__global__ void __launch_bounds__(kBandThreads) band_kernel(Params P, int max_w, int winm, int stage_bytes) {
     __shared__ double red[kBandThreads / 64];
     __shared__ int8_t done[kMaxItemsPerWg];
     TeamCtx tc = make_team(P);
-    BandUpdate<ST, BR, ASYNC> upd{max_w, winm, pipelined, stage_bytes, scw_stride};
+    BandUpdate<ST, ASYNC> upd{max_w, winm, stage_bytes};
     if constexpr (ASYNC)
         run_async<kBandThreads>(P, upd, tc, red, done);
     else
@@ -1055,18 +1429,10 @@ const void* cg_kernel_for(int kt, int r) {
     return cg_kernel_r<CT, 0, ASYNC>(r);
 }
 
-// 64-row blocks only for float32 storage: with float64 entries or float16
-// dequantisation the 64-entry diagonal row no longer fits in registers
 template <class ST>
-const void* band_kernel_for(bool async, int br) {
-    if constexpr (std::is_same<ST, float>::value) {
-        if (br == 64)
-            return async ? reinterpret_cast<const void*>(band_kernel<ST, 64, true>)
-                         : reinterpret_cast<const void*>(band_kernel<ST, 64, false>);
-    }
-    if (br != 32) return nullptr;
-    return async ? reinterpret_cast<const void*>(band_kernel<ST, 32, true>)
-                 : reinterpret_cast<const void*>(band_kernel<ST, 32, false>);
+const void* band_kernel_for(bool async) {
+    return async ? reinterpret_cast<const void*>(band_kernel<ST, true>)
+                 : reinterpret_cast<const void*>(band_kernel<ST, false>);
 }
 }  // namespace
 
@@ -1083,9 +1449,10 @@ const void* select_kernel(int solver, int storage, bool async, int ell_width, in
             return async ? cg_kernel_for<double, true>(ell_width, rclass) : cg_kernel_for<double, false>(ell_width, rclass);
         return async ? cg_kernel_for<float, true>(ell_width, rclass) : cg_kernel_for<float, false>(ell_width, rclass);
     }
-    if (storage == 0) return band_kernel_for<double>(async, rclass);
-    if (storage == 1) return band_kernel_for<float>(async, rclass);
-    return band_kernel_for<_Float16>(async, rclass);
+    (void)rclass;
+    if (storage == 0) return band_kernel_for<double>(async);
+    if (storage == 1) return band_kernel_for<float>(async);
+    return band_kernel_for<_Float16>(async);
 }
 
 hipError_t launch_solver(const void* kern, int solver, const Params& P, const int* band_args, size_t lds,
@@ -1101,8 +1468,8 @@ hipError_t launch_solver(const void* kern, int solver, const Params& P, const in
         return coop ? hipLaunchCooperativeKernel(kern, grid, block, args, lds, st)
                     : hipLaunchKernel(kern, grid, block, args, lds, st);
     }
-    int a0 = band_args[0], a1 = band_args[1], a2 = band_args[2], a3 = band_args[3], a4 = band_args[4];
-    void* args[] = {&p, &a0, &a1, &a2, &a3, &a4};
+    int a0 = band_args[0], a1 = band_args[1], a2 = band_args[2];
+    void* args[] = {&p, &a0, &a1, &a2};
     return coop ? hipLaunchCooperativeKernel(kern, grid, block, args, lds, st)
                 : hipLaunchKernel(kern, grid, block, args, lds, st);
 }
