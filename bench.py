@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--no-sync", action="store_true", help="skip the synchronous comparison (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 2 GiB device copy (hardware-counter calibration)")
+    ap.add_argument("--sweeps", type=int, default=0,
+                    help="fixed-sweep throughput mode: time N sweeps (synchronous) and N local solves per "
+                         "subdomain (asynchronous) instead of solving to the tolerance; value = sweep GB/s")
     ap.add_argument("--serve-count", type=int, default=200, help="systems in the serving stream")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     return ap.parse_args()
@@ -232,6 +235,77 @@ def serving_bench(args):
     }
     print(json.dumps(line), flush=True)
 
+def sweep_bench(args, A, b, h, bt, bps, st, stream, kind, storage, k, tol, gamma, part_kind, part_arg, setup_s):
+    """Fixed work: N synchronous sweeps, and N local solves per subdomain of the
+    asynchronous kernel (tolerance 0, so nothing stops early).  Sweep bandwidth =
+    algorithmic bytes of the local solves done / kernel time (HIP events on the
+    solve stream around the launches)."""
+    import numpy as np
+    import torch
+
+    N = args.sweeps
+
+    def run(mode, n):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        x, info = h.solve(bt, tol=0.0, mode=mode, max_sweeps=n)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return info[0], e0.elapsed_time(e1) * 1e-3, h.local_solve_counts()
+
+    for _ in range(args.warmup):
+        run("async", max(1, N // 10))
+        run("sync", max(1, N // 10))
+    t0 = time.perf_counter()
+    ar = [run("async", N) for _ in range(args.steps)]
+    wall = time.perf_counter() - t0
+    sr = [run("sync", N) for _ in range(args.steps)]
+    a_bytes = [float(np.dot(c, bps)) for _, _, c in ar]
+    a_gbps = float(np.mean([bb / i["kernel_seconds"] for bb, (i, _, _) in zip(a_bytes, ar)])) / 1e9
+    # the synchronous kernel computes one speculative update after the last sweep
+    s_bytes = [float((i["sweeps"] + 1) * bps.sum()) for i, _, _ in sr]
+    s_gbps = float(np.mean([bb / i["kernel_seconds"] for bb, (i, _, _) in zip(s_bytes, sr)])) / 1e9
+    workload = args.workload
+    traffic = traffic_from_profiles(f"{workload}_sweeps{N}", float(np.mean(a_bytes)))
+    line = {
+        "metric": METRIC,
+        "value": a_gbps,
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / max(1, args.steps),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if storage == "fp64" else f"f64 outer / {storage} local",
+        "data": "synthetic",
+        "config": {"workload": workload, "n": int(A.n), "subdomains": int(st["parts"]), "overlap": gamma,
+                   "local": f"{kind}{k if kind == 'cg' else ''}-{storage}", "mode": "fixed sweeps",
+                   "sweeps": N},
+        "async": {"GBps": a_gbps, "kernel_seconds": float(np.mean([i["kernel_seconds"] for i, _, _ in ar])),
+                  "local_solves_total": int(ar[-1][0]["total_local_solves"]),
+                  "ms_per_sweep_equivalent": 1e3 * float(np.mean([i["kernel_seconds"] for i, _, _ in ar])) * int(st["parts"])
+                  / max(1, int(ar[-1][0]["total_local_solves"]))},
+        "sync": {"GBps": s_gbps, "kernel_seconds": float(np.mean([i["kernel_seconds"] for i, _, _ in sr])),
+                 "ms_per_sweep": 1e3 * float(np.mean([i["kernel_seconds"] / (i["sweeps"] + 1) for i, _, _ in sr]))},
+        "setup_s": setup_s,
+        "roofline": {"bound": "hbm", "achieved": round(a_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(a_gbps / HBM_PEAK_GBPS, 4),
+                     "traffic": None if traffic is None else float(traffic),
+                     "kernel": f"persistent async {kind}{'-' + str(k) if kind == 'cg' else ''} {storage}",
+                     "algorithmic_bytes_per_launch": float(np.mean(a_bytes)),
+                     "kernel_seconds_per_launch": float(np.mean([i["kernel_seconds"] for i, _, _ in ar]))},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(A, b, part_kind, part_arg, gamma, kind, storage, k, N)
+        cb["unit"] = f"s for {N} synchronous sweeps (extrapolated)"
+        line["cpu_baseline"] = cb
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -288,6 +362,10 @@ def main():
         torch.cuda.synchronize()
         counts = h.local_solve_counts()
         return x, info[0], e0.elapsed_time(e1) * 1e-3, counts
+
+    if args.sweeps > 0:
+        sweep_bench(args, A, b, h, bt, bps, st, stream, kind, storage, k, tol, gamma, part_kind, part_arg, setup_s)
+        return
 
     for _ in range(args.warmup):
         solve("async")

@@ -208,7 +208,8 @@ ras_status ras_residual_history(const ras_handle* h, int32_t rhs, double* t_sec,
 ras_status ras_local_solve_counts(const ras_handle* h, int32_t rhs, int64_t* counts);
 ras_status ras_partition_sets(const ras_handle* h, int32_t* owner, int64_t* omega_ptr, int32_t* omega_idx);
 /* Autotuner: times `sweeps` synchronous sweeps from x = 0 for every feasible CG
- * team size (workgroups per subdomain) and keeps the fastest in the handle (used
+ * team size (workgroups per subdomain), twice each (the faster timing counts:
+ * a kernel variant's first launch carries one-time costs), and keeps the fastest in the handle (used
  * when ras_solve_opts.team is 0) and in a process-wide cache keyed by the
  * problem shape, so later handles of the same shape start tuned.  x_dev is
  * overwritten (work space).  best_team / best_ms_per_sweep may be NULL.  The

@@ -1494,28 +1494,35 @@ ras_status ras_autotune(ras_handle* h, const double* b_dev, double* x_dev, int32
         int best = 1;
         double best_ms = INFINITY;
         if (h->solver == RAS_LOCAL_CG) {
-            for (int t = 0; t < 5; ++t) {
-                const int T = kTeamSizes[t];
-                ras_solve_opts o{};
-                o.mode = RAS_MODE_SYNC;
-                o.tol = 0.0;
-                o.max_sweeps = sweeps;
-                o.team = T;
-                hip_check(hipMemsetAsync(x_dev, 0, h->plan->n * sizeof(double), h->stream), "clear x");
-                std::vector<InstSpec> specs{InstSpec{h, b_dev, x_dev, 0}};
-                ras_solve_info info{};
-                try {
-                    run_solve(specs, o, &info);
-                } catch (const Error& e) {
-                    if (e.status == RAS_E_UNSUPPORTED) continue;  // infeasible team size for this shape
-                    throw;
-                }
-                const double ms = 1e3 * info.kernel_seconds / (sweeps + 1);
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = T;
+            // two rounds over the feasible team sizes, the faster of each size's two
+            // timings counts (the first launch of a kernel variant carries one-time costs)
+            double ms_of[5] = {INFINITY, INFINITY, INFINITY, INFINITY, INFINITY};
+            for (int round = 0; round < 2; ++round) {
+                for (int t = 0; t < 5; ++t) {
+                    const int T = kTeamSizes[t];
+                    if (round == 1 && !(ms_of[t] < INFINITY)) continue;
+                    ras_solve_opts o{};
+                    o.mode = RAS_MODE_SYNC;
+                    o.tol = 0.0;
+                    o.max_sweeps = sweeps;
+                    o.team = T;
+                    hip_check(hipMemsetAsync(x_dev, 0, h->plan->n * sizeof(double), h->stream), "clear x");
+                    std::vector<InstSpec> specs{InstSpec{h, b_dev, x_dev, 0}};
+                    ras_solve_info info{};
+                    try {
+                        run_solve(specs, o, &info);
+                    } catch (const Error& e) {
+                        if (e.status == RAS_E_UNSUPPORTED) continue;  // infeasible team size for this shape
+                        throw;
+                    }
+                    ms_of[t] = std::min(ms_of[t], 1e3 * info.kernel_seconds / (sweeps + 1));
                 }
             }
+            for (int t = 0; t < 5; ++t)
+                if (ms_of[t] < best_ms) {
+                    best_ms = ms_of[t];
+                    best = kTeamSizes[t];
+                }
             h->tuned_team = best;
             std::lock_guard<std::mutex> lk(g_tune_mu);
             g_tune[{h->plan->n, h->plan->P, h->max_n, h->uniform_K, h->storage, h->cg_iters}] = best;
