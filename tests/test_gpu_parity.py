@@ -184,6 +184,53 @@ def test_sync_band_storage_matches_oracle(storage, tol):
     assert info[0]["converged"] and info[0]["rel_residual"] < 1e-8
 
 
+# band widths around the slab kernel's block structure (32-row blocks): near
+# columns partly outside the band (w < 63), far columns present, the widest slab
+# band (<= 144), and the row-major pass (w > 144)
+@pytest.mark.parametrize("case,storage,tol", [
+    ("2d70_w36", "fp64", 1e-9), ("2d100_w52", "fp32", 2e-5), ("3d16_w97", "fp64", 1e-9),
+    ("3d20_w141", "fp64", 1e-9), ("3d20_w141", "fp16", 2e-5), ("3d24_w193", "fp64", 1e-9), ("3d24_w193", "fp32", 2e-5)])
+def test_sync_band_widths_match_oracle(case, storage, tol):
+    ras = _ras()
+    _say(f"case: band width {case} {storage}")
+    A, part, gamma = {
+        "2d70_w36": (R.laplace2d(70), ("regular_2d", (2, 1)), 1),
+        "2d100_w52": (R.laplace2d(100), ("regular_2d", (2, 2)), 2),
+        "3d16_w97": (R.laplace3d(16), ("regular_3d", (2, 2, 2)), 2),
+        "3d20_w141": (R.laplace3d(20), ("regular_3d", (2, 2, 1)), 2),
+        "3d24_w193": (R.laplace3d(24), ("regular_3d", (2, 2, 1)), 2),
+    }[case]
+    b = R.uniform_rhs(A.n, 21)
+    orc = _oracle(A, *part, gamma, "chol", storage)
+    h = ras.setup(A, _spec(ras, A, *part), gamma, ras.local("chol", storage))
+    w_expect = int(case.split("_w")[1])
+    assert h.stats()["max_band"] == w_expect
+    for sweeps in (1, 2):
+        xo, ho, _ = orc.sync(b, 0.0, sweeps)
+        x, _ = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=sweeps)
+        assert _rel(x.cpu().numpy(), xo) <= tol
+
+
+def test_async_banded_runs_converge_every_time():
+    """Regression: asynchronous banded runs on many concurrent workgroups converge
+    in every repeat, with a bounded number of local solves (every update works on
+    one snapshot of the values it reads)."""
+    ras = _ras()
+    _say("case: async banded repeats")
+    A = R.laplace2d(96)
+    b = R.uniform_rhs(A.n, 16)
+    xd = schwarz.direct_solve(A, b)
+    for st in ("fp64", "fp32"):
+        h = ras.setup(A, ras.partition("regular_2d", (4, 4), grid=A.grid), 3, ras.local("chol", st))
+        for rep in range(5):
+            x, info = h.solve(_cuda(b), tol=1e-10, mode="async", max_sweeps=5000, max_seconds=60)
+            xx = x.cpu().numpy()
+            assert info[0]["converged"], info
+            assert info[0]["max_local_solves"] < 2000, info
+            assert schwarz.relative_residual(A, xx, b) < 1e-10
+            assert _rel(xx, xd) <= 1e-8
+
+
 def test_single_subdomain_is_direct_solve():
     ras = _ras()
     _say("case: one subdomain")

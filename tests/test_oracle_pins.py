@@ -397,3 +397,47 @@ def test_low_precision_local_solves_reach_tolerance(storage):
     x, hist, k = schwarz.RAS(A, owner, 2, "chol", storage).sync(b, 1e-8, 20000)
     assert hist[-1] < 1e-8
     assert np.linalg.norm(x - ref[0]) <= 1e-5 * np.linalg.norm(ref[0])
+
+
+# ------------------------------------------- P12: an asynchronous update reads each value once
+def _async_reads(ras, b, consistent, staleness, updates, seed):
+    """Asynchronous RAS with exact local solves where every update reads other
+    subdomains' values from the last `staleness` iterates: either one version per
+    value for the whole update (consistent), or a version per row entry (a value
+    read by several rows may be seen at different times)."""
+    rng = np.random.default_rng(seed)
+    M = ras.M.tocsr()
+    x = np.zeros(M.shape[0])
+    hist = [x]
+    for _ in range(updates):
+        p = int(rng.integers(ras.P))
+        s = ras.subs[p]
+        sub = M[s.omega]
+        H = np.array(hist)
+        L = len(hist)
+        if consistent:
+            ver = rng.integers(0, L, M.shape[0])[sub.indices]
+        else:
+            ver = rng.integers(0, L, sub.nnz)
+        vals = H[L - 1 - ver, sub.indices]
+        vals = np.where(ras.owner[sub.indices] == p, x[sub.indices], vals)
+        r = b[s.omega] - np.add.reduceat(sub.data * vals, sub.indptr[:-1])
+        x = x.copy()
+        x[s.owned] += s.solver(r)[s.pos]
+        hist = (hist + [x])[-staleness:]
+    return np.linalg.norm(b - M @ x) / np.linalg.norm(b)
+
+
+def test_async_update_must_read_each_value_once():
+    """Reading: an asynchronous subdomain update works on one copy of the values
+    it receives (Sec. 2.1), i.e. every row of its residual sees the same version
+    of a neighbour's value.  With exact local solves, per-entry versions break the
+    cancellation the local solve relies on and the iteration diverges under deep
+    staleness, while one version per value converges (the library takes a
+    snapshot per update for this reason)."""
+    A = R.laplace2d(24)
+    b = R.uniform_rhs(A.n, 3)
+    ras = schwarz.RAS(A, partition.regular_grid(A.grid, (4, 4)), 2, "chol")
+    for seed in (0, 1):
+        assert _async_reads(ras, b, True, 48, 3000, seed) < 1e-5
+        assert _async_reads(ras, b, False, 48, 3000, seed) > 1e3
