@@ -339,7 +339,8 @@ def main():
 
     cfg_name, kind, storage, k = WORKLOADS[args.workload]
     A, b, cfg = R.config_problem(cfg_name)
-    part_kind, part_arg = cfg["partition"]
+    part_kind, *part_rest = cfg["partition"]
+    part_arg = part_rest[0] if len(part_rest) == 1 else tuple(part_rest)
     gamma = cfg["overlap"]
     tol = cfg["tol"]
     stream = torch.cuda.current_stream()

@@ -25,6 +25,7 @@ constexpr int kBandRows = 32;       // rows per block of the banded triangular s
 // consecutive r touches consecutive addresses.
 constexpr int kSlabMaxW = 144;
 constexpr int kSlabFarWaves = 4;    // waves of the off-diagonal sums
+constexpr int kSlabParts = 2 * kSlabFarWaves;  // far partial sums per row (one per half-wave)
 constexpr int kSlabLead[3] = {2, 3, 4};  // blocks in flight: FP64, FP32, FP16 storage
 constexpr int kSlabWinTail = 16;    // mirrored slots after the solution window
 // row stride (compute-type entries) of the near + triangle buffer: 2 blocks
@@ -33,14 +34,14 @@ constexpr int kSlabWinTail = 16;    // mirrored slots after the solution window
 constexpr int slab_nt_stride(int compute_bytes) { return 2 * kBandRows + (compute_bytes == 8 ? 2 : 4); }
 // LDS bytes of the slab pass: stages of (factor block + 512 bytes of row
 // data), solution window + mirrored tail, near + triangle entries [2][rows][stride], row
-// data [2][3][rows], far partial sums [2][waves][rows], results [2][rows]
+// data [2][3][rows], far partial sums [2][parts][rows], results [2][rows]
 inline size_t slab_stage_bytes(int storage_bytes, int max_w) {
     return (static_cast<size_t>(kBandRows) * max_w * storage_bytes + 1023) / 1024 * 1024;
 }
 inline size_t slab_lds_bytes(int storage_bytes, int compute_bytes, int max_w, int win) {
     const int lead = kSlabLead[storage_bytes == 8 ? 0 : storage_bytes == 4 ? 1 : 2];
     const size_t elems = static_cast<size_t>(win) + kSlabWinTail + 2 * kBandRows * slab_nt_stride(compute_bytes) + 2 * 3 * kBandRows +
-                         2 * kSlabFarWaves * kBandRows + 2 * kBandRows;
+                         2 * kSlabParts * kBandRows + 2 * kBandRows;
     return (lead + 1) * (slab_stage_bytes(storage_bytes, max_w) + 512) + elems * compute_bytes;
 }
 constexpr int kMaxItemsPerWg = 1024;  // work items one workgroup may own

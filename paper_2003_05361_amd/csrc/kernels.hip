@@ -788,7 +788,7 @@ __device__ __forceinline__ double lane_value(double v, int m) {
 //   solution window [winm + 1];
 //   near + triangle entries [2][BR][NTS] (row r: near columns c < BR of the
 //     previous block, then triangle columns BR + m, zero outside the band);
-//   row data [2][3][BR]; far partial sums [2][waves][BR]; results [2][BR].
+//   row data [2][3][BR]; far partial sums [2][parts][BR]; results [2][BR].
 template <class ST>
 struct SlabPass {
     using C = SlabCfg<ST>;
@@ -811,6 +811,7 @@ struct SlabPass {
     int stage_bytes, n, w, winm, nblk, qlast;
     bool rev;
     int lane, wave;
+    CT uprev;  // solver wave: the previous block's results (lane r: row r)
 
     __device__ __forceinline__ RAS_LDS unsigned char* stage(int j) const {
         return stages + (j % S) * (stage_bytes + kRowBytes);
@@ -862,15 +863,14 @@ struct SlabPass {
         const int fw = w - BR;
         const int K = (max(fw, 0) + 7) / 8;
         const int ob = fp * K;
-        const RAS_LDS unsigned char* sp = st + (min(ob, w - 1) * BR + fr) * C::SZ;
         const RAS_LDS CT* wp = win + ((t0 + fr - w + ob) & winm);
+        // a fixed number of reads, addresses clamped into range, masks in arithmetic:
+        // no branch between the reads, so they are in flight together
         CT fe[C::KF], fy[C::KF];
 #pragma unroll
         for (int k = 0; k < C::KF; ++k) {
-            if (k < K) {
-                fe[k] = lds_entry<ST>(sp + k * BR * C::SZ);
-                fy[k] = wp[k];
-            }
+            fe[k] = lds_entry<ST>(st + (max(min(ob + k, w - 1), 0) * BR + fr) * C::SZ);
+            fy[k] = wp[k];
         }
         // near + triangle entries: thread (r = f % BR, d = f / BR) copies the
         // entries at o = w - 2 BR + 1 + d + 8 k (k < 8), i.e. column
@@ -901,16 +901,17 @@ struct SlabPass {
         CT acc0 = CT(0), acc1 = CT(0);
 #pragma unroll
         for (int k = 0; k < C::KF; k += 2) {
-            if (k < K) acc0 += (ob + k < fw - fr ? fe[k] : CT(0)) * fy[k];
-            if (k + 1 < C::KF && k + 1 < K) acc1 += (ob + k + 1 < fw - fr ? fe[k + 1] : CT(0)) * fy[k + 1];
+            acc0 += (k < K && ob + k < fw - fr ? fe[k] : CT(0)) * fy[k];
+            if (k + 1 < C::KF) acc1 += (k + 1 < K && ob + k + 1 < fw - fr ? fe[k + 1] : CT(0)) * fy[k + 1];
         }
-        CT acc = acc0 + acc1;
+        const CT acc = acc0 + acc1;
         RAS_LDS CT* dst = nt + (j & 1) * BR * NTS + rr * NTS;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int o = w - 2 * BR + 1 + d + 8 * k;
             const int c = o - (w - BR) + rr;
-            if (c >= 0 && o < w) dst[c] = o >= 0 ? ntv[k] : CT(0);
+            // slots outside the row's near + triangle range go to an unread padding column
+            dst[(c >= 0 && o < w) ? c : 2 * BR] = o >= 0 ? ntv[k] : CT(0);
         }
         if (f < BR) {
             RAS_LDS CT* rd = rowd + (j & 1) * 3 * BR + f;
@@ -918,8 +919,7 @@ struct SlabPass {
             rd[BR] = rdv[1];
             rd[2 * BR] = rdv[2];
         }
-        acc += __shfl_xor(acc, 32, 64);  // the two parts of row fr in this wave
-        if (lane < BR) part[((j & 1) * kSlabFarWaves + f / 64) * BR + fr] = acc;
+        part[((j & 1) * kSlabParts + fp) * BR + fr] = acc;
     }
 
     __device__ __forceinline__ void solve_block(int j) {
@@ -928,27 +928,35 @@ struct SlabPass {
         const int r = lane;
         const RAS_LDS CT* rd = rowd + (j & 1) * 3 * BR + r;
         const CT vin = rd[0], dinv = rd[BR], sc = rd[2 * BR];
-        const RAS_LDS CT* pb = part + (j & 1) * kSlabFarWaves * BR + r;
+        const RAS_LDS CT* pb = part + (j & 1) * kSlabParts * BR + r;
         CT fsum = pb[0];
 #pragma unroll
-        for (int k = 1; k < kSlabFarWaves; ++k) fsum += pb[k * BR];
+        for (int k = 1; k < kSlabParts; ++k) fsum += pb[k * BR];
         const RAS_LDS CT* ntr = nt + (j & 1) * BR * NTS + r * NTS;
-        // near columns: entries of row r times the previous block's results
-        // (the window slots t0 - BR .. t0 - 1 are contiguous and aligned)
-        const RAS_LDS CT* yp = win + ((t0 - BR) & winm);
         // all reads first (the triangle entries too), so they are in flight together
-        CT e[BR], yb[BR], tri[BR];
+        CT e[BR], tri[BR];
 #pragma unroll
-        for (int c = 0; c < BR; c += CV) {
-            lds_vec(ntr + c, e + c);
-            lds_vec(yp + c, yb + c);
-        }
+        for (int c = 0; c < BR; c += CV) lds_vec(ntr + c, e + c);
 #pragma unroll
         for (int m = 0; m < BR; m += CV) lds_vec(ntr + BR + m, tri + m);
         asm volatile("" ::: "memory");
+        // near columns: entries of row r times the previous block's results.  Four-
+        // byte compute types read them from the window (contiguous aligned slots, all
+        // lanes reading the same address); FP64 takes them from the lanes of this
+        // wave that computed them (uprev, zero before the first block), which keeps
+        // 64 registers free
         CT a[4] = {CT(0), CT(0), CT(0), CT(0)};
+        if constexpr (sizeof(CT) == 4) {
+            const RAS_LDS CT* yp = win + ((t0 - BR) & winm);
+            CT yb[BR];
 #pragma unroll
-        for (int c = 0; c < BR; ++c) a[c & 3] += e[c] * yb[c];
+            for (int c = 0; c < BR; c += CV) lds_vec(yp + c, yb + c);
+#pragma unroll
+            for (int c = 0; c < BR; ++c) a[c & 3] += e[c] * yb[c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < BR; ++c) a[c & 3] += e[c] * lane_value(uprev, c);
+        }
         const CT nsum = (a[0] + a[1]) + (a[2] + a[3]);
         CT u, g;
         if constexpr (kHalf) {
@@ -974,6 +982,7 @@ struct SlabPass {
         CT y = u;
         if constexpr (kHalf)
             if (rev) y = u / sc;
+        uprev = t < n ? u : CT(0);
         yout[(j & 1) * BR + r] = y;
         const int slot = t & winm;
         const CT wv = t < n ? u : CT(0);
@@ -991,6 +1000,7 @@ struct SlabPass {
         for (int i = tid; i <= winm + kSlabWinTail; i += kBandThreads) win[i] = CT(0);
         for (int i = tid; i < 2 * BR * NTS; i += kBandThreads) nt[i] = CT(0);
         __syncthreads();
+        uprev = CT(0);
         const bool loader = wave == 4 || wave == 6;
         const int lk = wave == 4 ? 0 : 1;
         const int far = wave >= 1 && wave <= 3 ? wave - 1 : wave == 5 ? 3 : -1;
@@ -1039,7 +1049,7 @@ __device__ __attribute__((noinline)) void slab_run(RAS_GLOBAL const unsigned cha
     ps.nt = ps.win + (winm + 1 + kSlabWinTail);
     ps.rowd = ps.nt + 2 * C::BR * C::NTS;
     ps.part = ps.rowd + 2 * 3 * C::BR;
-    ps.yout = ps.part + 2 * kSlabFarWaves * C::BR;
+    ps.yout = ps.part + 2 * kSlabParts * C::BR;
     ps.stage_bytes = stage_bytes;
     ps.n = n;
     ps.w = w;
