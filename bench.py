@@ -379,6 +379,13 @@ def main():
     wall = time.perf_counter() - t0
     a_times = [r[2] for r in runs]
     a_kernel = [r[1]["kernel_seconds"] for r in runs]
+
+    def dist(v):
+        v = np.asarray(v, dtype=np.float64)
+        return {"mean": float(v.mean()), "median": float(np.median(v)), "min": float(v.min()), "max": float(v.max())}
+
+    # local-solve spread of every asynchronous run (min / median / max over subdomains)
+    a_spread = [{"min": int(c.min()), "median": float(np.median(c)), "max": int(c.max())} for c in (r[3] for r in runs)]
     a_info = runs[-1][1]
     a_bytes = [float(np.dot(r[3], bps)) for r in runs]
     x_async = runs[-1][0]
@@ -390,6 +397,7 @@ def main():
         # the synchronous kernel also computes one speculative update after the last sweep
         s_bytes = [float((r[1]["sweeps"] + 1) * bps.sum()) for r in sruns]
         sync_res = dict(seconds=float(np.mean([r[2] for r in sruns])), sweeps=int(s_info["sweeps"]),
+                        seconds_stats=dist([r[2] for r in sruns]), sweeps_per_run=[int(r[1]["sweeps"]) for r in sruns],
                         kernel_seconds=float(np.mean([r[1]["kernel_seconds"] for r in sruns])),
                         rel_residual=s_info["rel_residual"],
                         model_GBps=float(np.mean([bb / r[1]["kernel_seconds"] for bb, r in zip(s_bytes, sruns)]) / 1e9))
@@ -427,7 +435,9 @@ def main():
         "config": {"workload": args.workload, "n": int(A.n), "subdomains": int(st["parts"]), "overlap": gamma,
                    "local": f"{kind}{k if kind == 'cg' else ''}-{storage}", "tol": tol, "mode": "async",
                    "team": int(tuned[0])},
-        "async": {"seconds": float(np.mean(a_times)), "local_solves_total": int(a_info["total_local_solves"]),
+        "async": {"seconds": float(np.mean(a_times)), "seconds_stats": dist(a_times), "runs": len(runs),
+                  "local_solve_spread": a_spread,
+                  "local_solves_total": int(a_info["total_local_solves"]),
                   "local_solves_min": int(a_info["min_local_solves"]), "local_solves_max": int(a_info["max_local_solves"]),
                   "rel_residual": relres, "launches": int(a_info["launches"])},
         "sync": sync_res,
