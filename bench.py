@@ -373,8 +373,9 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     runs = []
-    for _ in range(args.steps):
+    for i in range(args.steps):
         runs.append(solve("async"))
+        print(f"async run {i}: {runs[-1][2]:.3f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     a_times = [r[2] for r in runs]
@@ -392,7 +393,10 @@ def main():
 
     sync_res = None
     if not args.no_sync:
-        sruns = [solve("sync") for _ in range(max(1, args.steps))]
+        sruns = []
+        for i in range(max(1, args.steps)):
+            sruns.append(solve("sync"))
+            print(f"sync run {i}: {sruns[-1][2]:.3f} s, {sruns[-1][1]['sweeps']} sweeps", file=sys.stderr, flush=True)
         s_info = sruns[-1][1]
         # the synchronous kernel also computes one speculative update after the last sweep
         s_bytes = [float((r[1]["sweeps"] + 1) * bps.sum()) for r in sruns]
