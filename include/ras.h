@@ -163,6 +163,13 @@ ras_status ras_plan_get_stats(const ras_plan* plan, ras_plan_stats* out);
 /* Index sets: owner[n] (int32), omega_ptr[P+1] (int64), omega_idx[sum |Omega_p|]
  * (int32, ascending per subdomain).  Any output may be NULL.  */
 ras_status ras_plan_sets(const ras_plan* plan, int32_t* owner, int64_t* omega_ptr, int32_t* omega_idx);
+/* Communication volume between subdomains (Sec. 3.2.1, Fig. 2): volume is a
+ * caller-owned int64 array of P*P entries, row-major; volume[p*P + q] (q != p)
+ * receives the number of distinct points of Omega_p and of its external layer
+ * ext(Omega_p) (the columns Omega_p's rows reach outside Omega_p) that are owned
+ * by subdomain q, i.e. the values subdomain p reads from q for one local solve.
+ * The diagonal is 0.  RAS_E_ARG on a NULL argument.  */
+ras_status ras_plan_comm_volume(const ras_plan* plan, int64_t* volume);
 /* Float64 band factor of subdomain p: band[i*(w+1) + (j - i + w)] = L_ij for
  * i-w <= j <= i (zero outside the matrix); *w receives the half-bandwidth.
  * band may be NULL to query w (any local solver); with band non-NULL the

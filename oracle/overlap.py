@@ -58,3 +58,18 @@ def flatten_sets(sets) -> tuple[np.ndarray, np.ndarray]:
         ptr[p + 1] = ptr[p] + om.size
     idx = np.concatenate([om for (_, om, _) in sets]).astype(np.int32)
     return ptr, idx
+
+
+def comm_volume(owner: np.ndarray, sets) -> np.ndarray:
+    """Sec. 3.2.1 (Fig. 2): P x P communication volume.  Entry [p, q], q != p,
+    counts the points of Omega_p and of its external layer that subdomain q
+    owns, i.e. the values p needs from q to form its local problem once; the
+    diagonal is 0.  Rows are receivers, columns senders."""
+    P = len(sets)
+    vol = np.zeros((P, P), dtype=np.int64)
+    for p, (_, omega, ext) in enumerate(sets):
+        for i in list(omega) + list(ext):
+            q = int(owner[i])
+            if q != p:
+                vol[p, q] += 1
+    return vol

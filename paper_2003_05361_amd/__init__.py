@@ -78,6 +78,7 @@ SIGNATURES = {
                                   C.POINTER(LocalStruct), C.POINTER(_P)]),
     "ras_plan_get_stats": (C.c_int, [_P, C.POINTER(PlanStats)]),
     "ras_plan_sets": (C.c_int, [_P, _P, _P, _P]),
+    "ras_plan_comm_volume": (C.c_int, [_P, _P]),
     "ras_plan_factor": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int32)]),
     "ras_plan_factor_fp16": (C.c_int, [_P, C.c_int32, _P, _P]),
     "ras_plan_destroy": (None, [_P]),
@@ -224,6 +225,13 @@ class Plan:
         idx = np.empty(st["sum_local_rows"], dtype=np.int32)
         _check(lib().ras_plan_sets(self._p, owner.ctypes.data, ptr.ctypes.data, idx.ctypes.data))
         return owner, ptr, idx
+
+    def comm_volume(self) -> np.ndarray:
+        """P x P int64 matrix: [p, q] = values subdomain p reads from subdomain q's owned points per local solve."""
+        P = self.stats()["parts"]
+        v = np.empty((P, P), dtype=np.int64)
+        _check(lib().ras_plan_comm_volume(self._p, v.ctypes.data))
+        return v
 
     def band_width(self, p: int) -> int:
         """Lower half-bandwidth of subdomain p's local matrix."""

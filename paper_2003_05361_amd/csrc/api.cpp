@@ -260,17 +260,7 @@ void upload(ras_handle& h, const Plan& plan) {
         ev.assign(np * K, 0.0);
         eg.assign(np * K, 0);
         el.assign(np * K, 0);
-        // external columns: read by omega's rows, outside omega (sorted, unique)
-        xe.clear();
-        for (int64_t i = 0; i < n; ++i) {
-            const int32_t g = s.omega[i];
-            for (int64_t e = plan.row_ptr[g]; e < plan.row_ptr[g + 1]; ++e) {
-                const int32_t c = plan.col[e];
-                if (!std::binary_search(s.omega.begin(), s.omega.end(), c)) xe.push_back(c);
-            }
-        }
-        std::sort(xe.begin(), xe.end());
-        xe.erase(std::unique(xe.begin(), xe.end()), xe.end());
+        xe = external_set(plan, s);
         for (int64_t i = 0; i < n; ++i) {
             const int32_t g = s.omega[i];
             int k = 0;
@@ -1311,6 +1301,14 @@ ras_status ras_plan_sets(const ras_plan* plan, int32_t* owner, int64_t* omega_pt
     return guarded([&] {
         if (!plan) throw Error{RAS_E_ARG, "null plan"};
         copy_sets(*plan, owner, omega_ptr, omega_idx);
+        return RAS_OK;
+    });
+}
+
+ras_status ras_plan_comm_volume(const ras_plan* plan, int64_t* volume) {
+    return guarded([&] {
+        if (!plan || !volume) throw Error{RAS_E_ARG, "null argument"};
+        comm_volume(*plan, volume);
         return RAS_OK;
     });
 }

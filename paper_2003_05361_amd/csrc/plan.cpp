@@ -270,6 +270,30 @@ void build_overlap(Plan& plan) {
     });
 }
 
+std::vector<int32_t> external_set(const Plan& plan, const Subdomain& sd) {
+    std::vector<int32_t> xe;
+    for (int32_t g : sd.omega)
+        for (int64_t e = plan.row_ptr[g]; e < plan.row_ptr[g + 1]; ++e) {
+            const int32_t c = plan.col[e];
+            if (!std::binary_search(sd.omega.begin(), sd.omega.end(), c)) xe.push_back(c);
+        }
+    std::sort(xe.begin(), xe.end());
+    xe.erase(std::unique(xe.begin(), xe.end()), xe.end());
+    return xe;
+}
+
+void comm_volume(const Plan& plan, int64_t* volume) {
+    const int64_t P = plan.P;
+    std::fill(volume, volume + P * P, int64_t{0});
+    parallel_for(P, [&](int64_t p, int) {
+        int64_t* row = volume + p * P;
+        const Subdomain& sd = plan.subs[p];
+        for (int32_t g : sd.omega)
+            if (plan.owner[g] != p) ++row[plan.owner[g]];
+        for (int32_t g : external_set(plan, sd)) ++row[plan.owner[g]];  // never owned by p
+    });
+}
+
 // ------------------------------------------------------------------------------ factorisation
 uint16_t f64_to_f16_rne(double d) {
     uint64_t b;

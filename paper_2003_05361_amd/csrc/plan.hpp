@@ -48,6 +48,10 @@ struct Error {
 void validate_csr(const ras_csr& A);
 std::vector<int32_t> make_owner(const ras_csr& A, const ras_partition& part, int32_t* P_out);
 void build_overlap(Plan& plan);
+// ext(Omega_p): columns stored in Omega_p's rows that lie outside Omega_p (ascending, unique)
+std::vector<int32_t> external_set(const Plan& plan, const Subdomain& sd);
+// volume[p*P + q] = |(Omega_p u ext(Omega_p)) n O_q| for q != p, 0 on the diagonal
+void comm_volume(const Plan& plan, int64_t* volume);
 void factor_local(Plan& plan);
 uint16_t f64_to_f16_rne(double d);
 

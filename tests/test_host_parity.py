@@ -73,6 +73,31 @@ def test_index_sets_bit_exact(name, A, part, gamma):
     assert np.array_equal(idx2, idx)
 
 
+@pytest.mark.parametrize("name,A,part,gamma", CASES, ids=[c[0] for c in CASES])
+def test_comm_volume_bit_exact(name, A, part, gamma):
+    _lib_or_skip()
+    kind, arg = part
+    if kind == "rcb":
+        spec = ras.partition("rcb", arg[0], grid=A.grid, seed=arg[1], jitter=arg[2])
+    else:
+        spec = ras.partition(kind, arg, grid=A.grid)
+    plan = ras.Plan(A, spec, gamma, ras.local("cg", "fp64", 3))
+    owner, _, _ = plan.sets()
+    vol = plan.comm_volume()
+    ref = oover.comm_volume(owner, oover.subdomain_sets(A, owner, gamma))
+    assert vol.dtype == np.int64 and np.array_equal(vol, ref)
+
+
+def test_comm_volume_single_subdomain():
+    _lib_or_skip()
+    A = R.laplace2d(9)
+    plan = ras.Plan(A, ras.partition("regular_1d", 1, grid=A.grid), 3, ras.local("chol", "fp64"))
+    assert np.array_equal(plan.comm_volume(), np.zeros((1, 1), dtype=np.int64))
+    lib = ras.lib()
+    assert lib.ras_plan_comm_volume(plan._p, None) == -1
+    assert lib.ras_plan_comm_volume(None, np.zeros(1, np.int64).ctypes.data) == -1
+
+
 def test_rcb_config3_partition_bit_exact():
     """The 128^3, 256-part, jitter 0.4 partition of the 3-D workload."""
     _lib_or_skip()

@@ -192,6 +192,73 @@ def test_overlap_config1_sizes():
     assert [om.size for _, om, _ in sets] == [18 * 64, 20 * 64, 20 * 64, 18 * 64]
 
 
+# ----------------------------------------------------------------- communication volume (Fig. 2)
+def test_comm_volume_strips_closed_form():
+    """Strips of t grid lines of an N-wide grid: with gamma + 1 <= t, each strip
+    reads gamma overlap lines plus one external line from each neighbour."""
+    N, P = 24, 4
+    A = R.laplace2d(N)
+    owner = partition.regular_1d(A.n, P)
+    for gamma in (0, 1, 2, 5):
+        vol = overlap.comm_volume(owner, overlap.subdomain_sets(A, owner, gamma))
+        expect = np.zeros((P, P), dtype=np.int64)
+        for p in range(P - 1):
+            expect[p, p + 1] = expect[p + 1, p] = (gamma + 1) * N
+        assert np.array_equal(vol, expect), gamma
+
+
+def _manhattan_volume(A, owner, gamma):
+    """Brute force over a full grid with the 5/7-point stencil: graph distance from
+    a point to a set is the least Manhattan distance to it, so p needs every point
+    of another subdomain that lies within gamma + 1 of O_p."""
+    X = A.coords()
+    P = int(owner.max()) + 1
+    vol = np.zeros((P, P), dtype=np.int64)
+    for p in range(P):
+        own = X[owner == p]
+        d = np.abs(X[:, None, :] - own[None, :, :]).sum(axis=2).min(axis=1)
+        for i in np.flatnonzero((d <= gamma + 1) & (owner != p)):
+            vol[p, owner[i]] += 1
+    return vol
+
+
+@pytest.mark.parametrize("gamma", [0, 1, 2, 3])
+def test_comm_volume_matches_manhattan_brute_force(gamma):
+    cases = [
+        (R.laplace2d(13, 11), partition.regular_grid((13, 11, 1), (3, 2))),
+        (R.laplace2d(12), partition.regular_1d(144, 5)),  # strip boundaries off the grid lines
+        (R.laplace2d(14, 9), partition.rcb(R.laplace2d(14, 9).coords(), 6, 4, 0.3)),
+        (R.laplace3d(6), partition.regular_grid((6, 6, 6), (2, 3, 2))),
+    ]
+    for A, owner in cases:
+        vol = overlap.comm_volume(owner, overlap.subdomain_sets(A, owner, gamma))
+        assert np.array_equal(vol, _manhattan_volume(A, owner, gamma))
+
+
+def test_comm_volume_blocks_closed_form():
+    """Blocks of bx x by with gamma + 1 <= min(bx, by): an edge neighbour gives a
+    (gamma + 1)-deep slab along the shared side, a corner neighbour the lattice
+    points (dx, dy >= 1, dx + dy <= gamma + 1), gamma (gamma + 1) / 2 of them."""
+    A = R.laplace2d(24, 30)  # 3 x 2 blocks of 8 x 15
+    owner = partition.regular_grid(A.grid, (3, 2))
+    gamma = 3
+    vol = overlap.comm_volume(owner, overlap.subdomain_sets(A, owner, gamma))
+    bx, by = 8, 15
+    for p in range(6):
+        for q in range(6):
+            dxb = abs(p % 3 - q % 3)
+            dyb = abs(p // 3 - q // 3)
+            if p == q or dxb > 1 or dyb > 1:
+                e = 0
+            elif dyb == 0:
+                e = (gamma + 1) * by
+            elif dxb == 0:
+                e = (gamma + 1) * bx
+            else:
+                e = gamma * (gamma + 1) // 2
+            assert vol[p, q] == e, (p, q)
+
+
 def _rcb_literal(coords, ids, p0, m, w, out):
     if m == 1:
         for g in ids:
