@@ -109,7 +109,16 @@ typedef struct ras_local {
  *   max_sweeps: sweeps (SYNC) or local solves per subdomain (ASYNC/ORDERED).
  *   max_seconds <= 0: no time limit.  workgroups: 0 = library choice.
  *   team: workgroups cooperating on one subdomain's CG solve (1, 2, 4, 8 or
- *     16); 0 = the value found by ras_autotune, else a heuristic.  */
+ *     16); 0 = the value found by ras_autotune, else a heuristic.
+ *   pace (ASYNC only, at most 16): before reading its neighbours' values
+ *     for the next update, a subdomain that has completed more updates than
+ *     some neighbour waits for it, at most pace times the duration of its own
+ *     previous update, then reads whatever is there.  0 never waits (free
+ *     running).  Any value leaves the iteration asynchronous (Sec. 2.1: any
+ *     read schedule is admissible); it only chooses when the read happens, so
+ *     that evenly loaded subdomains read their neighbours' latest update
+ *     rather than the one before it.  Negative: library choice (0.25 for the
+ *     banded Cholesky solver, 0 for CG).  Ignored by SYNC and ORDERED.  */
 enum { RAS_MODE_SYNC = 0, RAS_MODE_ASYNC = 1, RAS_MODE_ORDERED = 2 };
 enum { RAS_DETECT_CENTRAL = 0, RAS_DETECT_DECENTRAL = 1 };
 typedef struct ras_solve_opts {
@@ -120,6 +129,7 @@ typedef struct ras_solve_opts {
     double max_seconds;
     int32_t workgroups;
     int32_t team;
+    double pace;
 } ras_solve_opts;
 
 typedef struct ras_solve_info {

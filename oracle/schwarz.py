@@ -194,6 +194,70 @@ class RAS:
                        relres=np.sqrt(float(r @ r) / bn2))
 
 
+    def async_timed(self, b: np.ndarray, tol: float, durations, offsets=None, pace: float = 0.0,
+                    max_rounds: int = 10**6):
+        """Timed asynchronous schedule (a model of the one-GPU persistent kernel).
+
+        Subdomain p runs updates back to back, each taking durations[p]; the first
+        starts at offsets[p].  An update reads x on Omega_p and its external layer
+        when it starts and publishes its owned values when it ends (Sec. 2.1: the
+        local solve works on whatever values are there when it reads).  Paced
+        reads: before starting, p waits until every neighbour has published at
+        least as many updates as p, for at most pace * durations[p]; pace = 0 never
+        waits.  Events at equal times publish before they read.  Stops when the
+        exact relative residual drops below tol after a publish, or when every
+        subdomain has published max_rounds updates.  Returns (x, info) with the
+        local-solve counts and the stop time."""
+        import heapq
+
+        P = self.P
+        dur = np.asarray(durations, dtype=np.float64)
+        off = np.zeros(P) if offsets is None else np.asarray(offsets, dtype=np.float64)
+        nbrs = self.neighbours()
+        x = np.zeros_like(b)
+        bn = np.linalg.norm(b)
+        counts = np.zeros(P, dtype=np.int64)
+        views = {}
+        waiting = {}  # p -> deadline
+        ev = [(off[p], 1, p) for p in range(P)]  # (time, 0 publish / 1 read / 2 wait deadline, p)
+        heapq.heapify(ev)
+
+        def behind(p):
+            return any(counts[q] < counts[p] for q in nbrs[p])
+
+        def start(p, t):
+            views[p] = x.copy()
+            heapq.heappush(ev, (t + dur[p], 0, p))
+
+        while ev:
+            t, kind, p = heapq.heappop(ev)
+            if kind == 1:
+                if counts[p] >= max_rounds:
+                    continue
+                if pace > 0 and behind(p):
+                    waiting[p] = t + pace * dur[p]
+                    heapq.heappush(ev, (waiting[p], 2, p))
+                else:
+                    start(p, t)
+            elif kind == 2:
+                if waiting.get(p) == t:
+                    del waiting[p]
+                    start(p, t)
+            else:
+                s = self.subs[p]
+                view = views.pop(p)
+                rp = b[s.omega] - self.M[s.omega] @ view
+                x[s.owned] = view[s.owned] + s.solver(rp)[s.pos]
+                counts[p] += 1
+                if np.linalg.norm(b - self.M @ x) < tol * bn:
+                    return x, dict(converged=True, local_solves=counts, time=t)
+                for q in [q for q in waiting if not behind(q)]:
+                    del waiting[q]
+                    start(q, t)
+                heapq.heappush(ev, (t, 1, p))
+        return x, dict(converged=False, local_solves=counts, time=t)
+
+
 def direct_solve(A, b: np.ndarray) -> np.ndarray:
     """FP64 direct reference solution: dense LU for n <= 4096, sparse LU otherwise."""
     if A.n <= 4096:

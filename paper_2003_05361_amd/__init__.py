@@ -30,6 +30,9 @@ LOCAL_KINDS = {"chol": 0, "cg": 1}
 STORAGES = {"fp64": 0, "fp32": 1, "fp16": 2}
 MODES = {"sync": 0, "async": 1, "ordered": 2}
 DETECT = {"central": 0, "decentral": 1}
+# asynchronous mode: neighbour wait budget before a read, in units of the previous update's time
+# (0 = free running, negative = the library's choice per local solver)
+DEFAULT_PACE = -1.0
 
 
 class CSRStruct(C.Structure):
@@ -48,7 +51,7 @@ class LocalStruct(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("detect", C.c_int32), ("tol", C.c_double), ("max_sweeps", C.c_int64),
-                ("max_seconds", C.c_double), ("workgroups", C.c_int32), ("team", C.c_int32)]
+                ("max_seconds", C.c_double), ("workgroups", C.c_int32), ("team", C.c_int32), ("pace", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -280,9 +283,9 @@ def _stream_ptr(stream):
     return C.c_void_p(getattr(stream, "cuda_stream", stream))
 
 
-def _opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team=0) -> SolveOpts:
+def _opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team=0, pace=None) -> SolveOpts:
     return SolveOpts(MODES[mode], DETECT[detect], float(tol), int(max_sweeps), float(max_seconds), int(workgroups),
-                     int(team))
+                     int(team), float(DEFAULT_PACE if pace is None else pace))
 
 
 class Handle:
@@ -300,7 +303,7 @@ class Handle:
 
     def solve(self, b, x0=None, tol: float = 1e-8, mode: str = "async", max_sweeps: int = 1_000_000,
               max_seconds: float = 0.0, detect: str = "central", workgroups: int = 0, team: int = 0,
-              allow_unconverged=True):
+              allow_unconverged=True, pace=None):
         """Solve A x = b on the device.  b: float64 CUDA tensor [n] or [nrhs, n].
         Returns (x, infos) with x the same shape as b."""
         import torch
@@ -312,7 +315,7 @@ class Handle:
         x = torch.zeros_like(b) if x0 is None else x0.to(torch.float64).contiguous().clone()
         infos = (SolveInfo * nrhs)()
         st = lib().ras_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), nrhs,
-                             C.byref(_opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team)), infos)
+                             C.byref(_opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team, pace)), infos)
         _check(st, (RAS_OK, RAS_NOT_CONVERGED) if allow_unconverged else (RAS_OK,))
         self.last_nrhs = nrhs
         return x, [i.as_dict() for i in infos]
@@ -377,7 +380,7 @@ def setup(A, part: dict, overlap: int, loc: dict, stream=None) -> Handle:
 
 def batch_solve(handles: Sequence[Handle], bs, xs=None, tol: float = 1e-8, mode: str = "async",
                 max_sweeps: int = 1_000_000, max_seconds: float = 0.0, detect: str = "central", workgroups: int = 0,
-                team: int = 0):
+                team: int = 0, pace=None):
     """Solve several systems in one persistent launch (same local solver kind/storage)."""
     import torch
 
@@ -391,7 +394,7 @@ def batch_solve(handles: Sequence[Handle], bs, xs=None, tol: float = 1e-8, mode:
     NR = (C.c_int32 * m)(*nr)
     infos = (SolveInfo * sum(nr))()
     st = lib().ras_batch_solve(m, H, B, X, NR,
-                               C.byref(_opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team)), infos)
+                               C.byref(_opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team, pace)), infos)
     _check(st, (RAS_OK, RAS_NOT_CONVERGED))
     out, k = [], 0
     for r in nr:

@@ -482,6 +482,8 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     if (o.mode != RAS_MODE_SYNC && o.mode != RAS_MODE_ASYNC && o.mode != RAS_MODE_ORDERED)
         throw Error{RAS_E_ARG, "unknown mode"};
     if (!(o.tol >= 0.0) || o.max_sweeps < 1) throw Error{RAS_E_ARG, "tol must be >= 0 and max_sweeps >= 1"};
+    if (o.detect != RAS_DETECT_CENTRAL && o.detect != RAS_DETECT_DECENTRAL) throw Error{RAS_E_ARG, "unknown detector"};
+    if (!(o.pace <= 16.0)) throw Error{RAS_E_ARG, "pace must be at most 16 (negative: library choice)"};
     // distinct handles, in first-use order
     std::vector<ras_handle*> hs;
     for (auto& sp : specs)
@@ -779,8 +781,12 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     P.res2_own = reinterpret_cast<double*>(base + o_res2);
     P.conv = reinterpret_cast<int32_t*>(base + o_conv);
     P.gflag = reinterpret_cast<int32_t*>(base + o_gflag);
-    if (o.detect != RAS_DETECT_CENTRAL && o.detect != RAS_DETECT_DECENTRAL) throw Error{RAS_E_ARG, "unknown detector"};
     P.detect = o.detect;
+    // library choice: banded direct solves run few, long, evenly timed updates, where
+    // reading the neighbours' latest update saves about a third of the updates; CG
+    // subdomains are many and unevenly timed, where waiting costs more than it saves
+    const double pace = o.pace < 0.0 ? (h0.solver == RAS_LOCAL_CHOL_BANDED ? 0.25 : 0.0) : o.pace;
+    P.pace = o.mode == RAS_MODE_ASYNC ? pace : 0.0;
     P.solves = reinterpret_cast<int64_t*>(base + o_solves);
     P.version = reinterpret_cast<uint32_t*>(base + o_version);
     P.team_ptr = reinterpret_cast<const int32_t*>(base + o_tptr);
@@ -1198,6 +1204,7 @@ struct ras_server {
                                                  r, sy->tol});
                 ras_solve_opts o{};
                 o.mode = RAS_MODE_ASYNC;
+                o.pace = -1.0;  // library choice per local solver
                 o.tol = kv.second.front()->tol;
                 o.max_sweeps = INT64_MAX / 4;
                 o.max_seconds = slice;

@@ -137,6 +137,7 @@ struct Params {
     int32_t detect;           // 0 centralized, 1 decentralized (asynchronous mode)
     int64_t max_ticks;        // wall-clock ticks allowed (<= 0: unlimited)
     int64_t sweep0;           // sync: first sweep index of this launch
+    double pace;              // async: neighbour wait budget, in units of the previous update's duration
 };
 
 }  // namespace ras

@@ -1228,6 +1228,30 @@ __device__ __forceinline__ void run_sync(const Params& P, U& upd, TeamCtx& tc, d
     }
 }
 
+// Paced read (asynchronous mode): a subdomain about to read its neighbours
+// waits, for at most `budget` wall-clock ticks, until every neighbour has
+// published at least as many updates as it has itself.  Evenly loaded
+// subdomains then read each other's latest update instead of the one before
+// it; a slow neighbour costs at most the budget.  Every thread of the
+// workgroup takes the same exits (both tests are block-wide votes).
+template <int B>
+__device__ __forceinline__ void paced_read_wait(const Params& P, const ItemDev& item, const InstDev& in, int it,
+                                                int64_t budget) {
+    const SubDev* sd = P.subs + item.sub;
+    const int nn = uni(sd->n_nbr);
+    const int32_t* nb = sd->nbr;
+    const uint32_t mine = ld_rlx(P.version + it);
+    const int64_t t0 = wall_clock64();
+    for (;;) {
+        int behind = 0;
+        for (int k = threadIdx.x; k < nn; k += B) behind |= ld_rlx(P.version + in.item_begin + nb[k]) < mine;
+        if (!__syncthreads_or(behind)) break;
+        if (__syncthreads_or(wall_clock64() - t0 >= budget)) break;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
 // Asynchronous iteration: no grid barrier.  Decisions that steer team-wide
 // control flow are taken by member 0 and broadcast to the team.
 template <int B, class U>
@@ -1238,6 +1262,7 @@ __device__ __forceinline__ void run_async(const Params& P, U& upd, TeamCtx& tc, 
     __shared__ int flag;
     for (int j = tid; j < ie - ib; j += B) done[j] = 0;
     __syncthreads();
+    int64_t last_dur = 0;  // wall-clock ticks of this workgroup's previous update (0: none yet)
     for (;;) {
         bool any = false;
         for (int j = ib; j < ie; ++j) {
@@ -1246,6 +1271,9 @@ __device__ __forceinline__ void run_async(const Params& P, U& upd, TeamCtx& tc, 
             const ItemDev item = load_item(P, it);
             const InstDev& in = P.insts[item.inst];
             InstState* st = P.ist + item.inst;
+            if (P.pace > 0.0 && tc.member == 0 && last_dur > 0)
+                paced_read_wait<B>(P, item, in, it, static_cast<int64_t>(P.pace * static_cast<double>(last_dur)));
+            const int64_t t_upd = wall_clock64();
             int v0 = 0;
             if (tc.member == 0 && tid == 0)
                 v0 = (ld_rlx(&st->stop) != 0) || (P.solves[it] >= in.max_sweeps) ||
@@ -1274,6 +1302,7 @@ __device__ __forceinline__ void run_async(const Params& P, U& upd, TeamCtx& tc, 
                 P.solves[it] += 1;
                 __hip_atomic_fetch_add(P.version + it, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
+            last_dur = wall_clock64() - t_upd;
             if (P.detect == 1 && tc.member == 0) {
                 // decentralized detection (Sec. 2.2, Sec. 3.3.2, after Bahi et al.): a
                 // subdomain raises its global flag once it and every neighbour report

@@ -7,7 +7,7 @@ about 1e-16 ||A|| ||x|| / ||b|| of cancellation error), iterates to 1e-9
 relative; float32 local arithmetic -- iterates after a
 fixed number of sweeps to 2e-5 relative (float32 unit roundoff 6e-8 times the
 growth of CG / triangular-solve rounding over a few sweeps); converged
-solutions to the BASELINE criteria: relative residual below tol (exact,
+solutions to the acceptance criteria: relative residual below tol (exact,
 recomputed) and 1e-6 relative error against the float64 direct solve where the
 right-hand side makes that attainable.
 """
@@ -308,6 +308,53 @@ def test_async_decentralized_detection(loc, st, k, team):
         assert info[0]["converged"], info
         assert schwarz.relative_residual(A, xx, b) < 1e-8
         assert _rel(xx, xd) <= 1e-6
+
+
+@pytest.mark.parametrize("pace", [0.0, 0.25, 16.0])
+def test_async_paced_reads(pace):
+    """Paced reads wait for slower neighbours before reading (bounded by pace times
+    the previous update's duration).  Evenly loaded banded subdomains then need
+    about as many updates as synchronous sweeps; every pace converges to the
+    direct solution."""
+    ras = _ras()
+    _say(f"case: async chol fp64 pace={pace}")
+    A = R.laplace2d(128)
+    b = R.uniform_rhs(A.n, 1)
+    xd = schwarz.direct_solve(A, b)
+    h = ras.setup(A, ras.partition("rcb", 6, grid=A.grid, seed=0, jitter=0.0), 4, ras.local("chol", "fp64"))
+    _, si = h.solve(_cuda(b), tol=1e-8, mode="sync", max_sweeps=100000, max_seconds=60)
+    x, info = h.solve(_cuda(b), tol=1e-8, mode="async", max_sweeps=200000, max_seconds=60, pace=pace)
+    xx = x.cpu().numpy()
+    assert info[0]["converged"], info
+    assert schwarz.relative_residual(A, xx, b) < 1e-8
+    assert _rel(xx, xd) <= 1e-6
+    if pace > 0:
+        assert np.median(h.local_solve_counts()) <= 1.15 * si[0]["sweeps"], (h.local_solve_counts(), si)
+
+
+def test_async_paced_cg_teams_converge():
+    ras = _ras()
+    _say("case: async cg fp64 team=4 pace=0.5")
+    A = R.laplace2d(96)
+    b = R.uniform_rhs(A.n, 18)
+    h = ras.setup(A, ras.partition("regular_2d", (4, 4), grid=A.grid), 3, ras.local("cg", "fp64", 10))
+    x, info = h.solve(_cuda(b), tol=1e-8, mode="async", max_sweeps=200000, max_seconds=60, team=4, pace=0.5)
+    assert info[0]["converged"], info
+    assert schwarz.relative_residual(A, x.cpu().numpy(), b) < 1e-8
+
+
+def test_pace_out_of_range_is_an_argument_error():
+    ras = _ras()
+    _say("case: pace argument errors")
+    A = R.laplace2d(16)
+    b = _cuda(R.uniform_rhs(A.n, 1))
+    h = ras.setup(A, ras.partition("regular_2d", (2, 2), grid=A.grid), 1, ras.local("chol", "fp64"))
+    for bad in (16.5, float("nan")):
+        with pytest.raises(ras.RasError) as e:
+            h.solve(b, tol=1e-8, mode="async", pace=bad)
+        assert e.value.status == -1
+    _, info = h.solve(b, tol=1e-8, mode="async", max_seconds=30)
+    assert info[0]["converged"]
 
 
 # ----------------------------------------------------------------------------- multi-RHS and batching

@@ -508,3 +508,37 @@ def test_async_update_must_read_each_value_once():
     for seed in (0, 1):
         assert _async_reads(ras, b, True, 48, 3000, seed) < 1e-5
         assert _async_reads(ras, b, False, 48, 3000, seed) > 1e3
+
+
+# ----------------------------------------------------------------- timed asynchronous schedule
+def _timed_case():
+    A = R.laplace2d(40)
+    owner = partition.rcb(A.coords(), 4, 0, 0.0)
+    return A, R.uniform_rhs(A.n, 1), schwarz.RAS(A, owner, 2, "chol", "fp64")
+
+
+def test_paced_lockstep_schedule_is_the_synchronous_iteration():
+    """Equal update times, start times a hair apart, reads that wait for the
+    neighbours: update k of every subdomain reads exactly the k-1st updates of
+    its neighbours, i.e. the synchronous (Jacobi-type) sweep of Eq. 3."""
+    A, b, ras = _timed_case()
+    K = 12
+    xs, _, _ = ras.sync(b, 0.0, K)
+    xa, info = ras.async_timed(b, 0.0, np.ones(ras.P), offsets=1e-3 * np.arange(ras.P), pace=16.0, max_rounds=K)
+    assert np.all(info["local_solves"] == K)
+    assert np.max(np.abs(xa - xs)) <= 1e-14 * np.max(np.abs(xs))
+
+
+def test_free_running_lockstep_schedule_reads_one_update_late():
+    """Without the wait, a subdomain that finishes a hair before its neighbour
+    reads the neighbour's update before last; evenly timed subdomains then need
+    markedly more updates than synchronous sweeps, and paced reads recover the
+    synchronous count up to the detection lag."""
+    A, b, ras = _timed_case()
+    _, _, k_sync = ras.sync(b, 1e-8, 5000)
+    off = 1e-3 * np.arange(ras.P)
+    _, free = ras.async_timed(b, 1e-8, np.ones(ras.P), offsets=off, pace=0.0)
+    _, paced = ras.async_timed(b, 1e-8, np.ones(ras.P), offsets=off, pace=0.25)
+    assert free["converged"] and paced["converged"]
+    assert np.median(free["local_solves"]) >= 1.3 * k_sync
+    assert np.median(paced["local_solves"]) <= k_sync + 1
