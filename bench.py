@@ -64,40 +64,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def bytes_per_local_solve(stats_subs, kind: str, storage: str, k: int) -> list:
-    """Algorithmic HBM bytes of one local solve of each subdomain (streaming model:
-    each array touched the minimum number of times per step, no reuse across CG
-    iterations): restrict + residual, local solve, restricted prolongation."""
-    s = 8 if storage == "fp64" else 4
-    out = []
-    for n, n_own, K, w in stats_subs:
-        res = n * (12 * K + 16)
-        pro = n_own * (16 + s)
-        if kind == "cg":
-            loc = k * n * (K * (s + 4) + 11 * s)
-        else:
-            sl = {"fp64": 8, "fp32": 4, "fp16": 2}[storage]
-            loc = 2 * n * (w + 1) * sl + 4 * n * s + (2 * n * 4 if storage == "fp16" else 0)
-        out.append(res + loc + pro)
-    return out
-
-
 def subdomain_shapes(A, part_kind, part_arg, gamma):
     """(n_p, owned_p, K_p, w_p) per subdomain from the library's own host setup."""
-    import numpy as np
-
     import paper_2003_05361_amd as ras
+    from paper_2003_05361_amd.perfmodel import subdomain_shapes as shapes_of
 
     plan = ras.Plan(A, part_spec(ras, A, part_kind, part_arg), gamma, ras.local("cg", "fp64", 1))
-    owner, ptr, idx = plan.sets()
-    rp = A.indptr
-    shapes = []
-    for p in range(len(ptr) - 1):
-        om = idx[ptr[p]:ptr[p + 1]]
-        n = om.size
-        n_own = int(np.count_nonzero(owner[om] == p))
-        K = int(np.max(rp[om + 1] - rp[om]))
-        shapes.append([n, n_own, K, plan.band_width(p)])
+    shapes = shapes_of(plan, A.indptr)
     plan.close()
     return shapes
 
@@ -336,6 +309,7 @@ def main():
 
     import paper_2003_05361_amd as ras
     import ras_inputs as R
+    from paper_2003_05361_amd.perfmodel import bytes_per_local_solve
 
     cfg_name, kind, storage, k = WORKLOADS[args.workload]
     A, b, cfg = R.config_problem(cfg_name)

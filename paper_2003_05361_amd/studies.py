@@ -1,0 +1,250 @@
+"""One-GPU parameter studies: partitioning scheme and overlap (Sec. 4.2, Figs. 2-4).
+
+Every case builds the host plan, records its shape (local rows, band width,
+band entries as the fill of the local factors, communication volume between
+subdomains as in Fig. 2), sets it up on the device and solves the same system
+synchronously and asynchronously to the tolerance, both through the library's
+device kernels.  The per-sweep breakdown is the algorithmic byte model of the
+three steps of one update (restriction and residual, local solve, restricted
+prolongation) with the values read from other subdomains' points singled out:
+the fused kernels do not expose a per-step clock, so the split is modelled and
+only the sweep time is measured.
+
+    python -m paper_2003_05361_amd.studies partitioners [--parts 4,16,36,64] [--overlap 4]
+    python -m paper_2003_05361_amd.studies overlap [--sizes 128,256] [--overlaps 0,1,2,4,8,12,16]
+
+Each case prints one JSON line; --markdown writes a summary with the tables and
+the communication-volume matrices.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+PARTITIONERS = ("regular_1d", "regular_2d", "rcb")
+
+
+def _square_split(P: int) -> tuple[int, int]:
+    a = int(math.isqrt(P))
+    while P % a:
+        a -= 1
+    return (P // a, a)
+
+
+def partition_spec(ras, A, kind: str, P: int) -> dict:
+    """Fig. 2's three schemes; recursive coordinate bisection stands in for the
+    graph partitioner (balanced parts with short boundaries)."""
+    if kind == "regular_1d":
+        return ras.partition("regular_1d", P, grid=A.grid)
+    if kind == "regular_2d":
+        return ras.partition("regular_2d", _square_split(P), grid=A.grid)
+    if kind == "rcb":
+        return ras.partition("rcb", P, grid=A.grid, seed=0, jitter=0.0)
+    raise ValueError(kind)
+
+
+def comm_summary(vol: np.ndarray) -> dict:
+    nb = np.count_nonzero(vol, axis=1)
+    recv = vol.sum(axis=1)
+    return {"total_values": int(vol.sum()), "max_recv": int(recv.max()), "mean_recv": float(recv.mean()),
+            "max_neighbours": int(nb.max()), "mean_neighbours": float(nb.mean())}
+
+
+def run_case(A, b, spec: dict, gamma: int, loc: dict, tol: float, max_seconds: float, stream, label: dict) -> dict:
+    import torch
+
+    import paper_2003_05361_amd as ras
+    from paper_2003_05361_amd.perfmodel import local_solve_parts, subdomain_shapes
+
+    t0 = time.perf_counter()
+    plan = ras.Plan(A, spec, gamma, loc)
+    st = plan.stats()
+    vol = plan.comm_volume()
+    shapes = subdomain_shapes(plan, A.indptr)
+    h = plan.setup(stream=stream)
+    setup_s = time.perf_counter() - t0
+    plan.close()
+    bt = torch.tensor(b, dtype=torch.float64, device="cuda")
+    h.solve(bt, tol=0.0, mode="sync", max_sweeps=2)  # first launch outside the timings
+
+    def timed(mode, pace=None):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        x, info = h.solve(bt, tol=tol, mode=mode, max_sweeps=1_000_000, max_seconds=max_seconds, pace=pace)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return info[0], e0.elapsed_time(e1) * 1e-3, h.local_solve_counts()
+
+    def async_result(info, sec, counts):
+        return {"converged": bool(info["converged"]), "seconds": sec, "rel_residual": info["rel_residual"],
+                "local_solves_min": int(counts.min()), "local_solves_median": float(np.median(counts)),
+                "local_solves_max": int(counts.max())}
+
+    s_info, s_sec, _ = timed("sync")
+    a_info, a_sec, a_counts = timed("async")  # the library's pace for this local solver
+    f_info, f_sec, f_counts = timed("async", 0.0)  # free running: reads never wait
+    h.close()
+
+    kind, storage, k = loc["kind"], loc.get("storage", "fp64"), loc.get("cg_iters", 0)
+    parts = np.array([local_solve_parts(sh, kind, storage, k) for sh in shapes]).sum(axis=0)
+    exchange = 8.0 * float(vol.sum())
+    sweep_bytes = float(parts.sum())
+    sweeps = int(s_info["sweeps"])
+    res = dict(label)
+    res.update({
+        "n": int(A.n), "parts": int(st["parts"]), "overlap": gamma, "local": f"{kind}-{storage}",
+        "local_rows_mean": st["sum_local_rows"] / st["parts"], "local_rows_max": int(st["max_local_rows"]),
+        "max_band": int(st["max_band"]), "band_entries": int(st["band_entries"]),
+        "comm": comm_summary(vol),
+        "setup_s": setup_s,
+        "sync": {"converged": bool(s_info["converged"]), "sweeps": sweeps, "seconds": s_sec,
+                 "ms_per_sweep": 1e3 * s_sec / max(1, sweeps), "rel_residual": s_info["rel_residual"]},
+        "async": async_result(a_info, a_sec, a_counts),
+        "async_free": async_result(f_info, f_sec, f_counts),
+        "async_speedup": s_sec / a_sec if a_sec > 0 else None,
+        "async_free_speedup": s_sec / f_sec if f_sec > 0 else None,
+        "model_bytes_per_sweep": {"restrict_residual": float(parts[0]), "local_solve": float(parts[1]),
+                                  "prolong": float(parts[2]), "exchange_of_residual": exchange},
+        "model_share": {"restrict_residual": float(parts[0]) / sweep_bytes, "local_solve": float(parts[1]) / sweep_bytes,
+                        "prolong": float(parts[2]) / sweep_bytes, "exchange": exchange / sweep_bytes},
+        "model_GBps_sync": sweep_bytes * (sweeps + 1) / s_info["kernel_seconds"] / 1e9
+        if s_info["kernel_seconds"] > 0 else None,
+    })
+    return res, vol
+
+
+def _progress(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def partitioners(args, stream) -> tuple[list, dict]:
+    """Fig. 3 analog: fixed local size (per_part unknowns), P grown, three schemes."""
+    import paper_2003_05361_amd as ras
+    import ras_inputs as R
+
+    rows, heat = [], {}
+    for P in args.parts:
+        N = int(round(math.sqrt(P * args.per_part)))
+        A = R.laplace2d(N)
+        b = R.uniform_rhs(A.n, 1)
+        for kind in PARTITIONERS:
+            _progress(f"partitioners: P={P} N={N} {kind}")
+            r, vol = run_case(A, b, partition_spec(ras, A, kind, P), args.overlap, ras.local("chol", "fp64"),
+                              args.tol, args.max_seconds, stream,
+                              {"study": "partitioners", "grid": N, "partitioner": kind})
+            print(json.dumps(r), flush=True)
+            rows.append(r)
+            if P == args.heatmap_parts:
+                heat[kind] = vol
+    base = {r["parts"]: r["sync"]["seconds"] for r in rows if r["partitioner"] == "regular_1d"}
+    for r in rows:
+        r["sync_speedup_vs_1d"] = base[r["parts"]] / r["sync"]["seconds"]
+    return rows, heat
+
+
+def overlaps(args, stream) -> tuple[list, dict]:
+    """Fig. 4 analog: one partition (bisection, args.nparts parts), overlap varied,
+    at each grid size."""
+    import paper_2003_05361_amd as ras
+    import ras_inputs as R
+
+    rows, heat = [], {}
+    for N in args.sizes:
+        A = R.laplace2d(N)
+        b = R.uniform_rhs(A.n, 1)
+        for gamma in args.overlaps:
+            _progress(f"overlap: N={N} gamma={gamma}")
+            r, vol = run_case(A, b, partition_spec(ras, A, "rcb", args.nparts), gamma, ras.local("chol", "fp64"),
+                              args.tol, args.max_seconds, stream, {"study": "overlap", "grid": N, "partitioner": "rcb"})
+            print(json.dumps(r), flush=True)
+            rows.append(r)
+            if N == args.sizes[0]:
+                heat[f"overlap {gamma}"] = vol
+    return rows, heat
+
+
+def _fmt_matrix(vol: np.ndarray) -> list:
+    P = vol.shape[0]
+    out = ["| p \\ q | " + " | ".join(str(q) for q in range(P)) + " |", "|---" * (P + 1) + "|"]
+    for p in range(P):
+        out.append(f"| {p} | " + " | ".join(str(int(v)) if v else "." for v in vol[p]) + " |")
+    return out
+
+
+def markdown(study: str, rows: list, heat: dict, cmd: str) -> str:
+    L = [f"# Parameter study: {study}", "", "Command (one MI355X):", "", f"    {cmd}", ""]
+    L += ["Local solves: banded Cholesky, float64; tolerance on the relative residual as given per row. "
+          "Times are HIP events around one solve call, setup excluded. Sweep time is the measured "
+          "synchronous time over its sweep count; the shares are the algorithmic byte model of one "
+          "sweep (exchange = 8 bytes per value read from another subdomain's points, a part of the "
+          "residual step).", ""]
+    L += ["Async runs twice: with paced reads (the library's choice for the banded solver: a subdomain "
+          "waits up to a quarter of its previous update's time for neighbours that are behind) and free "
+          "running (reads never wait). Updates = median local solves per subdomain.", ""]
+    L += ["| grid | P | scheme | overlap | max band | band entries | comm values | max nbrs | sync sweeps | "
+          "sync s | ms/sweep | async s (updates) | free async s (updates) | async speedup | free speedup | "
+          "sync speedup vs 1-D | residual / solve / prolong / exchange |",
+          "|---" * 17 + "|"]
+    for r in rows:
+        sh = r["model_share"]
+        conv = "" if r["sync"]["converged"] else " (not conv.)"
+        def amode(a):
+            c = "" if a["converged"] else " not conv."
+            return f"{a['seconds']:.4f} ({a['local_solves_median']:.0f}{c})"
+
+        vs1d = f"{r['sync_speedup_vs_1d']:.2f}" if "sync_speedup_vs_1d" in r else "-"
+        L.append(f"| {r['grid']}^2 | {r['parts']} | {r['partitioner']} | {r['overlap']} | {r['max_band']} | "
+                 f"{r['band_entries']} | {r['comm']['total_values']} | {r['comm']['max_neighbours']} | "
+                 f"{r['sync']['sweeps']}{conv} | {r['sync']['seconds']:.4f} | {r['sync']['ms_per_sweep']:.3f} | "
+                 f"{amode(r['async'])} | {amode(r['async_free'])} | {r['async_speedup']:.2f} | "
+                 f"{r['async_free_speedup']:.2f} | {vs1d} | "
+                 f"{sh['restrict_residual']:.2f} / {sh['local_solve']:.2f} / {sh['prolong']:.2f} / "
+                 f"{sh['exchange']:.3f} |")
+    for name, vol in heat.items():
+        L += ["", f"Communication volume, {name} (row p receives from column q; values per local solve):", ""]
+        L += _fmt_matrix(vol)
+    return "\n".join(L) + "\n"
+
+
+def _ints(s: str) -> list:
+    return [int(v) for v in s.split(",") if v]
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("study", choices=("partitioners", "overlap"))
+    ap.add_argument("--parts", type=_ints, default=[4, 16, 36, 64])
+    ap.add_argument("--per-part", type=int, default=4096)
+    ap.add_argument("--overlap", type=int, default=4)
+    ap.add_argument("--heatmap-parts", type=int, default=16)
+    ap.add_argument("--sizes", type=_ints, default=[128, 256])
+    ap.add_argument("--overlaps", type=_ints, default=[0, 1, 2, 4, 8, 12, 16])
+    ap.add_argument("--nparts", type=int, default=6)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--max-seconds", type=float, default=30.0)
+    ap.add_argument("--markdown", default=None)
+    args = ap.parse_args(argv)
+
+    import torch
+
+    if not torch.cuda.is_available():
+        raise SystemExit("the studies run the device solver: no GPU visible")
+    stream = torch.cuda.current_stream()
+    rows, heat = (partitioners if args.study == "partitioners" else overlaps)(args, stream)
+    if args.markdown:
+        cmd = "python -m paper_2003_05361_amd.studies " + " ".join(sys.argv[1:] if argv is None else argv)
+        with open(args.markdown, "w") as f:
+            f.write(markdown(args.study, rows, heat, cmd))
+    return rows
+
+
+if __name__ == "__main__":
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    main()

@@ -1,0 +1,76 @@
+"""The one-GPU parameter studies (partitioning scheme, overlap) on small grids:
+every case converges in both modes, the communication volume equals the
+oracle's, the synchronous sweep counts equal the oracle's, and more overlap
+never needs more synchronous sweeps on these Laplace problems (Sec. 4.2)."""
+import sys
+
+import numpy as np
+import pytest
+
+import ras_inputs as R
+from oracle import overlap as oover
+from oracle import partition as opart
+from oracle import schwarz
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_owner(A, scheme, P):
+    if scheme == "regular_1d":
+        return opart.regular_1d(A.n, P)
+    if scheme == "regular_2d":
+        from paper_2003_05361_amd.studies import _square_split
+
+        return opart.regular_grid(A.grid, _square_split(P))
+    return opart.rcb(A.coords(), P, 0, 0.0)
+
+
+def _oracle_sweeps(A, owner, gamma, tol):
+    b = R.uniform_rhs(A.n, 1)
+    _, _, k = schwarz.RAS(A, owner, gamma, "chol", "fp64").sync(b, tol, 5000)
+    return k
+
+
+def _check_rows(rows):
+    for r in rows:
+        A = R.laplace2d(r["grid"])
+        owner = _oracle_owner(A, r["partitioner"], r["parts"])
+        vol = oover.comm_volume(owner, oover.subdomain_sets(A, owner, r["overlap"]))
+        assert r["comm"]["total_values"] == int(vol.sum()), r
+        assert r["comm"]["max_neighbours"] == int(np.count_nonzero(vol, axis=1).max()), r
+        assert r["sync"]["converged"] and r["async"]["converged"], r
+        assert r["sync"]["rel_residual"] < 1e-8 and r["async"]["rel_residual"] < 1e-8, r
+        k = _oracle_sweeps(A, owner, r["overlap"], 1e-8)
+        assert abs(r["sync"]["sweeps"] - k) <= 1, (r["sync"]["sweeps"], k, r)
+
+
+def test_overlap_study_small():
+    from paper_2003_05361_amd import studies
+
+    _say("overlap study: 40^2, 4 parts, overlaps 0,1,2,4")
+    rows = studies.main(["overlap", "--sizes", "40", "--overlaps", "0,1,2,4", "--nparts", "4",
+                         "--max-seconds", "20"])
+    assert [r["overlap"] for r in rows] == [0, 1, 2, 4]
+    _check_rows(rows)
+    sweeps = [r["sync"]["sweeps"] for r in rows]
+    assert all(a >= b for a, b in zip(sweeps, sweeps[1:])), sweeps
+    vols = [r["comm"]["total_values"] for r in rows]
+    assert all(a < b for a, b in zip(vols, vols[1:])), vols
+
+
+def test_partitioner_study_small():
+    from paper_2003_05361_amd import studies
+
+    _say("partitioner study: 4 parts of 256 unknowns, overlap 2")
+    rows = studies.main(["partitioners", "--parts", "4", "--per-part", "256", "--overlap", "2",
+                         "--max-seconds", "20"])
+    assert [r["partitioner"] for r in rows] == ["regular_1d", "regular_2d", "rcb"]
+    _check_rows(rows)
+    # strips have at most two neighbours (Sec. 3.2.1)
+    assert rows[0]["comm"]["max_neighbours"] <= 2
+    assert rows[0]["sync_speedup_vs_1d"] == 1.0

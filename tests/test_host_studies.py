@@ -1,0 +1,32 @@
+"""Host-side pieces of the parameter studies (no GPU): the communication
+summary, the square split of the 2-D scheme and the markdown summary."""
+import numpy as np
+
+from paper_2003_05361_amd import studies
+
+
+def test_square_split():
+    assert studies._square_split(16) == (4, 4)
+    assert studies._square_split(6) == (3, 2)
+    assert studies._square_split(7) == (7, 1)
+
+
+def test_comm_summary():
+    vol = np.array([[0, 3, 0], [3, 0, 2], [0, 2, 0]], dtype=np.int64)
+    s = studies.comm_summary(vol)
+    assert s["total_values"] == 10 and s["max_recv"] == 5 and s["max_neighbours"] == 2
+    assert abs(s["mean_neighbours"] - 4 / 3) < 1e-15
+
+
+def test_markdown_summary():
+    row = {"grid": 64, "parts": 4, "partitioner": "rcb", "overlap": 2, "max_band": 40, "band_entries": 1000,
+           "comm": {"total_values": 10, "max_neighbours": 2},
+           "sync": {"converged": True, "sweeps": 30, "seconds": 0.01, "ms_per_sweep": 0.33},
+           "async": {"converged": False, "seconds": 0.02, "local_solves_median": 41.0},
+           "async_free": {"converged": True, "seconds": 0.03, "local_solves_median": 52.0},
+           "async_speedup": 0.5, "async_free_speedup": 0.33,
+           "model_share": {"restrict_residual": 0.2, "local_solve": 0.7, "prolong": 0.1, "exchange": 0.01}}
+    md = studies.markdown("overlap", [row], {"overlap 2": np.eye(2, dtype=np.int64)}, "python -m x overlap")
+    assert "| 64^2 | 4 | rcb | 2 | 40 |" in md
+    assert "0.0200 (41 not conv.)" in md and "0.0300 (52)" in md
+    assert "| 0 | 1 | . |" in md
