@@ -80,13 +80,20 @@ typedef struct ras_partition {
 } ras_partition;
 
 /* Local solver (Sec. 3.3.1): a Cholesky factor of the local matrix computed
- * once at setup and applied by two banded triangular solves per local solve,
- * or cg_iters steps of conjugate gradients from a zero initial guess.
+ * once at setup and applied by two triangular solves per local solve, or
+ * cg_iters steps of conjugate gradients from a zero initial guess.
+ *   CHOL_BANDED: the factor in the local (ascending global id) order, stored
+ *     as a band; suits grid-ordered subdomains with narrow bands.
+ *   CHOL_SPARSE: the factor of the local matrix reordered by nested
+ *     dissection, stored sparse and applied by level-scheduled triangular
+ *     solves (Sec. 3.3.1's sparse direct solver class); suits irregular
+ *     subdomains and wide bands.  The subdomain's vector is kept in LDS, so a
+ *     subdomain may have at most ras_sparse_max_rows(storage) local rows.
  * storage: FP64, FP32 (float32 values and float32 local arithmetic) or
  * FP16_ROWSCALED (factor rows scaled by their float32 max-abs, entries
  * rounded to float16, float32 arithmetic; banded Cholesky only).  The outer
  * residual, update and convergence test are always float64.  */
-enum { RAS_LOCAL_CHOL_BANDED = 0, RAS_LOCAL_CG = 1 };
+enum { RAS_LOCAL_CHOL_BANDED = 0, RAS_LOCAL_CG = 1, RAS_LOCAL_CHOL_SPARSE = 2 };
 enum { RAS_STORAGE_FP64 = 0, RAS_STORAGE_FP32 = 1, RAS_STORAGE_FP16_ROWSCALED = 2 };
 typedef struct ras_local {
     int32_t kind;
@@ -190,6 +197,19 @@ ras_status ras_plan_factor(const ras_plan* plan, int32_t p, double* band, int32_
  * even from float64), scale[i] = float32(max_j |L_ij|) (1 for an all-zero row).
  * RAS_E_STATE unless the solver is Cholesky with FP16_ROWSCALED storage.  */
 ras_status ras_plan_factor_fp16(const ras_plan* plan, int32_t p, uint16_t* half_bits, float* scale);
+/* Sparse factor of subdomain p (CHOL_SPARSE plans; RAS_E_STATE otherwise):
+ * perm[n] gives, for each elimination step k, the position in Omega_p (as
+ * returned by ras_plan_sets) of the local row eliminated at step k; the
+ * strictly lower part of L (rows in elimination order) is returned in CSR form
+ * row_ptr[n+1], col[nnz], val[nnz] with columns ascending in each row, and
+ * diag[n] holds L_kk, so that L L^T = P A_p P^T with (P A_p P^T)_{kl} =
+ * (A_p)_{perm[k], perm[l]}.  *nnz receives the entry count; every array may
+ * be NULL (query).  */
+ras_status ras_plan_sparse_factor(const ras_plan* plan, int32_t p, int32_t* perm, int64_t* row_ptr, int32_t* col,
+                                  double* val, double* diag, int64_t* nnz);
+/* Largest subdomain (local rows) the sparse Cholesky solver accepts for a
+ * storage kind (FP64 or FP32), or 0 for a storage it does not support.  */
+int64_t ras_sparse_max_rows(int32_t storage);
 void ras_plan_destroy(ras_plan* plan);
 
 /* ---- device setup and solve ------------------------------------------------------

@@ -26,7 +26,7 @@ RAS_OK, RAS_NOT_CONVERGED, RAS_PENDING = 0, 1, 2
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "PENDING", -1: "E_ARG", -2: "E_PATTERN", -3: "E_NOT_SPD",
                 -4: "E_NOMEM", -5: "E_HIP", -6: "E_STATE", -7: "E_DIVERGED", -8: "E_UNSUPPORTED"}
 PART_KINDS = {"regular_1d": 0, "regular_2d": 1, "regular_3d": 2, "rcb": 3, "explicit": 4}
-LOCAL_KINDS = {"chol": 0, "cg": 1}
+LOCAL_KINDS = {"chol": 0, "cg": 1, "chol_sparse": 2}
 STORAGES = {"fp64": 0, "fp32": 1, "fp16": 2}
 MODES = {"sync": 0, "async": 1, "ordered": 2}
 DETECT = {"central": 0, "decentral": 1}
@@ -84,6 +84,8 @@ SIGNATURES = {
     "ras_plan_comm_volume": (C.c_int, [_P, _P]),
     "ras_plan_factor": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int32)]),
     "ras_plan_factor_fp16": (C.c_int, [_P, C.c_int32, _P, _P]),
+    "ras_plan_sparse_factor": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P, _P]),
+    "ras_sparse_max_rows": (C.c_int64, [C.c_int32]),
     "ras_plan_destroy": (None, [_P]),
     "ras_setup": (C.c_int, [C.POINTER(CSRStruct), C.POINTER(PartitionStruct), C.c_int32, C.POINTER(LocalStruct),
                             _P, C.POINTER(_P)]),
@@ -153,7 +155,8 @@ def partition(kind: str, parts, grid=(1, 1, 1), seed: int = 0, jitter: float = 0
 
 
 def local(kind: str = "chol", storage: str = "fp64", cg_iters: int = 0) -> dict:
-    """Local solver (Sec. 3.3.1): banded Cholesky ("chol") or fixed-k CG ("cg"); storage fp64/fp32/fp16."""
+    """Local solver (Sec. 3.3.1): banded Cholesky ("chol"), nested-dissection sparse Cholesky
+    ("chol_sparse") or fixed-k CG ("cg"); storage fp64/fp32/fp16."""
     if kind not in LOCAL_KINDS or storage not in STORAGES:
         raise ValueError((kind, storage))
     return dict(kind=kind, storage=storage, cg_iters=int(cg_iters))
@@ -250,6 +253,22 @@ class Plan:
         band = np.empty((n, w.value + 1))
         _check(lib().ras_plan_factor(self._p, p, band.ctypes.data, C.byref(w)))
         return band, w.value
+
+    def sparse_factor(self, p: int):
+        """(perm, row_ptr, col, val, diag) of subdomain p's sparse Cholesky factor:
+        L L^T = A_p[perm][:, perm], L's strictly lower part in CSR, diag = L_kk."""
+        nnz = C.c_int64()
+        _check(lib().ras_plan_sparse_factor(self._p, p, None, None, None, None, None, C.byref(nnz)))
+        _, ptr, _ = self.sets()
+        n = int(ptr[p + 1] - ptr[p])
+        perm = np.empty(n, dtype=np.int32)
+        rp = np.empty(n + 1, dtype=np.int64)
+        col = np.empty(nnz.value, dtype=np.int32)
+        val = np.empty(nnz.value)
+        diag = np.empty(n)
+        _check(lib().ras_plan_sparse_factor(self._p, p, perm.ctypes.data, rp.ctypes.data, col.ctypes.data,
+                                            val.ctypes.data, diag.ctypes.data, C.byref(nnz)))
+        return perm, rp, col, val, diag
 
     def factor_fp16(self, p: int) -> tuple[np.ndarray, np.ndarray]:
         band, w = self.factor(p)
@@ -461,6 +480,11 @@ class Server:
             self._s = None
 
     __del__ = close
+
+
+def sparse_max_rows(storage: str = "fp64") -> int:
+    """Largest subdomain the sparse Cholesky solver accepts for a storage kind."""
+    return int(lib().ras_sparse_max_rows(STORAGES[storage]))
 
 
 def version() -> str:

@@ -40,19 +40,22 @@ def build(verbose: bool = False) -> str:
         # host setup: plain IEEE arithmetic (no contraction) keeps the partitioner bit-exact
         (["g++", *COMMON, "-ffp-contract=off", "-c", os.path.join(CSRC, "plan.cpp"), "-o",
           os.path.join(BUILD, "plan.o")]),
+        (["g++", *COMMON, "-ffp-contract=off", "-c", os.path.join(CSRC, "sparse.cpp"), "-o",
+          os.path.join(BUILD, "sparse.o")]),
         ([HIPCC, *COMMON, "-ffp-contract=off", "-c", os.path.join(CSRC, "api.cpp"), "-o",
           os.path.join(BUILD, "api.o")]),
         ([HIPCC, *COMMON, f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-x", "hip", "-c",
           os.path.join(CSRC, "kernels.hip"), "-o", os.path.join(BUILD, "kernels.o")]),
     ]
-    with cf.ThreadPoolExecutor(max_workers=3) as ex:
+    with cf.ThreadPoolExecutor(max_workers=4) as ex:
         outs = list(ex.map(_run, jobs))
     if verbose:
         for o in outs:
             sys.stdout.write(o)
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp,
-          os.path.join(BUILD, "plan.o"), os.path.join(BUILD, "api.o"), os.path.join(BUILD, "kernels.o"),
+          os.path.join(BUILD, "plan.o"), os.path.join(BUILD, "sparse.o"), os.path.join(BUILD, "api.o"),
+          os.path.join(BUILD, "kernels.o"),
           "-lpthread"])
     os.replace(tmp, LIB)
     return LIB

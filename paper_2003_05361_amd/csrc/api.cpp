@@ -143,10 +143,13 @@ ras_status guarded(F&& f) {
     }
 }
 
+constexpr size_t kLdsLimit = 160 * 1024 - 4096;  // leave room for the kernels' static LDS
+
 void build_plan(const ras_csr* A, const ras_partition* part, int32_t overlap, const ras_local* local, Plan& plan) {
     if (!A || !part || !local) throw Error{RAS_E_ARG, "null argument"};
     if (overlap < 0) throw Error{RAS_E_ARG, "overlap must be >= 0"};
-    if (local->kind != RAS_LOCAL_CHOL_BANDED && local->kind != RAS_LOCAL_CG) throw Error{RAS_E_ARG, "unknown local solver"};
+    if (local->kind != RAS_LOCAL_CHOL_BANDED && local->kind != RAS_LOCAL_CG && local->kind != RAS_LOCAL_CHOL_SPARSE)
+        throw Error{RAS_E_ARG, "unknown local solver"};
     if (local->storage < RAS_STORAGE_FP64 || local->storage > RAS_STORAGE_FP16_ROWSCALED)
         throw Error{RAS_E_ARG, "unknown storage"};
     if (local->kind == RAS_LOCAL_CG && local->storage == RAS_STORAGE_FP16_ROWSCALED)
@@ -162,7 +165,18 @@ void build_plan(const ras_csr* A, const ras_partition* part, int32_t overlap, co
     plan.val.assign(A->val, A->val + plan.nnz);
     plan.owner = make_owner(*A, *part, &plan.P);
     build_overlap(plan);
-    if (local->kind == RAS_LOCAL_CHOL_BANDED) factor_local(plan);
+    if (local->kind == RAS_LOCAL_CHOL_SPARSE) {
+        if (local->storage == RAS_STORAGE_FP16_ROWSCALED)
+            throw Error{RAS_E_ARG, "FP16_ROWSCALED storage applies to the banded Cholesky factor only"};
+        const int64_t lim = ras_sparse_max_rows(local->storage);
+        for (int32_t p = 0; p < plan.P; ++p)
+            if (static_cast<int64_t>(plan.subs[p].omega.size()) > lim)
+                throw Error{RAS_E_UNSUPPORTED, "subdomain " + std::to_string(p) + " has " +
+                                                   std::to_string(plan.subs[p].omega.size()) +
+                                                   " local rows; the sparse solver keeps at most " +
+                                                   std::to_string(lim) + " in LDS"};
+        sparse_factor_local(plan);
+    }
 }
 
 void plan_stats(const Plan& plan, ras_plan_stats* o) {
@@ -462,7 +476,7 @@ void drop_factors(Plan& plan) {
     }
 }
 
-constexpr size_t kLdsLimit = 160 * 1024 - 4096;  // leave room for the kernels' static LDS
+
 
 struct InstSpec {
     ras_handle* h;
@@ -1316,6 +1330,30 @@ ras_status ras_plan_comm_volume(const ras_plan* plan, int64_t* volume) {
     return guarded([&] {
         if (!plan || !volume) throw Error{RAS_E_ARG, "null argument"};
         comm_volume(*plan, volume);
+        return RAS_OK;
+    });
+}
+
+int64_t ras_sparse_max_rows(int32_t storage) {
+    if (storage == RAS_STORAGE_FP64) return static_cast<int64_t>(kLdsLimit / sizeof(double));
+    if (storage == RAS_STORAGE_FP32) return static_cast<int64_t>(kLdsLimit / sizeof(float));
+    return 0;
+}
+
+ras_status ras_plan_sparse_factor(const ras_plan* plan, int32_t p, int32_t* perm, int64_t* row_ptr, int32_t* col,
+                                  double* val, double* diag, int64_t* nnz) {
+    return guarded([&] {
+        if (!plan) throw Error{RAS_E_ARG, "null plan"};
+        if (p < 0 || p >= plan->P) throw Error{RAS_E_ARG, "subdomain out of range"};
+        if (plan->local.kind != RAS_LOCAL_CHOL_SPARSE) throw Error{RAS_E_STATE, "plan has no sparse factors"};
+        const SparseFactor& F = plan->subs[p].sf;
+        if (F.perm.size() != plan->subs[p].omega.size()) throw Error{RAS_E_STATE, "factor released"};
+        if (nnz) *nnz = static_cast<int64_t>(F.lj.size());
+        if (perm) std::copy(F.perm.begin(), F.perm.end(), perm);
+        if (row_ptr) std::copy(F.lp.begin(), F.lp.end(), row_ptr);
+        if (col) std::copy(F.lj.begin(), F.lj.end(), col);
+        if (val) std::copy(F.lx.begin(), F.lx.end(), val);
+        if (diag) std::copy(F.d.begin(), F.d.end(), diag);
         return RAS_OK;
     });
 }

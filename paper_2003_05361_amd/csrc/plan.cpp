@@ -18,32 +18,6 @@ int worker_count() {
     return std::min(n, 16);
 }
 
-// Runs f(i, worker) for i in [0, count) on up to worker_count() threads.
-template <class F>
-void parallel_for(int64_t count, F&& f) {
-    int nw = static_cast<int>(std::min<int64_t>(worker_count(), count));
-    if (nw <= 1) {
-        for (int64_t i = 0; i < count; ++i) f(i, 0);
-        return;
-    }
-    std::atomic<int64_t> next{0};
-    std::vector<std::thread> ts;
-    std::vector<Error> errs(nw, Error{RAS_OK, {}});
-    for (int t = 0; t < nw; ++t) {
-        ts.emplace_back([&, t] {
-            try {
-                for (int64_t i; (i = next.fetch_add(1)) < count;) f(i, t);
-            } catch (const Error& e) {
-                errs[t] = e;
-                next.store(count);
-            }
-        });
-    }
-    for (auto& th : ts) th.join();
-    for (auto& e : errs)
-        if (e.status != RAS_OK) throw e;
-}
-
 // ------------------------------------------------------------------------------ CSR checks
 void validate_csr(const ras_csr& A) {
     if (A.n < 1 || A.n > INT32_MAX) throw Error{RAS_E_ARG, "n must be in [1, 2^31)"};

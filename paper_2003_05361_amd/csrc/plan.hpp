@@ -7,13 +7,28 @@
 // factor of each local matrix (Sec. 3.3.1).
 #pragma once
 
+#include <atomic>
 #include <cstdint>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/ras.h"
 
 namespace ras {
+
+// Sparse Cholesky factor of a local matrix in elimination order: row k of the
+// permuted matrix is row perm[k] of Omega_p's local matrix (ascending global id).
+struct SparseFactor {
+    std::vector<int32_t> perm;   // elimination order -> position in omega
+    std::vector<int64_t> lp;     // [n + 1] rows of the strictly lower part of L
+    std::vector<int32_t> lj;     // column of each entry, ascending within a row
+    std::vector<double> lx;
+    std::vector<int64_t> cp;     // [n + 1] the same entries by columns (rows ascending)
+    std::vector<int32_t> ci;
+    std::vector<double> cx;
+    std::vector<double> d;       // diagonal of L
+};
 
 struct Subdomain {
     std::vector<int32_t> omega;  // overlapping set, ascending global ids
@@ -24,6 +39,7 @@ struct Subdomain {
     std::vector<double> L;       // Cholesky: row-major lower band, L[i*(w+1) + (j-i+w)]
     std::vector<uint16_t> Lh;    // FP16_ROWSCALED: float16 bits of L / scale(row)
     std::vector<float> scale;    // FP16_ROWSCALED: per-row scale
+    SparseFactor sf;             // sparse Cholesky solver only
 };
 
 struct Plan {
@@ -53,10 +69,39 @@ std::vector<int32_t> external_set(const Plan& plan, const Subdomain& sd);
 // volume[p*P + q] = |(Omega_p u ext(Omega_p)) n O_q| for q != p, 0 on the diagonal
 void comm_volume(const Plan& plan, int64_t* volume);
 void factor_local(Plan& plan);
+std::vector<int32_t> nested_dissection(const Plan& plan, const Subdomain& sd);
+void sparse_factor_local(Plan& plan);
 uint16_t f64_to_f16_rne(double d);
 
 uint64_t splitmix64_next(uint64_t& state);
 
 int worker_count();
+
+// Runs f(i, worker) for i in [0, count) on up to worker_count() threads.
+template <class F>
+inline void parallel_for(int64_t count, F&& f) {
+    int nw = static_cast<int>(std::min<int64_t>(worker_count(), count));
+    if (nw <= 1) {
+        for (int64_t i = 0; i < count; ++i) f(i, 0);
+        return;
+    }
+    std::atomic<int64_t> next{0};
+    std::vector<std::thread> ts;
+    std::vector<Error> errs(nw, Error{RAS_OK, {}});
+    for (int t = 0; t < nw; ++t) {
+        ts.emplace_back([&, t] {
+            try {
+                for (int64_t i; (i = next.fetch_add(1)) < count;) f(i, t);
+            } catch (const Error& e) {
+                errs[t] = e;
+                next.store(count);
+            }
+        });
+    }
+    for (auto& th : ts) th.join();
+    for (auto& e : errs)
+        if (e.status != RAS_OK) throw e;
+}
+
 
 }  // namespace ras

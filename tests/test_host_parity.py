@@ -261,3 +261,66 @@ def test_plan_stats_config2_shape():
     st = plan.stats()
     assert st["parts"] == 64 and st["max_ell_width"] == 5
     assert st["min_local_rows"] == 17414 and st["max_local_rows"] == 18456
+
+
+# ----------------------------------------------------------------------------- sparse Cholesky (host)
+SPARSE_CASES = [
+    ("poisson2d_40_2x2_g3", R.laplace2d(40), ("regular_2d", (2, 2)), 3),
+    ("laplace3d_12_rcb5_g1", R.laplace3d(12), ("rcb", (5, 2, 0.3)), 1),
+    ("tpfa2d_24_strips3_g2", R.tpfa2d(np.exp(2 * R.gaussian_random_field_2d(24, 4.0, 3)), 10.0), ("regular_1d", 3), 2),
+]
+
+
+@pytest.mark.parametrize("name,A,part,gamma", SPARSE_CASES, ids=[c[0] for c in SPARSE_CASES])
+def test_sparse_factor_is_cholesky_of_permuted_local_matrix(name, A, part, gamma):
+    """L L^T = A_p[perm][:, perm] with L lower triangular and a positive diagonal,
+    perm a permutation of the local rows (Sec. 3.3.1: exact local solves)."""
+    _lib_or_skip()
+    kind, arg = part
+    spec = (ras.partition("rcb", arg[0], grid=A.grid, seed=arg[1], jitter=arg[2]) if kind == "rcb"
+            else ras.partition(kind, arg, grid=A.grid))
+    plan = ras.Plan(A, spec, gamma, ras.local("chol_sparse", "fp64"))
+    owner, ptr, idx = plan.sets()
+    M = A.scipy().tocsr()
+    for p in range(len(ptr) - 1):
+        om = idx[ptr[p]:ptr[p + 1]]
+        n = om.size
+        perm, rp, col, val, diag = plan.sparse_factor(p)
+        assert np.array_equal(np.sort(perm), np.arange(n))
+        assert np.all(diag > 0)
+        L = np.zeros((n, n))
+        for k in range(n):
+            cs = col[rp[k]:rp[k + 1]]
+            assert np.all(cs < k) and np.all(np.diff(cs) > 0)
+            L[k, cs] = val[rp[k]:rp[k + 1]]
+            L[k, k] = diag[k]
+        Ap = M[om][:, om].toarray()[np.ix_(perm, perm)]
+        assert np.max(np.abs(L @ L.T - Ap)) <= 1e-12 * np.max(np.abs(Ap))
+
+
+def test_nested_dissection_reduces_fill_of_wide_bands():
+    """A strip of 8 grid lines of a 96-wide grid: the natural order's band is the
+    grid width, nested dissection keeps the factor several times smaller."""
+    _lib_or_skip()
+    A = R.laplace2d(96, 32)
+    plan = ras.Plan(A, ras.partition("regular_1d", 4, grid=A.grid), 0, ras.local("chol_sparse", "fp64"))
+    _, ptr, _ = plan.sets()
+    for p in range(4):
+        n = int(ptr[p + 1] - ptr[p])
+        _, rp, _, _, _ = plan.sparse_factor(p)
+        band_entries = n * (plan.band_width(p) + 1)
+        assert rp[-1] + n < 0.5 * band_entries, (rp[-1], band_entries)
+
+
+def test_sparse_solver_arguments():
+    _lib_or_skip()
+    A = R.laplace2d(12)
+    with pytest.raises(ras.RasError) as e:
+        ras.Plan(A, ras.partition("regular_2d", (2, 2), grid=A.grid), 1, ras.local("chol_sparse", "fp16"))
+    assert e.value.status == -1
+    assert ras.sparse_max_rows("fp64") > 18000 and ras.sparse_max_rows("fp32") == 2 * ras.sparse_max_rows("fp64")
+    assert ras.sparse_max_rows("fp16") == 0
+    plan = ras.Plan(A, ras.partition("regular_2d", (2, 2), grid=A.grid), 1, ras.local("chol", "fp64"))
+    with pytest.raises(ras.RasError) as e:
+        plan.sparse_factor(0)
+    assert e.value.status == -6
