@@ -162,7 +162,7 @@ typedef struct ras_plan_stats {
     int64_t max_local_rows;
     int32_t max_band;          /* max lower half-bandwidth of the local matrices */
     int32_t reserved;
-    int64_t band_entries;      /* sum_p |Omega_p| (w_p + 1) */
+    int64_t band_entries;      /* factor entries: sum_p |Omega_p| (w_p + 1); sparse solver: sum_p nnz(L_p) */
     int64_t device_bytes;      /* device memory the handle allocates for the matrix data */
 } ras_plan_stats;
 

@@ -110,10 +110,11 @@ struct ras_handle {
     int max_n = 0, max_w = 0, max_K = 0, uniform_K = 0;
     int max_w_rowmajor = -1;  // widest band kept row-major (w > kSlabMaxW), -1 if none
     bool any_slab = false;
+    bool sparse = false;      // sparse Cholesky solver: device local order = elimination order
     int64_t sum_n = 0;
     int64_t sum_snap = 0;  // sum over subdomains of n + n_ext (asynchronous snapshot size per right-hand side)
     ras_plan_stats stats{};
-    DevBuf omega, ell_val, ell_valf, ell_gcol, ell_lcol, band_f, band_b, scale, invd, ext;
+    DevBuf omega, ell_val, ell_valf, ell_gcol, ell_lcol, band_f, band_b, scale, invd, ext, sp_idx, sp_val;
     DevBuf csr_rp, csr_ci, csr_va, nbr;
     std::vector<SubDev> subs;  // host copy with device pointers
     // CG team windows: for team size kTeamSizes[t], per subdomain and member the
@@ -165,6 +166,7 @@ void build_plan(const ras_csr* A, const ras_partition* part, int32_t overlap, co
     plan.val.assign(A->val, A->val + plan.nnz);
     plan.owner = make_owner(*A, *part, &plan.P);
     build_overlap(plan);
+    if (local->kind == RAS_LOCAL_CHOL_BANDED) factor_local(plan);
     if (local->kind == RAS_LOCAL_CHOL_SPARSE) {
         if (local->storage == RAS_STORAGE_FP16_ROWSCALED)
             throw Error{RAS_E_ARG, "FP16_ROWSCALED storage applies to the banded Cholesky factor only"};
@@ -192,7 +194,8 @@ void plan_stats(const Plan& plan, ras_plan_stats* o) {
         o->min_local_rows = std::min(o->min_local_rows, n);
         o->max_local_rows = std::max(o->max_local_rows, n);
         o->max_band = std::max(o->max_band, s.w);
-        o->band_entries += n * (s.w + 1);
+        o->band_entries += plan.local.kind == RAS_LOCAL_CHOL_SPARSE ? static_cast<int64_t>(s.sf.lj.size()) + n
+                                                                    : n * (s.w + 1);
     }
 }
 
@@ -208,9 +211,49 @@ constexpr int64_t kSlabTailBytes = 4096;
 
 // Upload the plan: ELL rows of A on every overlapping set, local column map,
 // factors in the storage type (forward L and reversed transpose), global CSR.
+// Level-scheduled form of one triangular pass of a sparse factor.  rows_of(k)
+// lists the (row, value) dependencies of row k; `ascending` tells whether rows
+// are solved first to last (L) or last to first (L^T).
+struct SparsePass {
+    std::vector<int32_t> lev, rows, ep, col;
+    std::vector<double> val;
+};
+
+SparsePass sparse_pass(int32_t n, const std::vector<int64_t>& ptr, const std::vector<int32_t>& idx,
+                       const std::vector<double>& x, bool ascending) {
+    std::vector<int32_t> level(n, 0);
+    int32_t nlev = 0;
+    for (int32_t s = 0; s < n; ++s) {
+        const int32_t k = ascending ? s : n - 1 - s;
+        int32_t l = 0;
+        for (int64_t e = ptr[k]; e < ptr[k + 1]; ++e) l = std::max(l, level[idx[e]] + 1);
+        level[k] = l;
+        nlev = std::max(nlev, l + 1);
+    }
+    SparsePass sp;
+    sp.lev.assign(nlev + 1, 0);
+    for (int32_t k = 0; k < n; ++k) ++sp.lev[level[k] + 1];
+    for (int32_t l = 0; l < nlev; ++l) sp.lev[l + 1] += sp.lev[l];
+    std::vector<int32_t> pos(sp.lev.begin(), sp.lev.end() - 1);
+    sp.rows.assign(n, 0);
+    for (int32_t k = 0; k < n; ++k) sp.rows[pos[level[k]]++] = k;
+    sp.ep.assign(n + 1, 0);
+    for (int32_t t = 0; t < n; ++t) {
+        const int32_t k = sp.rows[t];
+        for (int64_t e = ptr[k]; e < ptr[k + 1]; ++e) {
+            sp.col.push_back(idx[e]);
+            sp.val.push_back(x[e]);
+        }
+        sp.ep[t + 1] = static_cast<int32_t>(sp.col.size());
+    }
+    return sp;
+}
+
 void upload(ras_handle& h, const Plan& plan) {
     const int P = plan.P;
+    const bool sparse = plan.local.kind == RAS_LOCAL_CHOL_SPARSE;
     const bool chol = plan.local.kind == RAS_LOCAL_CHOL_BANDED;
+    h.sparse = sparse;
     const int st = plan.local.storage;
     h.solver = plan.local.kind;
     h.storage = st;
@@ -236,11 +279,26 @@ void upload(ras_handle& h, const Plan& plan) {
     h.sum_n = row_off[P];
     const size_t cts = ct_size(st);
     const size_t sts = st == RAS_STORAGE_FP64 ? 8 : st == RAS_STORAGE_FP32 ? 4 : 2;
+    int64_t sp_idx_used = 0, sp_val_used = 0;
+    if (sparse) {
+        // per subdomain and pass: levels + rows + entry pointers + columns, each padded
+        // to 4 int32, and the values padded to 16 bytes
+        int64_t ni = 0, nv = 0;
+        for (int p = 0; p < P; ++p) {
+            const int64_t n = static_cast<int64_t>(plan.subs[p].omega.size());
+            const int64_t nnz = static_cast<int64_t>(plan.subs[p].sf.lj.size());
+            ni += 2 * ((n + 2 + 3) / 4 * 4 + (n + 3) / 4 * 4 + (n + 1 + 3) / 4 * 4 + (nnz + 3) / 4 * 4);
+            nv += 2 * ((nnz * static_cast<int64_t>(sts) + 15) / 16 * 16);
+        }
+        h.sp_idx.alloc(std::max<int64_t>(ni, 1) * sizeof(int32_t));
+        h.sp_val.alloc(std::max<int64_t>(nv, 16));
+    }
     h.omega.alloc(row_off[P] * sizeof(int32_t));
     h.ell_val.alloc(ell_off[P] * sizeof(double));
     if (!chol && st == RAS_STORAGE_FP32) h.ell_valf.alloc(ell_off[P] * sizeof(float));
     h.ell_gcol.alloc(ell_off[P] * sizeof(int32_t));
     h.ell_lcol.alloc(ell_off[P] * sizeof(int32_t));
+    if (sparse) h.invd.alloc(row_off[P] * cts);
     if (chol) {
         // tail: the last load round of a slab block may read up to one round past its end
         h.band_f.alloc(band_off[P] * sts + kSlabTailBytes);
@@ -269,14 +327,19 @@ void upload(ras_handle& h, const Plan& plan) {
         const int64_t n = static_cast<int64_t>(s.omega.size());
         const int64_t np = n_pad_of(n);
         const int K = s.ell_width;
+        // device local order: ascending global id, or the elimination order of the
+        // sparse factor (device row i is omega position dpos[i])
+        std::vector<int32_t> dpos(n), drow(n);
+        for (int64_t i = 0; i < n; ++i) dpos[i] = sparse ? s.sf.perm[i] : static_cast<int32_t>(i);
+        for (int64_t i = 0; i < n; ++i) drow[dpos[i]] = static_cast<int32_t>(i);
         om.resize(n);
-        for (int64_t i = 0; i < n; ++i) om[i] = s.owned[i] ? s.omega[i] : ~s.omega[i];
+        for (int64_t i = 0; i < n; ++i) om[i] = s.owned[dpos[i]] ? s.omega[dpos[i]] : ~s.omega[dpos[i]];
         ev.assign(np * K, 0.0);
         eg.assign(np * K, 0);
         el.assign(np * K, 0);
         xe = external_set(plan, s);
         for (int64_t i = 0; i < n; ++i) {
-            const int32_t g = s.omega[i];
+            const int32_t g = s.omega[dpos[i]];
             int k = 0;
             for (int64_t e = plan.row_ptr[g]; e < plan.row_ptr[g + 1]; ++e, ++k) {
                 const int32_t c = plan.col[e];
@@ -284,7 +347,7 @@ void upload(ras_handle& h, const Plan& plan) {
                 eg[k * np + i] = c;
                 auto it = std::lower_bound(s.omega.begin(), s.omega.end(), c);
                 if (it != s.omega.end() && *it == c)
-                    el[k * np + i] = static_cast<int32_t>(it - s.omega.begin());
+                    el[k * np + i] = drow[it - s.omega.begin()];
                 else
                     el[k * np + i] = static_cast<int32_t>(n + (std::lower_bound(xe.begin(), xe.end(), c) - xe.begin()));
             }
@@ -420,6 +483,65 @@ void upload(ras_handle& h, const Plan& plan) {
                 d.scale = h.scale.as<float>() + row_off[p];
             }
         }
+        if (sparse) {
+            const SparseFactor& F = s.sf;
+            const SparsePass fw = sparse_pass(static_cast<int32_t>(n), F.lp, F.lj, F.lx, true);
+            const SparsePass bw = sparse_pass(static_cast<int32_t>(n), F.cp, F.ci, F.cx, false);
+            const SparsePass* ps[2] = {&fw, &bw};
+            std::vector<int32_t> idx;
+            std::vector<unsigned char> vals;
+            int64_t ioff[2][4], voff[2];
+            for (int k = 0; k < 2; ++k) {
+                const SparsePass& q = *ps[k];
+                const std::vector<int32_t>* parts[4] = {&q.lev, &q.rows, &q.ep, &q.col};
+                for (int a = 0; a < 4; ++a) {
+                    ioff[k][a] = sp_idx_used + static_cast<int64_t>(idx.size());
+                    idx.insert(idx.end(), parts[a]->begin(), parts[a]->end());
+                    while (idx.size() % 4) idx.push_back(0);  // 16-byte aligned arrays
+                }
+                voff[k] = sp_val_used + static_cast<int64_t>(vals.size());
+                for (double x : q.val) {
+                    if (st == RAS_STORAGE_FP64) {
+                        const unsigned char* b = reinterpret_cast<const unsigned char*>(&x);
+                        vals.insert(vals.end(), b, b + 8);
+                    } else {
+                        const float f = static_cast<float>(x);
+                        const unsigned char* b = reinterpret_cast<const unsigned char*>(&f);
+                        vals.insert(vals.end(), b, b + 4);
+                    }
+                }
+                while (vals.size() % 16) vals.push_back(0);
+                d.sp_nlev[k] = static_cast<int32_t>(q.lev.size()) - 1;
+            }
+            hip_check(hipMemcpy(h.sp_idx.as<int32_t>() + sp_idx_used, idx.data(), idx.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice),
+                      "copy sparse index");
+            hip_check(hipMemcpy(static_cast<char*>(h.sp_val.p) + sp_val_used, vals.data(), vals.size(),
+                                hipMemcpyHostToDevice),
+                      "copy sparse values");
+            for (int k = 0; k < 2; ++k) {
+                d.sp_lev[k] = h.sp_idx.as<int32_t>() + ioff[k][0];
+                d.sp_rows[k] = h.sp_idx.as<int32_t>() + ioff[k][1];
+                d.sp_ep[k] = h.sp_idx.as<int32_t>() + ioff[k][2];
+                d.sp_col[k] = h.sp_idx.as<int32_t>() + ioff[k][3];
+                d.sp_val[k] = static_cast<char*>(h.sp_val.p) + voff[k];
+            }
+            sp_idx_used += static_cast<int64_t>(idx.size());
+            sp_val_used += static_cast<int64_t>(vals.size());
+            iv.resize(n * cts);
+            for (int64_t i = 0; i < n; ++i) {
+                if (st == RAS_STORAGE_FP64)
+                    reinterpret_cast<double*>(iv.data())[i] = 1.0 / F.d[i];
+                else
+                    reinterpret_cast<float*>(iv.data())[i] =
+                        static_cast<float>(1.0 / static_cast<double>(static_cast<float>(F.d[i])));
+            }
+            hip_check(hipMemcpy(static_cast<char*>(h.invd.p) + row_off[p] * cts, iv.data(), n * cts,
+                                hipMemcpyHostToDevice),
+                      "copy invd");
+            d.invd = static_cast<char*>(h.invd.p) + row_off[p] * cts;
+            d.sparse = 1;
+        }
         h.subs[p] = d;
     }
     // neighbours: subdomains owning a column read by a row of Omega_p (the
@@ -465,7 +587,7 @@ void upload(ras_handle& h, const Plan& plan) {
     h.stats.device_bytes = static_cast<int64_t>(h.omega.bytes + h.ell_val.bytes + h.ell_valf.bytes + h.ell_gcol.bytes +
                                                 h.ell_lcol.bytes + h.band_f.bytes + h.band_b.bytes + h.invd.bytes +
                                                 h.scale.bytes + h.csr_rp.bytes + h.csr_ci.bytes + h.csr_va.bytes +
-                                                h.ext.bytes);
+                                                h.ext.bytes + h.sp_idx.bytes + h.sp_val.bytes);
 }
 
 void drop_factors(Plan& plan) {
@@ -542,14 +664,17 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
             const size_t cts = ct_size(h0.storage);
             const int sts = h0.storage == RAS_STORAGE_FP64 ? 8 : h0.storage == RAS_STORAGE_FP32 ? 4 : 2;
             int wrm = -1, wslab = -1;
+            size_t wsparse = 0;
             for (ras_handle* h : hs) {
                 wrm = std::max(wrm, h->max_w_rowmajor);
                 if (h->any_slab) wslab = std::max(wslab, std::min(h->max_w, kSlabMaxW));
+                if (h->sparse) wsparse = std::max(wsparse, static_cast<size_t>(h->max_n) * cts);  // y in LDS
             }
             const int win = next_pow2(2 * max_w + 2 * kBandRows);
             size_t bytes = 0;
             if (wslab >= 0) bytes = std::max(bytes, slab_lds_bytes(sts, static_cast<int>(cts), wslab, win));
             if (wrm >= 0) bytes = std::max(bytes, (static_cast<size_t>(win) + static_cast<size_t>(kBandRows) * (wrm + 1)) * cts);
+            bytes = std::max(bytes, wsparse);
             c.rclass = kBandRows;
             c.winm = win - 1;
             c.lds = bytes;
@@ -1007,6 +1132,10 @@ int64_t estimate_device_bytes(const Plan& plan, int nrhs) {
         const int64_t ell = n_pad_of(n) * sd.ell_width;
         bytes += 8 * n + ell * (8 + 4 + 4 + (!chol && plan.local.storage == RAS_STORAGE_FP32 ? 4 : 0)) + 512;
         if (chol) bytes += 2 * ((band_elems(n, sd.w) + 63) / 64 * 64) * sts + n * cts + (plan.local.storage == 2 ? 4 * n : 0);
+        if (plan.local.kind == RAS_LOCAL_CHOL_SPARSE) {
+            const int64_t nnz = static_cast<int64_t>(sd.sf.lj.size());
+            bytes += 2 * (4 * (3 * n + 16) + nnz * (4 + sts) + 32) + n * cts;
+        }
     }
     if (chol) bytes += 2 * kSlabTailBytes;
     // per right-hand side: b, x, local vector, x snapshot (omega plus an external layer,

@@ -67,6 +67,17 @@ struct SubDev {
     int32_t n_ext;
     int32_t pad2_;
     int64_t snap_off;         // offset of this subdomain's x snapshot (n + n_ext values) per right-hand side
+    // sparse Cholesky (local rows in elimination order); pass 0 = L (forward), 1 = L^T (backward):
+    // rows of level l are sp_rows[pass][sp_lev[pass][l] .. sp_lev[pass][l + 1]); the entries of
+    // the row at level-order position t are [sp_ep[pass][t], sp_ep[pass][t + 1]) of sp_col / sp_val
+    const int32_t* sp_lev[2];
+    const int32_t* sp_rows[2];
+    const int32_t* sp_ep[2];
+    const int32_t* sp_col[2];
+    const void* sp_val[2];    // storage type
+    int32_t sp_nlev[2];
+    int32_t sparse;           // 1: sparse Cholesky factor (sp_* valid)
+    int32_t pad3_;
 };
 
 // One work item: subdomain `sub` of right-hand side (instance) `inst`.

@@ -1074,6 +1074,58 @@ __device__ __forceinline__ void slab_solve(const SubU& s, RAS_GLOBAL typename St
                  true);
 }
 
+// One level-scheduled triangular pass over a sparse factor (Sec. 3.3.1's
+// sparse direct solve): the rows of a level depend only on rows of earlier
+// levels, so each level is one parallel step,
+//   y[i] = (y[i] - sum_e val[e] * y[col[e]]) / L_ii   for every row i of the level,
+// with y resident in LDS and the entries streamed once from HBM.  A level with
+// few rows gets more lanes per row (up to a wave), a wide level one short group
+// per row; each group sums its row's entries and reduces across its lanes.
+template <class ST>
+__device__ __attribute__((noinline)) void sparse_run(RAS_GLOBAL const int32_t* lev, RAS_GLOBAL const int32_t* rows,
+                                                     RAS_GLOBAL const int32_t* ep, RAS_GLOBAL const int32_t* col,
+                                                     RAS_GLOBAL const ST* val,
+                                                     RAS_GLOBAL const typename StorageTraits<ST>::CT* invd, int nlev,
+                                                     RAS_LDS typename StorageTraits<ST>::CT* y) {
+    using CT = typename StorageTraits<ST>::CT;
+    constexpr int B = kBandThreads;
+    const int tid = threadIdx.x;
+    int t0 = uni(lev[0]);
+    for (int l = 0; l < nlev; ++l) {
+        const int t1 = uni(lev[l + 1]);
+        const int R = t1 - t0;
+        int G = 64;
+        while (G > 4 && R * G > 2 * B) G >>= 1;
+        const int gi = tid / G, gl = tid & (G - 1), ng = B / G;
+        for (int t = t0 + gi; t < t1; t += ng) {
+            const int i = rows[t];
+            const int e1 = ep[t + 1];
+            CT acc = CT(0);
+            for (int e = ep[t] + gl; e < e1; e += G) acc += static_cast<CT>(val[e]) * y[col[e]];
+            for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+            if (gl == 0) y[i] = (y[i] - acc) * invd[i];
+        }
+        __syncthreads();
+        t0 = t1;
+    }
+}
+
+template <class ST>
+__device__ __forceinline__ void sparse_solve(const SubDev* sd, int n, RAS_GLOBAL typename StorageTraits<ST>::CT* v,
+                                             RAS_GLOBAL const typename StorageTraits<ST>::CT* invd, unsigned char* lds) {
+    using CT = typename StorageTraits<ST>::CT;
+    RAS_LDS CT* y = (RAS_LDS CT*)(lds);
+    for (int i = threadIdx.x; i < n; i += kBandThreads) y[i] = v[i];
+    __syncthreads();
+#pragma unroll 1
+    for (int pass = 0; pass < 2; ++pass)
+        sparse_run<ST>(gptr(sd->sp_lev[pass]), gptr(sd->sp_rows[pass]), gptr(sd->sp_ep[pass]),
+                       gptr(sd->sp_col[pass]), gptr(static_cast<const ST*>(sd->sp_val[pass])), invd,
+                       uni(sd->sp_nlev[pass]), y);
+    for (int i = threadIdx.x; i < n; i += kBandThreads) v[i] = y[i];
+    __syncthreads();
+}
+
 template <class ST, bool ASYNC>
 struct BandUpdate {
     using CT = typename StorageTraits<ST>::CT;
@@ -1091,6 +1143,7 @@ struct BandUpdate {
         __shared__ CT gsum[kBandRows];
         const SubU s = load_sub(P.subs + item.sub);
         const int slab = uni(P.subs[item.sub].slab);
+        const int sparse = uni(P.subs[item.sub].sparse);
         const InstU in = load_inst(P.insts + item.inst);
         const int tid = threadIdx.x;
         const int n = s.n;
@@ -1121,7 +1174,10 @@ struct BandUpdate {
         // the loaders read v back through global-to-LDS loads
         __builtin_amdgcn_s_waitcnt(0);
         block_sum3<B>(own2, loc2, b2, red3);
-        if (slab) {
+        if (sparse) {
+            if constexpr (sizeof(ST) != 2)
+                sparse_solve<ST>(P.subs + item.sub, n, v, gptr(static_cast<const CT*>(s.invd)), smem);
+        } else if (slab) {
             slab_solve<ST>(s, v, smem, winm, stage_bytes);
         } else {
             RAS_GLOBAL ST* Lf = gptr(static_cast<const ST*>(s.band_f));

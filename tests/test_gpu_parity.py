@@ -211,6 +211,53 @@ def test_sync_band_widths_match_oracle(case, storage, tol):
         assert _rel(x.cpu().numpy(), xo) <= tol
 
 
+# sparse Cholesky local solves (nested dissection, level-scheduled triangular
+# passes): exact local solves like the band, so the synchronous iterates match the
+# oracle's exact-solve RAS to rounding (float64) or float32 rounding growth
+@pytest.mark.parametrize("case,storage,tol", [
+    ("2d96_4x4_g3", "fp64", 1e-9), ("3d16_rcb6_g1", "fp64", 1e-9), ("2d_strips_w320", "fp64", 1e-9),
+    ("2d96_4x4_g3", "fp32", 2e-5), ("3d16_rcb6_g1", "fp32", 2e-5)])
+def test_sync_sparse_cholesky_matches_oracle(case, storage, tol):
+    ras = _ras()
+    _say(f"case: sparse cholesky {case} {storage}")
+    A, part, gamma = {
+        "2d96_4x4_g3": (R.laplace2d(96), ("regular_2d", (4, 4)), 3),
+        "3d16_rcb6_g1": (R.laplace3d(16), ("rcb", (6, 5, 0.3)), 1),
+        "2d_strips_w320": (R.laplace2d(320, 24), ("regular_1d", 2), 2),
+    }[case]
+    b = R.uniform_rhs(A.n, 22)
+    orc = _oracle(A, *part, gamma, "chol", "fp64")
+    h = ras.setup(A, _spec(ras, A, *part), gamma, ras.local("chol_sparse", storage))
+    for sweeps in (1, 3):
+        xo, ho, _ = orc.sync(b, 0.0, sweeps)
+        x, _ = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=sweeps)
+        assert _rel(x.cpu().numpy(), xo) <= tol, (sweeps, _rel(x.cpu().numpy(), xo))
+    _, hist, _ = orc.sync(b, 0.0, 6)
+    h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=6)
+    _, hh = h.residual_history()
+    if storage == "fp64":
+        assert np.all(np.abs(hh[:7] - hist[:7]) <= 1e-9 * hist[:7] + 1e-13)
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_async_sparse_cholesky_converges(storage):
+    """Asynchronous (paced and free-running) sparse local solves reach the tolerance,
+    also where the natural-order band (grid width 700) is too wide for the band solver."""
+    ras = _ras()
+    for A, part, gamma in [(R.laplace2d(96), ("regular_2d", (4, 4)), 3),
+                           (R.laplace2d(700, 20), ("regular_1d", 2), 2)]:
+        _say(f"case: async sparse {A.grid} {part} {storage}")
+        b = R.uniform_rhs(A.n, 23)
+        xd = schwarz.direct_solve(A, b)
+        h = ras.setup(A, _spec(ras, A, *part), gamma, ras.local("chol_sparse", storage))
+        for pace in (None, 0.0):
+            x, info = h.solve(_cuda(b), tol=1e-9, mode="async", max_sweeps=100000, max_seconds=60, pace=pace)
+            xx = x.cpu().numpy()
+            assert info[0]["converged"], info
+            assert schwarz.relative_residual(A, xx, b) < 1e-9
+            assert _rel(xx, xd) <= 1e-6
+
+
 def test_async_banded_runs_converge_every_time():
     """Regression: asynchronous banded runs on many concurrent workgroups converge
     in every repeat, with a bounded number of local solves (every update works on
