@@ -33,6 +33,9 @@ WORKLOADS = {
     "diffusion2d_2048_16x16_fp64": ("diffusion2d_2048_16x16", "chol", "fp64", 0),
     "diffusion2d_2048_16x16_fp32": ("diffusion2d_2048_16x16", "chol", "fp32", 0),
     "diffusion2d_2048_16x16_fp16": ("diffusion2d_2048_16x16", "chol", "fp16", 0),
+    "diffusion2d_2048_16x16_sparse_fp64": ("diffusion2d_2048_16x16", "chol_sparse", "fp64", 0),
+    "poisson2d_512_strips64_sparse_fp64": ("poisson2d_512_strips64", "chol_sparse", "fp64", 0),
+    "poisson2d_512_strips64_fp64": ("poisson2d_512_strips64", "chol", "fp64", 0),
     "poisson2d_64_strips4": ("poisson2d_64_strips4", "chol", "fp64", 0),
     "serving": (None, None, None, 0),
 }
@@ -64,13 +67,15 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def subdomain_shapes(A, part_kind, part_arg, gamma):
-    """(n_p, owned_p, K_p, w_p) per subdomain from the library's own host setup."""
+def subdomain_shapes(A, part_kind, part_arg, gamma, kind="cg"):
+    """(n_p, owned_p, K_p, w_p[, nnz(L_p)]) per subdomain from the library's own host setup."""
     import paper_2003_05361_amd as ras
     from paper_2003_05361_amd.perfmodel import subdomain_shapes as shapes_of
 
-    plan = ras.Plan(A, part_spec(ras, A, part_kind, part_arg), gamma, ras.local("cg", "fp64", 1))
-    shapes = shapes_of(plan, A.indptr)
+    sparse = kind == "chol_sparse"
+    loc = ras.local("chol_sparse", "fp64") if sparse else ras.local("cg", "fp64", 1)
+    plan = ras.Plan(A, part_spec(ras, A, part_kind, part_arg), gamma, loc)
+    shapes = shapes_of(plan, A.indptr, sparse)
     plan.close()
     return shapes
 
@@ -97,7 +102,8 @@ def cpu_baseline(A, b, part_kind, part_arg, gamma, kind, storage, k, gpu_sync_sw
     else:
         owner = opart.regular_grid(A.grid, part_arg)
     with threadpool_limits(1):
-        orc = schwarz.RAS(A, owner, gamma, kind, storage, k)
+        # the sparse factor solves the same local systems exactly: the oracle's exact local solve
+        orc = schwarz.RAS(A, owner, gamma, "chol" if kind == "chol_sparse" else kind, storage, k)
         sweeps = 1
         t0 = time.perf_counter()
         orc.sync(b, 0.0, 1)
@@ -324,7 +330,7 @@ def main():
     tuned = h.autotune(bt, 20) if kind == "cg" else (1, None)  # part of setup, outside the timed steps
     setup_s = time.perf_counter() - t0
     st = h.stats()
-    shapes = subdomain_shapes(A, part_kind, part_arg, gamma)
+    shapes = subdomain_shapes(A, part_kind, part_arg, gamma, kind)
     bps = bytes_per_local_solve(shapes, kind, storage, k)
     bps = np.array(bps, dtype=np.float64)
 

@@ -211,16 +211,18 @@ constexpr int64_t kSlabTailBytes = 4096;
 
 // Upload the plan: ELL rows of A on every overlapping set, local column map,
 // factors in the storage type (forward L and reversed transpose), global CSR.
-// Level-scheduled form of one triangular pass of a sparse factor.  rows_of(k)
-// lists the (row, value) dependencies of row k; `ascending` tells whether rows
-// are solved first to last (L) or last to first (L^T).
+// Level-scheduled form of one triangular pass of a sparse factor: rows are
+// solved first to last (L, `ascending`) or last to first (L^T); (ptr, idx, x)
+// lists the off-diagonal dependencies (j, L_kj) of each row k, d the diagonal.
+// Stored per level-order position: {row, first entry, end, 0}; entries
+// (k, 1 / d_k) and then (j, -L_kj / d_k), so a row's update is one dot product.
 struct SparsePass {
-    std::vector<int32_t> lev, rows, ep, col;
+    std::vector<int32_t> lev, meta, col;
     std::vector<double> val;
 };
 
 SparsePass sparse_pass(int32_t n, const std::vector<int64_t>& ptr, const std::vector<int32_t>& idx,
-                       const std::vector<double>& x, bool ascending) {
+                       const std::vector<double>& x, const std::vector<double>& d, bool ascending) {
     std::vector<int32_t> level(n, 0);
     int32_t nlev = 0;
     for (int32_t s = 0; s < n; ++s) {
@@ -234,17 +236,21 @@ SparsePass sparse_pass(int32_t n, const std::vector<int64_t>& ptr, const std::ve
     sp.lev.assign(nlev + 1, 0);
     for (int32_t k = 0; k < n; ++k) ++sp.lev[level[k] + 1];
     for (int32_t l = 0; l < nlev; ++l) sp.lev[l + 1] += sp.lev[l];
-    std::vector<int32_t> pos(sp.lev.begin(), sp.lev.end() - 1);
-    sp.rows.assign(n, 0);
-    for (int32_t k = 0; k < n; ++k) sp.rows[pos[level[k]]++] = k;
-    sp.ep.assign(n + 1, 0);
+    std::vector<int32_t> pos(sp.lev.begin(), sp.lev.end() - 1), rows(n);
+    for (int32_t k = 0; k < n; ++k) rows[pos[level[k]]++] = k;
+    sp.meta.assign(4 * static_cast<size_t>(n), 0);
     for (int32_t t = 0; t < n; ++t) {
-        const int32_t k = sp.rows[t];
+        const int32_t k = rows[t];
+        const double inv = 1.0 / d[k];
+        sp.meta[4 * t] = k;
+        sp.meta[4 * t + 1] = static_cast<int32_t>(sp.col.size());
+        sp.col.push_back(k);
+        sp.val.push_back(inv);
         for (int64_t e = ptr[k]; e < ptr[k + 1]; ++e) {
             sp.col.push_back(idx[e]);
-            sp.val.push_back(x[e]);
+            sp.val.push_back(-x[e] * inv);
         }
-        sp.ep[t + 1] = static_cast<int32_t>(sp.col.size());
+        sp.meta[4 * t + 2] = static_cast<int32_t>(sp.col.size());
     }
     return sp;
 }
@@ -281,14 +287,14 @@ void upload(ras_handle& h, const Plan& plan) {
     const size_t sts = st == RAS_STORAGE_FP64 ? 8 : st == RAS_STORAGE_FP32 ? 4 : 2;
     int64_t sp_idx_used = 0, sp_val_used = 0;
     if (sparse) {
-        // per subdomain and pass: levels + rows + entry pointers + columns, each padded
-        // to 4 int32, and the values padded to 16 bytes
+        // per subdomain and pass: levels, position records and columns, each padded to
+        // 4 int32, and the values padded to 16 bytes
         int64_t ni = 0, nv = 0;
         for (int p = 0; p < P; ++p) {
             const int64_t n = static_cast<int64_t>(plan.subs[p].omega.size());
             const int64_t nnz = static_cast<int64_t>(plan.subs[p].sf.lj.size());
-            ni += 2 * ((n + 2 + 3) / 4 * 4 + (n + 3) / 4 * 4 + (n + 1 + 3) / 4 * 4 + (nnz + 3) / 4 * 4);
-            nv += 2 * ((nnz * static_cast<int64_t>(sts) + 15) / 16 * 16);
+            ni += 2 * ((n + 2 + 3) / 4 * 4 + 4 * n + (nnz + n + 3) / 4 * 4);
+            nv += 2 * (((nnz + n) * static_cast<int64_t>(sts) + 15) / 16 * 16);
         }
         h.sp_idx.alloc(std::max<int64_t>(ni, 1) * sizeof(int32_t));
         h.sp_val.alloc(std::max<int64_t>(nv, 16));
@@ -485,16 +491,16 @@ void upload(ras_handle& h, const Plan& plan) {
         }
         if (sparse) {
             const SparseFactor& F = s.sf;
-            const SparsePass fw = sparse_pass(static_cast<int32_t>(n), F.lp, F.lj, F.lx, true);
-            const SparsePass bw = sparse_pass(static_cast<int32_t>(n), F.cp, F.ci, F.cx, false);
+            const SparsePass fw = sparse_pass(static_cast<int32_t>(n), F.lp, F.lj, F.lx, F.d, true);
+            const SparsePass bw = sparse_pass(static_cast<int32_t>(n), F.cp, F.ci, F.cx, F.d, false);
             const SparsePass* ps[2] = {&fw, &bw};
             std::vector<int32_t> idx;
             std::vector<unsigned char> vals;
-            int64_t ioff[2][4], voff[2];
+            int64_t ioff[2][3], voff[2];
             for (int k = 0; k < 2; ++k) {
                 const SparsePass& q = *ps[k];
-                const std::vector<int32_t>* parts[4] = {&q.lev, &q.rows, &q.ep, &q.col};
-                for (int a = 0; a < 4; ++a) {
+                const std::vector<int32_t>* parts[3] = {&q.lev, &q.meta, &q.col};
+                for (int a = 0; a < 3; ++a) {
                     ioff[k][a] = sp_idx_used + static_cast<int64_t>(idx.size());
                     idx.insert(idx.end(), parts[a]->begin(), parts[a]->end());
                     while (idx.size() % 4) idx.push_back(0);  // 16-byte aligned arrays
@@ -521,9 +527,8 @@ void upload(ras_handle& h, const Plan& plan) {
                       "copy sparse values");
             for (int k = 0; k < 2; ++k) {
                 d.sp_lev[k] = h.sp_idx.as<int32_t>() + ioff[k][0];
-                d.sp_rows[k] = h.sp_idx.as<int32_t>() + ioff[k][1];
-                d.sp_ep[k] = h.sp_idx.as<int32_t>() + ioff[k][2];
-                d.sp_col[k] = h.sp_idx.as<int32_t>() + ioff[k][3];
+                d.sp_meta[k] = h.sp_idx.as<int32_t>() + ioff[k][1];
+                d.sp_col[k] = h.sp_idx.as<int32_t>() + ioff[k][2];
                 d.sp_val[k] = static_cast<char*>(h.sp_val.p) + voff[k];
             }
             sp_idx_used += static_cast<int64_t>(idx.size());
@@ -1134,7 +1139,7 @@ int64_t estimate_device_bytes(const Plan& plan, int nrhs) {
         if (chol) bytes += 2 * ((band_elems(n, sd.w) + 63) / 64 * 64) * sts + n * cts + (plan.local.storage == 2 ? 4 * n : 0);
         if (plan.local.kind == RAS_LOCAL_CHOL_SPARSE) {
             const int64_t nnz = static_cast<int64_t>(sd.sf.lj.size());
-            bytes += 2 * (4 * (3 * n + 16) + nnz * (4 + sts) + 32) + n * cts;
+            bytes += 2 * (4 * (5 * n + 16) + (nnz + n) * (4 + sts) + 32) + n * cts;
         }
     }
     if (chol) bytes += 2 * kSlabTailBytes;

@@ -67,12 +67,13 @@ struct SubDev {
     int32_t n_ext;
     int32_t pad2_;
     int64_t snap_off;         // offset of this subdomain's x snapshot (n + n_ext values) per right-hand side
-    // sparse Cholesky (local rows in elimination order); pass 0 = L (forward), 1 = L^T (backward):
-    // rows of level l are sp_rows[pass][sp_lev[pass][l] .. sp_lev[pass][l + 1]); the entries of
-    // the row at level-order position t are [sp_ep[pass][t], sp_ep[pass][t + 1]) of sp_col / sp_val
+    // sparse Cholesky (local rows in elimination order); pass 0 = L (forward), 1 = L^T (backward).
+    // Level l holds the level-order positions [sp_lev[pass][l], sp_lev[pass][l + 1]); position t
+    // has sp_meta[pass][4 t .. 4 t + 3] = {row i, first entry, end of entries, 0}.  Row i's entries
+    // (sp_col, sp_val) are (i, 1 / L_ii) followed by (j, -L_ij / L_ii), so that the new y_i is
+    // the dot product of the entries with the current y.
     const int32_t* sp_lev[2];
-    const int32_t* sp_rows[2];
-    const int32_t* sp_ep[2];
+    const int32_t* sp_meta[2];
     const int32_t* sp_col[2];
     const void* sp_val[2];    // storage type
     int32_t sp_nlev[2];

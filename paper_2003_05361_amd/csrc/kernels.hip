@@ -1076,18 +1076,18 @@ __device__ __forceinline__ void slab_solve(const SubU& s, RAS_GLOBAL typename St
 
 // One level-scheduled triangular pass over a sparse factor (Sec. 3.3.1's
 // sparse direct solve): the rows of a level depend only on rows of earlier
-// levels, so each level is one parallel step,
-//   y[i] = (y[i] - sum_e val[e] * y[col[e]]) / L_ii   for every row i of the level,
-// with y resident in LDS and the entries streamed once from HBM.  A level with
-// few rows gets more lanes per row (up to a wave), a wide level one short group
-// per row; each group sums its row's entries and reduces across its lanes.
+// levels, so each level is one parallel step.  Each row's stored entries carry
+// the diagonal scaling (first entry (i, 1 / L_ii), then (j, -L_ij / L_ii)), so
+// the new y_i is one dot product of the entries with y; y stays in LDS and the
+// entries stream once from HBM.  A level with few rows gets more lanes per row
+// (up to a wave), a wide level one short group per row; each group sums its
+// row's entries and reduces across its lanes.
 template <class ST>
-__device__ __attribute__((noinline)) void sparse_run(RAS_GLOBAL const int32_t* lev, RAS_GLOBAL const int32_t* rows,
-                                                     RAS_GLOBAL const int32_t* ep, RAS_GLOBAL const int32_t* col,
-                                                     RAS_GLOBAL const ST* val,
-                                                     RAS_GLOBAL const typename StorageTraits<ST>::CT* invd, int nlev,
+__device__ __attribute__((noinline)) void sparse_run(RAS_GLOBAL const int32_t* lev, RAS_GLOBAL const int32_t* meta,
+                                                     RAS_GLOBAL const int32_t* col, RAS_GLOBAL const ST* val, int nlev,
                                                      RAS_LDS typename StorageTraits<ST>::CT* y) {
     using CT = typename StorageTraits<ST>::CT;
+    typedef int i32x4 __attribute__((ext_vector_type(4)));
     constexpr int B = kBandThreads;
     const int tid = threadIdx.x;
     int t0 = uni(lev[0]);
@@ -1098,12 +1098,11 @@ __device__ __attribute__((noinline)) void sparse_run(RAS_GLOBAL const int32_t* l
         while (G > 4 && R * G > 2 * B) G >>= 1;
         const int gi = tid / G, gl = tid & (G - 1), ng = B / G;
         for (int t = t0 + gi; t < t1; t += ng) {
-            const int i = rows[t];
-            const int e1 = ep[t + 1];
+            const i32x4 m = *reinterpret_cast<const RAS_GLOBAL i32x4*>(meta + 4 * t);
             CT acc = CT(0);
-            for (int e = ep[t] + gl; e < e1; e += G) acc += static_cast<CT>(val[e]) * y[col[e]];
+            for (int e = m[1] + gl; e < m[2]; e += G) acc += static_cast<CT>(val[e]) * y[col[e]];
             for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
-            if (gl == 0) y[i] = (y[i] - acc) * invd[i];
+            if (gl == 0) y[m[0]] = acc;
         }
         __syncthreads();
         t0 = t1;
@@ -1112,16 +1111,15 @@ __device__ __attribute__((noinline)) void sparse_run(RAS_GLOBAL const int32_t* l
 
 template <class ST>
 __device__ __forceinline__ void sparse_solve(const SubDev* sd, int n, RAS_GLOBAL typename StorageTraits<ST>::CT* v,
-                                             RAS_GLOBAL const typename StorageTraits<ST>::CT* invd, unsigned char* lds) {
+                                             unsigned char* lds) {
     using CT = typename StorageTraits<ST>::CT;
     RAS_LDS CT* y = (RAS_LDS CT*)(lds);
     for (int i = threadIdx.x; i < n; i += kBandThreads) y[i] = v[i];
     __syncthreads();
 #pragma unroll 1
     for (int pass = 0; pass < 2; ++pass)
-        sparse_run<ST>(gptr(sd->sp_lev[pass]), gptr(sd->sp_rows[pass]), gptr(sd->sp_ep[pass]),
-                       gptr(sd->sp_col[pass]), gptr(static_cast<const ST*>(sd->sp_val[pass])), invd,
-                       uni(sd->sp_nlev[pass]), y);
+        sparse_run<ST>(gptr(sd->sp_lev[pass]), gptr(sd->sp_meta[pass]), gptr(sd->sp_col[pass]),
+                       gptr(static_cast<const ST*>(sd->sp_val[pass])), uni(sd->sp_nlev[pass]), y);
     for (int i = threadIdx.x; i < n; i += kBandThreads) v[i] = y[i];
     __syncthreads();
 }
@@ -1176,7 +1174,7 @@ struct BandUpdate {
         block_sum3<B>(own2, loc2, b2, red3);
         if (sparse) {
             if constexpr (sizeof(ST) != 2)
-                sparse_solve<ST>(P.subs + item.sub, n, v, gptr(static_cast<const CT*>(s.invd)), smem);
+                sparse_solve<ST>(P.subs + item.sub, n, v, smem);
         } else if (slab) {
             slab_solve<ST>(s, v, smem, winm, stage_bytes);
         } else {

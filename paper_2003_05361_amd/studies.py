@@ -66,7 +66,7 @@ def run_case(A, b, spec: dict, gamma: int, loc: dict, tol: float, max_seconds: f
     plan = ras.Plan(A, spec, gamma, loc)
     st = plan.stats()
     vol = plan.comm_volume()
-    shapes = subdomain_shapes(plan, A.indptr)
+    shapes = subdomain_shapes(plan, A.indptr, loc["kind"] == "chol_sparse")
     h = plan.setup(stream=stream)
     setup_s = time.perf_counter() - t0
     plan.close()
@@ -136,7 +136,7 @@ def partitioners(args, stream) -> tuple[list, dict]:
         b = R.uniform_rhs(A.n, 1)
         for kind in PARTITIONERS:
             _progress(f"partitioners: P={P} N={N} {kind}")
-            r, vol = run_case(A, b, partition_spec(ras, A, kind, P), args.overlap, ras.local("chol", "fp64"),
+            r, vol = run_case(A, b, partition_spec(ras, A, kind, P), args.overlap, ras.local(args.local, "fp64"),
                               args.tol, args.max_seconds, stream,
                               {"study": "partitioners", "grid": N, "partitioner": kind})
             print(json.dumps(r), flush=True)
@@ -161,7 +161,7 @@ def overlaps(args, stream) -> tuple[list, dict]:
         b = R.uniform_rhs(A.n, 1)
         for gamma in args.overlaps:
             _progress(f"overlap: N={N} gamma={gamma}")
-            r, vol = run_case(A, b, partition_spec(ras, A, "rcb", args.nparts), gamma, ras.local("chol", "fp64"),
+            r, vol = run_case(A, b, partition_spec(ras, A, "rcb", args.nparts), gamma, ras.local(args.local, "fp64"),
                               args.tol, args.max_seconds, stream, {"study": "overlap", "grid": N, "partitioner": "rcb"})
             print(json.dumps(r), flush=True)
             rows.append(r)
@@ -180,7 +180,8 @@ def _fmt_matrix(vol: np.ndarray) -> list:
 
 def markdown(study: str, rows: list, heat: dict, cmd: str) -> str:
     L = [f"# Parameter study: {study}", "", "Command (one MI355X):", "", f"    {cmd}", ""]
-    L += ["Local solves: banded Cholesky, float64; tolerance on the relative residual as given per row. "
+    L += [f"Local solves: {'nested-dissection sparse' if rows and rows[0].get('local', '').startswith('chol_sparse') else 'banded'} "
+          "Cholesky, float64; tolerance on the relative residual as given per row. "
           "Times are HIP events around one solve call, setup excluded. Sweep time is the measured "
           "synchronous time over its sweep count; the shares are the algorithmic byte model of one "
           "sweep (exchange = 8 bytes per value read from another subdomain's points, a part of the "
@@ -188,7 +189,7 @@ def markdown(study: str, rows: list, heat: dict, cmd: str) -> str:
     L += ["Async runs twice: with paced reads (the library's choice for the banded solver: a subdomain "
           "waits up to a quarter of its previous update's time for neighbours that are behind) and free "
           "running (reads never wait). Updates = median local solves per subdomain.", ""]
-    L += ["| grid | P | scheme | overlap | max band | band entries | comm values | max nbrs | sync sweeps | "
+    L += ["| grid | P | scheme | overlap | max band | factor entries | comm values | max nbrs | sync sweeps | "
           "sync s | ms/sweep | async s (updates) | free async s (updates) | async speedup | free speedup | "
           "sync speedup vs 1-D | residual / solve / prolong / exchange |",
           "|---" * 17 + "|"]
@@ -227,6 +228,8 @@ def main(argv=None):
     ap.add_argument("--sizes", type=_ints, default=[128, 256])
     ap.add_argument("--overlaps", type=_ints, default=[0, 1, 2, 4, 8, 12, 16])
     ap.add_argument("--nparts", type=int, default=6)
+    ap.add_argument("--local", default="chol", choices=("chol", "chol_sparse"),
+                    help="local direct solver: banded or nested-dissection sparse Cholesky")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-seconds", type=float, default=30.0)
     ap.add_argument("--markdown", default=None)

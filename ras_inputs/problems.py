@@ -193,6 +193,9 @@ CONFIGS = {
     "poisson2d_64_strips4": dict(
         dims=2, N=64, partition=("regular_1d", 4), overlap=2, local=("chol", "fp64", 0), tol=1e-10, mode="sync",
         rhs=("manufactured", 0)),
+    "poisson2d_512_strips64": dict(
+        dims=2, N=512, partition=("regular_1d", 64), overlap=4, local=("chol", "fp64", 0), tol=1e-8,
+        mode="async", rhs=("uniform", 1)),
     "poisson2d_1024_8x8": dict(
         dims=2, N=1024, partition=("regular_2d", (8, 8)), overlap=4, local=("cg", "fp64", 10), tol=1e-8,
         mode="async", rhs=("uniform", 1)),
