@@ -1082,30 +1082,129 @@ __device__ __forceinline__ void slab_solve(const SubU& s, RAS_GLOBAL typename St
 // entries stream once from HBM.  A level with few rows gets more lanes per row
 // (up to a wave), a wide level one short group per row; each group sums its
 // row's entries and reduces across its lanes.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+// lanes per row for a level of R rows: up to a wave for a few rows, fewer as
+// rows grow, at least 4
+__device__ __forceinline__ int sparse_group(int R) {
+    int G = 64;
+    while (G > 4 && R * G > 2 * kBandThreads) G >>= 1;
+    return G;
+}
+
+// Loads of one level that do not depend on y: this thread's first row record
+// and its first U entries, issued a level (entries) or two (record) ahead.
+template <class ST>
+struct SparseStage {
+    static constexpr int U = 8;
+    using CT = typename StorageTraits<ST>::CT;
+    int ta, tb, G;
+    i32x4 m;
+    CT v[U];
+    int c[U];
+
+    __device__ __forceinline__ void set(int a, int b) {
+        ta = a;
+        tb = b;
+        G = sparse_group(b - a);
+    }
+    __device__ __forceinline__ bool mine() const { return ta + static_cast<int>(threadIdx.x) / G < tb; }
+    __device__ __forceinline__ void load_record(RAS_GLOBAL const int32_t* meta) {
+        if (mine()) m = *reinterpret_cast<const RAS_GLOBAL i32x4*>(meta + 4 * (ta + static_cast<int>(threadIdx.x) / G));
+    }
+    __device__ __forceinline__ void load_entries(RAS_GLOBAL const int32_t* col, RAS_GLOBAL const ST* val) {
+        const bool ok = mine();
+        const int gl = static_cast<int>(threadIdx.x) & (G - 1);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            v[u] = CT(0);
+            c[u] = 0;
+            if (ok) {
+                const int e = m[1] + gl + u * G;
+                if (e < m[2]) {
+                    v[u] = static_cast<CT>(val[e]);
+                    c[u] = col[e];
+                }
+            }
+        }
+    }
+};
+
+// One level-scheduled triangular pass over a sparse factor (Sec. 3.3.1's
+// sparse direct solve): the rows of a level depend only on rows of earlier
+// levels, so each level is one parallel step.  Each row's stored entries carry
+// the diagonal scaling (first entry (i, 1 / L_ii), then (j, -L_ij / L_ii)), so
+// the new y_i is one dot product of the entries with y; y stays in LDS and the
+// entries stream once from HBM.  A level with few rows gets more lanes per row
+// (up to a wave), a wide level one short group per row; each group sums its
+// row's entries and reduces across its lanes.  The loads that do not depend
+// on y are pipelined across levels: the row record of level l + 2 and the
+// first entries of level l + 1 are in flight while level l computes.
 template <class ST>
 __device__ __attribute__((noinline)) void sparse_run(RAS_GLOBAL const int32_t* lev, RAS_GLOBAL const int32_t* meta,
                                                      RAS_GLOBAL const int32_t* col, RAS_GLOBAL const ST* val, int nlev,
                                                      RAS_LDS typename StorageTraits<ST>::CT* y) {
     using CT = typename StorageTraits<ST>::CT;
-    typedef int i32x4 __attribute__((ext_vector_type(4)));
+    using S = SparseStage<ST>;
     constexpr int B = kBandThreads;
     const int tid = threadIdx.x;
-    int t0 = uni(lev[0]);
+    if (nlev <= 0) return;
+    S cur, nxt, nn;
+    cur.set(uni(lev[0]), uni(lev[1]));
+    cur.load_record(meta);
+    cur.load_entries(col, val);
+    nxt.set(cur.tb, nlev > 1 ? uni(lev[2]) : cur.tb);
+    nxt.load_record(meta);
     for (int l = 0; l < nlev; ++l) {
-        const int t1 = uni(lev[l + 1]);
-        const int R = t1 - t0;
-        int G = 64;
-        while (G > 4 && R * G > 2 * B) G >>= 1;
+        if (l + 1 < nlev) nxt.load_entries(col, val);
+        nn.set(nxt.tb, l + 2 < nlev ? uni(lev[l + 3]) : nxt.tb);
+        nn.load_record(meta);
+        const int G = cur.G;
         const int gi = tid / G, gl = tid & (G - 1), ng = B / G;
-        for (int t = t0 + gi; t < t1; t += ng) {
-            const i32x4 m = *reinterpret_cast<const RAS_GLOBAL i32x4*>(meta + 4 * t);
+        int t = cur.ta + gi;
+        if (t < cur.tb) {
             CT acc = CT(0);
-            for (int e = m[1] + gl; e < m[2]; e += G) acc += static_cast<CT>(val[e]) * y[col[e]];
+#pragma unroll
+            for (int u = 0; u < S::U; ++u) acc += cur.v[u] * y[cur.c[u]];
+            for (int e = cur.m[1] + gl + S::U * G; e < cur.m[2]; e += G) acc += static_cast<CT>(val[e]) * y[col[e]];
             for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
-            if (gl == 0) y[m[0]] = acc;
+            if (gl == 0) y[cur.m[0]] = acc;
+        }
+        // further rows of a wide level, four per group at a time: all their records,
+        // then their first two entries per lane, are in flight together
+        for (t += ng; t < cur.tb; t += 4 * ng) {
+            i32x4 mm[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int tq = t + q * ng;
+                mm[q] = i32x4{0, 0, 0, 0};
+                if (tq < cur.tb) mm[q] = *reinterpret_cast<const RAS_GLOBAL i32x4*>(meta + 4 * tq);
+            }
+            CT vv[4][2];
+            int cc[4][2];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const int e = mm[q][1] + gl + k * G;
+                    vv[q][k] = CT(0);
+                    cc[q][k] = 0;
+                    if (e < mm[q][2]) {
+                        vv[q][k] = static_cast<CT>(val[e]);
+                        cc[q][k] = col[e];
+                    }
+                }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                CT acc = vv[q][0] * y[cc[q][0]] + vv[q][1] * y[cc[q][1]];
+                for (int e = mm[q][1] + gl + 2 * G; e < mm[q][2]; e += G) acc += static_cast<CT>(val[e]) * y[col[e]];
+                for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+                if (gl == 0 && t + q * ng < cur.tb) y[mm[q][0]] = acc;
+            }
         }
         __syncthreads();
-        t0 = t1;
+        cur = nxt;
+        nxt = nn;
     }
 }
 
