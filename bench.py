@@ -139,6 +139,25 @@ def traffic_from_profiles(workload: str, algo_bytes_per_launch: float):
 
 
 
+def occupancy_summary(occ, budget):
+    """Admitted systems and held device memory over the stream: time-weighted means,
+    maxima, and a coarse timeline (ten equal time bins, mean active systems)."""
+    import numpy as np
+
+    if occ.shape[0] < 2:
+        return None
+    t = occ[:, 0]
+    dt = np.diff(t, append=t[-1])
+    w = dt / max(dt.sum(), 1e-12)
+    bins = np.linspace(t[0], t[-1], 11)
+    idx = np.clip(np.searchsorted(bins, t, side="right") - 1, 0, 9)
+    timeline = [float(occ[idx == k, 1].mean()) if np.any(idx == k) else None for k in range(10)]
+    return {"samples": int(occ.shape[0]), "active_mean": float(np.dot(w, occ[:, 1])),
+            "active_max": int(occ[:, 1].max()), "queued_mean": float(np.dot(w, occ[:, 2])),
+            "queued_max": int(occ[:, 2].max()), "in_use_frac_of_budget_mean": float(np.dot(w, occ[:, 3])) / budget,
+            "in_use_frac_of_budget_max": float(occ[:, 3].max()) / budget, "active_timeline_10_bins": timeline}
+
+
 def serving_bench(args):
     """Continuous-batching service: a stream of independent SPD systems (half 2-D
     five-point, half 3-D seven-point finite volumes, log-normal coefficients,
@@ -162,8 +181,21 @@ def serving_bench(args):
     budget = int(args.serve_budget_gib * (1 << 30))
 
     def run(subset, arrivals):
+        import threading
+
         srv = ras.Server(budget, slice_seconds=0.02)
         t0 = time.perf_counter()
+        # admitted-slot occupancy over time: (seconds, active systems, queued systems, device bytes held)
+        occ, stop = [], threading.Event()
+
+        def sample():
+            while not stop.is_set():
+                q = srv.stats()
+                occ.append((time.perf_counter() - t0, q["active"], q["queued"], q["in_use_bytes"]))
+                stop.wait(0.05)
+
+        sampler = threading.Thread(target=sample, daemon=True)
+        sampler.start()
         tickets = []
         for (A, part, loc, B), ta in zip(subset, arrivals):
             delay = ta - (time.perf_counter() - t0)
@@ -178,8 +210,11 @@ def serving_bench(args):
             rhs += B.shape[0]
             bad += sum(1 for i in infos if not i["converged"])
         wall = time.perf_counter() - t0
+        stop.set()
+        sampler.join()
         st = srv.stats()
         srv.close()
+        run.occupancy = np.array(occ) if occ else np.zeros((0, 4))
         return wall, np.array(lat), rhs, bad, st
 
     warm = systems[: min(40, len(systems))]
@@ -207,6 +242,7 @@ def serving_bench(args):
                    "budget_bytes": budget, "tol": 1e-8},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "max": float(lat.max())},
+        "occupancy": occupancy_summary(run.occupancy, budget),
         "unconverged_rhs": int(bad),
         "server": st,
         "roofline": None,
