@@ -125,7 +125,7 @@ typedef struct ras_local {
  *     read schedule is admissible); it only chooses when the read happens, so
  *     that evenly loaded subdomains read their neighbours' latest update
  *     rather than the one before it.  Negative: library choice (0.25 for the
- *     banded Cholesky solver, 0 for CG).  Ignored by SYNC and ORDERED.  */
+ *     Cholesky solvers, 0 for CG).  Ignored by SYNC and ORDERED.  */
 enum { RAS_MODE_SYNC = 0, RAS_MODE_ASYNC = 1, RAS_MODE_ORDERED = 2 };
 enum { RAS_DETECT_CENTRAL = 0, RAS_DETECT_DECENTRAL = 1 };
 typedef struct ras_solve_opts {

@@ -926,10 +926,10 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     P.conv = reinterpret_cast<int32_t*>(base + o_conv);
     P.gflag = reinterpret_cast<int32_t*>(base + o_gflag);
     P.detect = o.detect;
-    // library choice: banded direct solves run few, long, evenly timed updates, where
+    // library choice: direct (Cholesky) solves run few, long, evenly timed updates, where
     // reading the neighbours' latest update saves about a third of the updates; CG
     // subdomains are many and unevenly timed, where waiting costs more than it saves
-    const double pace = o.pace < 0.0 ? (h0.solver == RAS_LOCAL_CHOL_BANDED ? 0.25 : 0.0) : o.pace;
+    const double pace = o.pace < 0.0 ? (h0.solver != RAS_LOCAL_CG ? 0.25 : 0.0) : o.pace;
     P.pace = o.mode == RAS_MODE_ASYNC ? pace : 0.0;
     P.solves = reinterpret_cast<int64_t*>(base + o_solves);
     P.version = reinterpret_cast<uint32_t*>(base + o_version);
