@@ -405,13 +405,14 @@ def test_pace_out_of_range_is_an_argument_error():
 
 
 # ----------------------------------------------------------------------------- multi-RHS and batching
-def test_multi_rhs_equals_single_sync():
+@pytest.mark.parametrize("loc", [("cg", 6), ("chol_sparse", 0)])
+def test_multi_rhs_equals_single_sync(loc):
     ras = _ras()
-    _say("case: multi rhs")
+    _say(f"case: multi rhs {loc}")
     torch = _torch()
     A = R.laplace2d(50)
     B = np.stack([R.uniform_rhs(A.n, s) for s in (1, 2, 3)])
-    h = ras.setup(A, ras.partition("regular_2d", (3, 3), grid=A.grid), 2, ras.local("cg", "fp64", 6))
+    h = ras.setup(A, ras.partition("regular_2d", (3, 3), grid=A.grid), 2, ras.local(loc[0], "fp64", loc[1]))
     X, infos = h.solve(_cuda(B), tol=1e-8, mode="sync", max_sweeps=100000)
     for j in range(3):
         x1, i1 = h.solve(_cuda(B[j]), tol=1e-8, mode="sync", max_sweeps=100000)
@@ -419,14 +420,15 @@ def test_multi_rhs_equals_single_sync():
         assert infos[j]["sweeps"] == i1[0]["sweeps"]
 
 
-def test_batch_equals_alone():
+@pytest.mark.parametrize("kind", ["chol", "chol_sparse"])
+def test_batch_equals_alone(kind):
     ras = _ras()
-    _say("case: batch")
+    _say(f"case: batch {kind}")
     torch = _torch()
     A1, A2 = R.laplace2d(40), R.laplace3d(12)
     b1, b2 = R.uniform_rhs(A1.n, 3), R.uniform_rhs(A2.n, 4)
-    h1 = ras.setup(A1, ras.partition("regular_2d", (2, 2), grid=A1.grid), 2, ras.local("chol", "fp64"))
-    h2 = ras.setup(A2, ras.partition("regular_3d", (2, 2, 2), grid=A2.grid), 1, ras.local("chol", "fp64"))
+    h1 = ras.setup(A1, ras.partition("regular_2d", (2, 2), grid=A1.grid), 2, ras.local(kind, "fp64"))
+    h2 = ras.setup(A2, ras.partition("regular_3d", (2, 2, 2), grid=A2.grid), 1, ras.local(kind, "fp64"))
     xs, infos = ras.batch_solve([h1, h2], [_cuda(b1), _cuda(b2)], tol=1e-9, mode="sync", max_sweeps=100000)
     a1, _ = h1.solve(_cuda(b1), tol=1e-9, mode="sync", max_sweeps=100000)
     a2, _ = h2.solve(_cuda(b2), tol=1e-9, mode="sync", max_sweeps=100000)
