@@ -110,15 +110,19 @@ private:
         int32_t depth = 0;
         std::vector<int32_t> q = bfs(*std::min_element(S.begin(), S.end()), id, &depth);
         if (q.size() < S.size()) {
-            // disconnected: order the component reached, then the rest, independently
-            std::vector<int32_t> rest;
-            const int32_t mark = stamp_;
-            for (int32_t v : S)
-                if (seen_[v] != mark) rest.push_back(v);
-            std::vector<int32_t> comp = std::move(q);
+            // disconnected: find every component, then order each independently
+            std::vector<std::vector<int32_t>> comps;
+            std::sort(S.begin(), S.end());
+            comps.push_back(std::move(q));
+            for (int32_t v : comps.back()) member_[v] = -id;  // claimed by a component
+            for (size_t k = 0; k < S.size(); ++k) {
+                if (member_[S[k]] != id) continue;
+                int32_t d = 0;
+                comps.push_back(bfs(S[k], id, &d));
+                for (int32_t v : comps.back()) member_[v] = -id;
+            }
             S.clear();
-            split(comp);
-            split(rest);
+            for (auto& c : comps) split(c);
             return;
         }
         // pseudo-peripheral root: restart from a least-degree vertex of the last level

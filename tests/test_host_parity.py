@@ -324,3 +324,23 @@ def test_sparse_solver_arguments():
     with pytest.raises(ras.RasError) as e:
         plan.sparse_factor(0)
     assert e.value.status == -6
+
+
+def test_sparse_factor_of_disconnected_local_matrices():
+    """Subdomains whose local matrix falls apart (a block-diagonal A: many small
+    independent systems) are ordered component by component."""
+    _lib_or_skip()
+    blocks = [R.laplace2d(7).scipy() for _ in range(60)] + [sp.identity(500, format="csr") * 3.0]
+    M = sp.block_diag(blocks, format="csr")
+    M.sort_indices()
+    M.indptr = M.indptr.astype(np.int64)
+    M.indices = M.indices.astype(np.int32)
+    plan = ras.Plan(M, ras.partition("regular_1d", 2), 1, ras.local("chol_sparse", "fp64"))
+    _, ptr, idx = plan.sets()
+    for p in range(2):
+        om = idx[ptr[p]:ptr[p + 1]]
+        perm, rp, col, val, diag = plan.sparse_factor(p)
+        assert np.array_equal(np.sort(perm), np.arange(om.size))
+        L = sp.csr_matrix((val, col, rp), shape=(om.size, om.size)) + sp.diags(diag)
+        Ap = M[om][:, om][perm][:, perm]
+        assert abs(L @ L.T - Ap).max() <= 1e-12 * abs(Ap).max()
