@@ -12,6 +12,7 @@ only the sweep time is measured.
 
     python -m paper_2003_05361_amd.studies partitioners [--parts 4,16,36,64] [--overlap 4]
     python -m paper_2003_05361_amd.studies overlap [--sizes 128,256] [--overlaps 0,1,2,4,8,12,16]
+    python -m paper_2003_05361_amd.studies time_to_tolerance [--config diffusion2d_2048_16x16] [--local chol]
 
 Each case prints one JSON line; --markdown writes a summary with the tables and
 the communication-volume matrices.
@@ -170,12 +171,88 @@ def overlaps(args, stream) -> tuple[list, dict]:
     return rows, heat
 
 
+def time_to_tolerance(args, stream) -> tuple[list, dict]:
+    """Solve a named workload to its tolerance, synchronously and asynchronously,
+    in chunks of at most args.chunk seconds (x carried from chunk to chunk, which
+    continues the same iteration), printing one progress line per chunk; the time
+    is the sum of the chunks' HIP-event times on the solve stream."""
+    import torch
+
+    import paper_2003_05361_amd as ras
+    import ras_inputs as R
+
+    A, b, cfg = R.config_problem(args.config)
+    kind, arg = cfg["partition"][0], cfg["partition"][1:]
+    arg = arg[0] if len(arg) == 1 else tuple(arg)
+    spec = (ras.partition("rcb", arg[0], grid=A.grid, seed=arg[1], jitter=arg[2]) if kind == "rcb"
+            else ras.partition(kind, arg, grid=A.grid))
+    loc = ras.local(args.local, args.storage, args.cg_iters)
+    t0 = time.perf_counter()
+    h = ras.setup(A, spec, cfg["overlap"], loc, stream=stream)
+    bt = torch.tensor(b, dtype=torch.float64, device="cuda")
+    setup_s = time.perf_counter() - t0
+    h.solve(bt, tol=0.0, mode="sync", max_sweeps=2)
+    rows = []
+    for mode in args.modes.split(","):
+        x = torch.zeros_like(bt)
+        total, counts, sweeps, info = 0.0, None, 0, None
+        while total < args.budget:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            x, infos = h.solve(bt, x0=x, tol=cfg["tol"], mode=mode, max_sweeps=1 << 40,
+                               max_seconds=min(args.chunk, args.budget - total))
+            e1.record(stream)
+            torch.cuda.synchronize()
+            total += e0.elapsed_time(e1) * 1e-3
+            info = infos[0]
+            c = h.local_solve_counts()
+            counts = c if counts is None else counts + c
+            sweeps += int(info["sweeps"])
+            _progress(json.dumps({"mode": mode, "seconds": total, "sweeps": sweeps,
+                                  "rel_residual": info["rel_residual"], "converged": bool(info["converged"])}))
+            if info["converged"]:
+                break
+        xh = x.cpu().numpy()
+        r = {"study": "time_to_tolerance", "config": args.config, "n": int(A.n), "local": f"{args.local}-{args.storage}",
+             "mode": mode, "converged": bool(info["converged"]), "seconds": total, "tol": cfg["tol"],
+             "rel_residual_host": float(np.linalg.norm(b - A.matvec(xh)) / np.linalg.norm(b)),
+             "local_solves_min": int(counts.min()), "local_solves_median": float(np.median(counts)),
+             "local_solves_max": int(counts.max()), "setup_s": setup_s}
+        if mode == "sync":
+            r["sweeps"] = sweeps
+            r["ms_per_sweep"] = 1e3 * total / max(1, sweeps)
+        print(json.dumps(r), flush=True)
+        rows.append(r)
+    h.close()
+    return rows, {}
+
+
 def _fmt_matrix(vol: np.ndarray) -> list:
     P = vol.shape[0]
     out = ["| p \\ q | " + " | ".join(str(q) for q in range(P)) + " |", "|---" * (P + 1) + "|"]
     for p in range(P):
         out.append(f"| {p} | " + " | ".join(str(int(v)) if v else "." for v in vol[p]) + " |")
     return out
+
+
+def markdown_ttt(rows: list, cmd: str) -> str:
+    L = [f"# Time to tolerance: {rows[0]['config']} ({rows[0]['local']})", "", "Command (one MI355X):", "",
+         f"    {cmd}", "",
+         "x0 = 0; the solve runs in chunks (x carried over, which continues the same iteration) so that "
+         "the run reports progress; seconds = the sum of the chunks' HIP-event times on the solve stream, "
+         "setup excluded. Asynchronous: the library's default read pacing. The residual is recomputed on "
+         "the host from the returned x.", "",
+         "| mode | converged | seconds | sweeps (sync) | ms per sweep | local solves min / median / max | host rel. residual |",
+         "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        L.append(f"| {r['mode']} | {r['converged']} | {r['seconds']:.1f} | {r.get('sweeps', '-')} | "
+                 f"{r['ms_per_sweep']:.3f} |" if "ms_per_sweep" in r else
+                 f"| {r['mode']} | {r['converged']} | {r['seconds']:.1f} | - | - |")
+        L[-1] += f" {r['local_solves_min']} / {r['local_solves_median']:.0f} / {r['local_solves_max']} | {r['rel_residual_host']:.3e} |"
+    if len(rows) == 2:
+        L += ["", f"Asynchronous speedup over synchronous: {rows[0]['seconds'] / rows[1]['seconds']:.3f}."]
+    return "\n".join(L) + "\n"
 
 
 def markdown(study: str, rows: list, heat: dict, cmd: str) -> str:
@@ -220,7 +297,13 @@ def _ints(s: str) -> list:
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("study", choices=("partitioners", "overlap"))
+    ap.add_argument("study", choices=("partitioners", "overlap", "time_to_tolerance"))
+    ap.add_argument("--config", default="diffusion2d_2048_16x16", help="time_to_tolerance: ras_inputs workload")
+    ap.add_argument("--storage", default="fp64")
+    ap.add_argument("--cg-iters", type=int, default=0)
+    ap.add_argument("--modes", default="sync,async")
+    ap.add_argument("--chunk", type=float, default=50.0)
+    ap.add_argument("--budget", type=float, default=1000.0, help="time_to_tolerance: seconds per mode at most")
     ap.add_argument("--parts", type=_ints, default=[4, 16, 36, 64])
     ap.add_argument("--per-part", type=int, default=4096)
     ap.add_argument("--overlap", type=int, default=4)
@@ -240,11 +323,12 @@ def main(argv=None):
     if not torch.cuda.is_available():
         raise SystemExit("the studies run the device solver: no GPU visible")
     stream = torch.cuda.current_stream()
-    rows, heat = (partitioners if args.study == "partitioners" else overlaps)(args, stream)
+    run = {"partitioners": partitioners, "overlap": overlaps, "time_to_tolerance": time_to_tolerance}[args.study]
+    rows, heat = run(args, stream)
     if args.markdown:
         cmd = "python -m paper_2003_05361_amd.studies " + " ".join(sys.argv[1:] if argv is None else argv)
         with open(args.markdown, "w") as f:
-            f.write(markdown(args.study, rows, heat, cmd))
+            f.write(markdown_ttt(rows, cmd) if args.study == "time_to_tolerance" else markdown(args.study, rows, heat, cmd))
     return rows
 
 
