@@ -214,6 +214,8 @@ def time_to_tolerance(args, stream) -> tuple[list, dict]:
             if info["converged"]:
                 break
         xh = x.cpu().numpy()
+        if args.save_x:
+            np.save(f"{args.save_x}_{mode}_{args.local}_{args.storage}.npy", xh)
         r = {"study": "time_to_tolerance", "config": args.config, "n": int(A.n), "local": f"{args.local}-{args.storage}",
              "mode": mode, "converged": bool(info["converged"]), "seconds": total, "tol": cfg["tol"],
              "rel_residual_host": float(np.linalg.norm(b - A.matvec(xh)) / np.linalg.norm(b)),
@@ -304,6 +306,7 @@ def main(argv=None):
     ap.add_argument("--modes", default="sync,async")
     ap.add_argument("--chunk", type=float, default=50.0)
     ap.add_argument("--budget", type=float, default=1000.0, help="time_to_tolerance: seconds per mode at most")
+    ap.add_argument("--save-x", default=None, help="time_to_tolerance: save each solution as <prefix>_<mode>_<local>_<storage>.npy")
     ap.add_argument("--parts", type=_ints, default=[4, 16, 36, 64])
     ap.add_argument("--per-part", type=int, default=4096)
     ap.add_argument("--overlap", type=int, default=4)
