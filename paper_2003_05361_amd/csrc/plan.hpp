@@ -69,7 +69,6 @@ std::vector<int32_t> external_set(const Plan& plan, const Subdomain& sd);
 // volume[p*P + q] = |(Omega_p u ext(Omega_p)) n O_q| for q != p, 0 on the diagonal
 void comm_volume(const Plan& plan, int64_t* volume);
 void factor_local(Plan& plan);
-std::vector<int32_t> nested_dissection(const Plan& plan, const Subdomain& sd);
 void sparse_factor_local(Plan& plan);
 uint16_t f64_to_f16_rne(double d);
 

@@ -177,11 +177,6 @@ private:
 
 }  // namespace
 
-std::vector<int32_t> nested_dissection(const Plan& plan, const Subdomain& sd) {
-    const LocalGraph G = local_graph(plan, sd);
-    return Dissector(G).order();
-}
-
 void sparse_factor_one(const Plan& plan, Subdomain& sd, int32_t p) {
     const LocalGraph G = local_graph(plan, sd);
     const int32_t n = G.n;
