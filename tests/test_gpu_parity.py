@@ -467,3 +467,54 @@ def test_config2_full_size_two_sweeps():
     assert _rel(x.cpu().numpy(), xo) <= 1e-9
     _, hg = h.residual_history()
     assert np.all(np.abs(hg - ho) <= 1e-9 * ho + 1e-13)
+
+
+# ----------------------------------------------------------------------------- full sizes, sampled
+def _oracle_subdomain_update(A, owner, p, gamma, r, local):
+    """The oracle's correction of subdomain p for the global residual r, on its
+    owned points (Eq. 3, one subdomain): (owned ids, delta)."""
+    from oracle import local as olocal
+    from oracle import overlap as oover
+
+    own = np.flatnonzero(owner == p)
+    lay = oover.bfs_layers(A, own, gamma)
+    om = np.sort(np.concatenate(lay))
+    solver = olocal.LocalSolver(olocal.local_matrix(A, om), *local)
+    d = solver(r[om])
+    pos = np.searchsorted(om, own)
+    return own, d[pos]
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", 1e-9), ("fp32", 2e-5), ("fp16", 2e-5)])
+def test_config4_full_size_first_sweep_sampled(storage, tol):
+    """2048^2 diffusion, 16x16 subdomains, overlap 4, banded Cholesky in the bench's
+    launch shape (256 workgroups, slab layout): one synchronous sweep from x = 0
+    against the oracle's update of sampled subdomains (corners, edge, interior)."""
+    ras = _ras()
+    _say(f"case: diffusion2d_2048_16x16 first sweep sampled {storage}")
+    A, b, cfg = R.config_problem("diffusion2d_2048_16x16")
+    h = ras.setup(A, ras.partition("regular_2d", (16, 16), grid=A.grid), 4, ras.local("chol", storage))
+    x, _ = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=1)
+    x = x.cpu().numpy()
+    owner = opart.regular_grid(A.grid, (16, 16))
+    for p in (0, 7, 136, 255):
+        own, d = _oracle_subdomain_update(A, owner, p, 4, b, ("chol", storage))
+        assert _rel(x[own], d) <= tol, (p, _rel(x[own], d))
+
+
+def test_config3_full_size_first_sweep_sampled():
+    """128^3 Laplacian, 256 RCB subdomains (jitter 0.4), overlap 1, CG-8 FP32 with
+    the autotuned team, as the bench launches it: one synchronous sweep from x = 0
+    against the oracle's float32 CG-8 update of sampled subdomains."""
+    ras = _ras()
+    _say("case: laplace3d_128_rcb256 first sweep sampled")
+    A, b, cfg = R.config_problem("laplace3d_128_rcb256")
+    h = ras.setup(A, ras.partition("rcb", 256, grid=A.grid, seed=3, jitter=0.4), 1, ras.local("cg", "fp32", 8))
+    bt = _cuda(b)
+    team, _ = h.autotune(bt, 20)
+    x, _ = h.solve(bt, tol=0.0, mode="sync", max_sweeps=1, team=team)
+    x = x.cpu().numpy()
+    owner = opart.rcb(A.coords(), 256, 3, 0.4)
+    for p in (0, 77, 160, 255):
+        own, d = _oracle_subdomain_update(A, owner, p, 1, b, ("cg", "fp32", 8))
+        assert _rel(x[own], d) <= 2e-5, (p, team, _rel(x[own], d))
