@@ -173,60 +173,71 @@ def overlaps(args, stream) -> tuple[list, dict]:
 
 def time_to_tolerance(args, stream) -> tuple[list, dict]:
     """Solve a named workload to its tolerance, synchronously and asynchronously,
-    in chunks of at most args.chunk seconds (x carried from chunk to chunk, which
-    continues the same iteration), printing one progress line per chunk; the time
-    is the sum of the chunks' HIP-event times on the solve stream."""
+    for each requested storage of the local solver, in chunks of at most
+    args.chunk seconds (x carried from chunk to chunk, which continues the same
+    iteration), printing one progress line per chunk; the time is the sum of the
+    chunks' HIP-event times on the solve stream.  With fp64 among the storages,
+    every solution's relative difference from the fp64 one of the same mode is
+    reported."""
     import torch
 
     import paper_2003_05361_amd as ras
     import ras_inputs as R
 
-    A, b, cfg = R.config_problem(args.config)
+    A, b, cfg = R.config_problem(args.config, args.grid)
     kind, arg = cfg["partition"][0], cfg["partition"][1:]
     arg = arg[0] if len(arg) == 1 else tuple(arg)
     spec = (ras.partition("rcb", arg[0], grid=A.grid, seed=arg[1], jitter=arg[2]) if kind == "rcb"
             else ras.partition(kind, arg, grid=A.grid))
-    loc = ras.local(args.local, args.storage, args.cg_iters)
-    t0 = time.perf_counter()
-    h = ras.setup(A, spec, cfg["overlap"], loc, stream=stream)
     bt = torch.tensor(b, dtype=torch.float64, device="cuda")
-    setup_s = time.perf_counter() - t0
-    h.solve(bt, tol=0.0, mode="sync", max_sweeps=2)
-    rows = []
-    for mode in args.modes.split(","):
-        x = torch.zeros_like(bt)
-        total, counts, sweeps, info = 0.0, None, 0, None
-        while total < args.budget:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            x, infos = h.solve(bt, x0=x, tol=cfg["tol"], mode=mode, max_sweeps=1 << 40,
-                               max_seconds=min(args.chunk, args.budget - total))
-            e1.record(stream)
-            torch.cuda.synchronize()
-            total += e0.elapsed_time(e1) * 1e-3
-            info = infos[0]
-            c = h.local_solve_counts()
-            counts = c if counts is None else counts + c
-            sweeps += int(info["sweeps"])
-            _progress(json.dumps({"mode": mode, "seconds": total, "sweeps": sweeps,
-                                  "rel_residual": info["rel_residual"], "converged": bool(info["converged"])}))
-            if info["converged"]:
-                break
-        xh = x.cpu().numpy()
-        if args.save_x:
-            np.save(f"{args.save_x}_{mode}_{args.local}_{args.storage}.npy", xh)
-        r = {"study": "time_to_tolerance", "config": args.config, "n": int(A.n), "local": f"{args.local}-{args.storage}",
-             "mode": mode, "converged": bool(info["converged"]), "seconds": total, "tol": cfg["tol"],
-             "rel_residual_host": float(np.linalg.norm(b - A.matvec(xh)) / np.linalg.norm(b)),
-             "local_solves_min": int(counts.min()), "local_solves_median": float(np.median(counts)),
-             "local_solves_max": int(counts.max()), "setup_s": setup_s}
-        if mode == "sync":
-            r["sweeps"] = sweeps
-            r["ms_per_sweep"] = 1e3 * total / max(1, sweeps)
+    storages = args.storages.split(",") if args.storages else [args.storage]
+    rows, sols = [], {}
+    for storage in storages:
+        t0 = time.perf_counter()
+        h = ras.setup(A, spec, cfg["overlap"], ras.local(args.local, storage, args.cg_iters), stream=stream)
+        setup_s = time.perf_counter() - t0
+        h.solve(bt, tol=0.0, mode="sync", max_sweeps=2)
+        for mode in args.modes.split(","):
+            x = torch.zeros_like(bt)
+            total, counts, sweeps, info = 0.0, None, 0, None
+            while total < args.budget:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                x, infos = h.solve(bt, x0=x, tol=cfg["tol"], mode=mode, max_sweeps=1 << 40,
+                                   max_seconds=min(args.chunk, args.budget - total))
+                e1.record(stream)
+                torch.cuda.synchronize()
+                total += e0.elapsed_time(e1) * 1e-3
+                info = infos[0]
+                c = h.local_solve_counts()
+                counts = c if counts is None else counts + c
+                sweeps += int(info["sweeps"])
+                _progress(json.dumps({"storage": storage, "mode": mode, "seconds": total, "sweeps": sweeps,
+                                      "rel_residual": info["rel_residual"], "converged": bool(info["converged"])}))
+                if info["converged"]:
+                    break
+            xh = x.cpu().numpy()
+            sols[(storage, mode)] = xh
+            if args.save_x:
+                np.save(f"{args.save_x}_{mode}_{args.local}_{storage}.npy", xh)
+            r = {"study": "time_to_tolerance", "config": args.config, "n": int(A.n),
+                 "local": f"{args.local}-{storage}", "mode": mode, "converged": bool(info["converged"]),
+                 "seconds": total, "tol": cfg["tol"],
+                 "rel_residual_host": float(np.linalg.norm(b - A.matvec(xh)) / np.linalg.norm(b)),
+                 "local_solves_min": int(counts.min()), "local_solves_median": float(np.median(counts)),
+                 "local_solves_max": int(counts.max()), "setup_s": setup_s}
+            if mode == "sync":
+                r["sweeps"] = sweeps
+                r["ms_per_sweep"] = 1e3 * total / max(1, sweeps)
+            rows.append(r)
+        h.close()
+    for r in rows:
+        ref = sols.get(("fp64", r["mode"]))
+        if ref is not None:
+            xs = sols[(r["local"].split("-")[-1], r["mode"])]
+            r["rel_diff_vs_fp64"] = float(np.linalg.norm(xs - ref) / np.linalg.norm(ref))
         print(json.dumps(r), flush=True)
-        rows.append(r)
-    h.close()
     return rows, {}
 
 
@@ -239,20 +250,22 @@ def _fmt_matrix(vol: np.ndarray) -> list:
 
 
 def markdown_ttt(rows: list, cmd: str) -> str:
-    L = [f"# Time to tolerance: {rows[0]['config']} ({rows[0]['local']})", "", "Command (one MI355X):", "",
+    L = [f"# Time to tolerance: {rows[0]['config']} (n = {rows[0]['n']})", "", "Command (one MI355X):", "",
          f"    {cmd}", "",
          "x0 = 0; the solve runs in chunks (x carried over, which continues the same iteration) so that "
          "the run reports progress; seconds = the sum of the chunks' HIP-event times on the solve stream, "
          "setup excluded. Asynchronous: the library's default read pacing. The residual is recomputed on "
          "the host from the returned x.", "",
-         "| mode | converged | seconds | sweeps (sync) | ms per sweep | local solves min / median / max | host rel. residual |",
-         "|---|---|---|---|---|---|---|"]
+         "| local | mode | converged | seconds | sweeps (sync) | ms per sweep | local solves min / median / max | "
+         "host rel. residual | rel. difference from FP64 |",
+         "|---|---|---|---|---|---|---|---|---|"]
     for r in rows:
-        L.append(f"| {r['mode']} | {r['converged']} | {r['seconds']:.1f} | {r.get('sweeps', '-')} | "
-                 f"{r['ms_per_sweep']:.3f} |" if "ms_per_sweep" in r else
-                 f"| {r['mode']} | {r['converged']} | {r['seconds']:.1f} | - | - |")
-        L[-1] += f" {r['local_solves_min']} / {r['local_solves_median']:.0f} / {r['local_solves_max']} | {r['rel_residual_host']:.3e} |"
-    if len(rows) == 2:
+        sw = f"{r['sweeps']} | {r['ms_per_sweep']:.3f}" if "ms_per_sweep" in r else "- | -"
+        dv = f"{r['rel_diff_vs_fp64']:.2e}" if "rel_diff_vs_fp64" in r else "-"
+        L.append(f"| {r['local']} | {r['mode']} | {r['converged']} | {r['seconds']:.1f} | {sw} | "
+                 f"{r['local_solves_min']} / {r['local_solves_median']:.0f} / {r['local_solves_max']} | "
+                 f"{r['rel_residual_host']:.3e} | {dv} |")
+    if len(rows) == 2 and rows[0]["local"] == rows[1]["local"]:
         L += ["", f"Asynchronous speedup over synchronous: {rows[0]['seconds'] / rows[1]['seconds']:.3f}."]
     return "\n".join(L) + "\n"
 
@@ -302,6 +315,8 @@ def main(argv=None):
     ap.add_argument("study", choices=("partitioners", "overlap", "time_to_tolerance"))
     ap.add_argument("--config", default="diffusion2d_2048_16x16", help="time_to_tolerance: ras_inputs workload")
     ap.add_argument("--storage", default="fp64")
+    ap.add_argument("--storages", default=None, help="time_to_tolerance: comma-separated storages (overrides --storage)")
+    ap.add_argument("--grid", type=int, default=None, help="time_to_tolerance: grid side override of the workload")
     ap.add_argument("--cg-iters", type=int, default=0)
     ap.add_argument("--modes", default="sync,async")
     ap.add_argument("--chunk", type=float, default=50.0)

@@ -33,12 +33,12 @@ def test_markdown_summary():
 
 
 def test_time_to_tolerance_summary():
-    rows = [{"config": "c", "local": "chol-fp64", "mode": "sync", "converged": True, "seconds": 10.0, "sweeps": 100,
+    rows = [{"config": "c", "n": 16, "local": "chol-fp64", "mode": "sync", "converged": True, "seconds": 10.0, "sweeps": 100,
              "ms_per_sweep": 100.0, "local_solves_min": 100, "local_solves_median": 100.0, "local_solves_max": 100,
              "rel_residual_host": 9e-9},
-            {"config": "c", "local": "chol-fp64", "mode": "async", "converged": True, "seconds": 8.0,
+            {"config": "c", "n": 16, "local": "chol-fp64", "mode": "async", "converged": True, "seconds": 8.0,
              "local_solves_min": 90, "local_solves_median": 95.0, "local_solves_max": 99, "rel_residual_host": 8e-9}]
     md = studies.markdown_ttt(rows, "python -m x time_to_tolerance")
-    assert "| sync | True | 10.0 | 100 | 100.000 | 100 / 100 / 100 | 9.000e-09 |" in md
-    assert "| async | True | 8.0 | - | - | 90 / 95 / 99 | 8.000e-09 |" in md
+    assert "| chol-fp64 | sync | True | 10.0 | 100 | 100.000 | 100 / 100 / 100 | 9.000e-09 | - |" in md
+    assert "| chol-fp64 | async | True | 8.0 | - | - | 90 / 95 / 99 | 8.000e-09 | - |" in md
     assert "speedup over synchronous: 1.250" in md
