@@ -42,3 +42,16 @@ def test_time_to_tolerance_summary():
     assert "| chol-fp64 | sync | True | 10.0 | 100 | 100.000 | 100 / 100 / 100 | 9.000e-09 | - |" in md
     assert "| chol-fp64 | async | True | 8.0 | - | - | 90 / 95 / 99 | 8.000e-09 | - |" in md
     assert "speedup over synchronous: 1.250" in md
+
+
+def test_byte_model_parts():
+    from paper_2003_05361_amd.perfmodel import local_solve_parts
+
+    # n = 10 local rows, 8 owned, K = 5, w = 3, nnz(L) = 20
+    res, loc, pro = local_solve_parts([10, 8, 5, 3, 20], "chol_sparse", "fp64", 0)
+    assert res == 10 * (12 * 5 + 16) and pro == 8 * (16 + 8)
+    assert loc == 2 * ((20 + 10) * (8 + 4) + 16 * 10) + 2 * 10 * 8
+    _, loc_b, _ = local_solve_parts([10, 8, 5, 3], "chol", "fp16", 0)
+    assert loc_b == 2 * 10 * 4 * 2 + 4 * 10 * 4 + 2 * 10 * 4
+    _, loc_c, _ = local_solve_parts([10, 8, 5, 3], "cg", "fp32", 8)
+    assert loc_c == 8 * 10 * (5 * 8 + 11 * 4)
