@@ -324,6 +324,9 @@ class Handle:
               max_seconds: float = 0.0, detect: str = "central", workgroups: int = 0, team: int = 0,
               allow_unconverged=True, pace=None):
         """Solve A x = b on the device.  b: float64 CUDA tensor [n] or [nrhs, n].
+        mode: "sync", "async" or "ordered"; detect: "central" or "decentral";
+        pace (async): neighbour wait budget before a read, in units of the
+        previous update's time (None: the library's choice per local solver).
         Returns (x, infos) with x the same shape as b."""
         import torch
 
