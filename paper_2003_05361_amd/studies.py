@@ -195,9 +195,14 @@ def time_to_tolerance(args, stream) -> tuple[list, dict]:
     for storage in storages:
         t0 = time.perf_counter()
         h = ras.setup(A, spec, cfg["overlap"], ras.local(args.local, storage, args.cg_iters), stream=stream)
+        if args.local == "cg":
+            h.autotune(bt, 20)  # team size, as the bench sets it up
         setup_s = time.perf_counter() - t0
         h.solve(bt, tol=0.0, mode="sync", max_sweeps=2)
-        for mode in args.modes.split(","):
+        for mode_name in args.modes.split(","):
+            # "async-decentral": the asynchronous solver with decentralized detection
+            mode, _, detect = mode_name.partition("-")
+            detect = detect or "central"
             x = torch.zeros_like(bt)
             total, counts, sweeps, info = 0.0, None, 0, None
             while total < args.budget:
@@ -205,7 +210,7 @@ def time_to_tolerance(args, stream) -> tuple[list, dict]:
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
                 x, infos = h.solve(bt, x0=x, tol=cfg["tol"], mode=mode, max_sweeps=1 << 40,
-                                   max_seconds=min(args.chunk, args.budget - total))
+                                   max_seconds=min(args.chunk, args.budget - total), detect=detect)
                 e1.record(stream)
                 torch.cuda.synchronize()
                 total += e0.elapsed_time(e1) * 1e-3
@@ -213,16 +218,16 @@ def time_to_tolerance(args, stream) -> tuple[list, dict]:
                 c = h.local_solve_counts()
                 counts = c if counts is None else counts + c
                 sweeps += int(info["sweeps"])
-                _progress(json.dumps({"storage": storage, "mode": mode, "seconds": total, "sweeps": sweeps,
+                _progress(json.dumps({"storage": storage, "mode": mode_name, "seconds": total, "sweeps": sweeps,
                                       "rel_residual": info["rel_residual"], "converged": bool(info["converged"])}))
                 if info["converged"]:
                     break
             xh = x.cpu().numpy()
-            sols[(storage, mode)] = xh
+            sols[(storage, mode_name)] = xh
             if args.save_x:
-                np.save(f"{args.save_x}_{mode}_{args.local}_{storage}.npy", xh)
+                np.save(f"{args.save_x}_{mode_name}_{args.local}_{storage}.npy", xh)
             r = {"study": "time_to_tolerance", "config": args.config, "n": int(A.n),
-                 "local": f"{args.local}-{storage}", "mode": mode, "converged": bool(info["converged"]),
+                 "local": f"{args.local}-{storage}", "mode": mode_name, "converged": bool(info["converged"]),
                  "seconds": total, "tol": cfg["tol"],
                  "rel_residual_host": float(np.linalg.norm(b - A.matvec(xh)) / np.linalg.norm(b)),
                  "local_solves_min": int(counts.min()), "local_solves_median": float(np.median(counts)),
@@ -318,7 +323,8 @@ def main(argv=None):
     ap.add_argument("--storages", default=None, help="time_to_tolerance: comma-separated storages (overrides --storage)")
     ap.add_argument("--grid", type=int, default=None, help="time_to_tolerance: grid side override of the workload")
     ap.add_argument("--cg-iters", type=int, default=0)
-    ap.add_argument("--modes", default="sync,async")
+    ap.add_argument("--modes", default="sync,async",
+                    help="time_to_tolerance: any of sync, async, async-decentral (decentralized detection)")
     ap.add_argument("--chunk", type=float, default=50.0)
     ap.add_argument("--budget", type=float, default=1000.0, help="time_to_tolerance: seconds per mode at most")
     ap.add_argument("--save-x", default=None, help="time_to_tolerance: save each solution as <prefix>_<mode>_<local>_<storage>.npy")
