@@ -137,7 +137,7 @@ def partitioners(args, stream) -> tuple[list, dict]:
         b = R.uniform_rhs(A.n, 1)
         for kind in PARTITIONERS:
             _progress(f"partitioners: P={P} N={N} {kind}")
-            r, vol = run_case(A, b, partition_spec(ras, A, kind, P), args.overlap, ras.local(args.local, "fp64"),
+            r, vol = run_case(A, b, partition_spec(ras, A, kind, P), args.overlap, ras.local(args.local, "fp64", args.cg_iters),
                               args.tol, args.max_seconds, stream,
                               {"study": "partitioners", "grid": N, "partitioner": kind})
             print(json.dumps(r), flush=True)
@@ -162,7 +162,7 @@ def overlaps(args, stream) -> tuple[list, dict]:
         b = R.uniform_rhs(A.n, 1)
         for gamma in args.overlaps:
             _progress(f"overlap: N={N} gamma={gamma}")
-            r, vol = run_case(A, b, partition_spec(ras, A, "rcb", args.nparts), gamma, ras.local(args.local, "fp64"),
+            r, vol = run_case(A, b, partition_spec(ras, A, "rcb", args.nparts), gamma, ras.local(args.local, "fp64", args.cg_iters),
                               args.tol, args.max_seconds, stream, {"study": "overlap", "grid": N, "partitioner": "rcb"})
             print(json.dumps(r), flush=True)
             rows.append(r)
@@ -335,8 +335,8 @@ def main(argv=None):
     ap.add_argument("--sizes", type=_ints, default=[128, 256])
     ap.add_argument("--overlaps", type=_ints, default=[0, 1, 2, 4, 8, 12, 16])
     ap.add_argument("--nparts", type=int, default=6)
-    ap.add_argument("--local", default="chol", choices=("chol", "chol_sparse"),
-                    help="local direct solver: banded or nested-dissection sparse Cholesky")
+    ap.add_argument("--local", default="chol", choices=("chol", "chol_sparse", "cg"),
+                    help="local solver: banded or nested-dissection sparse Cholesky, or CG (--cg-iters steps)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-seconds", type=float, default=30.0)
     ap.add_argument("--markdown", default=None)
