@@ -1,4 +1,5 @@
-"""One-GPU parameter studies: partitioning scheme and overlap (Sec. 4.2, Figs. 2-4).
+"""One-GPU parameter studies: partitioning scheme and overlap (Sec. 3.2.1 Fig. 2, Secs. 4.2-4.3 Figs. 3-4),
+and time to tolerance by local solver, storage, mode and detector (Secs. 4.5-4.6).
 
 Every case builds the host plan, records its shape (local rows, band width,
 band entries as the fill of the local factors, communication volume between

@@ -1,7 +1,7 @@
 """The one-GPU parameter studies (partitioning scheme, overlap) on small grids:
 every case converges in both modes, the communication volume equals the
 oracle's, the synchronous sweep counts equal the oracle's, and more overlap
-never needs more synchronous sweeps on these Laplace problems (Sec. 4.2)."""
+never needs more synchronous sweeps on these Laplace problems (Sec. 4.3)."""
 import sys
 
 import numpy as np
