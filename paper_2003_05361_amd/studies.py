@@ -211,7 +211,8 @@ def time_to_tolerance(args, stream) -> tuple[list, dict]:
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
                 x, infos = h.solve(bt, x0=x, tol=cfg["tol"], mode=mode, max_sweeps=1 << 40,
-                                   max_seconds=min(args.chunk, args.budget - total), detect=detect)
+                                   max_seconds=min(args.chunk, args.budget - total), detect=detect,
+                                   pace=args.pace)
                 e1.record(stream)
                 torch.cuda.synchronize()
                 total += e0.elapsed_time(e1) * 1e-3
@@ -228,7 +229,9 @@ def time_to_tolerance(args, stream) -> tuple[list, dict]:
             if args.save_x:
                 np.save(f"{args.save_x}_{mode_name}_{args.local}_{storage}.npy", xh)
             r = {"study": "time_to_tolerance", "config": args.config, "n": int(A.n),
-                 "local": f"{args.local}-{storage}", "mode": mode_name, "converged": bool(info["converged"]),
+                 "local": f"{args.local}-{storage}",
+                 "mode": mode_name if args.pace is None or mode == "sync" else f"{mode_name} pace {args.pace:g}",
+                 "converged": bool(info["converged"]),
                  "seconds": total, "tol": cfg["tol"],
                  "rel_residual_host": float(np.linalg.norm(b - A.matvec(xh)) / np.linalg.norm(b)),
                  "local_solves_min": int(counts.min()), "local_solves_median": float(np.median(counts)),
@@ -327,6 +330,8 @@ def main(argv=None):
     ap.add_argument("--modes", default="sync,async",
                     help="time_to_tolerance: any of sync, async, async-decentral (decentralized detection)")
     ap.add_argument("--chunk", type=float, default=50.0)
+    ap.add_argument("--pace", type=float, default=None,
+                    help="time_to_tolerance: asynchronous read pacing (default: the library's choice)")
     ap.add_argument("--budget", type=float, default=1000.0, help="time_to_tolerance: seconds per mode at most")
     ap.add_argument("--save-x", default=None, help="time_to_tolerance: save each solution as <prefix>_<mode>_<local>_<storage>.npy")
     ap.add_argument("--parts", type=_ints, default=[4, 16, 36, 64])
