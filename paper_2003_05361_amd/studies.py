@@ -250,6 +250,63 @@ def time_to_tolerance(args, stream) -> tuple[list, dict]:
     return rows, {}
 
 
+def batching(args, stream) -> tuple[list, dict]:
+    """Many independent systems: the 2-D systems of the serving stream (log-normal
+    finite volumes, regular boxes of about 4,096 unknowns, overlap 2, banded
+    Cholesky FP32, every right-hand side), solved to 1e-8 one launch per system
+    and all in one batched persistent launch, in both modes."""
+    import torch
+
+    import paper_2003_05361_amd as ras
+    import ras_inputs as R
+
+    specs = [sp for sp in R.serving_stream(count=4 * args.systems) if sp["dims"] == 2][: args.systems]
+    hs, bs = [], []
+    for sp in specs:
+        A, B, parts = R.serving_system(sp)
+        hs.append(ras.setup(A, ras.partition("regular_2d", parts, grid=A.grid), 2, ras.local("chol", "fp32"),
+                            stream=stream))
+        bs.append(torch.tensor(B, dtype=torch.float64, device="cuda"))
+    rows = []
+    for mode in ("sync", "async"):
+        ras.batch_solve(hs, bs, tol=1e-8, mode=mode, max_seconds=60)  # first launch outside the timings
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for h, b in zip(hs, bs):
+            h.solve(b, tol=1e-8, mode=mode, max_seconds=60)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_seq = e0.elapsed_time(e1) * 1e-3
+        e0.record(stream)
+        _, infos = ras.batch_solve(hs, bs, tol=1e-8, mode=mode, max_seconds=60)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_bat = e0.elapsed_time(e1) * 1e-3
+        conv = all(i["converged"] for inf in infos for i in inf)
+        nrhs = sum(int(b.shape[0]) for b in bs)
+        r = {"study": "batching", "systems": len(hs), "rhs": nrhs, "unknowns": int(sum(h.n for h in hs)),
+             "mode": mode, "one_launch_per_system_s": t_seq, "one_batched_launch_s": t_bat,
+             "speedup": t_seq / t_bat, "all_converged": conv}
+        print(json.dumps(r), flush=True)
+        rows.append(r)
+    return rows, {}
+
+
+def markdown_batching(rows: list, cmd: str) -> str:
+    L = ["# Batching: independent systems in one persistent launch", "", "Command (one MI355X):", "", f"    {cmd}", "",
+         "The 2-D systems of the seeded serving stream (log-normal finite volumes, regular boxes of about 4,096 "
+         "unknowns, overlap 2, banded Cholesky FP32, all right-hand sides), solved to 1e-8 from x = 0: once as "
+         "one launch per system (the same handles, back to back on one stream), once as one batched launch. "
+         "HIP-event times, a first batched launch of each mode untimed.", "",
+         "| mode | systems | right-hand sides | unknowns | one launch per system (s) | one batched launch (s) | speedup | all converged |",
+         "|---|---|---|---|---|---|---|---|"]
+    for r in rows:
+        L.append(f"| {r['mode']} | {r['systems']} | {r['rhs']} | {r['unknowns']} | {r['one_launch_per_system_s']:.3f} | "
+                 f"{r['one_batched_launch_s']:.3f} | {r['speedup']:.2f} | {r['all_converged']} |")
+    return "\n".join(L) + "\n"
+
+
 def _fmt_matrix(vol: np.ndarray) -> list:
     P = vol.shape[0]
     out = ["| p \\ q | " + " | ".join(str(q) for q in range(P)) + " |", "|---" * (P + 1) + "|"]
@@ -321,7 +378,8 @@ def _ints(s: str) -> list:
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("study", choices=("partitioners", "overlap", "time_to_tolerance"))
+    ap.add_argument("study", choices=("partitioners", "overlap", "time_to_tolerance", "batching"))
+    ap.add_argument("--systems", type=int, default=64, help="batching: number of systems")
     ap.add_argument("--config", default="diffusion2d_2048_16x16", help="time_to_tolerance: ras_inputs workload")
     ap.add_argument("--storage", default="fp64")
     ap.add_argument("--storages", default=None, help="time_to_tolerance: comma-separated storages (overrides --storage)")
@@ -353,12 +411,18 @@ def main(argv=None):
     if not torch.cuda.is_available():
         raise SystemExit("the studies run the device solver: no GPU visible")
     stream = torch.cuda.current_stream()
-    run = {"partitioners": partitioners, "overlap": overlaps, "time_to_tolerance": time_to_tolerance}[args.study]
+    run = {"partitioners": partitioners, "overlap": overlaps, "time_to_tolerance": time_to_tolerance,
+           "batching": batching}[args.study]
     rows, heat = run(args, stream)
     if args.markdown:
         cmd = "python -m paper_2003_05361_amd.studies " + " ".join(sys.argv[1:] if argv is None else argv)
         with open(args.markdown, "w") as f:
-            f.write(markdown_ttt(rows, cmd) if args.study == "time_to_tolerance" else markdown(args.study, rows, heat, cmd))
+            if args.study == "time_to_tolerance":
+                f.write(markdown_ttt(rows, cmd))
+            elif args.study == "batching":
+                f.write(markdown_batching(rows, cmd))
+            else:
+                f.write(markdown(args.study, rows, heat, cmd))
     return rows
 
 

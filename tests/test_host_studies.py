@@ -55,3 +55,10 @@ def test_byte_model_parts():
     assert loc_b == 2 * 10 * 4 * 2 + 4 * 10 * 4 + 2 * 10 * 4
     _, loc_c, _ = local_solve_parts([10, 8, 5, 3], "cg", "fp32", 8)
     assert loc_c == 8 * 10 * (5 * 8 + 11 * 4)
+
+
+def test_batching_summary():
+    rows = [{"mode": "sync", "systems": 4, "rhs": 9, "unknowns": 1000, "one_launch_per_system_s": 2.0,
+             "one_batched_launch_s": 0.5, "speedup": 4.0, "all_converged": True}]
+    md = studies.markdown_batching(rows, "python -m x batching")
+    assert "| sync | 4 | 9 | 1000 | 2.000 | 0.500 | 4.00 | True |" in md
