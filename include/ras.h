@@ -298,6 +298,35 @@ ras_status ras_server_get_stats(ras_server* srv, ras_server_stats* out);
 /* Stops the server: pending systems are dropped, threads joined, memory freed.  */
 void ras_server_destroy(ras_server* srv);
 
+/* ---- the stop rule after a persistent asynchronous launch (host only) ----------
+ * Sec. 3.3.2: the detector inside the kernel decides from local criteria and
+ * the latest (mixed-time) subdomain residuals, so after the launch the host
+ * recomputes the exact global relative residual and decides, per right-hand
+ * side, what follows.  ras_solve applies exactly this rule; it is exported so
+ * that it can be checked without a GPU.
+ * kernel_stop: why the kernel stopped this right-hand side (RAS_KSTOP_*);
+ * verified_relres: exact ||b - A x|| / ||b|| after the launch; tol: the
+ * solve's tolerance; min_local_solves: fewest local solves of any of its
+ * subdomains so far; max_sweeps / max_seconds: the solve options' limits
+ * (max_seconds <= 0: none); elapsed_seconds: device time since the first
+ * launch; ordered: nonzero for mode ORDERED (which runs its passes once).
+ * Returns, in this order of precedence:
+ *   RAS_STEP_DIVERGED  kernel_stop is DIVERGED or the residual is not finite;
+ *   RAS_STEP_CONVERGED verified_relres < tol;
+ *   RAS_STEP_LIMIT     min_local_solves >= max_sweeps, a time limit hit (in the
+ *                      kernel or after it), or ordered;
+ *   RAS_STEP_RESUME    otherwise: clear the detector's flags, launch again
+ *                      from the current x.
+ * ras_final_status maps a final step to the status ras_solve returns
+ * (CONVERGED -> RAS_OK, LIMIT -> RAS_NOT_CONVERGED, DIVERGED ->
+ * RAS_E_DIVERGED; RESUME -> RAS_E_STATE, it is not final).  */
+enum { RAS_KSTOP_RUNNING = 0, RAS_KSTOP_DETECTED = 1, RAS_KSTOP_TIME = 2, RAS_KSTOP_EXHAUSTED = 3,
+       RAS_KSTOP_DIVERGED = 4 };
+enum { RAS_STEP_CONVERGED = 0, RAS_STEP_RESUME = 1, RAS_STEP_DIVERGED = 2, RAS_STEP_LIMIT = 3 };
+int32_t ras_async_next_step(int32_t kernel_stop, double verified_relres, double tol, int64_t min_local_solves,
+                            int64_t max_sweeps, double elapsed_seconds, double max_seconds, int32_t ordered);
+ras_status ras_final_status(int32_t step);
+
 const char* ras_last_error(void);
 /* Library version string. */
 const char* ras_version(void);

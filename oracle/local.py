@@ -143,8 +143,6 @@ class LocalSolver:
                 self.cb32 = dequantize_rows_fp16(self.Lhat, self.scale)
             elif storage != "fp64":
                 raise ValueError(storage)
-        elif kind == "exact_dense":
-            self.dense = np.linalg.inv(Ap.toarray())
         elif kind != "cg":
             raise ValueError(kind)
 
@@ -153,6 +151,4 @@ class LocalSolver:
             if self.storage == "fp64":
                 return chol_solve_fp64(self.cb, r)
             return chol_solve_lowp(self.cb32, r)
-        if self.kind == "exact_dense":
-            return self.dense @ r
         return cg_fixed(self.Ap, r, self.k, np.float64 if self.storage == "fp64" else np.float32)

@@ -74,8 +74,11 @@ class RAS:
         return b[om] - self.M[om] @ x
 
     # -- synchronous RAS -------------------------------------------------------------
-    def sync(self, b: np.ndarray, tol: float, max_sweeps: int, x0: np.ndarray | None = None):
-        """Returns (x, hist, sweeps): hist[k] = ||b - A x^k|| / ||b||, sweeps = updates applied."""
+    def sync(self, b: np.ndarray, tol: float, max_sweeps: int, x0: np.ndarray | None = None, pool=None):
+        """Returns (x, hist, sweeps): hist[k] = ||b - A x^k|| / ||b||, sweeps = updates applied.
+        pool: optional concurrent.futures executor; the local solves of one sweep are
+        independent (they all read r^k), so they may run concurrently; their
+        corrections are still added in subdomain order, so the result is the same."""
         x = np.zeros_like(b) if x0 is None else x0.astype(np.float64).copy()
         bn = np.linalg.norm(b)
         hist = []
@@ -86,8 +89,11 @@ class RAS:
             if hist[-1] < tol or k == max_sweeps:
                 return x, np.array(hist), k
             x_next = x.copy()
-            for s in self.subs:
-                delta = s.solver(r[s.omega])
+            if pool is None:
+                deltas = (s.solver(r[s.omega]) for s in self.subs)
+            else:
+                deltas = pool.map(lambda s: s.solver(r[s.omega]), self.subs)
+            for s, delta in zip(self.subs, deltas):
                 x_next[s.owned] += delta[s.pos]
             x = x_next
             k += 1

@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 from typing import Sequence
 
 import numpy as np
@@ -23,6 +24,9 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libras.so")
 
 # ----------------------------------------------------------------------------- C mirrors
 RAS_OK, RAS_NOT_CONVERGED, RAS_PENDING = 0, 1, 2
+# why a persistent launch stopped a right-hand side, and the host's next step (Sec. 3.3.2)
+KSTOP = {"running": 0, "detected": 1, "time": 2, "exhausted": 3, "diverged": 4}
+STEPS = {0: "converged", 1: "resume", 2: "diverged", 3: "limit"}
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "PENDING", -1: "E_ARG", -2: "E_PATTERN", -3: "E_NOT_SPD",
                 -4: "E_NOMEM", -5: "E_HIP", -6: "E_STATE", -7: "E_DIVERGED", -8: "E_UNSUPPORTED"}
 PART_KINDS = {"regular_1d": 0, "regular_2d": 1, "regular_3d": 2, "rcb": 3, "explicit": 4}
@@ -107,6 +111,9 @@ SIGNATURES = {
     "ras_server_wait": (C.c_int, [_P, C.c_uint64, C.c_double]),
     "ras_server_get_stats": (C.c_int, [_P, _P]),
     "ras_server_destroy": (None, [_P]),
+    "ras_async_next_step": (C.c_int32, [C.c_int32, C.c_double, C.c_double, C.c_int64, C.c_int64, C.c_double,
+                                        C.c_double, C.c_int32]),
+    "ras_final_status": (C.c_int, [C.c_int32]),
     "ras_last_error": (C.c_char_p, []),
     "ras_version": (C.c_char_p, []),
 }
@@ -279,8 +286,9 @@ class Plan:
 
     def setup(self, stream=None) -> "Handle":
         h = _P()
-        _check(lib().ras_setup_from_plan(self._p, _stream_ptr(stream), C.byref(h)))
-        return Handle(h, self.n)
+        sp = _stream_ptr(stream)
+        _check(lib().ras_setup_from_plan(self._p, sp, C.byref(h)))
+        return Handle(h, self.n, sp)
 
     def close(self):
         if getattr(self, "_p", None) and _lib_handle is not None:
@@ -290,7 +298,11 @@ class Plan:
                 pass
             self._p = None
 
-    __del__ = close
+    def __del__(self):
+        # at interpreter shutdown the HIP runtime (or a profiler's tool library)
+        # may already be gone: leave the memory to the process exit then
+        if not sys.is_finalizing():
+            self.close()
 
 
 # ----------------------------------------------------------------------------- device handle
@@ -302,6 +314,17 @@ def _stream_ptr(stream):
     return C.c_void_p(getattr(stream, "cuda_stream", stream))
 
 
+def _order_before(stream_value: int):
+    """Wait on the host for torch's current stream unless it is the library's
+    stream (the library's calls block until their results are on the device,
+    so nothing is needed afterwards)."""
+    import torch
+
+    cur = torch.cuda.current_stream()
+    if (cur.cuda_stream or 0) != stream_value:
+        cur.synchronize()
+
+
 def _opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team=0, pace=None) -> SolveOpts:
     return SolveOpts(MODES[mode], DETECT[detect], float(tol), int(max_sweeps), float(max_seconds), int(workgroups),
                      int(team), float(DEFAULT_PACE if pace is None else pace))
@@ -310,10 +333,16 @@ def _opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team=0, pace=N
 class Handle:
     """A system set up on the device (Alg. 1's INITIALIZATION_AND_SETUP done)."""
 
-    def __init__(self, ptr, n: int):
+    def __init__(self, ptr, n: int, stream):
         self._h = ptr
         self.n = n
         self.last_nrhs = 0
+        self._stream = stream.value or 0  # the HIP stream the library uses for this handle
+
+    def _order_after_current_stream(self):
+        """The library reads b and x on the handle's stream; tensors made (or
+        written) on torch's current stream must be complete before that."""
+        _order_before(self._stream)
 
     def stats(self) -> dict:
         s = PlanStats()
@@ -336,6 +365,7 @@ class Handle:
         nrhs = 1 if b.dim() == 1 else b.shape[0]
         x = torch.zeros_like(b) if x0 is None else x0.to(torch.float64).contiguous().clone()
         infos = (SolveInfo * nrhs)()
+        self._order_after_current_stream()
         st = lib().ras_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), nrhs,
                              C.byref(_opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team, pace)), infos)
         _check(st, (RAS_OK, RAS_NOT_CONVERGED) if allow_unconverged else (RAS_OK,))
@@ -371,12 +401,14 @@ class Handle:
         x = torch.zeros_like(b)
         t = C.c_int32()
         ms = C.c_double()
+        self._order_after_current_stream()
         _check(lib().ras_autotune(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), int(sweeps),
                                   C.byref(t), C.byref(ms)))
         return t.value, ms.value
 
     def relative_residual(self, b, x) -> float:
         r = C.c_double()
+        self._order_after_current_stream()
         _check(lib().ras_relative_residual(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
                                            C.byref(r)))
         return r.value
@@ -389,15 +421,20 @@ class Handle:
                 pass
             self._h = None
 
-    __del__ = close
+    def __del__(self):
+        # at interpreter shutdown the HIP runtime (or a profiler's tool library)
+        # may already be gone: leave the memory to the process exit then
+        if not sys.is_finalizing():
+            self.close()
 
 
 def setup(A, part: dict, overlap: int, loc: dict, stream=None) -> Handle:
     keep = _Keep()
     h = _P()
+    sp = _stream_ptr(stream)
     _check(lib().ras_setup(C.byref(_csr(A, keep)), C.byref(_part(part, A, keep)), int(overlap),
-                           C.byref(_local(loc)), _stream_ptr(stream), C.byref(h)))
-    return Handle(h, len(A.indptr) - 1)
+                           C.byref(_local(loc)), sp, C.byref(h)))
+    return Handle(h, len(A.indptr) - 1, sp)
 
 
 def batch_solve(handles: Sequence[Handle], bs, xs=None, tol: float = 1e-8, mode: str = "async",
@@ -415,6 +452,8 @@ def batch_solve(handles: Sequence[Handle], bs, xs=None, tol: float = 1e-8, mode:
     X = (_P * m)(*[x.data_ptr() for x in xs])
     NR = (C.c_int32 * m)(*nr)
     infos = (SolveInfo * sum(nr))()
+    for h in handles:
+        h._order_after_current_stream()
     st = lib().ras_batch_solve(m, H, B, X, NR,
                                C.byref(_opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team, pace)), infos)
     _check(st, (RAS_OK, RAS_NOT_CONVERGED))
@@ -482,7 +521,25 @@ class Server:
                 pass
             self._s = None
 
-    __del__ = close
+    def __del__(self):
+        # at interpreter shutdown the HIP runtime (or a profiler's tool library)
+        # may already be gone: leave the memory to the process exit then
+        if not sys.is_finalizing():
+            self.close()
+
+
+def async_next_step(kernel_stop: str, verified_relres: float, tol: float, min_local_solves: int, max_sweeps: int,
+                    elapsed_seconds: float = 0.0, max_seconds: float = 0.0, ordered: bool = False) -> str:
+    """The library's decision after an asynchronous launch ends for one right-hand
+    side: "converged", "resume", "diverged" or "limit" (host only)."""
+    return STEPS[lib().ras_async_next_step(KSTOP[kernel_stop], float(verified_relres), float(tol),
+                                           int(min_local_solves), int(max_sweeps), float(elapsed_seconds),
+                                           float(max_seconds), int(bool(ordered)))]
+
+
+def final_status(step: str) -> int:
+    """The ras_solve status of a final step."""
+    return int(lib().ras_final_status({v: k for k, v in STEPS.items()}[step]))
 
 
 def sparse_max_rows(storage: str = "fp64") -> int:

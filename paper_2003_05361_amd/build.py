@@ -33,7 +33,19 @@ def _run(cmd):
     return p.stdout
 
 
-def build(verbose: bool = False) -> str:
+def _stale(cmd) -> bool:
+    """A compile step is stale when its object is older than its source or any header."""
+    out = cmd[cmd.index("-o") + 1]
+    src = cmd[cmd.index("-c") + 1]
+    if not os.path.exists(out):
+        return True
+    deps = [src] + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    deps.append(os.path.join(ROOT, "include", "ras.h"))
+    return any(os.path.getmtime(d) > os.path.getmtime(out) for d in deps)
+
+
+def build(verbose: bool = False, force: bool = True) -> str:
+    """Compile every source (force) or only the stale ones, then link libras.so."""
     os.makedirs(BUILD, exist_ok=True)
     os.makedirs(LIBDIR, exist_ok=True)
     jobs = [
@@ -42,19 +54,23 @@ def build(verbose: bool = False) -> str:
           os.path.join(BUILD, "plan.o")]),
         (["g++", *COMMON, "-ffp-contract=off", "-c", os.path.join(CSRC, "sparse.cpp"), "-o",
           os.path.join(BUILD, "sparse.o")]),
+        (["g++", *COMMON, "-c", os.path.join(CSRC, "control.cpp"), "-o", os.path.join(BUILD, "control.o")]),
         ([HIPCC, *COMMON, "-ffp-contract=off", "-c", os.path.join(CSRC, "api.cpp"), "-o",
           os.path.join(BUILD, "api.o")]),
         ([HIPCC, *COMMON, f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-x", "hip", "-c",
           os.path.join(CSRC, "kernels.hip"), "-o", os.path.join(BUILD, "kernels.o")]),
     ]
-    with cf.ThreadPoolExecutor(max_workers=4) as ex:
+    if not force:
+        jobs = [j for j in jobs if _stale(j)]
+    with cf.ThreadPoolExecutor(max_workers=5) as ex:
         outs = list(ex.map(_run, jobs))
     if verbose:
         for o in outs:
             sys.stdout.write(o)
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp,
-          os.path.join(BUILD, "plan.o"), os.path.join(BUILD, "sparse.o"), os.path.join(BUILD, "api.o"),
+          os.path.join(BUILD, "plan.o"), os.path.join(BUILD, "sparse.o"), os.path.join(BUILD, "control.o"),
+          os.path.join(BUILD, "api.o"),
           os.path.join(BUILD, "kernels.o"),
           "-lpthread"])
     os.replace(tmp, LIB)
@@ -62,4 +78,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, force="--changed" not in sys.argv))

@@ -984,7 +984,7 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
         return std::sqrt(out[0] / out[1]);
     };
     std::vector<int64_t> solves_h(nitems);
-    bool time_out = false;
+    std::vector<int32_t> step(ninst, RAS_STEP_RESUME);
     for (int launch = 0;; ++launch) {
         hip_check(hipEventRecord(ek0, stream), "event record");
         hip_check(launch_solver(kern, h0.solver, P, cfg.band_args, lds, stream, sync || T > 1),
@@ -1019,6 +1019,10 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
                     hip_check(launch_copy(specs[i].h->plan->n, insts[i].x1, insts[i].x0, stream), "copy result");
                 relres[i] = exact_relres(i);
                 verified[i] = 1;
+                // a synchronous solve ran its sweeps: only the verified residual decides
+                step[i] = !std::isfinite(relres[i]) ? RAS_STEP_DIVERGED
+                          : relres[i] < tol_v[i]    ? RAS_STEP_CONVERGED
+                                                    : RAS_STEP_LIMIT;
             }
             break;
         }
@@ -1035,15 +1039,10 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
             hist_t[i].push_back(ms_now * 1e-3);
             int64_t mn = INT64_MAX;
             for (int k = 0; k < insts[i].item_count; ++k) mn = std::min(mn, solves_h[insts[i].item_begin + k]);
-            const bool exhausted = mn >= o.max_sweeps;
-            const bool timed = ist[i].stop == 2 || (o.max_seconds > 0 && ms_now * 1e-3 > o.max_seconds);
-            if (ist[i].stop == 4 || !std::isfinite(relres[i])) {
+            step[i] = ras_async_next_step(ist[i].stop, relres[i], tol_v[i], mn, o.max_sweeps, ms_now * 1e-3,
+                                          o.max_seconds, ordered ? 1 : 0);
+            if (step[i] != RAS_STEP_RESUME) {
                 verified[i] = 1;
-                continue;
-            }
-            if (relres[i] < tol_v[i] || exhausted || timed || ordered) {
-                verified[i] = 1;
-                time_out = time_out || timed;
                 continue;
             }
             // resume: clear this instance's stop flag and its detection flags
@@ -1054,14 +1053,18 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
                       "clear flags");
             again = true;
         }
-        if (!again || launch > 10000) break;
+        if (!again) break;
+        if (launch > 10000) {  // give up resuming: report what the last verification found
+            for (int i = 0; i < ninst; ++i)
+                if (step[i] == RAS_STEP_RESUME) step[i] = RAS_STEP_LIMIT;
+            break;
+        }
         for (int i = 0; i < ninst; ++i) {
             if (verified[i]) ist[i].stop = 1;  // keep finished systems parked
             ist[i].hist_len = 0;
         }
         hip_check(hipMemcpy(P.ist, ist.data(), ninst * sizeof(InstState), hipMemcpyHostToDevice), "resume state");
     }
-    (void)time_out;
     hip_check(hipEventRecord(ev1, stream), "event");
     hip_check(hipEventSynchronize(ev1), "event");
     float ms = 0.0f;
@@ -1072,8 +1075,7 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     for (int i = 0; i < ninst; ++i) {
         ras_solve_info& inf = info[i];
         std::memset(&inf, 0, sizeof(inf));
-        const bool finite = std::isfinite(relres[i]);
-        inf.converged = finite && relres[i] < tol_v[i];
+        inf.converged = step[i] == RAS_STEP_CONVERGED;
         inf.launches = launches[i];
         inf.rel_residual = relres[i];
         inf.seconds = ms * 1e-3;
@@ -1103,8 +1105,9 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
         h->hist[r] = std::move(hist[i]);
         h->hist_t[r] = std::move(hist_t[i]);
         h->counts[r] = std::move(cnt);
-        if (!finite) status = RAS_E_DIVERGED;
-        else if (!inf.converged && status == RAS_OK) status = RAS_NOT_CONVERGED;
+        const ras_status si = ras_final_status(step[i]);
+        if (si < 0) status = si;
+        else if (si > 0 && status == RAS_OK) status = si;
     }
     if (status == RAS_E_DIVERGED) g_err = "non-finite residual";
     else if (status == RAS_NOT_CONVERGED) g_err = "tolerance not reached within max_sweeps / max_seconds";

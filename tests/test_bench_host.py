@@ -26,12 +26,17 @@ def test_traffic_lookup_follows_kernel_hash():
     path = os.path.join(ROOT, "profiles", "traffic_poisson2d_1024_8x8.json")
     t = json.load(open(path))
     ratio = t["counter_bytes_per_dispatch"] / t["algorithmic_bytes_per_dispatch"]
-    got = bench.traffic_from_profiles("poisson2d_1024_8x8", 1000.0)
+    got, src = bench.traffic_from_profiles("poisson2d_1024_8x8", 1000.0)
     if t["kernel_hash"] == bench.kernel_source_hash():
-        assert abs(got - 1000.0 * ratio) < 1e-9
+        assert abs(got - 1000.0 * ratio) < 1e-9 and src.startswith("derived_from_profile")
     else:
-        assert got is None
-    assert bench.traffic_from_profiles("no_such_workload", 1.0) is None
+        assert got is None and src is None
+    assert bench.traffic_from_profiles("no_such_workload", 1.0) == (None, None)
+
+
+def test_host_cpu_is_stated():
+    c = bench.host_cpu()
+    assert c["os_cpu_count"] == os.cpu_count() and c["affinity"] >= 1
 
 
 def test_more_than_one_gpu_is_refused():

@@ -70,6 +70,16 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def _agree(a, b, tol, what=""):
+    """Iterate parity, normwise and element by element:
+    ||a - b||_2 <= tol ||b||_2 and max_i |a_i - b_i| <= tol ||b||_inf."""
+    a, b = np.asarray(a), np.asarray(b)
+    assert a.shape == b.shape, (what, a.shape, b.shape)
+    nrm = _rel(a, b)
+    ew = float(np.max(np.abs(a - b), initial=0.0) / max(np.max(np.abs(b), initial=0.0), 1e-300))
+    assert nrm <= tol and ew <= tol, (what, "normwise", nrm, "elementwise", ew, "tol", tol)
+
+
 # ----------------------------------------------------------------------------- synchronous parity
 def test_config1_sync_exact_history_and_solution():
     """64^2 Poisson, 4 strips, overlap 2, banded Cholesky FP64, sync to 1e-10."""
@@ -85,7 +95,7 @@ def test_config1_sync_exact_history_and_solution():
     assert info[0]["converged"] and info[0]["sweeps"] == ko
     assert len(hg) == len(ho)
     assert np.all(np.abs(hg - ho) <= 1e-9 * ho + 1e-13)
-    assert _rel(x, xo) <= 1e-9
+    _agree(x, xo, 1e-9)
     assert info[0]["rel_residual"] < 1e-10
     xd = schwarz.direct_solve(A, b)
     assert _rel(x, xd) <= 1e-6
@@ -109,7 +119,7 @@ def test_sync_cg_fp64_matches_oracle(N, part, gamma, k):
         xo, ho, _ = orc.sync(b, 0.0, sweeps)
         x, info = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=sweeps)
         assert info[0]["sweeps"] == sweeps
-        assert _rel(x.cpu().numpy(), xo) <= 1e-9
+        _agree(x.cpu().numpy(), xo, 1e-9)
         _, hg = h.residual_history()
         assert np.all(np.abs(hg - ho) <= 1e-9 * ho + 1e-13)
 
@@ -128,7 +138,7 @@ def test_sync_cg_team_sizes_match_oracle(team):
     for sweeps in (1, 4):
         xo, ho, _ = orc.sync(b, 0.0, sweeps)
         x, info = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=sweeps, team=team)
-        assert _rel(x.cpu().numpy(), xo) <= 1e-9
+        _agree(x.cpu().numpy(), xo, 1e-9)
         _, hg = h.residual_history()
         assert np.all(np.abs(hg - ho) <= 1e-9 * ho + 1e-13)
     xa, info = h.solve(_cuda(b), tol=1e-8, mode="async", max_sweeps=100000, max_seconds=60, team=team)
@@ -146,7 +156,7 @@ def test_ordered_cg_team_is_multiplicative_schwarz(team):
     h = ras.setup(A, _spec(ras, A, *part), 2, ras.local("cg", "fp64", 5))
     xo, _ = orc.ordered(b, 3)
     x, _ = h.solve(_cuda(b), tol=0.0, mode="ordered", max_sweeps=3, team=team)
-    assert _rel(x.cpu().numpy(), xo) <= 1e-9
+    _agree(x.cpu().numpy(), xo, 1e-9)
 
 
 def test_sync_cg_fp32_3d_rcb_matches_oracle():
@@ -160,7 +170,7 @@ def test_sync_cg_fp32_3d_rcb_matches_oracle():
     for sweeps in (1, 4):
         xo, ho, _ = orc.sync(b, 0.0, sweeps)
         x, _ = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=sweeps)
-        assert _rel(x.cpu().numpy(), xo) <= 2e-5
+        _agree(x.cpu().numpy(), xo, 2e-5)
     # and it converges to the float64 tolerance (correction form)
     x, info = h.solve(_cuda(b), tol=1e-8, mode="sync", max_sweeps=5000)
     assert info[0]["converged"] and info[0]["rel_residual"] < 1e-8
@@ -179,7 +189,7 @@ def test_sync_band_storage_matches_oracle(storage, tol):
     for sweeps in (1, 3):
         xo, _, _ = orc.sync(b, 0.0, sweeps)
         x, _ = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=sweeps)
-        assert _rel(x.cpu().numpy(), xo) <= tol
+        _agree(x.cpu().numpy(), xo, tol)
     x, info = h.solve(_cuda(b), tol=1e-8, mode="sync", max_sweeps=20000)
     assert info[0]["converged"] and info[0]["rel_residual"] < 1e-8
 
@@ -208,7 +218,7 @@ def test_sync_band_widths_match_oracle(case, storage, tol):
     for sweeps in (1, 2):
         xo, ho, _ = orc.sync(b, 0.0, sweeps)
         x, _ = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=sweeps)
-        assert _rel(x.cpu().numpy(), xo) <= tol
+        _agree(x.cpu().numpy(), xo, tol)
 
 
 # sparse Cholesky local solves (nested dissection, level-scheduled triangular
@@ -231,7 +241,7 @@ def test_sync_sparse_cholesky_matches_oracle(case, storage, tol):
     for sweeps in (1, 3):
         xo, ho, _ = orc.sync(b, 0.0, sweeps)
         x, _ = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=sweeps)
-        assert _rel(x.cpu().numpy(), xo) <= tol, (sweeps, _rel(x.cpu().numpy(), xo))
+        _agree(x.cpu().numpy(), xo, tol, (sweeps, _rel(x.cpu().numpy(), xo)))
     _, hist, _ = orc.sync(b, 0.0, 6)
     h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=6)
     _, hh = h.residual_history()
@@ -286,7 +296,7 @@ def test_single_subdomain_is_direct_solve():
     h = ras.setup(A, ras.partition("regular_1d", 1), 0, ras.local("chol", "fp64"))
     x, info = h.solve(_cuda(b), tol=1e-12, mode="sync", max_sweeps=5)
     assert info[0]["sweeps"] == 1 and info[0]["converged"]
-    assert _rel(x.cpu().numpy(), schwarz.direct_solve(A, b)) <= 1e-12
+    _agree(x.cpu().numpy(), schwarz.direct_solve(A, b), 1e-12)
 
 
 def test_tiny_and_ragged_subdomains():
@@ -301,7 +311,7 @@ def test_tiny_and_ragged_subdomains():
         h = ras.setup(A, _spec(ras, A, *part), 1, ras.local(loc, st, k))
         xo, _, _ = orc.sync(b, 0.0, 3)
         x, _ = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=3)
-        assert _rel(x.cpu().numpy(), xo) <= 1e-9
+        _agree(x.cpu().numpy(), xo, 1e-9)
 
 
 # ----------------------------------------------------------------------------- ordered = RMS
@@ -318,7 +328,7 @@ def test_ordered_mode_is_multiplicative_schwarz(loc, k):
         xo, _ = orc.ordered(b, passes)
         x, info = h.solve(_cuda(b), tol=0.0, mode="ordered", max_sweeps=passes)
         assert info[0]["min_local_solves"] == passes and info[0]["max_local_solves"] == passes
-        assert _rel(x.cpu().numpy(), xo) <= 1e-9
+        _agree(x.cpu().numpy(), xo, 1e-9)
 
 
 # ----------------------------------------------------------------------------- asynchronous
@@ -420,24 +430,112 @@ def test_multi_rhs_equals_single_sync(loc):
         assert infos[j]["sweeps"] == i1[0]["sweeps"]
 
 
-@pytest.mark.parametrize("kind", ["chol", "chol_sparse"])
+@pytest.mark.parametrize("kind", ["chol", "chol_sparse", "cg"])
 def test_batch_equals_alone(kind):
+    """Systems batched into one launch give the same iterates as alone: bit for bit
+    for the direct solvers; for CG (fixed team of 2) the rows-per-thread split follows
+    the largest subdomain of the launch, so sums are taken in another order and the
+    iterates agree to rounding, with the same sweep counts."""
     ras = _ras()
     _say(f"case: batch {kind}")
     torch = _torch()
     A1, A2 = R.laplace2d(40), R.laplace3d(12)
     b1, b2 = R.uniform_rhs(A1.n, 3), R.uniform_rhs(A2.n, 4)
-    h1 = ras.setup(A1, ras.partition("regular_2d", (2, 2), grid=A1.grid), 2, ras.local(kind, "fp64"))
-    h2 = ras.setup(A2, ras.partition("regular_3d", (2, 2, 2), grid=A2.grid), 1, ras.local(kind, "fp64"))
-    xs, infos = ras.batch_solve([h1, h2], [_cuda(b1), _cuda(b2)], tol=1e-9, mode="sync", max_sweeps=100000)
-    a1, _ = h1.solve(_cuda(b1), tol=1e-9, mode="sync", max_sweeps=100000)
-    a2, _ = h2.solve(_cuda(b2), tol=1e-9, mode="sync", max_sweeps=100000)
-    assert torch.equal(xs[0], a1) and torch.equal(xs[1], a2)
-    ys, infos = ras.batch_solve([h1, h2], [_cuda(b1), _cuda(b2)], tol=1e-9, mode="async", max_sweeps=100000)
+    k = 6 if kind == "cg" else 0
+    team = 2 if kind == "cg" else 0
+    h1 = ras.setup(A1, ras.partition("regular_2d", (2, 2), grid=A1.grid), 2, ras.local(kind, "fp64", k))
+    h2 = ras.setup(A2, ras.partition("regular_3d", (2, 2, 2), grid=A2.grid), 1, ras.local(kind, "fp64", k))
+    xs, infos = ras.batch_solve([h1, h2], [_cuda(b1), _cuda(b2)], tol=1e-9, mode="sync", max_sweeps=100000,
+                                team=team)
+    a1, i1 = h1.solve(_cuda(b1), tol=1e-9, mode="sync", max_sweeps=100000, team=team)
+    a2, i2 = h2.solve(_cuda(b2), tol=1e-9, mode="sync", max_sweeps=100000, team=team)
+    assert infos[0][0]["sweeps"] == i1[0]["sweeps"] and infos[1][0]["sweeps"] == i2[0]["sweeps"]
+    if kind == "cg":
+        _agree(xs[0].cpu().numpy(), a1.cpu().numpy(), 1e-12)
+        _agree(xs[1].cpu().numpy(), a2.cpu().numpy(), 1e-12)
+        # and both equal the oracle's iteration
+        orc = _oracle(A1, "regular_2d", (2, 2), 2, "cg", "fp64", k)
+        xo, _, ko = orc.sync(b1, 1e-9, 100000)
+        assert ko == i1[0]["sweeps"]
+        _agree(a1.cpu().numpy(), xo, 1e-9)
+    else:
+        assert torch.equal(xs[0], a1) and torch.equal(xs[1], a2)
+    ys, infos = ras.batch_solve([h1, h2], [_cuda(b1), _cuda(b2)], tol=1e-9, mode="async", max_sweeps=100000,
+                                team=team)
     for y, A, b in ((ys[0], A1, b1), (ys[1], A2, b2)):
         yy = y.cpu().numpy()
         assert schwarz.relative_residual(A, yy, b) < 1e-9
         assert _rel(yy, schwarz.direct_solve(A, b)) <= 1e-6
+
+
+# ----------------------------------------------------------------------------- warnings and errors
+@pytest.mark.parametrize("loc,k", [("chol", 0), ("cg", 6)])
+def test_not_converged_returns_valid_iterate(loc, k):
+    """A limit reached before the tolerance: RAS_NOT_CONVERGED (a warning), a valid
+    iterate and info; with allow_unconverged=False the binding raises it."""
+    ras = _ras()
+    _say(f"case: not converged {loc}")
+    A = R.laplace2d(40)
+    b = R.uniform_rhs(A.n, 31)
+    part = ("regular_2d", (2, 2))
+    orc = _oracle(A, *part, 2, loc, "fp64", k)
+    h = ras.setup(A, _spec(ras, A, *part), 2, ras.local(loc, "fp64", k))
+    xo, ho, _ = orc.sync(b, 1e-12, 3)
+    x, info = h.solve(_cuda(b), tol=1e-12, mode="sync", max_sweeps=3)
+    assert not info[0]["converged"] and info[0]["sweeps"] == 3
+    _agree(x.cpu().numpy(), xo, 1e-9)
+    assert abs(info[0]["rel_residual"] - schwarz.relative_residual(A, x.cpu().numpy(), b)) <= 1e-9 * ho[-1]
+    with pytest.raises(ras.RasError) as e:
+        h.solve(_cuda(b), tol=1e-12, mode="sync", max_sweeps=3, allow_unconverged=False)
+    assert e.value.status == 1
+    # asynchronous: 5 local solves per subdomain, then the exact check fails -> limit
+    x, info = h.solve(_cuda(b), tol=1e-12, mode="async", max_sweeps=5, max_seconds=30)
+    xx = x.cpu().numpy()
+    assert not info[0]["converged"] and info[0]["max_local_solves"] == 5 and info[0]["min_local_solves"] == 5
+    assert np.all(np.isfinite(xx))
+    assert abs(info[0]["rel_residual"] - schwarz.relative_residual(A, xx, b)) <= 1e-9 * info[0]["rel_residual"]
+    # and the residual history ends with that exact value
+    _, hh = h.residual_history()
+    assert hh[-1] == info[0]["rel_residual"]
+
+
+@pytest.mark.parametrize("mode", ["sync", "async"])
+def test_non_finite_initial_guess_is_diverged(mode):
+    """A NaN in x0 makes every residual non-finite: RAS_E_DIVERGED, in both modes."""
+    ras = _ras()
+    _say(f"case: diverged {mode}")
+    A = R.laplace2d(40)
+    b = R.uniform_rhs(A.n, 32)
+    h = ras.setup(A, ras.partition("regular_2d", (2, 2), grid=A.grid), 2, ras.local("chol", "fp64"))
+    x0 = np.zeros(A.n)
+    x0[A.n // 2 + 7] = np.nan
+    with pytest.raises(ras.RasError) as e:
+        h.solve(_cuda(b), x0=_cuda(x0), tol=1e-8, mode=mode, max_sweeps=1000, max_seconds=30)
+    assert e.value.status == -7
+    # the handle stays usable
+    x, info = h.solve(_cuda(b), tol=1e-8, mode=mode, max_sweeps=100000, max_seconds=30)
+    assert info[0]["converged"] and schwarz.relative_residual(A, x.cpu().numpy(), b) < 1e-8
+
+
+def test_solve_under_a_side_stream():
+    """b written on a torch side stream, solve called under that stream: the library's
+    stream is ordered after it, and the result equals the default-stream solve."""
+    ras = _ras()
+    torch = _torch()
+    _say("case: side stream")
+    A = R.laplace2d(48)
+    b = R.uniform_rhs(A.n, 33)
+    h = ras.setup(A, ras.partition("regular_2d", (3, 3), grid=A.grid), 2, ras.local("cg", "fp64", 6))
+    x_ref, _ = h.solve(_cuda(b), tol=1e-9, mode="sync", max_sweeps=100000)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        bt = torch.empty(A.n, dtype=torch.float64, device="cuda")
+        bt.copy_(torch.from_numpy(b).pin_memory(), non_blocking=True)
+        bt.mul_(2.0).mul_(0.5)  # more (exact) work queued on the side stream before the solve
+        x, info = h.solve(bt, tol=1e-9, mode="sync", max_sweeps=100000)
+    torch.cuda.synchronize()
+    assert info[0]["converged"]
+    assert torch.equal(x, x_ref)
 
 
 def test_autotune_picks_a_feasible_team_and_keeps_parity():
@@ -451,7 +549,7 @@ def test_autotune_picks_a_feasible_team_and_keeps_parity():
     orc = _oracle(A, "regular_2d", (2, 2), 3, "cg", "fp64", 6)
     xo, _, _ = orc.sync(b, 0.0, 3)
     x, _ = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=3)  # team 0 -> the tuned one
-    assert _rel(x.cpu().numpy(), xo) <= 1e-9
+    _agree(x.cpu().numpy(), xo, 1e-9)
 
 
 # ----------------------------------------------------------------------------- full-size sampled checks
@@ -464,7 +562,7 @@ def test_config2_full_size_two_sweeps():
     xo, ho, _ = orc.sync(b, 0.0, 2)
     h = ras.setup(A, ras.partition("regular_2d", (8, 8), grid=A.grid), 4, ras.local("cg", "fp64", 10))
     x, info = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=2)
-    assert _rel(x.cpu().numpy(), xo) <= 1e-9
+    _agree(x.cpu().numpy(), xo, 1e-9)
     _, hg = h.residual_history()
     assert np.all(np.abs(hg - ho) <= 1e-9 * ho + 1e-13)
 
@@ -499,7 +597,7 @@ def test_config4_full_size_first_sweep_sampled(storage, tol):
     owner = opart.regular_grid(A.grid, (16, 16))
     for p in (0, 7, 136, 255):
         own, d = _oracle_subdomain_update(A, owner, p, 4, b, ("chol", storage))
-        assert _rel(x[own], d) <= tol, (p, _rel(x[own], d))
+        _agree(x[own], d, tol, (p, _rel(x[own], d)))
 
 
 def test_config3_full_size_first_sweep_sampled():
@@ -517,4 +615,4 @@ def test_config3_full_size_first_sweep_sampled():
     owner = opart.rcb(A.coords(), 256, 3, 0.4)
     for p in (0, 77, 160, 255):
         own, d = _oracle_subdomain_update(A, owner, p, 1, b, ("cg", "fp32", 8))
-        assert _rel(x[own], d) <= 2e-5, (p, team, _rel(x[own], d))
+        _agree(x[own], d, 2e-5, (p, team, _rel(x[own], d)))

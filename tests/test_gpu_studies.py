@@ -24,9 +24,10 @@ def _oracle_owner(A, scheme, P):
     if scheme == "regular_1d":
         return opart.regular_1d(A.n, P)
     if scheme == "regular_2d":
-        from paper_2003_05361_amd.studies import _square_split
-
-        return opart.regular_grid(A.grid, _square_split(P))
+        # the most nearly square factorisation P = px * py, px >= py
+        px, py = min(((P // d, d) for d in range(1, P + 1) if P % d == 0 and P // d >= d),
+                     key=lambda f: f[0] - f[1])
+        return opart.regular_grid(A.grid, (px, py))
     return opart.rcb(A.coords(), P, 0, 0.0)
 
 

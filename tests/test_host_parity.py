@@ -73,6 +73,39 @@ def test_index_sets_bit_exact(name, A, part, gamma):
     assert np.array_equal(idx2, idx)
 
 
+# the three full-size workloads, in the partitions and overlaps they are solved with
+FULL_SIZE = [
+    ("poisson2d_1024_8x8_g4", lambda: R.laplace2d(1024), ("regular_2d", (8, 8)), 4),
+    ("laplace3d_128_rcb256_g1", lambda: R.laplace3d(128), ("rcb", (256, 3, 0.4)), 1),
+    ("diffusion2d_2048_16x16_g4", lambda: R.config_problem("diffusion2d_2048_16x16")[0], ("regular_2d", (16, 16)), 4),
+]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,make,part,gamma", FULL_SIZE, ids=[c[0] for c in FULL_SIZE])
+def test_index_sets_bit_exact_full_size(name, make, part, gamma):
+    """owner, omega_ptr and omega_idx of the full-size workloads, bit-exact against
+    the oracle's partition and breadth-first overlap."""
+    _lib_or_skip()
+    A = make()
+    kind, arg = part
+    if kind == "rcb":
+        P, seed, jit = arg
+        owner = opart.rcb(A.coords(), P, seed, jit)
+        spec = ras.partition("rcb", P, grid=A.grid, seed=seed, jitter=jit)
+    else:
+        owner = opart.regular_grid(A.grid, arg)
+        spec = ras.partition(kind, arg, grid=A.grid)
+    plan = ras.Plan(A, spec, gamma, ras.local("cg", "fp64", 1))
+    o2, ptr2, idx2 = plan.sets()
+    plan.close()
+    assert np.array_equal(o2, owner)
+    ptr, idx = _oracle_sets(A, owner, gamma)
+    assert ptr2.dtype == np.int64 and idx2.dtype == np.int32
+    assert np.array_equal(ptr2, ptr)
+    assert np.array_equal(idx2, idx)
+
+
 @pytest.mark.parametrize("name,A,part,gamma", CASES, ids=[c[0] for c in CASES])
 def test_comm_volume_bit_exact(name, A, part, gamma):
     _lib_or_skip()
@@ -344,3 +377,36 @@ def test_sparse_factor_of_disconnected_local_matrices():
         L = sp.csr_matrix((val, col, rp), shape=(om.size, om.size)) + sp.diags(diag)
         Ap = M[om][:, om][perm][:, perm]
         assert abs(L @ L.T - Ap).max() <= 1e-12 * abs(Ap).max()
+
+
+# ----------------------------------------------------------------------------- stop rule (Sec. 3.3.2)
+def test_async_stop_rule():
+    """After an asynchronous launch the exact residual is verified; the library
+    resumes, stops or reports a limit / divergence by this rule (host only)."""
+    _lib_or_skip()
+    nxt = ras.async_next_step
+    # detector fired and verification passes / fails -> converged / resume
+    assert nxt("detected", 9e-9, 1e-8, 100, 1000) == "converged"
+    assert nxt("detected", 1.1e-8, 1e-8, 100, 1000) == "resume"
+    # equality is not below the tolerance (strict criterion)
+    assert nxt("detected", 1e-8, 1e-8, 100, 1000) == "resume"
+    # limits: local-solve count, kernel time limit, time passed after the kernel, ordered mode
+    assert nxt("exhausted", 1e-3, 1e-8, 1000, 1000) == "limit"
+    assert nxt("detected", 1e-3, 1e-8, 999, 1000) == "resume"
+    assert nxt("time", 1e-3, 1e-8, 10, 1000) == "limit"
+    assert nxt("detected", 1e-3, 1e-8, 10, 1000, elapsed_seconds=5.0, max_seconds=4.0) == "limit"
+    assert nxt("detected", 1e-3, 1e-8, 10, 1000, elapsed_seconds=5.0, max_seconds=0.0) == "resume"
+    assert nxt("running", 1e-3, 1e-8, 3, 3, ordered=True) == "limit"
+    assert nxt("running", 1e-3, 1e-8, 1, 3, ordered=True) == "limit"
+    # a converged verification wins over a limit hit at the same time
+    assert nxt("time", 1e-9, 1e-8, 1000, 1000) == "converged"
+    # divergence wins over everything
+    assert nxt("diverged", 1e-9, 1e-8, 1, 1000) == "diverged"
+    assert nxt("detected", float("nan"), 1e-8, 1, 1000) == "diverged"
+    assert nxt("detected", float("inf"), 1e-8, 1000, 1000) == "diverged"
+    # tolerance 0 never converges
+    assert nxt("exhausted", 0.0, 0.0, 5, 5) == "limit"
+    assert ras.final_status("converged") == 0
+    assert ras.final_status("limit") == 1
+    assert ras.final_status("diverged") == -7
+    assert ras.final_status("resume") == -6

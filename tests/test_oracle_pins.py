@@ -403,6 +403,21 @@ def test_more_overlap_fewer_sweeps():
     assert r2 < r1
 
 
+def test_sync_with_thread_pool_is_the_same_iteration():
+    """The local solves of one synchronous sweep all read r^k: running them on a
+    thread pool (the all-cores CPU baseline) gives the same iterates bit for bit."""
+    import concurrent.futures as cf
+
+    A = R.laplace2d(40)
+    b = R.uniform_rhs(A.n, 9)
+    for loc, k in (("chol", 0), ("cg", 5)):
+        ras = schwarz.RAS(A, partition.regular_grid(A.grid, (3, 3)), 2, loc, "fp64", k)
+        x1, h1, k1 = ras.sync(b, 0.0, 6)
+        with cf.ThreadPoolExecutor(4) as pool:
+            x2, h2, k2 = ras.sync(b, 0.0, 6, pool=pool)
+        assert k1 == k2 == 6 and np.array_equal(x1, x2) and np.array_equal(h1, h2)
+
+
 # ----------------------------------------------------------------- P10: ordered / asynchronous
 def test_ordered_zero_overlap_is_block_gauss_seidel():
     A = R.laplace2d(12)
