@@ -25,6 +25,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-1e-8 residual async vs sync RAS; sweep HBM GB/s vs peak; solves/s + p99"
 HBM_PEAK_GBPS = 8000.0
+# workloads whose working set fits the 256 MB Infinity Cache (MALL)
+MALL_RESIDENT = {"poisson2d_1024_8x8", "laplace3d_128_rcb256", "poisson2d_64_strips4"}
 
 WORKLOADS = {
     # name: (ras_inputs config, local kind, storage, cg iters, partition spec)
@@ -54,6 +56,8 @@ def parse():
     ap.add_argument("--sweeps", type=int, default=0,
                     help="fixed-sweep throughput mode: time N sweeps (synchronous) and N local solves per "
                          "subdomain (asynchronous) instead of solving to the tolerance; value = sweep GB/s")
+    ap.add_argument("--no-slab-legs", action="store_true",
+                    help="skip the fixed-sweep legs of the 2048^2 diffusion workload in the default run")
     ap.add_argument("--serve-count", type=int, default=200, help="systems in the serving stream")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     return ap.parse_args()
@@ -87,9 +91,30 @@ def part_spec(ras, A, kind, arg):
     return ras.partition(kind, arg, grid=A.grid)
 
 
-def cpu_baseline(A, b, part_kind, part_arg, gamma, kind, storage, k, gpu_sync_sweeps):
+def host_cpu() -> dict:
+    """Host CPU model and core count (lscpu, os.cpu_count)."""
+    import subprocess
+
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "os_cpu_count": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
+def cpu_baseline(A, b, part_kind, part_arg, gamma, kind, storage, k, gpu_sync_sweeps, budget=10.0):
     """The oracle (plain FP64 CPU synchronous RAS), timed on a bounded sample of
-    sweeps on this host, single-threaded, extrapolated to the GPU's sweep count."""
+    sweeps on this host -- single-threaded, then with the local solves of each sweep
+    on a thread pool over all usable cores (inner BLAS threads 1) -- and extrapolated
+    to the GPU's synchronous sweep count."""
+    import concurrent.futures as cf
+
     from threadpoolctl import threadpool_limits
 
     from oracle import partition as opart
@@ -101,42 +126,54 @@ def cpu_baseline(A, b, part_kind, part_arg, gamma, kind, storage, k, gpu_sync_sw
         owner = opart.rcb(A.coords(), *part_arg)
     else:
         owner = opart.regular_grid(A.grid, part_arg)
+    cpu = host_cpu()
+    # at most 16 workers: the host share of one GPU on the measurement machines
+    workers = max(1, min(16, cpu["affinity"] or os.cpu_count() or 1))
+    legs = {}
     with threadpool_limits(1):
         # the sparse factor solves the same local systems exactly: the oracle's exact local solve
         orc = schwarz.RAS(A, owner, gamma, "chol" if kind == "chol_sparse" else kind, storage, k)
-        sweeps = 1
-        t0 = time.perf_counter()
-        orc.sync(b, 0.0, 1)
-        t1 = time.perf_counter() - t0
-        budget = 15.0
-        sweeps = max(1, min(int(budget / max(t1, 1e-6)), 2000))
-        t0 = time.perf_counter()
-        orc.sync(b, 0.0, sweeps)
-        dt = time.perf_counter() - t0
-    per_sweep = dt / sweeps
+        for label, nw in (("single_core", 1), ("all_cores", workers)):
+            pool = cf.ThreadPoolExecutor(nw) if nw > 1 else None
+            t0 = time.perf_counter()
+            orc.sync(b, 0.0, 1, pool=pool)
+            t1 = time.perf_counter() - t0
+            sweeps = max(1, min(int(budget / max(t1, 1e-6)), 2000))
+            t0 = time.perf_counter()
+            orc.sync(b, 0.0, sweeps, pool=pool)
+            dt = time.perf_counter() - t0
+            if pool is not None:
+                pool.shutdown()
+            legs[label] = {"threads": nw, "sweeps": sweeps, "seconds": dt, "ms_per_sweep": 1e3 * dt / sweeps,
+                           "extrapolated_s": dt / sweeps * gpu_sync_sweeps}
+    best = min(legs.values(), key=lambda v: v["ms_per_sweep"])
     return {
-        "value": per_sweep * gpu_sync_sweeps,
+        "value": best["extrapolated_s"],
         "unit": "s (extrapolated time-to-tolerance)",
-        "cores": 1,
+        "cores": best["threads"],
         "kind": "oracle",
-        "sample": f"{sweeps} synchronous FP64 sweeps of the same workload in {dt:.2f} s on the host "
-                  f"({per_sweep * 1e3:.1f} ms/sweep), scaled by the GPU synchronous sweep count {gpu_sync_sweeps}",
+        "sample": f"{best['sweeps']} synchronous FP64 sweeps of the same workload in {best['seconds']:.2f} s on "
+                  f"{best['threads']} host threads ({best['ms_per_sweep']:.1f} ms/sweep; local solves of a sweep "
+                  f"on a thread pool, BLAS threads 1), scaled by the GPU synchronous sweep count {gpu_sync_sweeps}",
+        "legs": legs,
+        "host_cpu": cpu,
     }
 
 
 def traffic_from_profiles(workload: str, algo_bytes_per_launch: float):
-    """HBM bytes per launch from the committed hardware-counter summary, if it was
-    taken on the current kernel source; else None."""
+    """HBM bytes per launch derived from the committed hardware-counter summary
+    (copy-calibrated FETCH_SIZE + WRITE_SIZE over the streaming-model bytes of the
+    profiled dispatch, times this run's model bytes), if it was taken on the current
+    kernel source; else None.  Returns (bytes, source description)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
-        return None
+        return None, None
     with open(path) as f:
         t = json.load(f)
     if t.get("kernel_hash") != kernel_source_hash():
-        return None
+        return None, None
     ratio = t["counter_bytes_per_dispatch"] / t["algorithmic_bytes_per_dispatch"]
-    return ratio * algo_bytes_per_launch
-
+    return ratio * algo_bytes_per_launch, f"derived_from_profile profiles/traffic_{workload}.json (counter/model {ratio:.3f})"
 
 
 def occupancy_summary(occ, budget):
@@ -250,68 +287,103 @@ def serving_bench(args):
     }
     print(json.dumps(line), flush=True)
 
-def sweep_bench(args, A, b, h, bt, bps, st, stream, kind, storage, k, tol, gamma, part_kind, part_arg, setup_s):
-    """Fixed work: N synchronous sweeps, and N local solves per subdomain of the
-    asynchronous kernel (tolerance 0, so nothing stops early).  Sweep bandwidth =
-    algorithmic bytes of the local solves done / kernel time (HIP events on the
-    solve stream around the launches)."""
+def fixed_sweep_leg(h, bt, bps, N, reps, warmup, label_workload, kind, storage, k, with_sync=True):
+    """Fixed work on one handle: N local solves per subdomain of the asynchronous
+    kernel (tolerance 0, so nothing stops early), `reps` times, and N synchronous
+    sweeps.  Kernel time = HIP events the library records on the solve stream around
+    each persistent launch; bandwidth = algorithmic bytes of the local solves done
+    (streaming model) / kernel time."""
+    import numpy as np
+
+    for _ in range(warmup):
+        h.solve(bt, tol=0.0, mode="async", max_sweeps=max(1, N // 10))
+    t0 = time.perf_counter()
+    ar = []
+    for _ in range(reps):
+        _, info = h.solve(bt, tol=0.0, mode="async", max_sweeps=N)
+        ar.append((info[0], h.local_solve_counts()))
+    wall = time.perf_counter() - t0
+    a_bytes = [float(np.dot(c, bps)) for _, c in ar]
+    a_ks = [i["kernel_seconds"] for i, _ in ar]
+    a_gbps = float(np.mean([bb / ks for bb, ks in zip(a_bytes, a_ks)])) / 1e9
+    leg = {"workload": label_workload, "local": f"{kind}{k if kind == 'cg' else ''}-{storage}", "sweeps": N,
+           "wall_s": wall,
+           "async": {"GBps": a_gbps, "kernel_seconds": float(np.mean(a_ks)),
+                     "local_solves_total": int(ar[-1][0]["total_local_solves"]),
+                     "ms_per_sweep_equivalent": 1e3 * float(np.mean(a_ks)) * len(bps)
+                     / max(1, int(ar[-1][0]["total_local_solves"]))},
+           "algorithmic_bytes_per_launch": float(np.mean(a_bytes))}
+    if with_sync:
+        _, info = h.solve(bt, tol=0.0, mode="sync", max_sweeps=N)
+        i = info[0]
+        # the synchronous kernel computes one speculative update after the last sweep
+        sb = float((i["sweeps"] + 1) * bps.sum())
+        leg["sync"] = {"GBps": sb / i["kernel_seconds"] / 1e9, "kernel_seconds": i["kernel_seconds"],
+                       "ms_per_sweep": 1e3 * i["kernel_seconds"] / (i["sweeps"] + 1)}
+    traffic, src = traffic_from_profiles(f"{label_workload}_sweeps{N}", leg["algorithmic_bytes_per_launch"])
+    leg["roofline"] = {"bound": "hbm", "achieved": round(a_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                       "frac": round(a_gbps / HBM_PEAK_GBPS, 4), "traffic": traffic, "traffic_source": src,
+                       "kernel": f"persistent async {kind}{'-' + str(k) if kind == 'cg' else ''} {storage}",
+                       "workload": f"{label_workload}, {N} local solves per subdomain",
+                       "algorithmic_bytes_per_launch": leg["algorithmic_bytes_per_launch"],
+                       "kernel_seconds_per_launch": float(np.mean(a_ks))}
+    return leg
+
+
+def slab_legs(storages, N=200, reps=3):
+    """The 2048^2 log-normal diffusion workload (16 x 16 boxes, overlap 4, banded
+    Cholesky): factors of 1.3-5.1 GB per triangular pass, far beyond the 256 MB
+    Infinity Cache, so the sweep streams from HBM -- the honest roofline test."""
     import numpy as np
     import torch
 
+    import paper_2003_05361_amd as ras
+    import ras_inputs as R
+    from paper_2003_05361_amd.perfmodel import bytes_per_local_solve
+
+    A, b, cfg = R.config_problem("diffusion2d_2048_16x16")
+    shapes = subdomain_shapes(A, "regular_2d", (16, 16), 4, "chol")
+    bt = torch.tensor(b, dtype=torch.float64, device="cuda")
+    legs = []
+    for st in storages:
+        t0 = time.perf_counter()
+        h = ras.setup(A, ras.partition("regular_2d", (16, 16), grid=A.grid), 4, ras.local("chol", st))
+        setup_s = time.perf_counter() - t0
+        bps = np.array(bytes_per_local_solve(shapes, "chol", st, 0), dtype=np.float64)
+        leg = fixed_sweep_leg(h, bt, bps, N, reps, 1, f"diffusion2d_2048_16x16_{st}", "chol", st, 0)
+        leg["setup_s"] = setup_s
+        h.close()
+        torch.cuda.empty_cache()
+        print(f"slab leg {st}: {leg['async']['GBps']:.0f} GB/s async, {leg['sync']['GBps']:.0f} GB/s sync",
+              file=sys.stderr, flush=True)
+        legs.append(leg)
+    return legs
+
+
+def sweep_bench(args, A, b, h, bt, bps, st, kind, storage, k, gamma, part_kind, part_arg, setup_s):
+    """--sweeps N: fixed-work throughput of the named workload; value = sweep GB/s."""
+    leg = fixed_sweep_leg(h, bt, bps, args.sweeps, args.steps, args.warmup, args.workload, kind, storage, k,
+                          with_sync=not args.no_sync)
     N = args.sweeps
-
-    def run(mode, n):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        x, info = h.solve(bt, tol=0.0, mode=mode, max_sweeps=n)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        return info[0], e0.elapsed_time(e1) * 1e-3, h.local_solve_counts()
-
-    for _ in range(args.warmup):
-        run("async", max(1, N // 10))
-        run("sync", max(1, N // 10))
-    t0 = time.perf_counter()
-    ar = [run("async", N) for _ in range(args.steps)]
-    wall = time.perf_counter() - t0
-    sr = [run("sync", N) for _ in range(args.steps)]
-    a_bytes = [float(np.dot(c, bps)) for _, _, c in ar]
-    a_gbps = float(np.mean([bb / i["kernel_seconds"] for bb, (i, _, _) in zip(a_bytes, ar)])) / 1e9
-    # the synchronous kernel computes one speculative update after the last sweep
-    s_bytes = [float((i["sweeps"] + 1) * bps.sum()) for i, _, _ in sr]
-    s_gbps = float(np.mean([bb / i["kernel_seconds"] for bb, (i, _, _) in zip(s_bytes, sr)])) / 1e9
-    workload = args.workload
-    traffic = traffic_from_profiles(f"{workload}_sweeps{N}", float(np.mean(a_bytes)))
     line = {
         "metric": METRIC,
-        "value": a_gbps,
+        "value": leg["async"]["GBps"],
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / max(1, args.steps),
+        "ms_per_step": 1e3 * leg["wall_s"] / max(1, args.steps),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if storage == "fp64" else f"f64 outer / {storage} local",
         "data": "synthetic",
-        "config": {"workload": workload, "n": int(A.n), "subdomains": int(st["parts"]), "overlap": gamma,
-                   "local": f"{kind}{k if kind == 'cg' else ''}-{storage}", "mode": "fixed sweeps",
-                   "sweeps": N},
-        "async": {"GBps": a_gbps, "kernel_seconds": float(np.mean([i["kernel_seconds"] for i, _, _ in ar])),
-                  "local_solves_total": int(ar[-1][0]["total_local_solves"]),
-                  "ms_per_sweep_equivalent": 1e3 * float(np.mean([i["kernel_seconds"] for i, _, _ in ar])) * int(st["parts"])
-                  / max(1, int(ar[-1][0]["total_local_solves"]))},
-        "sync": {"GBps": s_gbps, "kernel_seconds": float(np.mean([i["kernel_seconds"] for i, _, _ in sr])),
-                 "ms_per_sweep": 1e3 * float(np.mean([i["kernel_seconds"] / (i["sweeps"] + 1) for i, _, _ in sr]))},
+        "config": {"workload": args.workload, "n": int(A.n), "subdomains": int(st["parts"]), "overlap": gamma,
+                   "local": leg["local"], "mode": "fixed sweeps", "sweeps": N},
+        "async": leg["async"],
+        "sync": leg.get("sync"),
         "setup_s": setup_s,
-        "roofline": {"bound": "hbm", "achieved": round(a_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(a_gbps / HBM_PEAK_GBPS, 4),
-                     "traffic": None if traffic is None else float(traffic),
-                     "kernel": f"persistent async {kind}{'-' + str(k) if kind == 'cg' else ''} {storage}",
-                     "algorithmic_bytes_per_launch": float(np.mean(a_bytes)),
-                     "kernel_seconds_per_launch": float(np.mean([i["kernel_seconds"] for i, _, _ in ar]))},
+        "roofline": leg["roofline"],
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
@@ -381,7 +453,8 @@ def main():
         return x, info[0], e0.elapsed_time(e1) * 1e-3, counts
 
     if args.sweeps > 0:
-        sweep_bench(args, A, b, h, bt, bps, st, stream, kind, storage, k, tol, gamma, part_kind, part_arg, setup_s)
+        sweep_bench(args, A, b, h, bt, bps, st, kind, storage, k, gamma, part_kind, part_arg, setup_s)
+        h.close()
         return
 
     for _ in range(args.warmup):
@@ -427,18 +500,31 @@ def main():
     relres = float(np.linalg.norm(b - A.matvec(xa)) / np.linalg.norm(b))
     achieved = float(np.mean([bb / ks for bb, ks in zip(a_bytes, a_kernel)])) / 1e9
     algo_per_launch = float(np.mean(a_bytes))
-    traffic = traffic_from_profiles(args.workload, algo_per_launch)
-    roof = {
+    traffic, traffic_src = traffic_from_profiles(args.workload, algo_per_launch)
+    ks_mean = float(np.mean(a_kernel))
+    own_roof = {
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBPS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBPS, 4),
-        "traffic": None if traffic is None else float(traffic),
+        "traffic": traffic,
+        "traffic_source": traffic_src,
+        "counter_GBps": None if traffic is None else round(traffic / ks_mean / 1e9, 1),
         "kernel": f"persistent async {kind}{'-' + str(k) if kind == 'cg' else ''} {storage}",
+        "workload": f"{args.workload}, solve to tolerance",
         "algorithmic_bytes_per_launch": algo_per_launch,
-        "kernel_seconds_per_launch": float(np.mean(a_kernel)),
+        "kernel_seconds_per_launch": ks_mean,
     }
+    if args.workload in MALL_RESIDENT:
+        own_roof["note"] = ("working set resident in the 256 MB Infinity Cache: the streaming-model rate is not an "
+                            "HBM rate and may exceed the HBM peak; counter_GBps is the measured fabric rate")
+    legs = []
+    if args.workload == "poisson2d_1024_8x8" and not args.no_slab_legs:
+        legs = slab_legs(("fp64", "fp16"))
+    # the roofline row: the streamed (beyond-cache) sweep of the 2048^2 diffusion
+    # workload when it ran, else this workload's own kernel
+    roof = dict(legs[0]["roofline"]) if legs else own_roof
     line = {
         "metric": METRIC,
         "value": float(np.mean(a_times)),
@@ -464,12 +550,15 @@ def main():
         "async_speedup_vs_sync": None if sync_res is None else sync_res["seconds"] / float(np.mean(a_times)),
         "setup_s": setup_s,
         "roofline": roof,
+        "rooflines": [own_roof] + [leg["roofline"] for leg in legs],
+        "sweep_legs": legs,
     }
     if not args.no_cpu_baseline and sync_res is not None:
         line["cpu_baseline"] = cpu_baseline(A, b, part_kind, part_arg, gamma, kind, storage, k, sync_res["sweeps"])
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)
+    h.close()
 
 
 if __name__ == "__main__":

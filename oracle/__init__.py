@@ -11,6 +11,8 @@ Modules
   partition  -- owned sets: regular-1d/2d/3d (Sec. 3.2.1) and seeded recursive
                 coordinate bisection standing in for the edge-cut partitioner.
   overlap    -- overlapping index sets by breadth-first layers (Sec. 2.1, Fig. 1).
+  residual   -- the outer residual b - A x in compensated float64 (Dot2 of
+                Ogita, Rump and Oishi): the convergence measure of Sec. 3.3.2.
   local      -- local subdomain matrices and solvers: banded Cholesky factor
                 once, triangular solves per iteration (Sec. 3.3.1); fixed-k CG;
                 reduced-precision variants.
@@ -26,4 +28,4 @@ except the asynchronous trajectory, which is nondeterministic by design
 (Sec. 2.1): its *final result* is pinned (verified residual and error against
 the direct solve) but the trajectory itself is "parity unpinned".
 """
-from . import partition, overlap, local, schwarz  # noqa: F401
+from . import partition, overlap, residual, local, schwarz  # noqa: F401

@@ -367,7 +367,7 @@ class Handle:
         infos = (SolveInfo * nrhs)()
         self._order_after_current_stream()
         st = lib().ras_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), nrhs,
-                             C.byref(_opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team, pace)), infos)
+                C.byref(_opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team, pace)), infos)
         _check(st, (RAS_OK, RAS_NOT_CONVERGED) if allow_unconverged else (RAS_OK,))
         self.last_nrhs = nrhs
         return x, [i.as_dict() for i in infos]

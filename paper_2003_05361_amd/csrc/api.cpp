@@ -125,8 +125,15 @@ struct ras_handle {
     // last solve
     std::vector<std::vector<double>> hist, hist_t;
     std::vector<std::vector<int64_t>> counts;
-    // reusable per-solve workspace
-    DevBuf ws_x1, ws_scratch, ws_hist, ws_red;
+    DevBuf ws_red;  // reduction slots of ras_relative_residual
+    // timing events of the solves on this handle, created once at setup
+    struct Events {
+        hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+        ~Events() {
+            for (hipEvent_t& v : e)
+                if (v) (void)hipEventDestroy(v);
+        }
+    } ev;
 };
 
 namespace {
@@ -613,8 +620,18 @@ struct InstSpec {
     double tol = -1.0;  // per-system tolerance (< 0: the solve options' tol)
 };
 
+// Where a solve's workspace lives: a fresh allocation (default), a buffer that
+// is reused and grown across solves (serving), or a fixed caller-visible area
+// that must not be exceeded (no allocation at all).
+struct Workspace {
+    DevBuf* reuse = nullptr;
+    void* fixed = nullptr;
+    size_t fixed_bytes = 0;
+};
+
 // One persistent solve over a set of right-hand sides of one or more systems.
-ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_solve_info* info) {
+ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_solve_info* info,
+                     const Workspace& where = Workspace{}) {
     ras_handle& h0 = *specs[0].h;
     hipStream_t stream = h0.stream;
     hip_check(hipSetDevice(h0.device), "hipSetDevice");
@@ -856,8 +873,20 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     const int nparts = 512;
     const size_t o_red = carve((2 * nparts + 2) * sizeof(double));
     DevBuf ws;
-    ws.alloc(off);
-    char* base = ws.as<char>();
+    char* base = nullptr;
+    if (where.fixed) {
+        if (off > where.fixed_bytes)
+            throw Error{RAS_E_NOMEM, "solve workspace needs " + std::to_string(off) +
+                                         " bytes; the fixed no-allocation scratch holds " +
+                                         std::to_string(where.fixed_bytes)};
+        base = static_cast<char*>(where.fixed);
+    } else if (where.reuse) {
+        where.reuse->ensure(off);
+        base = where.reuse->as<char>();
+    } else {
+        ws.alloc(off);
+        base = ws.as<char>();
+    }
     for (int i = 0; i < ninst; ++i) {
         InstDev& in = insts[i];
         in.b = specs[i].b;
@@ -949,20 +978,7 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     P.max_ticks = o.max_seconds > 0 ? static_cast<int64_t>(o.max_seconds * h0.clock_khz * 1000.0) : 0;
     P.sweep0 = 0;
 
-    hipEvent_t ev0, ev1, ek0, ek1;
-    hip_check(hipEventCreate(&ev0), "event");
-    hip_check(hipEventCreate(&ev1), "event");
-    hip_check(hipEventCreate(&ek0), "event");
-    hip_check(hipEventCreate(&ek1), "event");
-    struct EvGuard {
-        hipEvent_t a, b, c, d;
-        ~EvGuard() {
-            (void)hipEventDestroy(a);
-            (void)hipEventDestroy(b);
-            (void)hipEventDestroy(c);
-            (void)hipEventDestroy(d);
-        }
-    } evg{ev0, ev1, ek0, ek1};
+    hipEvent_t ev0 = h0.ev.e[0], ev1 = h0.ev.e[1], ek0 = h0.ev.e[2], ek1 = h0.ev.e[3];
     double kernel_s = 0.0;
     hip_check(launch_stamp(P.ist, ninst, stream), "stamp");
     hip_check(hipEventRecord(ev0, stream), "event record");
@@ -1121,6 +1137,8 @@ void init_device(ras_handle& h, void* stream) {
     hip_check(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h.device), "wall clock rate");
     h.clock_khz = khz > 0 ? khz : 100000;
     hip_check(hipDeviceGetAttribute(&h.num_cu, hipDeviceAttributeMultiprocessorCount, h.device), "CU count");
+    for (hipEvent_t& e : h.ev.e)
+        if (!e) hip_check(hipEventCreate(&e), "event");
 }
 
 

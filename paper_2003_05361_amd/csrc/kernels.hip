@@ -306,6 +306,33 @@ __device__ __forceinline__ float load_as<float>(const void* base, int64_t idx) {
 }
 
 // ------------------------------------------------------------------------------ residual
+// The outer residual is accumulated with compensated (double-word) arithmetic,
+// the Dot2 scheme of Ogita, Rump and Oishi (SIAM J. Sci. Comput. 26, 2005):
+// each product a x is split exactly into p + pe with one FMA (TwoProduct),
+// each running subtraction s - p exactly into t + te (Knuth's TwoSum), and the
+// rounding errors te - pe are summed apart and added once at the end.  The
+// result is as accurate as if it were computed in twice float64's precision
+// and then rounded: near convergence r = b - A x cancels, and a plain float64
+// sum carries an absolute error of about eps |A| |x|, which on strongly varying
+// coefficients sits at the tolerance itself.  Contraction is off so that the
+// compiler cannot fuse p into the subtraction.
+struct CompAcc {
+    double s, c;
+};
+
+__device__ __forceinline__ void comp_sub(CompAcc& r, double a, double x) {
+#pragma clang fp contract(off)
+    const double p = a * x;
+    const double pe = __builtin_fma(a, x, -p);
+    const double t = r.s - p;
+    const double z = t - r.s;
+    const double te = (r.s - (t - z)) - (p + z);
+    r.s = t;
+    r.c += te - pe;
+}
+
+__device__ __forceinline__ double comp_value(const CompAcc& r) { return r.s + r.c; }
+
 // r_i = b_g - sum_k A_{g, col_k} x_{col_k} for local row i (global g).  ELL
 // slot k of row i sits at k * n_pad + i.  KT > 0: compile-time row width.
 template <int KT, bool ATOMIC>
@@ -315,7 +342,7 @@ __device__ __forceinline__ double row_residual(const SubU& s, RAS_GLOBAL double*
     owned = e >= 0;
     const int32_t g = owned ? e : ~e;
     bg = b[g];
-    double acc = bg;
+    CompAcc acc{bg, 0.0};
     if constexpr (KT > 0) {
         int32_t c[KT];
         double a[KT];
@@ -325,14 +352,14 @@ __device__ __forceinline__ double row_residual(const SubU& s, RAS_GLOBAL double*
             a[k] = (s.ell_val + static_cast<uint32_t>(k * s.n_pad))[static_cast<uint32_t>(i)];
         }
 #pragma unroll
-        for (int k = 0; k < KT; ++k) acc -= a[k] * ldx<ATOMIC>(x + c[k]);
+        for (int k = 0; k < KT; ++k) comp_sub(acc, a[k], ldx<ATOMIC>(x + c[k]));
     } else {
         for (int k = 0; k < s.K; ++k) {
             const uint32_t idx = static_cast<uint32_t>(k * s.n_pad + i);
-            acc -= s.ell_val[idx] * ldx<ATOMIC>(x + s.ell_gcol[idx]);
+            comp_sub(acc, s.ell_val[idx], ldx<ATOMIC>(x + s.ell_gcol[idx]));
         }
     }
-    return acc;
+    return comp_value(acc);
 }
 
 // Asynchronous updates read x once.  A residual row reads a neighbour-owned
@@ -367,7 +394,7 @@ __device__ __forceinline__ double row_residual_snap(const SubU& s, RAS_GLOBAL do
     owned = e >= 0;
     const int32_t g = owned ? e : ~e;
     bg = b[g];
-    double acc = bg;
+    CompAcc acc{bg, 0.0};
     if constexpr (KT > 0) {
         int32_t c[KT];
         double a[KT];
@@ -377,14 +404,14 @@ __device__ __forceinline__ double row_residual_snap(const SubU& s, RAS_GLOBAL do
             a[k] = (s.ell_val + static_cast<uint32_t>(k * s.n_pad))[static_cast<uint32_t>(i)];
         }
 #pragma unroll
-        for (int k = 0; k < KT; ++k) acc -= a[k] * ldg_dev(xs + c[k]);
+        for (int k = 0; k < KT; ++k) comp_sub(acc, a[k], ldg_dev(xs + c[k]));
     } else {
         for (int k = 0; k < s.K; ++k) {
             const uint32_t idx = static_cast<uint32_t>(k * s.n_pad + i);
-            acc -= s.ell_val[idx] * ldg_dev(xs + s.ell_lcol[idx]);
+            comp_sub(acc, s.ell_val[idx], ldg_dev(xs + s.ell_lcol[idx]));
         }
     }
-    return acc;
+    return comp_value(acc);
 }
 
 // ------------------------------------------------------------------------------ CG update
@@ -1543,9 +1570,10 @@ __global__ void __launch_bounds__(kRedThreads)
     double sr = 0.0, sb = 0.0;
     for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedThreads) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * kRedThreads) {
-        double acc = b[i];
+        CompAcc ca{b[i], 0.0};
         if (x != nullptr)
-            for (int64_t e = rp[i]; e < rp[i + 1]; ++e) acc -= va[e] * x[ci[e]];
+            for (int64_t e = rp[i]; e < rp[i + 1]; ++e) comp_sub(ca, va[e], x[ci[e]]);
+        const double acc = comp_value(ca);
         sr += acc * acc;
         sb += b[i] * b[i];
     }

@@ -418,6 +418,73 @@ def test_sync_with_thread_pool_is_the_same_iteration():
         assert k1 == k2 == 6 and np.array_equal(x1, x2) and np.array_equal(h1, h2)
 
 
+# ----------------------------------------------------------------- outer residual (Sec. 3.3.2)
+def _exact_residual(M, x, b):
+    """b - M x in exact rational arithmetic, rounded once to float64."""
+    from fractions import Fraction
+
+    out = np.empty(M.shape[0])
+    for i in range(M.shape[0]):
+        acc = Fraction(float(b[i]))
+        for e in range(M.indptr[i], M.indptr[i + 1]):
+            acc -= Fraction(float(M.data[e])) * Fraction(float(x[M.indices[e]]))
+        out[i] = float(acc)
+    return out
+
+
+def test_error_free_transformations_are_exact():
+    from fractions import Fraction
+
+    from oracle import residual as ores
+
+    rng = np.random.default_rng(40)
+    a = rng.standard_normal(2000) * 10.0 ** rng.integers(-8, 9, 2000)
+    c = rng.standard_normal(2000) * 10.0 ** rng.integers(-8, 9, 2000)
+    p, e = ores.two_product(a, c)
+    s, t = ores.two_sum(a, c)
+    for i in range(2000):
+        assert Fraction(p[i]) + Fraction(e[i]) == Fraction(a[i]) * Fraction(c[i])
+        assert Fraction(s[i]) + Fraction(t[i]) == Fraction(a[i]) + Fraction(c[i])
+        assert p[i] == a[i] * c[i] and s[i] == a[i] + c[i]
+
+
+def test_compensated_residual_against_exact_arithmetic():
+    """Where b - A x cancels (b = fl(A x), log-normal coefficients, |x| ~ 1e4), the
+    compensated residual meets Dot2's bound |r^ - r| <= u |r| + gamma_n^2 (|b| + |A||x|)
+    against the exact rational residual, while a plain float64 evaluation is off by
+    about u (|A||x|), i.e. by the size of r itself."""
+    from oracle import residual as ores
+
+    g = R.gaussian_random_field_2d(24, 4.0, 41)
+    A = R.tpfa2d(np.exp(2.0 * g), 10.0)
+    M = A.scipy()
+    rng = np.random.default_rng(42)
+    x = rng.uniform(-1.0, 1.0, A.n) * 1e4
+    b = M @ x  # plain float64: the exact residual is the rounding error of this product
+    r_exact = _exact_residual(M, x, b)
+    r_comp = ores.residual(M, x, b)
+    u = 2.0 ** -53
+    n = int(np.diff(M.indptr).max()) + 1
+    gamma = n * u / (1 - n * u)
+    mag = np.abs(b) + np.abs(M) @ np.abs(x)
+    assert np.all(np.abs(r_comp - r_exact) <= u * np.abs(r_exact) + gamma ** 2 * mag)
+    # the case has teeth: plain float64 misses rows by far more than the bound
+    r_plain = b - M @ x
+    assert np.max(np.abs(r_plain - r_exact) / mag) > 1e3 * gamma ** 2
+    # a subset of rows gives the same values as the full evaluation
+    rows = np.arange(3, A.n, 7)
+    assert np.array_equal(ores.residual(M, x, b, rows), r_comp[rows])
+
+
+def test_relative_residual_of_an_exact_solution():
+    """An exactly representable solution: x integer, b = A x exactly (integer
+    coefficients): the compensated residual is exactly zero."""
+    A = R.laplace2d(20)
+    x = np.random.default_rng(43).integers(-1000, 1000, A.n).astype(np.float64)
+    b = A.scipy() @ x
+    assert schwarz.relative_residual(A, x, b) == 0.0
+
+
 # ----------------------------------------------------------------- P10: ordered / asynchronous
 def test_ordered_zero_overlap_is_block_gauss_seidel():
     A = R.laplace2d(12)
