@@ -227,6 +227,27 @@ ras_status ras_handle_get_stats(const ras_handle* h, ras_plan_stats* out);
 ras_status ras_solve(ras_handle* h, const double* b_dev, double* x_dev, int32_t nrhs, const ras_solve_opts* opts,
                      ras_solve_info* info);
 
+/* For callers that cannot allocate device memory during a solve (code that
+ * runs under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same solve as ras_solve -- same arguments, kernels, results
+ * and status codes -- whose workspace (work tables, per-subdomain state, the
+ * synchronous second iterate, asynchronous snapshots, local vectors, residual
+ * history) is carved from a fixed device array of RAS_NOALLOC_SCRATCH_BYTES
+ * bytes that the library holds on every device it runs on, until the process
+ * ends.  The call allocates and frees no device memory.  A solve whose
+ * workspace does not fit returns RAS_E_NOMEM, naming the bytes needed and
+ * available, before any device work.  The workspace is about 8 bytes per
+ * local row per right-hand side, plus 8 bytes per unknown (SYNC's second
+ * iterate) or per snapshot slot (ASYNC), plus 16 bytes per history entry
+ * (min(max_sweeps + 1, 2^20) entries SYNC, min(max_sweeps + 1, 2^16) ASYNC).
+ * Every call on one device uses that device's one array, which keeps the last
+ * call's contents (everything a solve reads is written or cleared by the
+ * solve first): calls that overlap in time on one device -- from several host
+ * threads or on several streams -- race and must be serialised by the caller.  */
+enum { RAS_NOALLOC_SCRATCH_BYTES = 32 * 1024 * 1024 };
+ras_status ras_solve_noalloc(ras_handle* h, const double* b_dev, double* x_dev, int32_t nrhs,
+                             const ras_solve_opts* opts, ras_solve_info* info);
+
 /* Several systems (handles) in one persistent launch; handles must share the
  * local solver kind and storage.  b[i], x[i] are device arrays of handle i
  * with nrhs[i] right-hand sides; info has sum(nrhs) entries, in order.  */

@@ -34,6 +34,8 @@ LOCAL_KINDS = {"chol": 0, "cg": 1, "chol_sparse": 2}
 STORAGES = {"fp64": 0, "fp32": 1, "fp16": 2}
 MODES = {"sync": 0, "async": 1, "ordered": 2}
 DETECT = {"central": 0, "decentral": 1}
+# size of the library's fixed device workspace of ras_solve_noalloc (per device)
+NOALLOC_SCRATCH_BYTES = 32 * 1024 * 1024
 # asynchronous mode: neighbour wait budget before a read, in units of the previous update's time
 # (0 = free running, negative = the library's choice per local solver)
 DEFAULT_PACE = -1.0
@@ -96,6 +98,7 @@ SIGNATURES = {
     "ras_setup_from_plan": (C.c_int, [_P, _P, C.POINTER(_P)]),
     "ras_handle_get_stats": (C.c_int, [_P, C.POINTER(PlanStats)]),
     "ras_solve": (C.c_int, [_P, _P, _P, C.c_int32, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
+    "ras_solve_noalloc": (C.c_int, [_P, _P, _P, C.c_int32, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
     "ras_batch_solve": (C.c_int, [C.c_int32, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.POINTER(C.c_int32),
                                   C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
     "ras_residual_history": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int64, C.POINTER(C.c_int64)]),
@@ -351,12 +354,14 @@ class Handle:
 
     def solve(self, b, x0=None, tol: float = 1e-8, mode: str = "async", max_sweeps: int = 1_000_000,
               max_seconds: float = 0.0, detect: str = "central", workgroups: int = 0, team: int = 0,
-              allow_unconverged=True, pace=None):
+              allow_unconverged=True, pace=None, noalloc: bool = False):
         """Solve A x = b on the device.  b: float64 CUDA tensor [n] or [nrhs, n].
         mode: "sync", "async" or "ordered"; detect: "central" or "decentral";
         pace (async): neighbour wait budget before a read, in units of the
         previous update's time (None: the library's choice per local solver).
-        Returns (x, infos) with x the same shape as b."""
+        noalloc: run through ras_solve_noalloc (workspace in the library's fixed
+        device scratch of NOALLOC_SCRATCH_BYTES; x is still allocated here unless
+        x0 is given).  Returns (x, infos) with x the same shape as b."""
         import torch
 
         if b.device.type != "cuda" or b.dtype != torch.float64:
@@ -366,7 +371,8 @@ class Handle:
         x = torch.zeros_like(b) if x0 is None else x0.to(torch.float64).contiguous().clone()
         infos = (SolveInfo * nrhs)()
         self._order_after_current_stream()
-        st = lib().ras_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), nrhs,
+        fn = lib().ras_solve_noalloc if noalloc else lib().ras_solve
+        st = fn(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), nrhs,
                 C.byref(_opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team, pace)), infos)
         _check(st, (RAS_OK, RAS_NOT_CONVERGED) if allow_unconverged else (RAS_OK,))
         self.last_nrhs = nrhs

@@ -33,6 +33,7 @@ hipError_t launch_residual(int64_t n, const int64_t* rp, const int32_t* ci, cons
                            const double* x, double* parts, int nparts, double* out, hipStream_t st);
 hipError_t launch_copy(int64_t n, const double* src, double* dst, hipStream_t st);
 hipError_t launch_stamp(InstState* ist, int n, hipStream_t st);
+hipError_t noalloc_scratch(void** ptr);
 }  // namespace ras
 
 using namespace ras;
@@ -1610,6 +1611,25 @@ ras_status ras_solve(ras_handle* h, const double* b_dev, double* x_dev, int32_t 
         h->hist_t.clear();
         h->counts.clear();
         return run_solve(specs, *opts, info);
+    });
+}
+
+ras_status ras_solve_noalloc(ras_handle* h, const double* b_dev, double* x_dev, int32_t nrhs,
+                             const ras_solve_opts* opts, ras_solve_info* info) {
+    return guarded([&] {
+        if (!h || !b_dev || !x_dev || !opts || !info || nrhs < 1) throw Error{RAS_E_ARG, "invalid argument"};
+        hip_check(hipSetDevice(h->device), "hipSetDevice");
+        Workspace where;
+        hip_check(noalloc_scratch(&where.fixed), "address of the no-allocation scratch");
+        where.fixed_bytes = kNoAllocScratchBytes;
+        std::vector<InstSpec> specs;
+        for (int r = 0; r < nrhs; ++r)
+            specs.push_back(InstSpec{h, b_dev + static_cast<int64_t>(r) * h->plan->n,
+                                     x_dev + static_cast<int64_t>(r) * h->plan->n, r});
+        h->hist.clear();
+        h->hist_t.clear();
+        h->counts.clear();
+        return run_solve(specs, *opts, info, where);
     });
 }
 

@@ -9,6 +9,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "../../include/ras.h"
+
 namespace ras {
 
 constexpr int kCgThreads = 256;     // workgroup size of the CG kernels
@@ -28,6 +30,8 @@ constexpr int kSlabFarWaves = 4;    // waves of the off-diagonal sums
 constexpr int kSlabParts = 2 * kSlabFarWaves;  // far partial sums per row (one per half-wave)
 constexpr int kSlabLead[3] = {2, 3, 4};  // blocks in flight: FP64, FP32, FP16 storage
 constexpr int kSlabWinTail = 16;    // mirrored slots after the solution window
+// fixed device workspace of ras_solve_noalloc (per device, held until process exit)
+constexpr size_t kNoAllocScratchBytes = RAS_NOALLOC_SCRATCH_BYTES;
 // row stride (compute-type entries) of the near + triangle buffer: 2 blocks
 // of columns plus padding that keeps 16-byte rows aligned and spreads the
 // rows of a wavefront over the LDS banks

@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <type_traits>
 
 #include "device.hpp"
@@ -1713,6 +1714,33 @@ hipError_t launch_copy(int64_t n, const double* src, double* dst, hipStream_t st
 hipError_t launch_stamp(InstState* ist, int n, hipStream_t st) {
     stamp_start<<<1, 256, 0, st>>>(ist, n);
     return hipGetLastError();
+}
+
+// ---- fixed workspace of the solve that allocates nothing ---------------------------
+// Every device that loads this code object holds one copy of the array until
+// the process ends.  Host code never uses the array's name as an address: the
+// device address of each device's copy comes from hipGetSymbolAddress, taken
+// once per device with that device current, and only that address is handed
+// to kernels and copies.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(void** ptr) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (addr[dev] == nullptr) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 }  // namespace ras
