@@ -239,13 +239,21 @@ def serving_bench(args):
             if delay > 0:
                 time.sleep(delay)
             tickets.append(srv.submit(A, part, 2, loc, B, 1e-8))
+            if len(tickets) % 200 == 0:
+                print(f"serving: {len(tickets)} submitted, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                      flush=True)
         lat, rhs, bad = [], 0, 0
-        for (A, part, loc, B), tk in zip(subset, tickets):
+        for k, ((A, part, loc, B), tk) in enumerate(zip(subset, tickets)):
             srv.wait(tk, 600.0)
             done, x, infos, l = srv.poll(tk, A.n, B.shape[0])
             lat.append(l)
             rhs += B.shape[0]
             bad += sum(1 for i in infos if not i["converged"])
+            if (k + 1) % 100 == 0:
+                q = srv.stats()
+                print(f"serving: {k + 1} of {len(subset)} retired, {time.perf_counter() - t0:.1f} s, "
+                      f"active {q['active']}, queued {q['queued']}, in use {q['in_use_bytes'] / 2**30:.2f} GiB",
+                      file=sys.stderr, flush=True)
         wall = time.perf_counter() - t0
         stop.set()
         sampler.join()

@@ -95,11 +95,24 @@ typedef struct ras_partition {
  * residual, update and convergence test are always float64.  */
 enum { RAS_LOCAL_CHOL_BANDED = 0, RAS_LOCAL_CG = 1, RAS_LOCAL_CHOL_SPARSE = 2 };
 enum { RAS_STORAGE_FP64 = 0, RAS_STORAGE_FP32 = 1, RAS_STORAGE_FP16_ROWSCALED = 2 };
+/* Transmission condition on the artificial boundary of a subdomain.
+ *   DIRICHLET: the local matrix is A[Omega_p, Omega_p] (restricted additive
+ *     Schwarz, Sec. 2.1).
+ *   ROBIN: optimized restricted additive Schwarz (ORAS, the paper's future
+ *     work, Sec. 5) with a Robin condition in algebraic form: the local matrix
+ *     is A[Omega_p, Omega_p] - (1 - robin_q) diag(e), where e_i is the sum of
+ *     |a_ij| over the columns j of row i outside Omega_p (the row's coupling
+ *     across the artificial boundary); robin_q in (0, 1], 1 = DIRICHLET.  The
+ *     global iteration is unchanged (the correction form keeps the solution of
+ *     A x = b the fixed point); only the local matrices, and so their factors,
+ *     change.  Direct local solvers only (CHOL_BANDED, CHOL_SPARSE).  */
+enum { RAS_TRANSMISSION_DIRICHLET = 0, RAS_TRANSMISSION_ROBIN = 1 };
 typedef struct ras_local {
     int32_t kind;
     int32_t cg_iters;
     int32_t storage;
-    int32_t reserved;
+    int32_t transmission;
+    double robin_q;
 } ras_local;
 
 /* Solve options.
@@ -265,6 +278,15 @@ ras_status ras_residual_history(const ras_handle* h, int32_t rhs, double* t_sec,
  * "subdomain update" counts); counts[P].  */
 ras_status ras_local_solve_counts(const ras_handle* h, int32_t rhs, int64_t* counts);
 ras_status ras_partition_sets(const ras_handle* h, int32_t* owner, int64_t* omega_ptr, int32_t* omega_idx);
+/* Where the last solve's time went, per subdomain (the per-function runtime
+ * breakdown of Sec. 4.2-4.6), measured with the device wall clock by the
+ * workgroup owning the subdomain: seconds[4*p + k] for k = 0 restriction and
+ * residual (the asynchronous read snapshot included), 1 local solve, 2
+ * restricted prolongation and publication of the owned values, 3 everything
+ * else (SYNC: waiting at the sweep barrier and the convergence check, charged
+ * to the first subdomain of each workgroup; ASYNC: paced waits before reads and
+ * detection work).  seconds has 4 P entries.  */
+ras_status ras_phase_seconds(const ras_handle* h, int32_t rhs, double* seconds);
 /* Autotuner: times `sweeps` synchronous sweeps from x = 0 for every feasible CG
  * team size (workgroups per subdomain), twice each (the faster timing counts:
  * a kernel variant's first launch carries one-time costs), and keeps the fastest in the handle (used
@@ -274,6 +296,15 @@ ras_status ras_partition_sets(const ras_handle* h, int32_t* owner, int64_t* omeg
  * banded solver has one configuration: it returns team 1.  */
 ras_status ras_autotune(ras_handle* h, const double* b_dev, double* x_dev, int32_t sweeps, int32_t* best_team,
                         double* best_ms_per_sweep);
+/* The banded Cholesky factor of subdomain p as the solves use it, read back
+ * from the device (Sec. 3.3.1: computed once at setup -- by ras_setup on the
+ * device, in float64, then stored in the handle's storage type):
+ * band[i*(w+1) + (j - i + w)] = L_ij as float64 (FP32 entries widened, FP16
+ * entries times their row scale; the diagonal is the reciprocal of the stored
+ * 1 / L_ii); *w receives the half-bandwidth.  band may be NULL to query w.
+ * RAS_E_STATE unless the local solver is CHOL_BANDED; RAS_E_ARG for p out of
+ * range.  */
+ras_status ras_handle_factor(const ras_handle* h, int32_t p, double* band, int32_t* w);
 /* Exact ||b - A x|| / ||b|| of device vectors (the post-termination check of
  * Sec. 3.3.2), computed by the library's verification kernel.  */
 ras_status ras_relative_residual(ras_handle* h, const double* b_dev, const double* x_dev, double* relres);
@@ -316,8 +347,10 @@ ras_status ras_server_poll(ras_server* srv, uint64_t ticket, double* x_host, ras
 /* Blocks until the ticket has retired (RAS_OK) or timeout_seconds elapse (RAS_PENDING).  */
 ras_status ras_server_wait(ras_server* srv, uint64_t ticket, double timeout_seconds);
 ras_status ras_server_get_stats(ras_server* srv, ras_server_stats* out);
-/* Stops the server: pending systems are dropped, threads joined, memory freed.  */
-void ras_server_destroy(ras_server* srv);
+/* Stops the server: pending systems are dropped, threads joined, memory freed.
+ * NULL-safe; returns RAS_OK, or RAS_E_HIP if releasing the server's own stream
+ * failed (the server is gone either way).  */
+ras_status ras_server_destroy(ras_server* srv);
 
 /* ---- the stop rule after a persistent asynchronous launch (host only) ----------
  * Sec. 3.3.2: the detector inside the kernel decides from local criteria and

@@ -32,6 +32,30 @@ def local_matrix(A, omega: np.ndarray) -> sp.csr_matrix:
     return M
 
 
+def outside_coupling(A, omega: np.ndarray) -> np.ndarray:
+    """e_i = sum of |a_ij| over the columns j of row omega[i] that lie outside omega."""
+    M = A.scipy()
+    inside = np.zeros(A.n, dtype=bool)
+    inside[omega] = True
+    rows = abs(M[omega]).tocsr()
+    e = np.zeros(omega.size)
+    for i in range(omega.size):
+        cols = rows.indices[rows.indptr[i]:rows.indptr[i + 1]]
+        vals = rows.data[rows.indptr[i]:rows.indptr[i + 1]]
+        e[i] = vals[~inside[cols]].sum()
+    return e
+
+
+def robin_local_matrix(A, omega: np.ndarray, q: float) -> sp.csr_matrix:
+    """Optimized Schwarz (Sec. 5 names it as future work) with a Robin condition on the
+    artificial boundary, in algebraic form.  Reading: A[omega, omega] with the
+    diagonal lowered by (1 - q) e_i, e_i the row's coupling to points outside omega
+    (q = 1: the Dirichlet local matrix of RAS; smaller q moves the condition from
+    Dirichlet towards Neumann)."""
+    Ap = local_matrix(A, omega)
+    return (Ap - sp.diags((1.0 - q) * outside_coupling(A, omega))).tocsr()
+
+
 def lower_bandwidth(Ap: sp.csr_matrix) -> int:
     """w = max over stored entries (i, j) of i - j."""
     rows = np.repeat(np.arange(Ap.shape[0]), np.diff(Ap.indptr))

@@ -35,7 +35,7 @@ import numpy as np
 import scipy.sparse.linalg as spla
 
 from . import residual as ores
-from .local import LocalSolver, local_matrix
+from .local import LocalSolver, local_matrix, robin_local_matrix
 from .overlap import subdomain_sets
 
 
@@ -52,14 +52,16 @@ class RAS:
     """Setup of the Schwarz solver: subdomains, local matrices, local solvers."""
 
     def __init__(self, A, owner: np.ndarray, gamma: int, local: str = "chol", storage: str = "fp64",
-                 cg_iters: int = 0):
+                 cg_iters: int = 0, robin_q: float | None = None):
+        """robin_q: optimized RAS with Robin transmission (oracle.local.robin_local_matrix);
+        None: RAS with the Dirichlet local matrices."""
         self.A = A
         self.M = A.scipy()
         self.owner = np.asarray(owner, dtype=np.int32)
         self.gamma = gamma
         self.subs = []
         for own, om, ext in subdomain_sets(A, self.owner, gamma):
-            Ap = local_matrix(A, om)
+            Ap = local_matrix(A, om) if robin_q is None else robin_local_matrix(A, om, robin_q)
             self.subs.append(Subdomain(own, om, ext, np.searchsorted(om, own), LocalSolver(Ap, local, storage, cg_iters)))
 
     @property

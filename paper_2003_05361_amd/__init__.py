@@ -52,7 +52,8 @@ class PartitionStruct(C.Structure):
 
 
 class LocalStruct(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("cg_iters", C.c_int32), ("storage", C.c_int32), ("reserved", C.c_int32)]
+    _fields_ = [("kind", C.c_int32), ("cg_iters", C.c_int32), ("storage", C.c_int32), ("transmission", C.c_int32),
+                ("robin_q", C.c_double)]
 
 
 class SolveOpts(C.Structure):
@@ -105,6 +106,8 @@ SIGNATURES = {
     "ras_local_solve_counts": (C.c_int, [_P, C.c_int32, _P]),
     "ras_partition_sets": (C.c_int, [_P, _P, _P, _P]),
     "ras_relative_residual": (C.c_int, [_P, _P, _P, C.POINTER(C.c_double)]),
+    "ras_handle_factor": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int32)]),
+    "ras_phase_seconds": (C.c_int, [_P, C.c_int32, _P]),
     "ras_autotune": (C.c_int, [_P, _P, _P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "ras_destroy": (None, [_P]),
     "ras_server_create": (C.c_int, [C.c_int64, C.c_double, _P, C.POINTER(_P)]),
@@ -113,7 +116,7 @@ SIGNATURES = {
     "ras_server_poll": (C.c_int, [_P, C.c_uint64, _P, _P, C.POINTER(C.c_double)]),
     "ras_server_wait": (C.c_int, [_P, C.c_uint64, C.c_double]),
     "ras_server_get_stats": (C.c_int, [_P, _P]),
-    "ras_server_destroy": (None, [_P]),
+    "ras_server_destroy": (C.c_int, [_P]),
     "ras_async_next_step": (C.c_int32, [C.c_int32, C.c_double, C.c_double, C.c_int64, C.c_int64, C.c_double,
                                         C.c_double, C.c_int32]),
     "ras_final_status": (C.c_int, [C.c_int32]),
@@ -164,12 +167,14 @@ def partition(kind: str, parts, grid=(1, 1, 1), seed: int = 0, jitter: float = 0
     return dict(kind=kind, parts=parts, grid=tuple(grid), seed=int(seed), jitter=float(jitter), owner=owner)
 
 
-def local(kind: str = "chol", storage: str = "fp64", cg_iters: int = 0) -> dict:
+def local(kind: str = "chol", storage: str = "fp64", cg_iters: int = 0, robin_q=None) -> dict:
     """Local solver (Sec. 3.3.1): banded Cholesky ("chol"), nested-dissection sparse Cholesky
-    ("chol_sparse") or fixed-k CG ("cg"); storage fp64/fp32/fp16."""
+    ("chol_sparse") or fixed-k CG ("cg"); storage fp64/fp32/fp16.  robin_q in (0, 1]:
+    Robin transmission (optimized RAS): the local matrices' diagonals are lowered by
+    (1 - robin_q) times each row's coupling to points outside the subdomain; None: RAS."""
     if kind not in LOCAL_KINDS or storage not in STORAGES:
         raise ValueError((kind, storage))
-    return dict(kind=kind, storage=storage, cg_iters=int(cg_iters))
+    return dict(kind=kind, storage=storage, cg_iters=int(cg_iters), robin_q=robin_q)
 
 
 class _Keep:
@@ -214,7 +219,9 @@ def _part(p: dict, A, keep: _Keep) -> PartitionStruct:
 
 
 def _local(l: dict) -> LocalStruct:
-    return LocalStruct(LOCAL_KINDS[l["kind"]], int(l.get("cg_iters", 0)), STORAGES[l.get("storage", "fp64")], 0)
+    q = l.get("robin_q")
+    return LocalStruct(LOCAL_KINDS[l["kind"]], int(l.get("cg_iters", 0)), STORAGES[l.get("storage", "fp64")],
+                       0 if q is None else 1, 1.0 if q is None else float(q))
 
 
 # ----------------------------------------------------------------------------- host-only plan
@@ -301,10 +308,10 @@ class Plan:
                 pass
             self._p = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter shutdown the HIP runtime (or a profiler's tool library)
         # may already be gone: leave the memory to the process exit then
-        if not sys.is_finalizing():
+        if not _finalizing():
             self.close()
 
 
@@ -391,6 +398,16 @@ class Handle:
         _check(lib().ras_local_solve_counts(self._h, rhs, c.ctypes.data))
         return c
 
+    PHASES = ("residual", "local_solve", "prolong", "other")
+
+    def phase_seconds(self, rhs: int = 0) -> np.ndarray:
+        """[P, 4] seconds of the last solve per subdomain in the phases PHASES
+        (device wall clock)."""
+        P = self.stats()["parts"]
+        out = np.empty((P, 4))
+        _check(lib().ras_phase_seconds(self._h, int(rhs), out.ctypes.data))
+        return out
+
     def partition_sets(self):
         st = self.stats()
         owner = np.empty(self.n, dtype=np.int32)
@@ -412,6 +429,17 @@ class Handle:
                                   C.byref(t), C.byref(ms)))
         return t.value, ms.value
 
+    def factor(self, p: int) -> tuple[np.ndarray, int]:
+        """Subdomain p's banded Cholesky factor as the solves use it (read back from
+        the device): (band [n, w+1] float64, w), band[i, j - i + w] = L_ij."""
+        w = C.c_int32()
+        _check(lib().ras_handle_factor(self._h, int(p), None, C.byref(w)))
+        owner, ptr, _ = self.partition_sets()
+        n = int(ptr[p + 1] - ptr[p])
+        band = np.empty((n, w.value + 1))
+        _check(lib().ras_handle_factor(self._h, int(p), band.ctypes.data, C.byref(w)))
+        return band, w.value
+
     def relative_residual(self, b, x) -> float:
         r = C.c_double()
         self._order_after_current_stream()
@@ -427,10 +455,10 @@ class Handle:
                 pass
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter shutdown the HIP runtime (or a profiler's tool library)
         # may already be gone: leave the memory to the process exit then
-        if not sys.is_finalizing():
+        if not _finalizing():
             self.close()
 
 
@@ -527,10 +555,10 @@ class Server:
                 pass
             self._s = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter shutdown the HIP runtime (or a profiler's tool library)
         # may already be gone: leave the memory to the process exit then
-        if not sys.is_finalizing():
+        if not _finalizing():
             self.close()
 
 

@@ -34,6 +34,7 @@ hipError_t launch_residual(int64_t n, const int64_t* rp, const int32_t* ci, cons
 hipError_t launch_copy(int64_t n, const double* src, double* dst, hipStream_t st);
 hipError_t launch_stamp(InstState* ist, int n, hipStream_t st);
 hipError_t noalloc_scratch(void** ptr);
+hipError_t launch_band_factor(const FactorJob* jobs, int njobs, int storage, int max_n, hipStream_t st);
 }  // namespace ras
 
 using namespace ras;
@@ -126,6 +127,7 @@ struct ras_handle {
     // last solve
     std::vector<std::vector<double>> hist, hist_t;
     std::vector<std::vector<int64_t>> counts;
+    std::vector<std::vector<double>> phase_s;  // [rhs][P * 4] seconds per subdomain and phase
     DevBuf ws_red;  // reduction slots of ras_relative_residual
     // timing events of the solves on this handle, created once at setup
     struct Events {
@@ -154,7 +156,10 @@ ras_status guarded(F&& f) {
 
 constexpr size_t kLdsLimit = 160 * 1024 - 4096;  // leave room for the kernels' static LDS
 
-void build_plan(const ras_csr* A, const ras_partition* part, int32_t overlap, const ras_local* local, Plan& plan) {
+// host_factor: banded Cholesky factors computed here (plans that are queried on
+// the host); otherwise upload() factors on the device
+void build_plan(const ras_csr* A, const ras_partition* part, int32_t overlap, const ras_local* local, Plan& plan,
+                bool host_factor = true) {
     if (!A || !part || !local) throw Error{RAS_E_ARG, "null argument"};
     if (overlap < 0) throw Error{RAS_E_ARG, "overlap must be >= 0"};
     if (local->kind != RAS_LOCAL_CHOL_BANDED && local->kind != RAS_LOCAL_CG && local->kind != RAS_LOCAL_CHOL_SPARSE)
@@ -164,6 +169,13 @@ void build_plan(const ras_csr* A, const ras_partition* part, int32_t overlap, co
     if (local->kind == RAS_LOCAL_CG && local->storage == RAS_STORAGE_FP16_ROWSCALED)
         throw Error{RAS_E_ARG, "FP16_ROWSCALED storage applies to the Cholesky factor only"};
     if (local->kind == RAS_LOCAL_CG && local->cg_iters < 1) throw Error{RAS_E_ARG, "cg_iters must be >= 1"};
+    if (local->transmission != RAS_TRANSMISSION_DIRICHLET && local->transmission != RAS_TRANSMISSION_ROBIN)
+        throw Error{RAS_E_ARG, "unknown transmission condition"};
+    if (local->transmission == RAS_TRANSMISSION_ROBIN) {
+        if (local->kind == RAS_LOCAL_CG)
+            throw Error{RAS_E_ARG, "Robin transmission needs a direct local solver (CHOL_BANDED or CHOL_SPARSE)"};
+        if (!(local->robin_q > 0.0 && local->robin_q <= 1.0)) throw Error{RAS_E_ARG, "robin_q must be in (0, 1]"};
+    }
     validate_csr(*A);
     plan.n = A->n;
     plan.nnz = A->row_ptr[A->n];
@@ -174,7 +186,16 @@ void build_plan(const ras_csr* A, const ras_partition* part, int32_t overlap, co
     plan.val.assign(A->val, A->val + plan.nnz);
     plan.owner = make_owner(*A, *part, &plan.P);
     build_overlap(plan);
-    if (local->kind == RAS_LOCAL_CHOL_BANDED) factor_local(plan);
+    if (local->kind == RAS_LOCAL_CHOL_BANDED) {
+        if (host_factor) {
+            factor_local(plan);
+        } else {
+            // bands beyond the device factorisation's column buffer are factored here
+            parallel_for(plan.P, [&](int64_t p, int) {
+                if (plan.subs[p].w > kMaxFactorW) factor_one(plan, plan.subs[p], static_cast<int32_t>(p));
+            });
+        }
+    }
     if (local->kind == RAS_LOCAL_CHOL_SPARSE) {
         if (local->storage == RAS_STORAGE_FP16_ROWSCALED)
             throw Error{RAS_E_ARG, "FP16_ROWSCALED storage applies to the banded Cholesky factor only"};
@@ -263,6 +284,54 @@ SparsePass sparse_pass(int32_t n, const std::vector<int64_t>& ptr, const std::ve
     return sp;
 }
 
+// Banded Cholesky factors of the listed subdomains computed on the device
+// (float64, in a temporary band buffer), then laid out in the storage type the
+// solves read (band_f, band_b, invd, FP16 scales) by device kernels.
+void device_factor(ras_handle& h, const Plan& plan, const std::vector<int>& ps) {
+    const int st = plan.local.storage;
+    std::vector<int64_t> loff(ps.size() + 1, 0);
+    int max_n = 0;
+    for (size_t k = 0; k < ps.size(); ++k) {
+        const auto& s = plan.subs[ps[k]];
+        loff[k + 1] = loff[k] + static_cast<int64_t>(s.omega.size()) * (s.w + 1);
+        max_n = std::max<int>(max_n, static_cast<int>(s.omega.size()));
+    }
+    DevBuf L, jobs_d, fail_d;
+    L.alloc(std::max<int64_t>(loff.back(), 1) * sizeof(double));
+    fail_d.alloc(ps.size() * sizeof(int32_t));
+    std::vector<FactorJob> jobs(ps.size());
+    for (size_t k = 0; k < ps.size(); ++k) {
+        const SubDev& d = h.subs[ps[k]];
+        FactorJob& j = jobs[k];
+        j.ell_val = d.ell_val;
+        j.ell_lcol = d.ell_lcol;
+        j.n = d.n;
+        j.n_pad = d.n_pad;
+        j.K = d.K;
+        j.w = d.w;
+        j.L = L.as<double>() + loff[k];
+        j.fail = fail_d.as<int32_t>() + k;
+        j.band_f = const_cast<void*>(d.band_f);
+        j.band_b = const_cast<void*>(d.band_b);
+        j.invd = const_cast<void*>(d.invd);
+        j.scale = const_cast<float*>(d.scale);
+        j.slab = d.slab;
+        j.robin_shift = robin_shift_factor(plan.local);
+    }
+    jobs_d.alloc(jobs.size() * sizeof(FactorJob));
+    hip_check(hipMemcpy(jobs_d.p, jobs.data(), jobs.size() * sizeof(FactorJob), hipMemcpyHostToDevice), "copy jobs");
+    hip_check(launch_band_factor(jobs_d.as<FactorJob>(), static_cast<int>(jobs.size()), st, max_n, h.stream),
+              "band factorisation");
+    std::vector<int32_t> fail(ps.size());
+    hip_check(hipMemcpyAsync(fail.data(), fail_d.p, ps.size() * sizeof(int32_t), hipMemcpyDeviceToHost, h.stream),
+              "copy factor status");
+    hip_check(hipStreamSynchronize(h.stream), "band factorisation");
+    for (size_t k = 0; k < ps.size(); ++k)
+        if (fail[k] >= 0)
+            throw Error{RAS_E_NOT_SPD, "non-positive pivot in subdomain " + std::to_string(ps[k]) + " at local row " +
+                                           std::to_string(fail[k])};
+}
+
 void upload(ras_handle& h, const Plan& plan) {
     const int P = plan.P;
     const bool sparse = plan.local.kind == RAS_LOCAL_CHOL_SPARSE;
@@ -317,6 +386,9 @@ void upload(ras_handle& h, const Plan& plan) {
         // tail: the last load round of a slab block may read up to one round past its end
         h.band_f.alloc(band_off[P] * sts + kSlabTailBytes);
         h.band_b.alloc(band_off[P] * sts + kSlabTailBytes);
+        // rows past the end of a subdomain's last slab block read as zero
+        hip_check(hipMemset(h.band_f.p, 0, band_off[P] * sts + kSlabTailBytes), "clear band");
+        hip_check(hipMemset(h.band_b.p, 0, band_off[P] * sts + kSlabTailBytes), "clear band");
         h.invd.alloc(row_off[P] * cts);
         if (st == RAS_STORAGE_FP16_ROWSCALED) h.scale.alloc(row_off[P] * sizeof(float));
     }
@@ -329,6 +401,7 @@ void upload(ras_handle& h, const Plan& plan) {
     hip_check(hipMemcpy(h.csr_va.p, plan.val.data(), plan.nnz * sizeof(double), hipMemcpyHostToDevice), "copy val");
 
     h.subs.resize(P);
+    std::vector<int> dev_factor;  // banded subdomains factored on the device
     std::vector<int32_t> om;
     std::vector<double> ev;
     std::vector<float> evf;
@@ -431,7 +504,15 @@ void upload(ras_handle& h, const Plan& plan) {
         d.K = K;
         d.w = s.w;
         d.row_off = row_off[p];
-        if (chol) {
+        if (chol && s.L.empty()) {
+            // factored on the device after this loop
+            d.slab = s.w <= kSlabMaxW ? 1 : 0;
+            d.band_f = static_cast<char*>(h.band_f.p) + band_off[p] * sts;
+            d.band_b = static_cast<char*>(h.band_b.p) + band_off[p] * sts;
+            d.invd = static_cast<char*>(h.invd.p) + row_off[p] * cts;
+            if (st == RAS_STORAGE_FP16_ROWSCALED) d.scale = h.scale.as<float>() + row_off[p];
+            dev_factor.push_back(p);
+        } else if (chol) {
             const int64_t ld = s.w + 1;
             const int w = s.w;
             const double* L = s.L.data();
@@ -557,6 +638,7 @@ void upload(ras_handle& h, const Plan& plan) {
         }
         h.subs[p] = d;
     }
+    if (!dev_factor.empty()) device_factor(h, plan, dev_factor);
     // neighbours: subdomains owning a column read by a row of Omega_p (the
     // residual's interface columns included); used by decentralized detection
     {
@@ -618,7 +700,8 @@ struct InstSpec {
     const double* b;
     double* x;
     int rhs;
-    double tol = -1.0;  // per-system tolerance (< 0: the solve options' tol)
+    double tol = -1.0;     // per-system tolerance (< 0: the solve options' tol)
+    double bnorm2 = -1.0;  // ||b||^2 if already known (< 0: computed by the solve)
 };
 
 // Where a solve's workspace lives: a fresh allocation (default), a buffer that
@@ -858,6 +941,7 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     const size_t o_conv = carve(nitems * sizeof(int32_t));
     const size_t o_gflag = carve(nitems * sizeof(int32_t));
     const size_t o_solves = carve(nitems * sizeof(int64_t));
+    const size_t o_phase = carve(4 * static_cast<size_t>(nitems) * sizeof(int64_t));
     const size_t o_version = carve(nitems * sizeof(uint32_t));
     const size_t o_tptr = carve((nteams + 1) * sizeof(int32_t));
     const size_t o_titems = carve(team_items.size() * sizeof(int32_t));
@@ -872,7 +956,9 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     const size_t o_snap = carve(snap_elems * sizeof(double));
     const size_t o_hist = carve(2 * static_cast<size_t>(ninst) * hist_cap * sizeof(double));
     const int nparts = 512;
-    const size_t o_red = carve((2 * nparts + 2) * sizeof(double));
+    // reduction slots: partial sums (reused launch after launch on the stream) and two
+    // results per right-hand side, so that all norms of a step come back in one copy
+    const size_t o_red = carve((2 * nparts + 2 * static_cast<size_t>(ninst)) * sizeof(double));
     DevBuf ws;
     char* base = nullptr;
     if (where.fixed) {
@@ -901,19 +987,32 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
         in.max_sweeps = o.max_sweeps;
         in.tol2 = tol_v[i] * tol_v[i];
         in.leader = owner_wg[in.item_begin];
-        // ||b||^2 (deterministic two-pass reduction)
-        ras_handle* h = specs[i].h;
-        double out[2];
-        hip_check(launch_residual(h->plan->n, h->csr_rp.as<int64_t>(), h->csr_ci.as<int32_t>(), h->csr_va.as<double>(),
-                                  specs[i].b, nullptr, reinterpret_cast<double*>(base + o_red), nparts,
-                                  reinterpret_cast<double*>(base + o_red) + 2 * nparts, stream),
-                  "norm of b");
-        hip_check(hipMemcpyAsync(out, reinterpret_cast<double*>(base + o_red) + 2 * nparts, 2 * sizeof(double),
-                                 hipMemcpyDeviceToHost, stream),
-                  "copy norm");
-        hip_check(hipStreamSynchronize(stream), "sync norm");
-        in.bnorm2 = out[1];
-        if (!(in.bnorm2 > 0.0)) throw Error{RAS_E_ARG, "right-hand side " + std::to_string(i) + " is zero"};
+    }
+    {
+        // ||b||^2 of the right-hand sides not given one (deterministic two-pass
+        // reductions), all returned in one copy
+        double* red0 = reinterpret_cast<double*>(base + o_red);
+        std::vector<double> out(2 * static_cast<size_t>(ninst), 0.0);
+        bool any = false;
+        for (int i = 0; i < ninst; ++i) {
+            if (specs[i].bnorm2 >= 0.0) continue;
+            ras_handle* h = specs[i].h;
+            hip_check(launch_residual(h->plan->n, h->csr_rp.as<int64_t>(), h->csr_ci.as<int32_t>(),
+                                      h->csr_va.as<double>(), specs[i].b, nullptr, red0, nparts,
+                                      red0 + 2 * nparts + 2 * i, stream),
+                      "norm of b");
+            any = true;
+        }
+        if (any) {
+            hip_check(hipMemcpyAsync(out.data(), red0 + 2 * nparts, out.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                     stream),
+                      "copy norms");
+            hip_check(hipStreamSynchronize(stream), "sync norms");
+        }
+        for (int i = 0; i < ninst; ++i) {
+            insts[i].bnorm2 = specs[i].bnorm2 >= 0.0 ? specs[i].bnorm2 : out[2 * i + 1];
+            if (!(insts[i].bnorm2 > 0.0)) throw Error{RAS_E_ARG, "right-hand side " + std::to_string(i) + " is zero"};
+        }
     }
     std::vector<InstState> ist(ninst);
     for (auto& s : ist) {
@@ -943,6 +1042,7 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     hip_check(hipMemsetAsync(base + o_conv, 0, nitems * sizeof(int32_t), stream), "clear");
     hip_check(hipMemsetAsync(base + o_gflag, 0, nitems * sizeof(int32_t), stream), "clear");
     hip_check(hipMemsetAsync(base + o_solves, 0, nitems * sizeof(int64_t), stream), "clear");
+    hip_check(hipMemsetAsync(base + o_phase, 0, 4 * static_cast<size_t>(nitems) * sizeof(int64_t), stream), "clear");
     hip_check(hipMemsetAsync(base + o_version, 0, nitems * sizeof(uint32_t), stream), "clear");
     if (sync)  // x^0 lives in the caller's buffer; the other buffer is filled by the first sweep
         hip_check(hipMemsetAsync(base + o_x1, 0, x1_elems * sizeof(double), stream), "clear");
@@ -962,6 +1062,7 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     const double pace = o.pace < 0.0 ? (h0.solver != RAS_LOCAL_CG ? 0.25 : 0.0) : o.pace;
     P.pace = o.mode == RAS_MODE_ASYNC ? pace : 0.0;
     P.solves = reinterpret_cast<int64_t*>(base + o_solves);
+    P.phase = reinterpret_cast<int64_t*>(base + o_phase);
     P.version = reinterpret_cast<uint32_t*>(base + o_version);
     P.team_ptr = reinterpret_cast<const int32_t*>(base + o_tptr);
     P.team_items = reinterpret_cast<const int32_t*>(base + o_titems);
@@ -990,15 +1091,23 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     std::vector<int> launches(ninst, 0);
     const double tick_s = 1.0 / (static_cast<double>(h0.clock_khz) * 1000.0);
     double* red = reinterpret_cast<double*>(base + o_red);
-    auto exact_relres = [&](int i) {
-        ras_handle* h = specs[i].h;
-        double out[2];
-        hip_check(launch_residual(h->plan->n, h->csr_rp.as<int64_t>(), h->csr_ci.as<int32_t>(), h->csr_va.as<double>(),
-                                  specs[i].b, specs[i].x, red, nparts, red + 2 * nparts, stream),
-                  "verification residual");
-        hip_check(hipMemcpyAsync(out, red + 2 * nparts, 2 * sizeof(double), hipMemcpyDeviceToHost, stream), "copy");
+    // exact relative residuals of the listed right-hand sides (the verification of
+    // Sec. 3.3.2): one reduction launch each, one copy and one wait for all
+    std::vector<double> vout(2 * static_cast<size_t>(ninst));
+    auto exact_relres = [&](const std::vector<int>& which) {
+        if (which.empty()) return;
+        for (int i : which) {
+            ras_handle* h = specs[i].h;
+            hip_check(launch_residual(h->plan->n, h->csr_rp.as<int64_t>(), h->csr_ci.as<int32_t>(),
+                                      h->csr_va.as<double>(), specs[i].b, specs[i].x, red, nparts,
+                                      red + 2 * nparts + 2 * i, stream),
+                      "verification residual");
+        }
+        hip_check(hipMemcpyAsync(vout.data(), red + 2 * nparts, vout.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                 stream),
+                  "copy");
         hip_check(hipStreamSynchronize(stream), "sync verification");
-        return std::sqrt(out[0] / out[1]);
+        for (int i : which) relres[i] = std::sqrt(vout[2 * i] / vout[2 * i + 1]);
     };
     std::vector<int64_t> solves_h(nitems);
     std::vector<int32_t> step(ninst, RAS_STEP_RESUME);
@@ -1015,26 +1124,43 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
         }
         for (int i = 0; i < ninst; ++i)
             if (!verified[i]) ++launches[i];
-        hip_check(hipMemcpy(ist.data(), P.ist, ninst * sizeof(InstState), hipMemcpyDeviceToHost), "copy state");
-        hip_check(hipMemcpy(solves_h.data(), P.solves, nitems * sizeof(int64_t), hipMemcpyDeviceToHost), "copy counts");
-        // collect history entries written by this launch
-        for (int i = 0; i < ninst; ++i) {
-            const int64_t len = std::min(ist[i].hist_len, hist_cap);
-            if (len > 0) {
-                std::vector<double> hv(len), ht(len);
-                hip_check(hipMemcpy(hv.data(), insts[i].hist, len * sizeof(double), hipMemcpyDeviceToHost), "hist");
-                hip_check(hipMemcpy(ht.data(), insts[i].hist_t, len * sizeof(double), hipMemcpyDeviceToHost), "hist");
-                for (int64_t k = 0; k < len; ++k) {
-                    hist[i].push_back(hv[k]);
-                    hist_t[i].push_back(ht[k] * tick_s);
-                }
+        hip_check(hipMemcpyAsync(ist.data(), P.ist, ninst * sizeof(InstState), hipMemcpyDeviceToHost, stream),
+                  "copy state");
+        hip_check(hipMemcpyAsync(solves_h.data(), P.solves, nitems * sizeof(int64_t), hipMemcpyDeviceToHost, stream),
+                  "copy counts");
+        hip_check(hipStreamSynchronize(stream), "copy state");
+        // collect the history entries written by this launch (one wait for all)
+        {
+            std::vector<std::vector<double>> hv(ninst), ht(ninst);
+            bool any = false;
+            for (int i = 0; i < ninst; ++i) {
+                const int64_t len = std::min(ist[i].hist_len, hist_cap);
+                if (len <= 0) continue;
+                hv[i].resize(len);
+                ht[i].resize(len);
+                hip_check(hipMemcpyAsync(hv[i].data(), insts[i].hist, len * sizeof(double), hipMemcpyDeviceToHost,
+                                         stream),
+                          "hist");
+                hip_check(hipMemcpyAsync(ht[i].data(), insts[i].hist_t, len * sizeof(double), hipMemcpyDeviceToHost,
+                                         stream),
+                          "hist");
+                any = true;
             }
+            if (any) hip_check(hipStreamSynchronize(stream), "hist");
+            for (int i = 0; i < ninst; ++i)
+                for (size_t k = 0; k < hv[i].size(); ++k) {
+                    hist[i].push_back(hv[i][k]);
+                    hist_t[i].push_back(ht[i][k] * tick_s);
+                }
         }
         if (sync) {
-            for (int i = 0; i < ninst; ++i) {
+            std::vector<int> all(ninst);
+            std::iota(all.begin(), all.end(), 0);
+            for (int i = 0; i < ninst; ++i)
                 if (ist[i].result_buf == 1)
                     hip_check(launch_copy(specs[i].h->plan->n, insts[i].x1, insts[i].x0, stream), "copy result");
-                relres[i] = exact_relres(i);
+            exact_relres(all);
+            for (int i = 0; i < ninst; ++i) {
                 verified[i] = 1;
                 // a synchronous solve ran its sweeps: only the verified residual decides
                 step[i] = !std::isfinite(relres[i]) ? RAS_STEP_DIVERGED
@@ -1049,9 +1175,12 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
         hip_check(hipEventRecord(ev1, stream), "event");
         hip_check(hipEventSynchronize(ev1), "event");
         hip_check(hipEventElapsedTime(&ms_now, ev0, ev1), "elapsed");
+        std::vector<int> pending;
+        for (int i = 0; i < ninst; ++i)
+            if (!verified[i]) pending.push_back(i);
+        exact_relres(pending);
         for (int i = 0; i < ninst; ++i) {
             if (verified[i]) continue;
-            relres[i] = exact_relres(i);
             hist[i].push_back(relres[i]);
             hist_t[i].push_back(ms_now * 1e-3);
             int64_t mn = INT64_MAX;
@@ -1087,6 +1216,9 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     float ms = 0.0f;
     hip_check(hipEventElapsedTime(&ms, ev0, ev1), "elapsed");
     hip_check(hipMemcpy(solves_h.data(), P.solves, nitems * sizeof(int64_t), hipMemcpyDeviceToHost), "copy counts");
+    std::vector<int64_t> phase_h(4 * static_cast<size_t>(nitems));
+    hip_check(hipMemcpy(phase_h.data(), P.phase, phase_h.size() * sizeof(int64_t), hipMemcpyDeviceToHost),
+              "copy phases");
 
     ras_status status = RAS_OK;
     for (int i = 0; i < ninst; ++i) {
@@ -1122,6 +1254,11 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
         h->hist[r] = std::move(hist[i]);
         h->hist_t[r] = std::move(hist_t[i]);
         h->counts[r] = std::move(cnt);
+        if (static_cast<int>(h->phase_s.size()) <= r) h->phase_s.resize(r + 1);
+        std::vector<double> ph(4 * static_cast<size_t>(insts[i].item_count));
+        for (size_t k = 0; k < ph.size(); ++k)
+            ph[k] = static_cast<double>(phase_h[4 * static_cast<size_t>(insts[i].item_begin) + k]) * tick_s;
+        h->phase_s[r] = std::move(ph);
         const ras_status si = ras_final_status(step[i]);
         if (si < 0) status = si;
         else if (si > 0 && status == RAS_OK) status = si;
@@ -1159,6 +1296,8 @@ int64_t estimate_device_bytes(const Plan& plan, int nrhs) {
         const int64_t ell = n_pad_of(n) * sd.ell_width;
         bytes += 8 * n + ell * (8 + 4 + 4 + (!chol && plan.local.storage == RAS_STORAGE_FP32 ? 4 : 0)) + 512;
         if (chol) bytes += 2 * ((band_elems(n, sd.w) + 63) / 64 * 64) * sts + n * cts + (plan.local.storage == 2 ? 4 * n : 0);
+        // the float64 band of the device factorisation, held while the system is set up
+        if (chol && sd.L.empty()) bytes += 8 * n * (sd.w + 1);
         if (plan.local.kind == RAS_LOCAL_CHOL_SPARSE) {
             const int64_t nnz = static_cast<int64_t>(sd.sf.lj.size());
             bytes += 2 * (4 * (5 * n + 16) + (nnz + n) * (4 + sts) + 32) + n * cts;
@@ -1192,6 +1331,7 @@ struct SrvSystem {
     uint64_t ticket = 0;
     ras_handle* h = nullptr;
     DevBuf b, x;
+    std::vector<double> bnorm2;  // ||b||^2 per right-hand side, computed once at admission
     int nrhs = 1;
     int64_t n = 0;
     double tol = 1e-8;
@@ -1229,6 +1369,8 @@ struct ras_server {
     bool stop = false;
     int64_t in_use = 0, peak = 0, slices = 0, submitted_n = 0, completed_n = 0;
     double device_seconds = 0.0;
+    DevBuf ws;   // slice workspace, reused (grown when a larger batch needs it)
+    DevBuf red;  // reduction slots for the admission norms
     std::thread planner, driver;
 
     void finish(uint64_t ticket, SrvResult&& r) {
@@ -1253,7 +1395,8 @@ struct ras_server {
                 ras_csr A{static_cast<int64_t>(rq->rp.size()) - 1, rq->rp.data(), rq->ci.data(), rq->va.data()};
                 if (!rq->owner.empty()) rq->part.owner = rq->owner.data();
                 rq->plan = std::make_unique<ras_plan>();
-                build_plan(&A, &rq->part, rq->overlap, &rq->local, *rq->plan);
+                // partition and overlap here; the factors are computed on the device at admission
+                build_plan(&A, &rq->part, rq->overlap, &rq->local, *rq->plan, false);
                 rq->bytes = estimate_device_bytes(*rq->plan, rq->nrhs);
                 std::vector<int64_t>().swap(rq->rp);
                 std::vector<int32_t>().swap(rq->ci);
@@ -1305,7 +1448,21 @@ struct ras_server {
         sys->x.alloc(vb);
         hip_check(hipMemcpyAsync(sys->b.p, rq.b.data(), vb, hipMemcpyHostToDevice, stream), "upload b");
         hip_check(hipMemsetAsync(sys->x.p, 0, vb, stream), "clear x");
+        // ||b||^2 of every right-hand side, once (the slices reuse it)
+        const int nparts = 512;
+        red.ensure((2 * nparts + 2 * static_cast<size_t>(sys->nrhs)) * sizeof(double));
+        double* r0 = red.as<double>();
+        for (int r = 0; r < sys->nrhs; ++r)
+            hip_check(launch_residual(sys->n, h->csr_rp.as<int64_t>(), h->csr_ci.as<int32_t>(), h->csr_va.as<double>(),
+                                      sys->b.as<double>() + r * sys->n, nullptr, r0, nparts, r0 + 2 * nparts + 2 * r,
+                                      stream),
+                      "norm of b");
+        std::vector<double> out(2 * static_cast<size_t>(sys->nrhs));
+        hip_check(hipMemcpyAsync(out.data(), r0 + 2 * nparts, out.size() * sizeof(double), hipMemcpyDeviceToHost, stream),
+                  "copy norms");
         hip_check(hipStreamSynchronize(stream), "admit");
+        sys->bnorm2.resize(sys->nrhs);
+        for (int r = 0; r < sys->nrhs; ++r) sys->bnorm2[r] = out[2 * r + 1];
         sys->h = h.release();
         sys->acc.assign(sys->nrhs, ras_solve_info{});
         return sys;
@@ -1371,7 +1528,7 @@ struct ras_server {
                 for (SrvSystem* sy : kv.second)
                     for (int r = 0; r < sy->nrhs; ++r)
                         specs.push_back(InstSpec{sy->h, sy->b.as<double>() + r * sy->n, sy->x.as<double>() + r * sy->n,
-                                                 r, sy->tol});
+                                                 r, sy->tol, sy->bnorm2[r]});
                 ras_solve_opts o{};
                 o.mode = RAS_MODE_ASYNC;
                 o.pace = -1.0;  // library choice per local solver
@@ -1382,7 +1539,9 @@ struct ras_server {
                 ras_status st = RAS_OK;
                 std::string msg;
                 try {
-                    st = run_solve(specs, o, infos.data());
+                    Workspace where;
+                    where.reuse = &ws;
+                    st = run_solve(specs, o, infos.data(), where);
                 } catch (const Error& e) {
                     st = e.status;
                     msg = e.msg;
@@ -1576,7 +1735,7 @@ ras_status ras_setup(const ras_csr* A, const ras_partition* part, int32_t overla
     return guarded([&] {
         if (!out) throw Error{RAS_E_ARG, "null output"};
         auto plan = std::make_unique<ras_plan>();
-        build_plan(A, part, overlap, local, *plan);
+        build_plan(A, part, overlap, local, *plan, false);  // banded factors: on the device, in upload
         auto h = std::make_unique<ras_handle>();
         init_device(*h, hip_stream);
         upload(*h, *plan);
@@ -1680,6 +1839,56 @@ ras_status ras_partition_sets(const ras_handle* h, int32_t* owner, int64_t* omeg
     return guarded([&] {
         if (!h) throw Error{RAS_E_ARG, "null handle"};
         copy_sets(*h->plan, owner, omega_ptr, omega_idx);
+        return RAS_OK;
+    });
+}
+
+ras_status ras_phase_seconds(const ras_handle* h, int32_t rhs, double* seconds) {
+    return guarded([&] {
+        if (!h || !seconds) throw Error{RAS_E_ARG, "null argument"};
+        if (rhs < 0 || rhs >= static_cast<int32_t>(h->phase_s.size()) || h->phase_s[rhs].empty())
+            throw Error{RAS_E_STATE, "no solve recorded for this rhs"};
+        std::copy(h->phase_s[rhs].begin(), h->phase_s[rhs].end(), seconds);
+        return RAS_OK;
+    });
+}
+
+ras_status ras_handle_factor(const ras_handle* h, int32_t p, double* band, int32_t* w) {
+    return guarded([&] {
+        if (!h || !w) throw Error{RAS_E_ARG, "null argument"};
+        if (h->solver != RAS_LOCAL_CHOL_BANDED) throw Error{RAS_E_STATE, "the local solver is not banded Cholesky"};
+        if (p < 0 || p >= static_cast<int32_t>(h->subs.size())) throw Error{RAS_E_ARG, "subdomain out of range"};
+        const SubDev& d = h->subs[p];
+        *w = d.w;
+        if (!band) return RAS_OK;
+        hip_check(hipSetDevice(h->device), "hipSetDevice");
+        const int64_t n = d.n, ld = d.w + 1;
+        const size_t sts = h->storage == RAS_STORAGE_FP64 ? 8 : h->storage == RAS_STORAGE_FP32 ? 4 : 2;
+        const size_t cts = ct_size(h->storage);
+        const int64_t elems = band_elems(n, d.w);
+        std::vector<unsigned char> bf(elems * sts), iv(n * cts);
+        std::vector<float> sc(n, 1.0f);
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        hip_check(hipMemcpy(bf.data(), d.band_f, bf.size(), hipMemcpyDeviceToHost), "copy band");
+        hip_check(hipMemcpy(iv.data(), d.invd, iv.size(), hipMemcpyDeviceToHost), "copy invd");
+        if (d.scale) hip_check(hipMemcpy(sc.data(), d.scale, n * sizeof(float), hipMemcpyDeviceToHost), "copy scale");
+        auto entry = [&](int64_t i) -> double {
+            if (h->storage == RAS_STORAGE_FP64) return reinterpret_cast<const double*>(bf.data())[i];
+            if (h->storage == RAS_STORAGE_FP32) return reinterpret_cast<const float*>(bf.data())[i];
+            _Float16 hv;
+            std::memcpy(&hv, bf.data() + 2 * i, 2);
+            return static_cast<double>(static_cast<float>(hv));
+        };
+        for (int64_t t = 0; t < n; ++t) {
+            const double rs = h->storage == RAS_STORAGE_FP16_ROWSCALED ? static_cast<double>(sc[t]) : 1.0;
+            for (int64_t o = 0; o < d.w; ++o) {
+                const int64_t di = d.slab ? ((t / kBandRows) * d.w + o) * kBandRows + t % kBandRows : t * ld + o;
+                band[t * ld + o] = entry(di) * rs;
+            }
+            const double inv = h->storage == RAS_STORAGE_FP64 ? reinterpret_cast<const double*>(iv.data())[t]
+                                                               : reinterpret_cast<const float*>(iv.data())[t];
+            band[t * ld + d.w] = 1.0 / inv;
+        }
         return RAS_OK;
     });
 }
@@ -1872,8 +2081,8 @@ ras_status ras_server_get_stats(ras_server* srv, ras_server_stats* out) {
     });
 }
 
-void ras_server_destroy(ras_server* srv) {
-    if (!srv) return;
+ras_status ras_server_destroy(ras_server* srv) {
+    if (!srv) return RAS_OK;
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         srv->stop = true;
@@ -1883,8 +2092,10 @@ void ras_server_destroy(ras_server* srv) {
     if (srv->planner.joinable()) srv->planner.join();
     if (srv->driver.joinable()) srv->driver.join();
     srv->active.clear();
-    if (srv->own_stream) (void)hipStreamDestroy(srv->stream);
+    ras_status st = RAS_OK;
+    if (srv->own_stream && hipStreamDestroy(srv->stream) != hipSuccess) st = fail(RAS_E_HIP, "hipStreamDestroy");
     delete srv;
+    return st;
 }
 
 

@@ -30,6 +30,7 @@ constexpr int kSlabFarWaves = 4;    // waves of the off-diagonal sums
 constexpr int kSlabParts = 2 * kSlabFarWaves;  // far partial sums per row (one per half-wave)
 constexpr int kSlabLead[3] = {2, 3, 4};  // blocks in flight: FP64, FP32, FP16 storage
 constexpr int kSlabWinTail = 16;    // mirrored slots after the solution window
+constexpr int kMaxFactorW = 1024;   // widest band the device factorisation takes
 // fixed device workspace of ras_solve_noalloc (per device, held until process exit)
 constexpr size_t kNoAllocScratchBytes = RAS_NOALLOC_SCRATCH_BYTES;
 // row stride (compute-type entries) of the near + triangle buffer: 2 blocks
@@ -85,6 +86,27 @@ struct SubDev {
     int32_t pad3_;
 };
 
+// Device factorisation of one subdomain's banded local matrix (Sec. 3.3.1: the
+// Cholesky factor is computed once, at setup): A_p's lower band is gathered from
+// the subdomain's ELL rows (local columns) into L[n][w+1] (row-major, diagonal at
+// offset w) and factored in place in float64.  fail receives the first local row
+// with a non-positive (or non-finite) pivot, or -1.
+struct FactorJob {
+    const double* ell_val;
+    const int32_t* ell_lcol;
+    int32_t n, n_pad, K, w;
+    double* L;
+    int32_t* fail;
+    // layout of the factor as the triangular solves read it (see the upload code)
+    void* band_f;        // L in the storage type: slab blocks [o][r] (w <= kSlabMaxW) or row-major [n][w+1]
+    void* band_b;        // the reversed transpose J L^T J, same layout
+    void* invd;          // [n] 1 / L_ii as the solves see it (compute type)
+    float* scale;        // [n] FP16 row scales (FP16_ROWSCALED only)
+    int32_t slab;
+    int32_t pad_;
+    double robin_shift;  // Robin transmission: diagonal minus robin_shift * (coupling outside omega)
+};
+
 // One work item: subdomain `sub` of right-hand side (instance) `inst`.
 struct ItemDev {
     int32_t inst;
@@ -136,6 +158,7 @@ struct Params {
     int32_t* conv;            // [n_items] local criterion met (async)
     int32_t* gflag;           // [n_items] global-convergence flag (decentralized detection)
     int64_t* solves;          // [n_items] local solves done
+    int64_t* phase;           // [n_items][4] wall-clock ticks: residual, local solve, prolongation, other
     uint32_t* version;        // [n_items] published updates (async)
     const int32_t* team_ptr;  // [n_teams + 1]
     const int32_t* team_items;  // item ids per team, in visiting order

@@ -23,6 +23,7 @@
 // host then verifies the exact residual and resumes if it fails.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <mutex>
 #include <type_traits>
@@ -207,6 +208,8 @@ struct TeamCtx {
     RAS_GLOBAL uint32_t* bar;  // {count, generation}
     RAS_GLOBAL double* buf;    // [2][T][4]
     uint32_t phase;            // barriers passed (slot parity)
+    // wall-clock stamps of the current update (thread 0): residual done, local solve done
+    int64_t st_res, st_solve;
 };
 
 __device__ __forceinline__ TeamCtx make_team(const Params& P) {
@@ -217,6 +220,8 @@ __device__ __forceinline__ TeamCtx make_team(const Params& P) {
     tc.bar = gptr(P.team_bar) + 2 * tc.team;
     tc.buf = gptr(P.team_buf) + static_cast<int64_t>(tc.team) * 8 * tc.T;
     tc.phase = 0;
+    tc.st_res = 0;
+    tc.st_solve = 0;
     return tc;
 }
 
@@ -502,6 +507,7 @@ struct CgUpdate {
             v4[3] = static_cast<double>(block_sum<B>(rr, redc));
         }
         team_sum<CT, 4>(tc, v4, 0x8u);
+        if (tid == 0) tc.st_res = wall_clock64();
         own2 = v4[0];
         loc2 = v4[1];
         b2 = v4[2];
@@ -578,6 +584,7 @@ struct CgUpdate {
             rho = rho_new;
             __syncthreads();
         }
+        if (tid == 0) tc.st_solve = wall_clock64();
         // restricted prolongation: owned points only
 #pragma unroll
         for (int j = 0; j < R; ++j) {
@@ -1299,6 +1306,7 @@ struct BandUpdate {
         // the loaders read v back through global-to-LDS loads
         __builtin_amdgcn_s_waitcnt(0);
         block_sum3<B>(own2, loc2, b2, red3);
+        if (tid == 0) tc.st_res = wall_clock64();
         if (sparse) {
             if constexpr (sizeof(ST) != 2)
                 sparse_solve<ST>(P.subs + item.sub, n, v, smem);
@@ -1313,6 +1321,7 @@ struct BandUpdate {
             band_pass<ST>(Lf, s.scale, false, iv, n, s.w, v, stage, win, winm, gsum);
             band_pass<ST>(Lr, s.scale, true, iv, n, s.w, v, stage, win, winm, gsum);
         }
+        if (tid == 0) tc.st_solve = wall_clock64();
         for (int i = tid; i < n; i += B) {
             const int32_t e = s.omega[i];
             if (e >= 0) {
@@ -1362,12 +1371,20 @@ __device__ __forceinline__ void run_sync(const Params& P, U& upd, TeamCtx& tc, d
             RAS_GLOBAL double* xc = par ? iu.x1 : iu.x0;
             RAS_GLOBAL double* xn = par ? iu.x0 : iu.x1;
             double own2, loc2, b2;
+            const int64_t t_upd = wall_clock64();
             upd(P, tc, item, xc, xn, own2, loc2, b2);
             if (tid == 0 && tc.member == 0) {
                 P.res2_own[par * P.n_items + it] = own2;
                 P.solves[it] += 1;
+                if (P.phase) {
+                    int64_t* ph = P.phase + 4 * static_cast<int64_t>(it);
+                    ph[0] += tc.st_res - t_upd;
+                    ph[1] += tc.st_solve - tc.st_res;
+                    ph[2] += wall_clock64() - tc.st_solve;
+                }
             }
         }
+        const int64_t t_bar = wall_clock64();
         grid_barrier(P.bar, static_cast<uint32_t>(P.n_wg));
         // uniform exit: every system's stop decision of an earlier sweep is visible now
         int running = 0;
@@ -1405,6 +1422,9 @@ __device__ __forceinline__ void run_sync(const Params& P, U& upd, TeamCtx& tc, d
         if (wg == 0 && tid == 0 && P.max_ticks > 0 && abort_at > s + 1 &&
             wall_clock64() - P.ist[0].t0 > P.max_ticks)
             P.bar->abort_at = s + 1;
+        // barrier wait and the convergence check, charged to the team's first item
+        if (P.phase && tid == 0 && tc.member == 0)
+            P.phase[4 * static_cast<int64_t>(P.team_items[ib]) + 3] += wall_clock64() - t_bar;
         __syncthreads();
     }
 }
@@ -1452,6 +1472,7 @@ __device__ __forceinline__ void run_async(const Params& P, U& upd, TeamCtx& tc, 
             const ItemDev item = load_item(P, it);
             const InstDev& in = P.insts[item.inst];
             InstState* st = P.ist + item.inst;
+            const int64_t t_item = wall_clock64();
             if (P.pace > 0.0 && tc.member == 0 && last_dur > 0)
                 paced_read_wait<B>(P, item, in, it, static_cast<int64_t>(P.pace * static_cast<double>(last_dur)));
             const int64_t t_upd = wall_clock64();
@@ -1483,7 +1504,8 @@ __device__ __forceinline__ void run_async(const Params& P, U& upd, TeamCtx& tc, 
                 P.solves[it] += 1;
                 __hip_atomic_fetch_add(P.version + it, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
-            last_dur = wall_clock64() - t_upd;
+            const int64_t t_pub = wall_clock64();
+            last_dur = t_pub - t_upd;
             if (P.detect == 1 && tc.member == 0) {
                 // decentralized detection (Sec. 2.2, Sec. 3.3.2, after Bahi et al.): a
                 // subdomain raises its global flag once it and every neighbour report
@@ -1527,6 +1549,15 @@ __device__ __forceinline__ void run_async(const Params& P, U& upd, TeamCtx& tc, 
                     else if (P.max_ticks > 0 && now - st->t0 > P.max_ticks) stop = 2;
                     if (stop) st_rlx(&st->stop, stop);
                 }
+            }
+            if (P.phase && tid == 0 && tc.member == 0) {
+                // residual (snapshot included), local solve, prolongation and publish,
+                // other: paced wait before the read and detection after the publish
+                int64_t* ph = P.phase + 4 * static_cast<int64_t>(it);
+                ph[0] += tc.st_res - t_upd;
+                ph[1] += tc.st_solve - tc.st_res;
+                ph[2] += t_pub - tc.st_solve;
+                ph[3] += (t_upd - t_item) + (wall_clock64() - t_pub);
             }
             __syncthreads();
         }
@@ -1713,6 +1744,182 @@ hipError_t launch_copy(int64_t n, const double* src, double* dst, hipStream_t st
 
 hipError_t launch_stamp(InstState* ist, int n, hipStream_t st) {
     stamp_start<<<1, 256, 0, st>>>(ist, n);
+    return hipGetLastError();
+}
+
+// ---- banded Cholesky factorisation on the device --------------------------------------
+// One workgroup per subdomain.  Right-looking: for each column j, the pivot
+// L_jj = sqrt(a_jj), the column below it scaled by 1 / L_jj, then the rank-one
+// update of the w x w window of rows j+1 .. j+w that the column reaches.  The
+// band stays in global memory (each window is L2-resident); three workgroup
+// barriers per column order the steps.
+constexpr int kFactorThreads = 512;
+
+__global__ void __launch_bounds__(kFactorThreads) band_factor_kernel(const FactorJob* __restrict__ jobs) {
+    const FactorJob jb = jobs[blockIdx.x];
+    const int n = jb.n, w = jb.w, ld = w + 1;
+    const int tid = threadIdx.x;
+    double* __restrict__ L = jb.L;
+    __shared__ double colv[kMaxFactorW + 1];
+    __shared__ int bad;
+    for (int64_t e = tid; e < static_cast<int64_t>(n) * ld; e += kFactorThreads) L[e] = 0.0;
+    if (tid == 0) bad = -1;
+    __syncthreads();
+    // A_p's lower band from the ELL rows; padding slots carry value 0 at the
+    // row's own column, so entries are accumulated, never overwritten
+    // (Robin transmission: the diagonal is lowered by a fraction of the row's
+    // coupling to the external columns, slots >= n)
+    for (int i = tid; i < n; i += kFactorThreads) {
+        double out = 0.0;
+        for (int k = 0; k < jb.K; ++k) {
+            const int64_t slot = static_cast<int64_t>(k) * jb.n_pad + i;
+            const int c = jb.ell_lcol[slot];
+            if (c >= n) out += fabs(jb.ell_val[slot]);
+            else if (c <= i && c >= i - w) L[static_cast<int64_t>(i) * ld + (c - i + w)] += jb.ell_val[slot];
+        }
+        L[static_cast<int64_t>(i) * ld + w] -= jb.robin_shift * out;
+    }
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        if (tid == 0) {
+            const double d = L[static_cast<int64_t>(j) * ld + w];
+            if (!(d > 0.0) || !__builtin_isfinite(d)) {
+                bad = j;
+            } else {
+                const double piv = sqrt(d);
+                L[static_cast<int64_t>(j) * ld + w] = piv;
+                colv[0] = 1.0 / piv;
+            }
+        }
+        __syncthreads();
+        if (bad >= 0) break;
+        const int m = min(w, n - 1 - j);  // rows below the pivot inside the band
+        const double inv = colv[0];
+        for (int a = tid; a < m; a += kFactorThreads) {
+            const int i = j + 1 + a;
+            double* e = L + static_cast<int64_t>(i) * ld + (j - i + w);
+            const double v = *e * inv;
+            *e = v;
+            colv[1 + a] = v;
+        }
+        __syncthreads();
+        for (int q = tid; q < m * m; q += kFactorThreads) {
+            const int a = q / m, c = q - a * m;
+            if (c <= a) {
+                const int i = j + 1 + a, k = j + 1 + c;
+                L[static_cast<int64_t>(i) * ld + (k - i + w)] -= colv[1 + a] * colv[1 + c];
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *jb.fail = bad;
+}
+
+// float64 -> float16 bits, round to nearest even, in one rounding
+__device__ __forceinline__ uint16_t f64_to_f16_bits(double d) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, d);
+    const uint16_t sign = static_cast<uint16_t>((b >> 48) & 0x8000u);
+    const int64_t ex = static_cast<int64_t>((b >> 52) & 0x7ff);
+    const uint64_t man = b & ((1ull << 52) - 1);
+    if (ex == 0x7ff) return static_cast<uint16_t>(sign | 0x7c00u | (man ? 0x200u : 0u));
+    if (ex == 0) return sign;
+    const int e = static_cast<int>(ex) - 1023;
+    const uint64_t m = man | (1ull << 52);
+    if (e > 15) return static_cast<uint16_t>(sign | 0x7c00u);
+    if (e >= -14) {
+        uint64_t q = m >> 42;
+        const uint64_t rem = m & ((1ull << 42) - 1), half = 1ull << 41;
+        if (rem > half || (rem == half && (q & 1))) ++q;
+        int he = e + 15;
+        if (q == 2048) {
+            q = 1024;
+            ++he;
+        }
+        if (he >= 31) return static_cast<uint16_t>(sign | 0x7c00u);
+        return static_cast<uint16_t>(sign | (he << 10) | (q & 0x3ffu));
+    }
+    const int sh = 28 - e;
+    if (sh > 63) return sign;
+    uint64_t q = m >> sh;
+    const uint64_t rem = m & ((1ull << sh) - 1), half = 1ull << (sh - 1);
+    if (rem > half || (rem == half && (q & 1))) ++q;
+    return static_cast<uint16_t>(sign | q);
+}
+
+// FP16_ROWSCALED: s_i = float32(max_o |L_io|) (1 for an all-zero row)
+__global__ void band_scale_kernel(const FactorJob* __restrict__ jobs) {
+    const FactorJob jb = jobs[blockIdx.y];
+    const int ld = jb.w + 1;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < jb.n; i += gridDim.x * blockDim.x) {
+        double mx = 0.0;
+        for (int o = 0; o < ld; ++o) mx = fmax(mx, fabs(jb.L[static_cast<int64_t>(i) * ld + o]));
+        float sc = static_cast<float>(mx);
+        if (!(sc > 0.0f)) sc = 1.0f;
+        jb.scale[i] = sc;
+    }
+}
+
+// The factor as the triangular solves read it: entry (t, o) of L and of the
+// reversed transpose (row (n-1-t) + w - o of L at offset o) in the storage type,
+// at the slab position ((t / BR) w + o) BR + t % BR (o < w; the diagonal is kept
+// as its reciprocal in invd) or the row-major position t (w+1) + o.
+template <int ST>
+__global__ void band_layout_kernel(const FactorJob* __restrict__ jobs) {
+    const FactorJob jb = jobs[blockIdx.y];
+    const int n = jb.n, w = jb.w, ld = w + 1;
+    const int olim = jb.slab ? w : ld;
+    const int64_t total = static_cast<int64_t>(n) * olim;
+    const double* L = jb.L;
+    for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int t = static_cast<int>(e / olim), o = static_cast<int>(e - static_cast<int64_t>(t) * olim);
+        const int r = (n - 1 - t) + w - o;  // row of L read by the reversed transpose
+        const int64_t di = jb.slab ? (static_cast<int64_t>(t / kBandRows) * w + o) * kBandRows + t % kBandRows
+                                   : static_cast<int64_t>(t) * ld + o;
+        const double lf = L[static_cast<int64_t>(t) * ld + o];
+        const double lb = r < n ? L[static_cast<int64_t>(r) * ld + o] : 0.0;
+        if constexpr (ST == RAS_STORAGE_FP64) {
+            static_cast<double*>(jb.band_f)[di] = lf;
+            static_cast<double*>(jb.band_b)[di] = lb;
+        } else if constexpr (ST == RAS_STORAGE_FP32) {
+            static_cast<float*>(jb.band_f)[di] = static_cast<float>(lf);
+            static_cast<float*>(jb.band_b)[di] = static_cast<float>(lb);
+        } else {
+            static_cast<uint16_t*>(jb.band_f)[di] = f64_to_f16_bits(lf / static_cast<double>(jb.scale[t]));
+            static_cast<uint16_t*>(jb.band_b)[di] =
+                r < n ? f64_to_f16_bits(lb / static_cast<double>(jb.scale[r])) : static_cast<uint16_t>(0);
+        }
+        if (o == 0) {
+            // reciprocal of the diagonal as the triangular solves see it
+            const double dg = L[static_cast<int64_t>(t) * ld + w];
+            if constexpr (ST == RAS_STORAGE_FP64) {
+                static_cast<double*>(jb.invd)[t] = 1.0 / dg;
+            } else if constexpr (ST == RAS_STORAGE_FP32) {
+                static_cast<float*>(jb.invd)[t] =
+                    static_cast<float>(1.0 / static_cast<double>(static_cast<float>(dg)));
+            } else {
+                const uint16_t hb = f64_to_f16_bits(dg / static_cast<double>(jb.scale[t]));
+                const float deq = static_cast<float>(__builtin_bit_cast(_Float16, hb)) * jb.scale[t];
+                static_cast<float*>(jb.invd)[t] = static_cast<float>(1.0 / static_cast<double>(deq));
+            }
+        }
+    }
+}
+
+hipError_t launch_band_factor(const FactorJob* jobs, int njobs, int storage, int max_n, hipStream_t st) {
+    band_factor_kernel<<<njobs, kFactorThreads, 0, st>>>(jobs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 grid(std::max(1, std::min(64, (max_n + 255) / 256)), njobs);
+    if (storage == RAS_STORAGE_FP16_ROWSCALED) {
+        band_scale_kernel<<<grid, 256, 0, st>>>(jobs);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const dim3 lgrid(256, njobs);
+    if (storage == RAS_STORAGE_FP64) band_layout_kernel<RAS_STORAGE_FP64><<<lgrid, 256, 0, st>>>(jobs);
+    else if (storage == RAS_STORAGE_FP32) band_layout_kernel<RAS_STORAGE_FP32><<<lgrid, 256, 0, st>>>(jobs);
+    else band_layout_kernel<RAS_STORAGE_FP16_ROWSCALED><<<lgrid, 256, 0, st>>>(jobs);
     return hipGetLastError();
 }
 

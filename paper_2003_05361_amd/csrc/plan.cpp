@@ -299,23 +299,30 @@ uint16_t f64_to_f16_rne(double d) {
     return static_cast<uint16_t>(sign | q);  // q == 1024 encodes the smallest normal
 }
 
-static void factor_one(const Plan& plan, Subdomain& sd, int32_t p) {
+void factor_one(const Plan& plan, Subdomain& sd, int32_t p) {
     const int64_t n = static_cast<int64_t>(sd.omega.size());
     const int32_t w = sd.w;
     const int64_t ld = w + 1;
     sd.L.assign(n * ld, 0.0);
     double* L = sd.L.data();
-    // scatter the lower band of A[omega, omega]
+    // scatter the lower band of A[omega, omega]; Robin transmission lowers the
+    // diagonal by a fraction of the row's coupling to points outside omega
+    const double shift = robin_shift_factor(plan.local);
     for (int64_t i = 0; i < n; ++i) {
         const int32_t g = sd.omega[i];
+        double out = 0.0;
         for (int64_t e = plan.row_ptr[g]; e < plan.row_ptr[g + 1]; ++e) {
             const int32_t c = plan.col[e];
-            if (c > g) break;
             auto it = std::lower_bound(sd.omega.begin(), sd.omega.end(), c);
-            if (it == sd.omega.end() || *it != c) continue;
+            if (it == sd.omega.end() || *it != c) {
+                out += std::fabs(plan.val[e]);
+                continue;
+            }
+            if (c > g) continue;
             const int64_t j = it - sd.omega.begin();
             L[i * ld + (j - i + w)] = plan.val[e];
         }
+        L[i * ld + w] -= shift * out;
     }
     // row-oriented (Cholesky-Banachiewicz) band factorisation, in place
     for (int64_t i = 0; i < n; ++i) {

@@ -69,6 +69,13 @@ std::vector<int32_t> external_set(const Plan& plan, const Subdomain& sd);
 // volume[p*P + q] = |(Omega_p u ext(Omega_p)) n O_q| for q != p, 0 on the diagonal
 void comm_volume(const Plan& plan, int64_t* volume);
 void factor_local(Plan& plan);
+// Robin transmission (ORAS): the local matrix's diagonal is reduced by this
+// factor times the row's coupling to points outside the subdomain (0: Dirichlet)
+inline double robin_shift_factor(const ras_local& l) {
+    return l.transmission == RAS_TRANSMISSION_ROBIN ? 1.0 - l.robin_q : 0.0;
+}
+// float64 banded Cholesky factor of one subdomain's local matrix on the host (sd.L)
+void factor_one(const Plan& plan, Subdomain& sd, int32_t p);
 void sparse_factor_local(Plan& plan);
 uint16_t f64_to_f16_rne(double d);
 

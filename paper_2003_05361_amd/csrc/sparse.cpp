@@ -37,12 +37,16 @@ LocalGraph local_graph(const Plan& plan, const Subdomain& sd) {
     G.n = static_cast<int32_t>(sd.omega.size());
     G.ptr.assign(G.n + 1, 0);
     G.diag.assign(G.n, 0.0);
+    const double shift = robin_shift_factor(plan.local);  // Robin transmission (ORAS)
     for (int32_t i = 0; i < G.n; ++i) {
         const int32_t g = sd.omega[i];
         for (int64_t e = plan.row_ptr[g]; e < plan.row_ptr[g + 1]; ++e) {
             const int32_t c = plan.col[e];
             auto it = std::lower_bound(sd.omega.begin(), sd.omega.end(), c);
-            if (it == sd.omega.end() || *it != c) continue;
+            if (it == sd.omega.end() || *it != c) {
+                G.diag[i] -= shift * std::fabs(plan.val[e]);
+                continue;
+            }
             const int32_t j = static_cast<int32_t>(it - sd.omega.begin());
             if (j == i) {
                 G.diag[i] += plan.val[e];

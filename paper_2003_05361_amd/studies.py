@@ -89,8 +89,16 @@ def run_case(A, b, spec: dict, gamma: int, loc: dict, tol: float, max_seconds: f
                 "local_solves_min": int(counts.min()), "local_solves_median": float(np.median(counts)),
                 "local_solves_max": int(counts.max())}
 
+    def shares():
+        # measured device time per phase, summed over subdomains (Figs. 3a, 4a, 7a)
+        ph = h.phase_seconds().sum(axis=0)
+        tot = float(ph.sum())
+        return {k: float(v) / tot if tot > 0 else 0.0 for k, v in zip(h.PHASES, ph)}, tot
+
     s_info, s_sec, _ = timed("sync")
+    s_share, s_phase_total = shares()
     a_info, a_sec, a_counts = timed("async")  # the library's pace for this local solver
+    a_share, _ = shares()
     f_info, f_sec, f_counts = timed("async", 0.0)  # free running: reads never wait
     h.close()
 
@@ -112,6 +120,9 @@ def run_case(A, b, spec: dict, gamma: int, loc: dict, tol: float, max_seconds: f
         "async_free": async_result(f_info, f_sec, f_counts),
         "async_speedup": s_sec / a_sec if a_sec > 0 else None,
         "async_free_speedup": s_sec / f_sec if f_sec > 0 else None,
+        "measured_share_sync": s_share,
+        "measured_share_async": a_share,
+        "measured_phase_seconds_sync": s_phase_total,
         "model_bytes_per_sweep": {"restrict_residual": float(parts[0]), "local_solve": float(parts[1]),
                                   "prolong": float(parts[2]), "exchange_of_residual": exchange},
         "model_share": {"restrict_residual": float(parts[0]) / sweep_bytes, "local_solve": float(parts[1]) / sweep_bytes,
@@ -225,6 +236,7 @@ def time_to_tolerance(args, stream) -> tuple[list, dict]:
                 if info["converged"]:
                     break
             xh = x.cpu().numpy()
+            relres_dev = h.relative_residual(bt, x)
             sols[(storage, mode_name)] = xh
             if args.save_x:
                 np.save(f"{args.save_x}_{mode_name}_{args.local}_{storage}.npy", xh)
@@ -233,7 +245,8 @@ def time_to_tolerance(args, stream) -> tuple[list, dict]:
                  "mode": mode_name if args.pace is None or mode == "sync" else f"{mode_name} pace {args.pace:g}",
                  "converged": bool(info["converged"]),
                  "seconds": total, "tol": cfg["tol"],
-                 "rel_residual_host": float(np.linalg.norm(b - A.matvec(xh)) / np.linalg.norm(b)),
+                 "rel_residual": relres_dev,
+                 "rel_residual_host_plain": float(np.linalg.norm(b - A.matvec(xh)) / np.linalg.norm(b)),
                  "local_solves_min": int(counts.min()), "local_solves_median": float(np.median(counts)),
                  "local_solves_max": int(counts.max()), "setup_s": setup_s}
             if mode == "sync":
@@ -248,6 +261,65 @@ def time_to_tolerance(args, stream) -> tuple[list, dict]:
             r["rel_diff_vs_fp64"] = float(np.linalg.norm(xs - ref) / np.linalg.norm(ref))
         print(json.dumps(r), flush=True)
     return rows, {}
+
+
+def oras(args, stream) -> tuple[list, dict]:
+    """Optimized RAS (Robin transmission, the paper's future work) against RAS on a
+    named workload with a direct local solver: synchronous sweeps and seconds to the
+    tolerance, and the asynchronous (library pace) seconds, for each Robin weight q
+    (q = 1 is RAS)."""
+    import torch
+
+    import paper_2003_05361_amd as ras
+    import ras_inputs as R
+
+    A, b, cfg = R.config_problem(args.config, args.grid)
+    kind, arg = cfg["partition"][0], cfg["partition"][1:]
+    arg = arg[0] if len(arg) == 1 else tuple(arg)
+    spec = (ras.partition("rcb", arg[0], grid=A.grid, seed=arg[1], jitter=arg[2]) if kind == "rcb"
+            else ras.partition(kind, arg, grid=A.grid))
+    bt = torch.tensor(b, dtype=torch.float64, device="cuda")
+    rows = []
+    for q in args.robin_q:
+        h = ras.setup(A, spec, cfg["overlap"], ras.local(args.local, args.storage, robin_q=None if q >= 1.0 else q),
+                      stream=stream)
+        h.solve(bt, tol=0.0, mode="sync", max_sweeps=2)
+        res = {"study": "oras", "config": args.config, "n": int(A.n), "local": f"{args.local}-{args.storage}",
+               "robin_q": q, "tol": args.tol}
+        for mode in ("sync", "async"):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            x, infos = h.solve(bt, tol=args.tol, mode=mode, max_sweeps=1_000_000, max_seconds=args.max_seconds)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            i = infos[0]
+            c = h.local_solve_counts()
+            res[mode] = {"converged": bool(i["converged"]), "seconds": e0.elapsed_time(e1) * 1e-3,
+                         "sweeps": int(i["sweeps"]), "local_solves_median": float(np.median(c)),
+                         "rel_residual": i["rel_residual"]}
+        h.close()
+        _progress(json.dumps(res))
+        rows.append(res)
+    return rows, {}
+
+
+def markdown_oras(rows: list, cmd: str) -> str:
+    L = [f"# Optimized RAS (Robin transmission) vs RAS: {rows[0]['config']} (n = {rows[0]['n']})", "",
+         "Command (one MI355X):", "", f"    {cmd}", "",
+         "Local matrices A[Omega_p, Omega_p] with the diagonal lowered by (1 - q) times each row's coupling "
+         "to points outside the subdomain (q = 1: RAS). Same kernels; times are HIP events around one solve, "
+         f"setup excluded; local solver {rows[0]['local']}, tolerance {rows[0]['tol']:g}.", "",
+         "| q | sync sweeps | sync s | async s (median local solves) | sweeps vs RAS |", "|---|---|---|---|---|"]
+    base = next((r["sync"]["sweeps"] for r in rows if r["robin_q"] >= 1.0), None)
+    for r in rows:
+        s, a = r["sync"], r["async"]
+        nc = "" if s["converged"] else " (not conv.)"
+        anc = "" if a["converged"] else " not conv."
+        ratio = f"{base / s['sweeps']:.2f}x fewer" if base and s["sweeps"] and s["converged"] else "-"
+        L.append(f"| {r['robin_q']:g} | {s['sweeps']}{nc} | {s['seconds']:.3f} | {a['seconds']:.3f} "
+                 f"({a['local_solves_median']:.0f}{anc}) | {ratio} |")
+    return "\n".join(L) + "\n"
 
 
 def batching(args, stream) -> tuple[list, dict]:
@@ -320,17 +392,17 @@ def markdown_ttt(rows: list, cmd: str) -> str:
          f"    {cmd}", "",
          "x0 = 0; the solve runs in chunks (x carried over, which continues the same iteration) so that "
          "the run reports progress; seconds = the sum of the chunks' HIP-event times on the solve stream, "
-         "setup excluded. Asynchronous: the library's default read pacing. The residual is recomputed on "
-         "the host from the returned x.", "",
+         "setup excluded. The relative residual is the library's compensated float64 recomputation "
+         "from the returned x; the plain float64 host value is beside it.", "",
          "| local | mode | converged | seconds | sweeps (sync) | ms per sweep | local solves min / median / max | "
-         "host rel. residual | rel. difference from FP64 |",
-         "|---|---|---|---|---|---|---|---|---|"]
+         "rel. residual | plain float64 host | rel. difference from FP64 |",
+         "|---|---|---|---|---|---|---|---|---|---|"]
     for r in rows:
         sw = f"{r['sweeps']} | {r['ms_per_sweep']:.3f}" if "ms_per_sweep" in r else "- | -"
         dv = f"{r['rel_diff_vs_fp64']:.2e}" if "rel_diff_vs_fp64" in r else "-"
         L.append(f"| {r['local']} | {r['mode']} | {r['converged']} | {r['seconds']:.1f} | {sw} | "
                  f"{r['local_solves_min']} / {r['local_solves_median']:.0f} / {r['local_solves_max']} | "
-                 f"{r['rel_residual_host']:.3e} | {dv} |")
+                 f"{r['rel_residual']:.3e} | {r['rel_residual_host_plain']:.3e} | {dv} |")
     if len(rows) == 2 and rows[0]["local"] == rows[1]["local"]:
         L += ["", f"Asynchronous speedup over synchronous: {rows[0]['seconds'] / rows[1]['seconds']:.3f}."]
     return "\n".join(L) + "\n"
@@ -341,18 +413,20 @@ def markdown(study: str, rows: list, heat: dict, cmd: str) -> str:
     L += [f"Local solves: {'nested-dissection sparse' if rows and rows[0].get('local', '').startswith('chol_sparse') else 'banded'} "
           "Cholesky, float64; tolerance on the relative residual as given per row. "
           "Times are HIP events around one solve call, setup excluded. Sweep time is the measured "
-          "synchronous time over its sweep count; the shares are the algorithmic byte model of one "
-          "sweep (exchange = 8 bytes per value read from another subdomain's points, a part of the "
-          "residual step).", ""]
+          "synchronous time over its sweep count. The shares are measured: device wall-clock time "
+          "per phase summed over subdomains (residual = restriction and residual, with the read "
+          "snapshot when asynchronous; solve = local solve; prolong = restricted prolongation and "
+          "publication; other = waiting at the sweep barrier and the convergence check when "
+          "synchronous, paced waits and detection when asynchronous).", ""]
     L += ["Async runs twice: with paced reads (the library's choice for the banded solver: a subdomain "
           "waits up to a quarter of its previous update's time for neighbours that are behind) and free "
           "running (reads never wait). Updates = median local solves per subdomain.", ""]
     L += ["| grid | P | scheme | overlap | max band | factor entries | comm values | max nbrs | sync sweeps | "
           "sync s | ms/sweep | async s (updates) | free async s (updates) | async speedup | free speedup | "
-          "sync speedup vs 1-D | residual / solve / prolong / exchange |",
-          "|---" * 17 + "|"]
+          "sync speedup vs 1-D | sync: residual / solve / prolong / other | async: residual / solve / prolong / other |",
+          "|---" * 18 + "|"]
     for r in rows:
-        sh = r["model_share"]
+        ss, sa = r["measured_share_sync"], r["measured_share_async"]
         conv = "" if r["sync"]["converged"] else " (not conv.)"
         def amode(a):
             c = "" if a["converged"] else " not conv."
@@ -364,8 +438,8 @@ def markdown(study: str, rows: list, heat: dict, cmd: str) -> str:
                  f"{r['sync']['sweeps']}{conv} | {r['sync']['seconds']:.4f} | {r['sync']['ms_per_sweep']:.3f} | "
                  f"{amode(r['async'])} | {amode(r['async_free'])} | {r['async_speedup']:.2f} | "
                  f"{r['async_free_speedup']:.2f} | {vs1d} | "
-                 f"{sh['restrict_residual']:.2f} / {sh['local_solve']:.2f} / {sh['prolong']:.2f} / "
-                 f"{sh['exchange']:.3f} |")
+                 f"{ss['residual']:.2f} / {ss['local_solve']:.2f} / {ss['prolong']:.2f} / {ss['other']:.2f} | "
+                 f"{sa['residual']:.2f} / {sa['local_solve']:.2f} / {sa['prolong']:.2f} / {sa['other']:.2f} |")
     for name, vol in heat.items():
         L += ["", f"Communication volume, {name} (row p receives from column q; values per local solve):", ""]
         L += _fmt_matrix(vol)
@@ -378,7 +452,9 @@ def _ints(s: str) -> list:
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("study", choices=("partitioners", "overlap", "time_to_tolerance", "batching"))
+    ap.add_argument("study", choices=("partitioners", "overlap", "time_to_tolerance", "batching", "oras"))
+    ap.add_argument("--robin-q", type=lambda v: [float(t) for t in v.split(",") if t],
+                    default=[1.0, 0.7, 0.5, 0.3, 0.2, 0.1], help="oras: Robin weights (1 = RAS)")
     ap.add_argument("--systems", type=int, default=64, help="batching: number of systems")
     ap.add_argument("--config", default="diffusion2d_2048_16x16", help="time_to_tolerance: ras_inputs workload")
     ap.add_argument("--storage", default="fp64")
@@ -412,7 +488,7 @@ def main(argv=None):
         raise SystemExit("the studies run the device solver: no GPU visible")
     stream = torch.cuda.current_stream()
     run = {"partitioners": partitioners, "overlap": overlaps, "time_to_tolerance": time_to_tolerance,
-           "batching": batching}[args.study]
+           "batching": batching, "oras": oras}[args.study]
     rows, heat = run(args, stream)
     if args.markdown:
         cmd = "python -m paper_2003_05361_amd.studies " + " ".join(sys.argv[1:] if argv is None else argv)
@@ -421,6 +497,8 @@ def main(argv=None):
                 f.write(markdown_ttt(rows, cmd))
             elif args.study == "batching":
                 f.write(markdown_batching(rows, cmd))
+            elif args.study == "oras":
+                f.write(markdown_oras(rows, cmd))
             else:
                 f.write(markdown(args.study, rows, heat, cmd))
     return rows

@@ -468,6 +468,33 @@ def test_batch_equals_alone(kind):
         assert _rel(yy, schwarz.direct_solve(A, b)) <= 1e-6
 
 
+# ----------------------------------------------------------------------------- optimized Schwarz
+@pytest.mark.parametrize("kind,storage,tol", [("chol", "fp64", 1e-9), ("chol_sparse", "fp64", 1e-9),
+                                              ("chol", "fp32", 2e-5)])
+def test_oras_matches_oracle(kind, storage, tol):
+    """Robin transmission (optimized RAS): the same kernels on the modified local
+    matrices reproduce the oracle's ORAS iterates, and converge in fewer sweeps than RAS."""
+    ras = _ras()
+    _say(f"case: oras {kind} {storage}")
+    A = R.laplace2d(64)
+    b = R.uniform_rhs(A.n, 1)
+    part = ("regular_1d", 4)
+    orc = schwarz.RAS(A, _owner(A, *part), 2, "chol", storage, robin_q=0.3)
+    h = ras.setup(A, _spec(ras, A, *part), 2, ras.local(kind, storage, robin_q=0.3))
+    for sweeps in (1, 3):
+        xo, ho, _ = orc.sync(b, 0.0, sweeps)
+        x, _ = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=sweeps)
+        _agree(x.cpu().numpy(), xo, tol)
+    _, _, ko = orc.sync(b, 1e-8, 5000)
+    x, info = h.solve(_cuda(b), tol=1e-8, mode="sync", max_sweeps=5000)
+    assert info[0]["converged"] and abs(info[0]["sweeps"] - ko) <= (0 if storage == "fp64" else 1)
+    hr = ras.setup(A, _spec(ras, A, *part), 2, ras.local(kind, storage))
+    _, ir = hr.solve(_cuda(b), tol=1e-8, mode="sync", max_sweeps=5000)
+    assert info[0]["sweeps"] < ir[0]["sweeps"]
+    xa, ia = h.solve(_cuda(b), tol=1e-8, mode="async", max_sweeps=100000, max_seconds=30)
+    assert ia[0]["converged"] and schwarz.relative_residual(A, xa.cpu().numpy(), b) < 1e-8
+
+
 # ----------------------------------------------------------------------------- warnings and errors
 @pytest.mark.parametrize("loc,k", [("chol", 0), ("cg", 6)])
 def test_not_converged_returns_valid_iterate(loc, k):

@@ -75,3 +75,28 @@ def test_partitioner_study_small():
     # strips have at most two neighbours (Sec. 3.2.1)
     assert rows[0]["comm"]["max_neighbours"] <= 2
     assert rows[0]["sync_speedup_vs_1d"] == 1.0
+
+
+@pytest.mark.parametrize("loc,k", [("chol", 0), ("cg", 8)])
+def test_phase_breakdown_accounts_for_the_kernel_time(loc, k):
+    """The measured per-phase times (residual, local solve, prolongation, other) of
+    each subdomain's workgroup add up to its share of the kernel time."""
+    import torch
+
+    import paper_2003_05361_amd as ras
+
+    _say(f"case: phase breakdown {loc}")
+    A = R.laplace2d(96)
+    b = torch.tensor(R.uniform_rhs(A.n, 3), dtype=torch.float64, device="cuda")
+    h = ras.setup(A, ras.partition("regular_2d", (4, 4), grid=A.grid), 3, ras.local(loc, "fp64", k))
+    _, info = h.solve(b, tol=0.0, mode="sync", max_sweeps=200, team=1 if loc == "cg" else 0)
+    ph = h.phase_seconds()
+    ks = info[0]["kernel_seconds"]
+    assert ph.shape == (16, 4) and np.all(ph >= 0)
+    per_wg = ph.sum(axis=1)  # one subdomain per workgroup here
+    assert np.all(per_wg <= 1.02 * ks) and np.all(per_wg >= 0.7 * ks), (per_wg, ks)
+    assert np.all(ph[:, 1] > 0) and np.all(ph[:, 0] > 0)
+    _, info = h.solve(b, tol=1e-8, mode="async", max_sweeps=100000, max_seconds=30, team=1 if loc == "cg" else 0)
+    ph = h.phase_seconds()
+    assert np.all(ph >= 0) and np.all(ph.sum(axis=1) <= 1.02 * info[0]["kernel_seconds"])
+    h.close()

@@ -410,3 +410,37 @@ def test_async_stop_rule():
     assert ras.final_status("limit") == 1
     assert ras.final_status("diverged") == -7
     assert ras.final_status("resume") == -6
+
+
+# ----------------------------------------------------------------------------- Robin transmission (ORAS)
+def test_oras_argument_errors():
+    _lib_or_skip()
+    A = R.laplace2d(16)
+    for loc in (ras.local("cg", "fp64", 4, robin_q=0.5), ras.local("chol", "fp64", robin_q=0.0),
+                ras.local("chol", "fp64", robin_q=1.5), ras.local("chol_sparse", "fp64", robin_q=-1.0)):
+        with pytest.raises(ras.RasError) as e:
+            ras.Plan(A, ras.partition("regular_1d", 2), 1, loc)
+        assert e.value.status == -1
+
+
+def test_oras_host_factor_is_cholesky_of_robin_local_matrix():
+    """The library's host factor of an ORAS plan is the Cholesky factor of the oracle's
+    Robin local matrix (A[omega, omega] with the diagonal lowered by (1 - q) e)."""
+    _lib_or_skip()
+    g = R.gaussian_random_field_2d(40, 6.0, 21)
+    A = R.tpfa2d(np.exp(2 * g), 10.0)
+    owner = opart.regular_grid(A.grid, (2, 2))
+    plan = ras.Plan(A, ras.partition("regular_2d", (2, 2), grid=A.grid), 3, ras.local("chol", "fp64", robin_q=0.4))
+    for p, (_, om, _) in enumerate(oover.subdomain_sets(A, owner, 3)):
+        band, w = plan.factor(p)
+        Ap = olocal.robin_local_matrix(A, om, 0.4).toarray()
+        Lref = np.linalg.cholesky(Ap)
+        n = om.size
+        L = np.zeros((n, n))
+        for i in range(n):
+            for o in range(w + 1):
+                j = i - w + o
+                if j >= 0:
+                    L[i, j] = band[i, o]
+        assert np.max(np.abs(L - Lref)) <= 1e-12 * np.abs(Lref).max()
+    plan.close()

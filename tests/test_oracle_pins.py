@@ -485,6 +485,68 @@ def test_relative_residual_of_an_exact_solution():
     assert schwarz.relative_residual(A, x, b) == 0.0
 
 
+# ----------------------------------------------------------------- optimized Schwarz (Robin transmission)
+def test_robin_with_q_one_is_ras():
+    A = R.laplace2d(30)
+    b = R.uniform_rhs(A.n, 44)
+    owner = partition.regular_grid(A.grid, (2, 3))
+    x1, h1, _ = schwarz.RAS(A, owner, 2, "chol").sync(b, 0.0, 5)
+    x2, h2, _ = schwarz.RAS(A, owner, 2, "chol", robin_q=1.0).sync(b, 0.0, 5)
+    assert np.array_equal(x1, x2) and np.array_equal(h1, h2)
+
+
+def test_robin_local_matrix_by_hand():
+    """5-point 2-D Laplacian, 4 x 4 grid, two 1-D strips, no overlap: the first strip's
+    rows 4..7 each couple to one point outside (|a| = 1), so their diagonal 4 becomes
+    4 - (1 - q); rows 0..3 keep 4; off-diagonals are unchanged."""
+    A = R.laplace2d(4)
+    om = np.arange(8)
+    q = 0.25
+    Ap = local.robin_local_matrix(A, om, q).toarray()
+    ref = A.scipy().toarray()[:8, :8].copy()
+    ref[np.arange(4, 8), np.arange(4, 8)] = 4.0 - 0.75
+    assert np.array_equal(Ap, ref)
+    assert np.array_equal(local.outside_coupling(A, om), np.array([0, 0, 0, 0, 1, 1, 1, 1.0]))
+
+
+@pytest.mark.parametrize("gamma", [1, 3])
+def test_optimal_robin_two_subdomains_exact_after_two_sweeps(gamma):
+    """With transparent transmission (the exact Schur complement of the outside part,
+    which for a tridiagonal matrix only changes the boundary row's diagonal), two
+    overlapping subdomains of a 1-D problem give the exact solution after two sweeps
+    (the optimal Schwarz method, Gander 2006).  The oracle's Robin form lowers the
+    diagonal by (1 - q) e_i; here q is chosen per subdomain so that the lowered
+    diagonal equals the Schur complement's."""
+    n = 40
+    A = R.laplace2d(n, 1)  # tridiag(-1, 4, -1)
+    M = A.scipy().toarray()
+    owner = partition.regular_1d(n, 2)
+    b = R.uniform_rhs(n, 45)
+    orc = schwarz.RAS(A, owner, gamma, "chol")
+    for sd in orc.subs:
+        out = np.setdiff1d(np.arange(n), sd.omega)
+        schur = M[np.ix_(sd.omega, out)] @ np.linalg.solve(M[np.ix_(out, out)], M[np.ix_(out, sd.omega)])
+        e = local.outside_coupling(A, sd.omega)
+        i = int(np.flatnonzero(e)[0])  # the one boundary row
+        q = 1.0 - schur[i, i] / e[i]
+        Ap = local.robin_local_matrix(A, sd.omega, q)
+        assert np.allclose(Ap.toarray(), M[np.ix_(sd.omega, sd.omega)] - schur, atol=1e-15)
+        sd.solver = local.LocalSolver(Ap, "chol")
+    _, hist, _ = orc.sync(b, 0.0, 3)
+    assert hist[1] > 1e-4 and hist[2] < 1e-14 and hist[3] < 1e-14
+
+
+def test_robin_reduces_sweeps_on_strips():
+    A = R.laplace2d(64)
+    b = R.uniform_rhs(A.n, 1)
+    owner = partition.regular_1d(A.n, 4)
+    k_ras = schwarz.RAS(A, owner, 2, "chol").sync(b, 1e-8, 3000)[2]
+    k_oras = schwarz.RAS(A, owner, 2, "chol", robin_q=0.1).sync(b, 1e-8, 3000)[2]
+    assert k_ras == 113 and k_oras < k_ras / 3
+    x = schwarz.RAS(A, owner, 2, "chol", robin_q=0.1).sync(b, 1e-10, 3000)[0]
+    assert np.linalg.norm(x - schwarz.direct_solve(A, b)) <= 1e-8 * np.linalg.norm(x)
+
+
 # ----------------------------------------------------------------- P10: ordered / asynchronous
 def test_ordered_zero_overlap_is_block_gauss_seidel():
     A = R.laplace2d(12)
