@@ -303,8 +303,8 @@ def fixed_sweep_leg(h, bt, bps, N, reps, warmup, label_workload, kind, storage, 
     (streaming model) / kernel time."""
     import numpy as np
 
-    for _ in range(warmup):
-        h.solve(bt, tol=0.0, mode="async", max_sweeps=max(1, N // 10))
+    for _ in range(warmup):  # the same launch as the timed ones (one profile average for all)
+        h.solve(bt, tol=0.0, mode="async", max_sweeps=N)
     t0 = time.perf_counter()
     ar = []
     for _ in range(reps):

@@ -316,6 +316,7 @@ void device_factor(ras_handle& h, const Plan& plan, const std::vector<int>& ps) 
         j.invd = const_cast<void*>(d.invd);
         j.scale = const_cast<float*>(d.scale);
         j.slab = d.slab;
+        j.tri_inv = d.tri_inv;
         j.robin_shift = robin_shift_factor(plan.local);
     }
     jobs_d.alloc(jobs.size() * sizeof(FactorJob));
@@ -330,6 +331,45 @@ void device_factor(ras_handle& h, const Plan& plan, const std::vector<int>& ps) 
         if (fail[k] >= 0)
             throw Error{RAS_E_NOT_SPD, "non-positive pivot in subdomain " + std::to_string(ps[k]) + " at local row " +
                                            std::to_string(fail[k])};
+}
+
+// Host form of the device's block inverses: the strictly lower part of the
+// inverse of each 32-row block's diagonal triangle of L (rev: of its reversed
+// transpose), float64 (FP32: from the float32-rounded triangle), written to the
+// block's triangle slots of the slab layout.
+void store_block_inverses(const double* L, int64_t n, int w, int st, bool rev, unsigned char* dst) {
+    constexpr int BR = kBandRows;
+    const int64_t ld = w + 1;
+    double T[BR][BR], G[BR][BR];
+    for (int64_t t0 = 0, blk = 0; t0 < n; t0 += BR, ++blk) {
+        for (int r = 0; r < BR; ++r)
+            for (int c = 0; c < BR; ++c) {
+                double v = r == c ? 1.0 : 0.0;
+                if (c <= r && t0 + r < n) {
+                    const int64_t i = rev ? n - 1 - t0 - c : t0 + r;
+                    v = L[i * ld + (c - r + w)];
+                    if (st == RAS_STORAGE_FP32) v = static_cast<double>(static_cast<float>(v));
+                }
+                T[r][c] = v;
+            }
+        for (int m = 0; m < BR; ++m)
+            for (int r = 0; r < BR; ++r) {
+                if (r < m) {
+                    G[r][m] = 0.0;
+                    continue;
+                }
+                double s = r == m ? 1.0 : 0.0;
+                for (int k = m; k < r; ++k) s -= T[r][k] * G[k][m];
+                G[r][m] = s / T[r][r];
+            }
+        for (int r = 0; r < BR; ++r)
+            for (int c = 0; c < r; ++c) {
+                if (t0 + r >= n) continue;
+                const int64_t di = (blk * w + (w - r + c)) * BR + r;
+                if (st == RAS_STORAGE_FP64) reinterpret_cast<double*>(dst)[di] = G[r][c];
+                else reinterpret_cast<float*>(dst)[di] = static_cast<float>(G[r][c]);
+            }
+    }
 }
 
 void upload(ras_handle& h, const Plan& plan) {
@@ -504,6 +544,7 @@ void upload(ras_handle& h, const Plan& plan) {
         d.K = K;
         d.w = s.w;
         d.row_off = row_off[p];
+        if (chol) d.tri_inv = tri_inverse_ok(s.w, st) ? 1 : 0;
         if (chol && s.L.empty()) {
             // factored on the device after this loop
             d.slab = s.w <= kSlabMaxW ? 1 : 0;
@@ -559,6 +600,12 @@ void upload(ras_handle& h, const Plan& plan) {
                 }
             }
             d.slab = slab ? 1 : 0;
+            if (d.tri_inv) {
+                // the triangle slots of every block hold the inverse of the block's triangle
+                // (the same layout the device factorisation writes)
+                for (int pass = 0; pass < 2; ++pass)
+                    store_block_inverses(L, n, w, st, pass == 1, pass == 0 ? bf.data() : bb.data());
+            }
             hip_check(hipMemcpy(static_cast<char*>(h.band_f.p) + band_off[p] * sts, bf.data(), elems * sts,
                                 hipMemcpyHostToDevice),
                       "copy band_f");
@@ -1888,6 +1935,31 @@ ras_status ras_handle_factor(const ras_handle* h, int32_t p, double* band, int32
             const double inv = h->storage == RAS_STORAGE_FP64 ? reinterpret_cast<const double*>(iv.data())[t]
                                                                : reinterpret_cast<const float*>(iv.data())[t];
             band[t * ld + d.w] = 1.0 / inv;
+        }
+        if (d.tri_inv) {
+            // the triangle slots hold G = T^-1 per 32-row block (diagonal: the reciprocals
+            // just read); invert back in float64 to report the factor's own triangle
+            constexpr int BR = kBandRows;
+            for (int64_t t0 = 0; t0 < n; t0 += BR) {
+                const int nb = static_cast<int>(std::min<int64_t>(BR, n - t0));
+                double G[BR][BR], T[BR][BR];
+                for (int r = 0; r < nb; ++r)
+                    for (int c = 0; c < nb; ++c)
+                        G[r][c] = c > r ? 0.0 : c == r ? 1.0 / band[(t0 + r) * ld + d.w]
+                                                       : band[(t0 + r) * ld + (c - r + d.w)];
+                for (int m = 0; m < nb; ++m)
+                    for (int r = 0; r < nb; ++r) {
+                        if (r < m) {
+                            T[r][m] = 0.0;
+                            continue;
+                        }
+                        double s = r == m ? 1.0 : 0.0;
+                        for (int k = m; k < r; ++k) s -= G[r][k] * T[k][m];
+                        T[r][m] = s / G[r][r];
+                    }
+                for (int r = 0; r < nb; ++r)
+                    for (int c = 0; c < r; ++c) band[(t0 + r) * ld + (c - r + d.w)] = T[r][c];
+            }
         }
         return RAS_OK;
     });

@@ -843,8 +843,10 @@ struct SlabPass {
     RAS_LDS CT* rowd;
     RAS_LDS CT* part;
     RAS_LDS CT* yout;
+    RAS_LDS CT* bcast;  // [BR] the solver's per-lane values, read back by every lane
     int stage_bytes, n, w, winm, nblk, qlast;
     bool rev;
+    bool tri_inv;  // triangle slots hold the inverse of the block's diagonal triangle
     int lane, wave;
     CT uprev;  // solver wave: the previous block's results (lane r: row r)
 
@@ -1006,23 +1008,81 @@ struct SlabPass {
             g = dinv;
             u = (vin - (fsum + nsum)) * g;
         }
-        CT Ld[BR];
+        {
+            CT Ld[BR];
 #pragma unroll
-        for (int m = 0; m < BR; ++m) Ld[m] = tri[m] * g;
-        // lane m's value is final once steps 0 .. m - 1 are done; entries
-        // with m >= r are zero, so later steps leave it unchanged
+            for (int m = 0; m < BR; ++m) Ld[m] = tri[m] * g;
+            // lane m's value is final once steps 0 .. m - 1 are done; entries
+            // with m >= r are zero, so later steps leave it unchanged
 #pragma unroll
-        for (int m = 0; m < BR - 1; ++m) u -= Ld[m] * lane_value(u, m);
+            for (int m = 0; m < BR - 1; ++m) u -= Ld[m] * lane_value(u, m);
+        }
+        finish_block(j, u, sc);
+    }
+
+    // the block's results: solution window (and its mirrored tail), results for
+    // the store wave, and (FP64) the previous block's values kept in this wave
+    __device__ __forceinline__ void finish_block(int j, CT u, CT sc) {
+        const int t0 = j * BR;
+        const int r = lane;
         const int t = t0 + r;
         CT y = u;
         if constexpr (kHalf)
             if (rev) y = u / sc;
+        (void)sc;
         uprev = t < n ? u : CT(0);
         yout[(j & 1) * BR + r] = y;
         const int slot = t & winm;
         const CT wv = t < n ? u : CT(0);
         win[slot] = wv;
         if (slot < C::KF) win[winm + 1 + slot] = wv;  // mirrored tail
+    }
+
+    // Solver step with the block's triangle stored inverted (FP64 / FP32): y = G c,
+    // G = T^-1 (diagonal 1 / L_rr; strictly lower part in the triangle slots) and
+    // c = v - far - near sums.  Values cross lanes through LDS (one store per lane,
+    // broadcast reads; a wave's LDS accesses complete in order), never through a
+    // dependent readlane chain.  Entries are read when they are needed, so that the
+    // near row, the window and the inverse are not all held in registers at once.
+    __device__ __forceinline__ void solve_block_inv(int j) {
+        if (lane >= BR) return;
+        const int t0 = j * BR;
+        const int r = lane;
+        const RAS_LDS CT* rd = rowd + (j & 1) * 3 * BR + r;
+        const CT vin = rd[0], dinv = rd[BR];
+        const RAS_LDS CT* pb = part + (j & 1) * kSlabParts * BR + r;
+        CT fsum = pb[0];
+#pragma unroll
+        for (int k = 1; k < kSlabParts; ++k) fsum += pb[k * BR];
+        const RAS_LDS CT* ntr = nt + (j & 1) * BR * NTS + r * NTS;
+        const RAS_LDS CT* yp = win + ((t0 - BR) & winm);
+        CT a[4] = {CT(0), CT(0), CT(0), CT(0)};
+#pragma unroll
+        for (int c0 = 0; c0 < BR; c0 += 8) {
+            CT e[8], yb[8];
+#pragma unroll
+            for (int c = 0; c < 8; c += CV) {
+                lds_vec(ntr + c0 + c, e + c);
+                lds_vec(yp + c0 + c, yb + c);
+            }
+#pragma unroll
+            for (int c = 0; c < 8; ++c) a[c & 3] += e[c] * yb[c];
+        }
+        const CT c = vin - (fsum + ((a[0] + a[1]) + (a[2] + a[3])));
+        bcast[r] = c;
+        CT acc[4] = {c * dinv, CT(0), CT(0), CT(0)};
+#pragma unroll
+        for (int m0 = 0; m0 < BR; m0 += 8) {
+            CT g[8], cb[8];
+#pragma unroll
+            for (int m = 0; m < 8; m += CV) {
+                lds_vec(ntr + BR + m0 + m, g + m);
+                lds_vec(bcast + m0 + m, cb + m);
+            }
+#pragma unroll
+            for (int m = 0; m < 8; ++m) acc[m & 3] += g[m] * cb[m];
+        }
+        finish_block(j, (acc[0] + acc[1]) + (acc[2] + acc[3]), CT(1));
     }
 
     __device__ __forceinline__ void store_block(int j) {
@@ -1045,19 +1105,35 @@ struct SlabPass {
         }
         lds_barrier();
         // step j: solver on block j - 1, far work on block j, loads of block
-        // j + D (into the stage block j - 1 used), stores of block j - 2
-        for (int j = 0; j <= nblk + 1; ++j) {
-            if (wave == 0) {
-                if (j >= 1 && j <= nblk) solve_block(j - 1);
-            } else if (far >= 0) {
+        // j + D (into the stage block j - 1 used), stores of block j - 2.  Every
+        // role runs its own copy of the step loop (the same steps, one barrier
+        // each): values a role keeps across steps are then live in its loop only,
+        // not in every wave's, which keeps the register file free of the other
+        // roles' loop invariants.
+        if (wave == 0) {
+            for (int j = 0; j <= nblk + 1; ++j) {
+                if (j >= 1 && j <= nblk) {
+                    if (!kHalf && tri_inv) solve_block_inv(j - 1);
+                    else solve_block(j - 1);
+                }
+                lds_barrier();
+            }
+        } else if (far >= 0) {
+            for (int j = 0; j <= nblk + 1; ++j) {
                 if (j < nblk) far_work(far * 64 + lane, j);
-            } else if (loader) {
+                lds_barrier();
+            }
+        } else if (loader) {
+            for (int j = 0; j <= nblk + 1; ++j) {
                 load_block(lk, j + D);
                 wait_vm<(D - 1) * C::QW>();  // block j + 1 has landed
-            } else {
-                if (j >= 2) store_block(j - 2);
+                lds_barrier();
             }
-            lds_barrier();
+        } else {
+            for (int j = 0; j <= nblk + 1; ++j) {
+                if (j >= 2) store_block(j - 2);
+                lds_barrier();
+            }
         }
         if (loader || wave == 7) wait_vm<0>();
         __syncthreads();
@@ -1071,7 +1147,7 @@ __device__ __attribute__((noinline)) void slab_run(RAS_GLOBAL const unsigned cha
                                                    RAS_GLOBAL typename StorageTraits<ST>::CT* invd,
                                                    RAS_GLOBAL float* scale, RAS_GLOBAL typename StorageTraits<ST>::CT* v,
                                                    RAS_LDS unsigned char* lds, int stage_bytes, int n, int w, int winm,
-                                                   bool rev) {
+                                                   bool rev, bool tri_inv) {
     using C = SlabCfg<ST>;
     using CT = typename C::CT;
     SlabPass<ST> ps;
@@ -1085,6 +1161,7 @@ __device__ __attribute__((noinline)) void slab_run(RAS_GLOBAL const unsigned cha
     ps.rowd = ps.nt + 2 * C::BR * C::NTS;
     ps.part = ps.rowd + 2 * 3 * C::BR;
     ps.yout = ps.part + 2 * kSlabParts * C::BR;
+    ps.bcast = ps.yout + 2 * C::BR;
     ps.stage_bytes = stage_bytes;
     ps.n = n;
     ps.w = w;
@@ -1092,6 +1169,7 @@ __device__ __attribute__((noinline)) void slab_run(RAS_GLOBAL const unsigned cha
     ps.nblk = (n + C::BR - 1) / C::BR;
     ps.qlast = max((w * C::BR * C::SZ + 1023) / 1024 - 1, 0);  // last 1 KB piece of a block
     ps.rev = rev;
+    ps.tri_inv = tri_inv;
     ps.lane = threadIdx.x & 63;
     ps.wave = uni(static_cast<int>(threadIdx.x >> 6));
     ps.run();
@@ -1099,14 +1177,14 @@ __device__ __attribute__((noinline)) void slab_run(RAS_GLOBAL const unsigned cha
 
 template <class ST>
 __device__ __forceinline__ void slab_solve(const SubU& s, RAS_GLOBAL typename StorageTraits<ST>::CT* v,
-                                           unsigned char* lds, int winm, int stage_bytes) {
+                                           unsigned char* lds, int winm, int stage_bytes, bool tri_inv) {
     using CT = typename StorageTraits<ST>::CT;
     RAS_GLOBAL CT* invd = gptr(static_cast<const CT*>(s.invd));
     RAS_LDS unsigned char* l = (RAS_LDS unsigned char*)(lds);
     slab_run<ST>(gptr(static_cast<const unsigned char*>(s.band_f)), invd, s.scale, v, l, stage_bytes, s.n, s.w, winm,
-                 false);
+                 false, tri_inv);
     slab_run<ST>(gptr(static_cast<const unsigned char*>(s.band_b)), invd, s.scale, v, l, stage_bytes, s.n, s.w, winm,
-                 true);
+                 true, tri_inv);
 }
 
 // One level-scheduled triangular pass over a sparse factor (Sec. 3.3.1's
@@ -1275,6 +1353,7 @@ struct BandUpdate {
         __shared__ CT gsum[kBandRows];
         const SubU s = load_sub(P.subs + item.sub);
         const int slab = uni(P.subs[item.sub].slab);
+        const int tri_inv = uni(P.subs[item.sub].tri_inv);
         const int sparse = uni(P.subs[item.sub].sparse);
         const InstU in = load_inst(P.insts + item.inst);
         const int tid = threadIdx.x;
@@ -1311,7 +1390,7 @@ struct BandUpdate {
             if constexpr (sizeof(ST) != 2)
                 sparse_solve<ST>(P.subs + item.sub, n, v, smem);
         } else if (slab) {
-            slab_solve<ST>(s, v, smem, winm, stage_bytes);
+            slab_solve<ST>(s, v, smem, winm, stage_bytes, tri_inv != 0);
         } else {
             RAS_GLOBAL ST* Lf = gptr(static_cast<const ST*>(s.band_f));
             RAS_GLOBAL ST* Lr = gptr(static_cast<const ST*>(s.band_b));
@@ -1906,6 +1985,63 @@ __global__ void band_layout_kernel(const FactorJob* __restrict__ jobs) {
     }
 }
 
+// FP64 / FP32 slab factors: the triangle slots of every 32-row block (of L for
+// the forward pass, of its reversed transpose for the backward pass) receive the
+// strictly lower part of the inverse G of the block's diagonal triangle T,
+// computed in float64 (FP32: from T rounded to float32, the factor the solves
+// use), so the solver applies the triangle as y = G c.  One workgroup per block,
+// a thread per column of G (forward substitution on the unit vector).
+template <int ST>
+__global__ void __launch_bounds__(64) block_inverse_kernel(const FactorJob* __restrict__ jobs) {
+    const FactorJob jb = jobs[blockIdx.z];
+    if (!jb.tri_inv) return;
+    constexpr int BR = kBandRows;
+    const int n = jb.n, w = jb.w, ld = w + 1;
+    const int nblk = (n + BR - 1) / BR;
+    const bool rev = blockIdx.y == 1;
+    __shared__ double T[BR][BR + 1];
+    __shared__ double G[BR][BR + 1];
+    for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int t0 = blk * BR;
+        for (int e = threadIdx.x; e < BR * BR; e += 64) {
+            const int r = e / BR, c = e - (e / BR) * BR;
+            double v = r == c ? 1.0 : 0.0;  // rows past n: identity
+            if (c <= r && t0 + r < n) {
+                // entry (t0 + r, t0 + c) of L, or of its reversed transpose
+                // (= L[n-1-(t0+c)][n-1-(t0+r)]); both at band offset c - r + w
+                const int64_t i = rev ? static_cast<int64_t>(n - 1 - t0 - c) : static_cast<int64_t>(t0 + r);
+                v = jb.L[i * ld + (c - r + w)];
+                if constexpr (ST == RAS_STORAGE_FP32) v = static_cast<double>(static_cast<float>(v));
+            }
+            T[r][c] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < BR) {
+            const int m = threadIdx.x;
+            for (int r = 0; r < BR; ++r) {
+                if (r < m) {
+                    G[r][m] = 0.0;
+                    continue;
+                }
+                double s = r == m ? 1.0 : 0.0;
+                for (int k = m; k < r; ++k) s -= T[r][k] * G[k][m];
+                G[r][m] = s / T[r][r];
+            }
+        }
+        __syncthreads();
+        void* dst = rev ? jb.band_b : jb.band_f;
+        for (int e = threadIdx.x; e < BR * BR; e += 64) {
+            const int r = e / BR, c = e - (e / BR) * BR;
+            if (c < r && t0 + r < n) {
+                const int64_t di = (static_cast<int64_t>(blk) * w + (w - r + c)) * BR + r;
+                if constexpr (ST == RAS_STORAGE_FP64) static_cast<double*>(dst)[di] = G[r][c];
+                else static_cast<float*>(dst)[di] = static_cast<float>(G[r][c]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 hipError_t launch_band_factor(const FactorJob* jobs, int njobs, int storage, int max_n, hipStream_t st) {
     band_factor_kernel<<<njobs, kFactorThreads, 0, st>>>(jobs);
     hipError_t e = hipGetLastError();
@@ -1920,6 +2056,11 @@ hipError_t launch_band_factor(const FactorJob* jobs, int njobs, int storage, int
     if (storage == RAS_STORAGE_FP64) band_layout_kernel<RAS_STORAGE_FP64><<<lgrid, 256, 0, st>>>(jobs);
     else if (storage == RAS_STORAGE_FP32) band_layout_kernel<RAS_STORAGE_FP32><<<lgrid, 256, 0, st>>>(jobs);
     else band_layout_kernel<RAS_STORAGE_FP16_ROWSCALED><<<lgrid, 256, 0, st>>>(jobs);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 igrid(std::max(1, std::min(256, (max_n + kBandRows - 1) / kBandRows)), 2, njobs);
+    if (storage == RAS_STORAGE_FP64) block_inverse_kernel<RAS_STORAGE_FP64><<<igrid, 64, 0, st>>>(jobs);
+    else if (storage == RAS_STORAGE_FP32) block_inverse_kernel<RAS_STORAGE_FP32><<<igrid, 64, 0, st>>>(jobs);
     return hipGetLastError();
 }
 

@@ -66,9 +66,17 @@ def test_device_factor_storage_cast(storage):
     for p in range(plan.stats()["parts"]):
         Ld, w = h.factor(p)
         if storage == "fp32":
+            # far and near entries are float32(L_ij); the triangle of each 32-row block is
+            # stored inverted (the solver applies it as a product) and read back by
+            # inverting again in float64, so it carries that round trip's rounding
             Lh, _ = plan.factor(p)
             off = Lh[:, :w].astype(np.float32).astype(np.float64)
-            assert np.all(np.abs(Ld[:, :w] - off) <= 2.0 ** -23 * np.abs(off) + 1e-300)
+            r = np.arange(Lh.shape[0])[:, None] % 32
+            tri = np.arange(w)[None, :] >= w - r
+            err = np.abs(Ld[:, :w] - off)
+            assert np.all(err[~tri] <= 2.0 ** -23 * np.abs(off[~tri]) + 1e-300)
+            rowmax = np.abs(Lh).max(axis=1, keepdims=True) * np.ones_like(off)
+            assert np.all(err[tri] <= 1e-5 * rowmax[tri])
         else:
             bits, sc = plan.factor_fp16(p)
             deq = bits.view(np.float16).astype(np.float64) * sc.astype(np.float64)[:, None]
@@ -92,3 +100,26 @@ def test_device_factor_reports_non_spd():
         ras.setup(A, ras.partition("regular_1d", 2), 1, ras.local("chol", "fp64"))
     assert e.value.status == -3
     assert "subdomain 0" in str(e.value) and "local row 7" in str(e.value)
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_host_and_device_layouts_give_the_same_iteration(storage, tol):
+    """A handle set up from a host-factored plan (host layout, host block inverses) and
+    one factored on the device iterate alike."""
+    import torch
+
+    ras = _ras()
+    _say(f"case: host vs device layout {storage}")
+    A = R.tpfa2d(np.exp(2.0 * R.gaussian_random_field_2d(64, 8.0, 4)), 10.0)
+    spec = ras.partition("regular_2d", (2, 2), grid=A.grid)
+    b = torch.tensor(R.uniform_rhs(A.n, 7), dtype=torch.float64, device="cuda")
+    plan = ras.Plan(A, spec, 4, ras.local("chol", storage))
+    hh = plan.setup()
+    hd = ras.setup(A, spec, 4, ras.local("chol", storage))
+    xh, _ = hh.solve(b, tol=0.0, mode="sync", max_sweeps=5)
+    xd, _ = hd.solve(b, tol=0.0, mode="sync", max_sweeps=5)
+    xh, xd = xh.cpu().numpy(), xd.cpu().numpy()
+    assert np.max(np.abs(xh - xd)) <= tol * np.max(np.abs(xh))
+    hh.close()
+    hd.close()
+    plan.close()
