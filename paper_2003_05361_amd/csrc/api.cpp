@@ -118,6 +118,7 @@ struct ras_handle {
     ras_plan_stats stats{};
     DevBuf omega, ell_val, ell_valf, ell_gcol, ell_lcol, band_f, band_b, scale, invd, ext, sp_idx, sp_val;
     DevBuf csr_rp, csr_ci, csr_va, nbr;
+    DevBuf tri_g;  // FP16 slab: packed float32 inverses of the block triangles (both passes)
     std::vector<SubDev> subs;  // host copy with device pointers
     // CG team windows: for team size kTeamSizes[t], per subdomain and member the
     // LDS window [lo, hi) of local rows its rows reference
@@ -317,6 +318,8 @@ void device_factor(ras_handle& h, const Plan& plan, const std::vector<int>& ps) 
         j.scale = const_cast<float*>(d.scale);
         j.slab = d.slab;
         j.tri_inv = d.tri_inv;
+        j.tri_g[0] = const_cast<float*>(d.tri_g[0]);
+        j.tri_g[1] = const_cast<float*>(d.tri_g[1]);
         j.robin_shift = robin_shift_factor(plan.local);
     }
     jobs_d.alloc(jobs.size() * sizeof(FactorJob));
@@ -337,7 +340,8 @@ void device_factor(ras_handle& h, const Plan& plan, const std::vector<int>& ps) 
 // inverse of each 32-row block's diagonal triangle of L (rev: of its reversed
 // transpose), float64 (FP32: from the float32-rounded triangle), written to the
 // block's triangle slots of the slab layout.
-void store_block_inverses(const double* L, int64_t n, int w, int st, bool rev, unsigned char* dst) {
+void store_block_inverses(const double* L, int64_t n, int w, int st, bool rev, unsigned char* dst,
+                          const uint16_t* Lh = nullptr, const float* scale = nullptr, float* gdst = nullptr) {
     constexpr int BR = kBandRows;
     const int64_t ld = w + 1;
     double T[BR][BR], G[BR][BR];
@@ -349,6 +353,11 @@ void store_block_inverses(const double* L, int64_t n, int w, int st, bool rev, u
                     const int64_t i = rev ? n - 1 - t0 - c : t0 + r;
                     v = L[i * ld + (c - r + w)];
                     if (st == RAS_STORAGE_FP32) v = static_cast<double>(static_cast<float>(v));
+                    if (st == RAS_STORAGE_FP16_ROWSCALED) {
+                        _Float16 hv;
+                        std::memcpy(&hv, &Lh[i * ld + (c - r + w)], 2);
+                        v = static_cast<double>(static_cast<float>(hv) * scale[i]);
+                    }
                 }
                 T[r][c] = v;
             }
@@ -364,6 +373,10 @@ void store_block_inverses(const double* L, int64_t n, int w, int st, bool rev, u
             }
         for (int r = 0; r < BR; ++r)
             for (int c = 0; c < r; ++c) {
+                if (st == RAS_STORAGE_FP16_ROWSCALED) {
+                    gdst[blk * kTriPackFloats + (r * (r - 1)) / 2 + c] = t0 + r < n ? static_cast<float>(G[r][c]) : 0.0f;
+                    continue;
+                }
                 if (t0 + r >= n) continue;
                 const int64_t di = (blk * w + (w - r + c)) * BR + r;
                 if (st == RAS_STORAGE_FP64) reinterpret_cast<double*>(dst)[di] = G[r][c];
@@ -381,7 +394,7 @@ void upload(ras_handle& h, const Plan& plan) {
     h.solver = plan.local.kind;
     h.storage = st;
     h.cg_iters = plan.local.cg_iters;
-    std::vector<int64_t> row_off(P + 1, 0), ell_off(P + 1, 0), band_off(P + 1, 0);
+    std::vector<int64_t> row_off(P + 1, 0), ell_off(P + 1, 0), band_off(P + 1, 0), trig_off(P + 1, 0);
     int uniformK = -1;
     for (int p = 0; p < P; ++p) {
         const auto& s = plan.subs[p];
@@ -391,6 +404,10 @@ void upload(ras_handle& h, const Plan& plan) {
         // 64-element aligned starts (16-byte aligned blocks for the 16-byte loads)
         band_off[p + 1] = band_off[p] + (chol ? (band_elems(n, s.w) + 63) / 64 * 64 : 0);
         if (chol && s.w <= kSlabMaxW) h.any_slab = true;
+        // FP16 slab subdomains: packed triangle inverses, both passes
+        trig_off[p + 1] = trig_off[p] + (chol && st == RAS_STORAGE_FP16_ROWSCALED && tri_inverse_ok(s.w, st)
+                                             ? 2 * ((n + kBandRows - 1) / kBandRows) * kTriPackFloats
+                                             : 0);
         if (chol && s.w > kSlabMaxW) h.max_w_rowmajor = std::max(h.max_w_rowmajor, s.w);
         h.max_n = std::max<int>(h.max_n, static_cast<int>(n));
         h.max_w = std::max(h.max_w, s.w);
@@ -431,6 +448,7 @@ void upload(ras_handle& h, const Plan& plan) {
         hip_check(hipMemset(h.band_b.p, 0, band_off[P] * sts + kSlabTailBytes), "clear band");
         h.invd.alloc(row_off[P] * cts);
         if (st == RAS_STORAGE_FP16_ROWSCALED) h.scale.alloc(row_off[P] * sizeof(float));
+        if (trig_off[P] > 0) h.tri_g.alloc(trig_off[P] * sizeof(float));
     }
     h.csr_rp.alloc((plan.n + 1) * sizeof(int64_t));
     h.csr_ci.alloc(plan.nnz * sizeof(int32_t));
@@ -545,6 +563,11 @@ void upload(ras_handle& h, const Plan& plan) {
         d.w = s.w;
         d.row_off = row_off[p];
         if (chol) d.tri_inv = tri_inverse_ok(s.w, st) ? 1 : 0;
+        if (trig_off[p + 1] > trig_off[p]) {
+            const int64_t half = (trig_off[p + 1] - trig_off[p]) / 2;
+            d.tri_g[0] = h.tri_g.as<float>() + trig_off[p];
+            d.tri_g[1] = h.tri_g.as<float>() + trig_off[p] + half;
+        }
         if (chol && s.L.empty()) {
             // factored on the device after this loop
             d.slab = s.w <= kSlabMaxW ? 1 : 0;
@@ -601,10 +624,17 @@ void upload(ras_handle& h, const Plan& plan) {
             }
             d.slab = slab ? 1 : 0;
             if (d.tri_inv) {
-                // the triangle slots of every block hold the inverse of the block's triangle
-                // (the same layout the device factorisation writes)
+                // the inverse of every block's triangle: in the triangle slots (FP64 / FP32)
+                // or packed in float32 beside the factor (FP16), as the device factorisation writes it
+                const int64_t half = (trig_off[p + 1] - trig_off[p]) / 2;
+                std::vector<float> gh(2 * half);
                 for (int pass = 0; pass < 2; ++pass)
-                    store_block_inverses(L, n, w, st, pass == 1, pass == 0 ? bf.data() : bb.data());
+                    store_block_inverses(L, n, w, st, pass == 1, pass == 0 ? bf.data() : bb.data(), s.Lh.data(),
+                                         s.scale.data(), gh.data() + pass * half);
+                if (half > 0)
+                    hip_check(hipMemcpy(h.tri_g.as<float>() + trig_off[p], gh.data(), gh.size() * sizeof(float),
+                                        hipMemcpyHostToDevice),
+                              "copy triangle inverses");
             }
             hip_check(hipMemcpy(static_cast<char*>(h.band_f.p) + band_off[p] * sts, bf.data(), elems * sts,
                                 hipMemcpyHostToDevice),
@@ -729,7 +759,7 @@ void upload(ras_handle& h, const Plan& plan) {
     h.stats.device_bytes = static_cast<int64_t>(h.omega.bytes + h.ell_val.bytes + h.ell_valf.bytes + h.ell_gcol.bytes +
                                                 h.ell_lcol.bytes + h.band_f.bytes + h.band_b.bytes + h.invd.bytes +
                                                 h.scale.bytes + h.csr_rp.bytes + h.csr_ci.bytes + h.csr_va.bytes +
-                                                h.ext.bytes + h.sp_idx.bytes + h.sp_val.bytes);
+                                                h.ext.bytes + h.sp_idx.bytes + h.sp_val.bytes + h.tri_g.bytes);
 }
 
 void drop_factors(Plan& plan) {
@@ -1343,6 +1373,8 @@ int64_t estimate_device_bytes(const Plan& plan, int nrhs) {
         const int64_t ell = n_pad_of(n) * sd.ell_width;
         bytes += 8 * n + ell * (8 + 4 + 4 + (!chol && plan.local.storage == RAS_STORAGE_FP32 ? 4 : 0)) + 512;
         if (chol) bytes += 2 * ((band_elems(n, sd.w) + 63) / 64 * 64) * sts + n * cts + (plan.local.storage == 2 ? 4 * n : 0);
+        if (chol && plan.local.storage == RAS_STORAGE_FP16_ROWSCALED && tri_inverse_ok(sd.w, plan.local.storage))
+            bytes += 2 * ((n + kBandRows - 1) / kBandRows) * kTriPackBytes;
         // the float64 band of the device factorisation, held while the system is set up
         if (chol && sd.L.empty()) bytes += 8 * n * (sd.w + 1);
         if (plan.local.kind == RAS_LOCAL_CHOL_SPARSE) {
@@ -1936,7 +1968,7 @@ ras_status ras_handle_factor(const ras_handle* h, int32_t p, double* band, int32
                                                                : reinterpret_cast<const float*>(iv.data())[t];
             band[t * ld + d.w] = 1.0 / inv;
         }
-        if (d.tri_inv) {
+        if (d.tri_inv && h->storage != RAS_STORAGE_FP16_ROWSCALED) {
             // the triangle slots hold G = T^-1 per 32-row block (diagonal: the reciprocals
             // just read); invert back in float64 to report the factor's own triangle
             constexpr int BR = kBandRows;

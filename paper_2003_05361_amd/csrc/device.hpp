@@ -30,14 +30,19 @@ constexpr int kSlabFarWaves = 4;    // waves of the off-diagonal sums
 constexpr int kSlabParts = 2 * kSlabFarWaves;  // far partial sums per row (one per half-wave)
 constexpr int kSlabLead[3] = {2, 3, 4};  // blocks in flight: FP64, FP32, FP16 storage
 constexpr int kSlabWinTail = 16;    // mirrored slots after the solution window
-constexpr int kMaxFactorW = 1024;
+constexpr int kMaxFactorW = 1024;  // widest band the device factorisation takes
 // The slab layout stores, per 32-row block, the strictly lower triangle of the
 // block's diagonal triangle at offsets o >= w - r (row r); its inverse has no
 // more nonzeros only if every such position has a slot, i.e. w >= kBandRows - 1.
-// FP16 storage keeps the factor's own entries (row-scaled quantisation of L).
+// FP64 / FP32 store the inverse in those slots; FP16 keeps the factor's own
+// (row-scaled, quantised) entries there and the inverse of the dequantised
+// triangle, in float32, in a separate packed array (kTriPackBytes per block).
 inline bool tri_inverse_ok(int w, int storage) {
-    return w <= kSlabMaxW && w >= kBandRows - 1 && storage != 2;
-}   // widest band the device factorisation takes
+    (void)storage;
+    return w <= kSlabMaxW && w >= kBandRows - 1;
+}
+constexpr int kTriPackFloats = 512;  // 496 strictly lower entries (row r at r (r - 1) / 2), padded
+constexpr int kTriPackBytes = kTriPackFloats * 4;
 // fixed device workspace of ras_solve_noalloc (per device, held until process exit)
 constexpr size_t kNoAllocScratchBytes = RAS_NOALLOC_SCRATCH_BYTES;
 // row stride (compute-type entries) of the near + triangle buffer: 2 blocks
@@ -54,7 +59,8 @@ inline size_t slab_lds_bytes(int storage_bytes, int compute_bytes, int max_w, in
     const int lead = kSlabLead[storage_bytes == 8 ? 0 : storage_bytes == 4 ? 1 : 2];
     const size_t elems = static_cast<size_t>(win) + kSlabWinTail + 2 * kBandRows * slab_nt_stride(compute_bytes) + 2 * 3 * kBandRows +
                          2 * kSlabParts * kBandRows + 2 * kBandRows + kBandRows;  // ..., results, broadcast
-    return (lead + 1) * (slab_stage_bytes(storage_bytes, max_w) + 512) + elems * compute_bytes;
+    const size_t tri = storage_bytes == 2 ? kTriPackBytes : 0;  // FP16: the block's packed triangle inverse
+    return (lead + 1) * (slab_stage_bytes(storage_bytes, max_w) + tri + 512) + elems * compute_bytes;
 }
 constexpr int kMaxItemsPerWg = 1024;  // work items one workgroup may own
 
@@ -77,14 +83,15 @@ struct SubDev {
     int32_t slab;             // 1: band_f / band_b in the slab layout (w <= kSlabMaxW)
     const int32_t* ext;       // [n_ext] global ids of the columns outside omega that omega's rows read
     int32_t n_ext;
-    int32_t tri_inv;          // slab, FP64/FP32: the triangle slots of each block hold the inverse of
-                              // the block's diagonal triangle (strictly lower part), see tri_inverse_ok
+    int32_t tri_inv;          // slab: the solver applies each block's triangle as its inverse, read from
+                              // the triangle slots (FP64/FP32) or from tri_g (FP16), see tri_inverse_ok
     int64_t snap_off;         // offset of this subdomain's x snapshot (n + n_ext values) per right-hand side
     // sparse Cholesky (local rows in elimination order); pass 0 = L (forward), 1 = L^T (backward).
     // Level l holds the level-order positions [sp_lev[pass][l], sp_lev[pass][l + 1]); position t
     // has sp_meta[pass][4 t .. 4 t + 3] = {row i, first entry, end of entries, 0}.  Row i's entries
     // (sp_col, sp_val) are (i, 1 / L_ii) followed by (j, -L_ij / L_ii), so that the new y_i is
     // the dot product of the entries with the current y.
+    const float* tri_g[2];    // FP16 slab: packed float32 block-triangle inverses of L and of J L^T J
     const int32_t* sp_lev[2];
     const int32_t* sp_meta[2];
     const int32_t* sp_col[2];
@@ -110,6 +117,7 @@ struct FactorJob {
     void* band_b;        // the reversed transpose J L^T J, same layout
     void* invd;          // [n] 1 / L_ii as the solves see it (compute type)
     float* scale;        // [n] FP16 row scales (FP16_ROWSCALED only)
+    float* tri_g[2];     // FP16: packed block-triangle inverses (forward, backward), else null
     int32_t slab;
     int32_t tri_inv;     // store the block triangles inverted (see SubDev)
     double robin_shift;  // Robin transmission: diagonal minus robin_shift * (coupling outside omega)

@@ -733,7 +733,8 @@ struct SlabCfg {
     static constexpr int S = D + 1;                               // LDS stages
     static constexpr int QMAX = (kSlabMaxW * BR * SZ + 1023) / 1024;   // 1 KB pieces of a block
     static constexpr int QH = (QMAX + 1) / 2;                     // pieces per loader wave
-    static constexpr int QW = QH + 1;                             // + one row-data load
+    static constexpr int GB = StorageTraits<ST>::kHalf ? kTriPackBytes : 0;  // FP16: triangle inverse bytes
+    static constexpr int QW = QH + 1 + (GB > 0 ? 1 : 0);          // + one row-data load (+ one inverse piece)
     static constexpr int NTS = slab_nt_stride(static_cast<int>(sizeof(CT)));  // near/triangle row stride
     static constexpr int CV = 16 / static_cast<int>(sizeof(CT));  // compute-type entries per 16 bytes
     static constexpr int KF = (kSlabMaxW - BR + 7) / 8;           // far columns per thread, widest band
@@ -836,6 +837,7 @@ struct SlabPass {
     RAS_GLOBAL const unsigned char* slab;
     RAS_GLOBAL CT* invd;
     RAS_GLOBAL float* scale;
+    RAS_GLOBAL const unsigned char* gtri;  // FP16: packed triangle inverses of this pass (block-major)
     RAS_GLOBAL CT* v;
     RAS_LDS unsigned char* stages;
     RAS_LDS CT* win;
@@ -851,7 +853,7 @@ struct SlabPass {
     CT uprev;  // solver wave: the previous block's results (lane r: row r)
 
     __device__ __forceinline__ RAS_LDS unsigned char* stage(int j) const {
-        return stages + (j % S) * (stage_bytes + kRowBytes);
+        return stages + (j % S) * (stage_bytes + C::GB + kRowBytes);
     }
     __device__ __forceinline__ int row_index(int t) const { return rev ? n - 1 - t : t; }
 
@@ -865,7 +867,15 @@ struct SlabPass {
             const int q = min(2 * i + k, qlast);
             __builtin_amdgcn_global_load_lds(src + q * 1024, (RAS_LDS void*)(st + q * 1024), 16, 0, 0);
         }
-        RAS_LDS unsigned char* rw = st + stage_bytes;
+        if constexpr (C::GB > 0) {
+            // FP16: one 1 KB piece of the block's packed triangle inverse per loader;
+            // subdomains without inverses read the first 2 KB of their own band
+            // (inside the allocation's tail padding) and ignore them
+            const int64_t gofs = tri_inv ? static_cast<int64_t>(jj) * C::GB : 0;
+            __builtin_amdgcn_global_load_lds(gtri + gofs + k * 1024 + lane * 16,
+                                             (RAS_LDS void*)(st + stage_bytes + k * 1024), 16, 0, 0);
+        }
+        RAS_LDS unsigned char* rw = st + stage_bytes + C::GB;
         if constexpr (sizeof(CT) == 8) {
             // two dwords per row: lane l carries half l & 1 of row l >> 1
             const int t = min(jj * BR + (lane >> 1), n - 1);
@@ -924,7 +934,7 @@ struct SlabPass {
         }
         CT rdv[3];
         if (f < BR) {
-            const RAS_LDS unsigned char* rw = st + stage_bytes;
+            const RAS_LDS unsigned char* rw = st + stage_bytes + C::GB;
             if constexpr (sizeof(CT) == 8) {
                 rdv[0] = reinterpret_cast<const RAS_LDS CT*>(rw)[f];
                 rdv[1] = reinterpret_cast<const RAS_LDS CT*>(rw + 256)[f];
@@ -943,12 +953,15 @@ struct SlabPass {
         }
         const CT acc = acc0 + acc1;
         RAS_LDS CT* dst = nt + (j & 1) * BR * NTS + rr * NTS;
+        // FP16 with inverses: the store wave writes the triangle columns (from the
+        // block's float32 inverse), so they are left out here
+        const int cmax = (kHalf && tri_inv) ? BR : 2 * BR;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int o = w - 2 * BR + 1 + d + 8 * k;
             const int c = o - (w - BR) + rr;
             // slots outside the row's near + triangle range go to an unread padding column
-            dst[(c >= 0 && o < w) ? c : 2 * BR] = o >= 0 ? ntv[k] : CT(0);
+            dst[(c >= 0 && c < cmax && o < w) ? c : 2 * BR] = o >= 0 ? ntv[k] : CT(0);
         }
         if (f < BR) {
             RAS_LDS CT* rd = rowd + (j & 1) * 3 * BR + f;
@@ -1017,19 +1030,18 @@ struct SlabPass {
 #pragma unroll
             for (int m = 0; m < BR - 1; ++m) u -= Ld[m] * lane_value(u, m);
         }
-        finish_block(j, u, sc);
-    }
-
-    // the block's results: solution window (and its mirrored tail), results for
-    // the store wave, and (FP64) the previous block's values kept in this wave
-    __device__ __forceinline__ void finish_block(int j, CT u, CT sc) {
-        const int t0 = j * BR;
-        const int r = lane;
-        const int t = t0 + r;
         CT y = u;
         if constexpr (kHalf)
             if (rev) y = u / sc;
-        (void)sc;
+        finish_block(j, y, u);
+    }
+
+    // the block's results y (to the store wave) and the window values u (y, or y
+    // times the row scale in FP16 backward passes), also kept in this wave (FP64)
+    __device__ __forceinline__ void finish_block(int j, CT y, CT u) {
+        const int t0 = j * BR;
+        const int r = lane;
+        const int t = t0 + r;
         uprev = t < n ? u : CT(0);
         yout[(j & 1) * BR + r] = y;
         const int slot = t & winm;
@@ -1049,7 +1061,7 @@ struct SlabPass {
         const int t0 = j * BR;
         const int r = lane;
         const RAS_LDS CT* rd = rowd + (j & 1) * 3 * BR + r;
-        const CT vin = rd[0], dinv = rd[BR];
+        const CT vin = rd[0], dinv = rd[BR], sc = rd[2 * BR];
         const RAS_LDS CT* pb = part + (j & 1) * kSlabParts * BR + r;
         CT fsum = pb[0];
 #pragma unroll
@@ -1057,32 +1069,63 @@ struct SlabPass {
         const RAS_LDS CT* ntr = nt + (j & 1) * BR * NTS + r * NTS;
         const RAS_LDS CT* yp = win + ((t0 - BR) & winm);
         CT a[4] = {CT(0), CT(0), CT(0), CT(0)};
+        // reads in flight together: all at once for 4-byte types, eight at a time for
+        // float64 (whose 32-entry rows would not fit the registers beside the rest)
+        constexpr int CH = sizeof(CT) == 4 ? BR : 8;
 #pragma unroll
-        for (int c0 = 0; c0 < BR; c0 += 8) {
-            CT e[8], yb[8];
+        for (int c0 = 0; c0 < BR; c0 += CH) {
+            CT e[CH], yb[CH];
 #pragma unroll
-            for (int c = 0; c < 8; c += CV) {
+            for (int c = 0; c < CH; c += CV) {
                 lds_vec(ntr + c0 + c, e + c);
                 lds_vec(yp + c0 + c, yb + c);
             }
 #pragma unroll
-            for (int c = 0; c < 8; ++c) a[c & 3] += e[c] * yb[c];
+            for (int c = 0; c < CH; ++c) a[c & 3] += e[c] * yb[c];
         }
-        const CT c = vin - (fsum + ((a[0] + a[1]) + (a[2] + a[3])));
+        // FP16: L's entries are stored divided by their row scale; forward passes
+        // multiply the row's sums by it, backward passes keep it folded into the
+        // solution window (which then holds y times the scale)
+        const CT sums = fsum + ((a[0] + a[1]) + (a[2] + a[3]));
+        const CT c = (kHalf && !rev) ? vin - sc * sums : vin - sums;
         bcast[r] = c;
         CT acc[4] = {c * dinv, CT(0), CT(0), CT(0)};
 #pragma unroll
-        for (int m0 = 0; m0 < BR; m0 += 8) {
-            CT g[8], cb[8];
+        for (int m0 = 0; m0 < BR; m0 += CH) {
+            CT g[CH], cb[CH];
 #pragma unroll
-            for (int m = 0; m < 8; m += CV) {
+            for (int m = 0; m < CH; m += CV) {
                 lds_vec(ntr + BR + m0 + m, g + m);
                 lds_vec(bcast + m0 + m, cb + m);
             }
 #pragma unroll
-            for (int m = 0; m < 8; ++m) acc[m & 3] += g[m] * cb[m];
+            for (int m = 0; m < CH; ++m) acc[m & 3] += g[m] * cb[m];
         }
-        finish_block(j, (acc[0] + acc[1]) + (acc[2] + acc[3]), CT(1));
+        const CT y = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        finish_block(j, y, (kHalf && rev) ? y * sc : y);
+    }
+
+    // FP16 with inverses (store wave): block j's float32 triangle inverse, packed
+    // in its stage (row r at r (r - 1) / 2), into the triangle columns of the
+    // solver's row buffer; the solver reads it at the next step
+    __device__ __forceinline__ void copy_tri(int j) {
+        const RAS_LDS float* gp = reinterpret_cast<const RAS_LDS float*>(stage(j) + stage_bytes);
+        RAS_LDS CT* dst = nt + (j & 1) * BR * NTS + BR;
+        // lane: column m, rows 2 i + (lane >= 32); all reads in flight, then the writes
+        // (no branches: every read index stays inside the packed block, and entries on
+        // or above the diagonal go to the row's unread padding column)
+        const int m = lane & (BR - 1), hi = lane >> 5;
+        CT val[BR / 2];
+#pragma unroll
+        for (int i = 0; i < BR / 2; ++i) {
+            const int r = 2 * i + hi;
+            val[i] = gp[(r * (r - 1)) / 2 + m];
+        }
+#pragma unroll
+        for (int i = 0; i < BR / 2; ++i) {
+            const int r = 2 * i + hi;
+            dst[r * NTS + (m < r ? m : BR)] = val[i];
+        }
     }
 
     __device__ __forceinline__ void store_block(int j) {
@@ -1113,7 +1156,7 @@ struct SlabPass {
         if (wave == 0) {
             for (int j = 0; j <= nblk + 1; ++j) {
                 if (j >= 1 && j <= nblk) {
-                    if (!kHalf && tri_inv) solve_block_inv(j - 1);
+                    if (tri_inv) solve_block_inv(j - 1);
                     else solve_block(j - 1);
                 }
                 lds_barrier();
@@ -1132,6 +1175,8 @@ struct SlabPass {
         } else {
             for (int j = 0; j <= nblk + 1; ++j) {
                 if (j >= 2) store_block(j - 2);
+                if constexpr (kHalf)
+                    if (tri_inv && j < nblk) copy_tri(j);
                 lds_barrier();
             }
         }
@@ -1145,7 +1190,8 @@ struct SlabPass {
 template <class ST>
 __device__ __attribute__((noinline)) void slab_run(RAS_GLOBAL const unsigned char* slab,
                                                    RAS_GLOBAL typename StorageTraits<ST>::CT* invd,
-                                                   RAS_GLOBAL float* scale, RAS_GLOBAL typename StorageTraits<ST>::CT* v,
+                                                   RAS_GLOBAL float* scale, RAS_GLOBAL const unsigned char* gtri,
+                                                   RAS_GLOBAL typename StorageTraits<ST>::CT* v,
                                                    RAS_LDS unsigned char* lds, int stage_bytes, int n, int w, int winm,
                                                    bool rev, bool tri_inv) {
     using C = SlabCfg<ST>;
@@ -1154,9 +1200,10 @@ __device__ __attribute__((noinline)) void slab_run(RAS_GLOBAL const unsigned cha
     ps.slab = slab;
     ps.invd = invd;
     ps.scale = scale;
+    ps.gtri = gtri;
     ps.v = v;
     ps.stages = lds;
-    ps.win = (RAS_LDS CT*)(lds + C::S * (stage_bytes + SlabPass<ST>::kRowBytes));
+    ps.win = (RAS_LDS CT*)(lds + C::S * (stage_bytes + C::GB + SlabPass<ST>::kRowBytes));
     ps.nt = ps.win + (winm + 1 + kSlabWinTail);
     ps.rowd = ps.nt + 2 * C::BR * C::NTS;
     ps.part = ps.rowd + 2 * 3 * C::BR;
@@ -1177,14 +1224,20 @@ __device__ __attribute__((noinline)) void slab_run(RAS_GLOBAL const unsigned cha
 
 template <class ST>
 __device__ __forceinline__ void slab_solve(const SubU& s, RAS_GLOBAL typename StorageTraits<ST>::CT* v,
-                                           unsigned char* lds, int winm, int stage_bytes, bool tri_inv) {
+                                           unsigned char* lds, int winm, int stage_bytes, bool tri_inv,
+                                           const float* gf, const float* gb) {
     using CT = typename StorageTraits<ST>::CT;
     RAS_GLOBAL CT* invd = gptr(static_cast<const CT*>(s.invd));
     RAS_LDS unsigned char* l = (RAS_LDS unsigned char*)(lds);
-    slab_run<ST>(gptr(static_cast<const unsigned char*>(s.band_f)), invd, s.scale, v, l, stage_bytes, s.n, s.w, winm,
-                 false, tri_inv);
-    slab_run<ST>(gptr(static_cast<const unsigned char*>(s.band_b)), invd, s.scale, v, l, stage_bytes, s.n, s.w, winm,
-                 true, tri_inv);
+    // FP16 subdomains without inverses stream a dummy piece from their own band (valid memory)
+    RAS_GLOBAL const unsigned char* g0 =
+        gf ? gptr(reinterpret_cast<const unsigned char*>(gf)) : gptr(static_cast<const unsigned char*>(s.band_f));
+    RAS_GLOBAL const unsigned char* g1 =
+        gb ? gptr(reinterpret_cast<const unsigned char*>(gb)) : gptr(static_cast<const unsigned char*>(s.band_b));
+    slab_run<ST>(gptr(static_cast<const unsigned char*>(s.band_f)), invd, s.scale, g0, v, l, stage_bytes, s.n, s.w,
+                 winm, false, tri_inv);
+    slab_run<ST>(gptr(static_cast<const unsigned char*>(s.band_b)), invd, s.scale, g1, v, l, stage_bytes, s.n, s.w,
+                 winm, true, tri_inv);
 }
 
 // One level-scheduled triangular pass over a sparse factor (Sec. 3.3.1's
@@ -1390,7 +1443,8 @@ struct BandUpdate {
             if constexpr (sizeof(ST) != 2)
                 sparse_solve<ST>(P.subs + item.sub, n, v, smem);
         } else if (slab) {
-            slab_solve<ST>(s, v, smem, winm, stage_bytes, tri_inv != 0);
+            slab_solve<ST>(s, v, smem, winm, stage_bytes, tri_inv != 0, P.subs[item.sub].tri_g[0],
+                           P.subs[item.sub].tri_g[1]);
         } else {
             RAS_GLOBAL ST* Lf = gptr(static_cast<const ST*>(s.band_f));
             RAS_GLOBAL ST* Lr = gptr(static_cast<const ST*>(s.band_b));
@@ -2008,10 +2062,16 @@ __global__ void __launch_bounds__(64) block_inverse_kernel(const FactorJob* __re
             double v = r == c ? 1.0 : 0.0;  // rows past n: identity
             if (c <= r && t0 + r < n) {
                 // entry (t0 + r, t0 + c) of L, or of its reversed transpose
-                // (= L[n-1-(t0+c)][n-1-(t0+r)]); both at band offset c - r + w
+                // (= L[n-1-(t0+c)][n-1-(t0+r)]); both at band offset c - r + w;
+                // as the solves see it (FP32: rounded; FP16: quantised, then dequantised)
                 const int64_t i = rev ? static_cast<int64_t>(n - 1 - t0 - c) : static_cast<int64_t>(t0 + r);
                 v = jb.L[i * ld + (c - r + w)];
                 if constexpr (ST == RAS_STORAGE_FP32) v = static_cast<double>(static_cast<float>(v));
+                if constexpr (ST == RAS_STORAGE_FP16_ROWSCALED) {
+                    const float s = jb.scale[i];
+                    const uint16_t hb = f64_to_f16_bits(v / static_cast<double>(s));
+                    v = static_cast<double>(static_cast<float>(__builtin_bit_cast(_Float16, hb)) * s);
+                }
             }
             T[r][c] = v;
         }
@@ -2030,9 +2090,14 @@ __global__ void __launch_bounds__(64) block_inverse_kernel(const FactorJob* __re
         }
         __syncthreads();
         void* dst = rev ? jb.band_b : jb.band_f;
+        float* gdst = jb.tri_g[rev ? 1 : 0];
         for (int e = threadIdx.x; e < BR * BR; e += 64) {
             const int r = e / BR, c = e - (e / BR) * BR;
-            if (c < r && t0 + r < n) {
+            if constexpr (ST == RAS_STORAGE_FP16_ROWSCALED) {
+                // packed float32 rows (row r at r (r - 1) / 2), zero past n
+                if (c < r) gdst[static_cast<int64_t>(blk) * kTriPackFloats + (r * (r - 1)) / 2 + c] =
+                    t0 + r < n ? static_cast<float>(G[r][c]) : 0.0f;
+            } else if (c < r && t0 + r < n) {
                 const int64_t di = (static_cast<int64_t>(blk) * w + (w - r + c)) * BR + r;
                 if constexpr (ST == RAS_STORAGE_FP64) static_cast<double*>(dst)[di] = G[r][c];
                 else static_cast<float*>(dst)[di] = static_cast<float>(G[r][c]);
@@ -2061,6 +2126,7 @@ hipError_t launch_band_factor(const FactorJob* jobs, int njobs, int storage, int
     const dim3 igrid(std::max(1, std::min(256, (max_n + kBandRows - 1) / kBandRows)), 2, njobs);
     if (storage == RAS_STORAGE_FP64) block_inverse_kernel<RAS_STORAGE_FP64><<<igrid, 64, 0, st>>>(jobs);
     else if (storage == RAS_STORAGE_FP32) block_inverse_kernel<RAS_STORAGE_FP32><<<igrid, 64, 0, st>>>(jobs);
+    else block_inverse_kernel<RAS_STORAGE_FP16_ROWSCALED><<<igrid, 64, 0, st>>>(jobs);
     return hipGetLastError();
 }
 
