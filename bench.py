@@ -135,9 +135,10 @@ def cpu_baseline(A, b, part_kind, part_arg, gamma, kind, storage, k, gpu_sync_sw
         orc = schwarz.RAS(A, owner, gamma, "chol" if kind == "chol_sparse" else kind, storage, k)
         for label, nw in (("single_core", 1), ("all_cores", workers)):
             pool = cf.ThreadPoolExecutor(nw) if nw > 1 else None
+            # calibrate on two sweeps (the first one of a pool also starts its threads)
             t0 = time.perf_counter()
-            orc.sync(b, 0.0, 1, pool=pool)
-            t1 = time.perf_counter() - t0
+            orc.sync(b, 0.0, 2, pool=pool)
+            t1 = (time.perf_counter() - t0) / 2
             sweeps = max(1, min(int(budget / max(t1, 1e-6)), 2000))
             t0 = time.perf_counter()
             orc.sync(b, 0.0, sweeps, pool=pool)
