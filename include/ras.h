@@ -220,6 +220,23 @@ ras_status ras_plan_factor_fp16(const ras_plan* plan, int32_t p, uint16_t* half_
  * be NULL (query).  */
 ras_status ras_plan_sparse_factor(const ras_plan* plan, int32_t p, int32_t* perm, int64_t* row_ptr, int32_t* col,
                                   double* val, double* diag, int64_t* nnz);
+/* Solve schedule of subdomain p's sparse factor for one pass (0: forward with
+ * L, 1: backward with L^T), as the device applies it (CHOL_SPARSE plans;
+ * RAS_E_STATE otherwise).  Level scheduling of the triangular solves (Sec.
+ * 3.3.1), with every dense diagonal block of at least *min_block rows (0:
+ * none) solved in two steps by the partitioned-inverse form: its rows first
+ * subtract their products with rows outside the block, then take their dot
+ * products with the explicit inverse of the block's triangle.  Value slots 0..n-1
+ * are the local vector in elimination order (ras_plan_sparse_factor's perm),
+ * slots n..n+*slots-1 hold block partial results between the two steps.  The
+ * records of step s are step_ptr[s] .. step_ptr[s+1]-1; record r writes slot
+ * meta[4r] with the sum over entries e in [meta[4r+1], meta[4r+2]) of
+ * val[e] * slot[col[e]] (meta[4r+3] = 0), reading only slots written in earlier
+ * steps (or the vector's initial values).  Every pointer may be NULL (query
+ * the counts first): *nsteps, *nrec records, *nent entries.  */
+ras_status ras_plan_sparse_schedule(const ras_plan* plan, int32_t p, int32_t pass, int32_t* nsteps, int64_t* nrec,
+                                    int64_t* nent, int32_t* slots, int32_t* min_block, int32_t* step_ptr,
+                                    int32_t* meta, int32_t* col, double* val);
 /* Largest subdomain (local rows) the sparse Cholesky solver accepts for a
  * storage kind (FP64 or FP32), or 0 for a storage it does not support.  */
 int64_t ras_sparse_max_rows(int32_t storage);

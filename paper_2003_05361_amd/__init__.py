@@ -92,6 +92,9 @@ SIGNATURES = {
     "ras_plan_factor": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int32)]),
     "ras_plan_factor_fp16": (C.c_int, [_P, C.c_int32, _P, _P]),
     "ras_plan_sparse_factor": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P, _P]),
+    "ras_plan_sparse_schedule": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                           C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P, _P,
+                                           _P, _P]),
     "ras_sparse_max_rows": (C.c_int64, [C.c_int32]),
     "ras_plan_destroy": (None, [_P]),
     "ras_setup": (C.c_int, [C.POINTER(CSRStruct), C.POINTER(PartitionStruct), C.c_int32, C.POINTER(LocalStruct),
@@ -286,6 +289,22 @@ class Plan:
         _check(lib().ras_plan_sparse_factor(self._p, p, perm.ctypes.data, rp.ctypes.data, col.ctypes.data,
                                             val.ctypes.data, diag.ctypes.data, C.byref(nnz)))
         return perm, rp, col, val, diag
+
+    def sparse_schedule(self, p: int, pass_: int) -> dict:
+        """Solve schedule of subdomain p's sparse factor for one pass (0: L, 1: L^T):
+        step_ptr, meta (records x 4: slot written, first entry, end, 0), col, val,
+        slots (block slots beyond n) and min_block."""
+        ns, nr, ne = C.c_int32(), C.c_int64(), C.c_int64()
+        sl, mb = C.c_int32(), C.c_int32()
+        _check(lib().ras_plan_sparse_schedule(self._p, p, pass_, C.byref(ns), C.byref(nr), C.byref(ne), C.byref(sl),
+                                              C.byref(mb), None, None, None, None))
+        step = np.empty(ns.value + 1, dtype=np.int32)
+        meta = np.empty((nr.value, 4), dtype=np.int32)
+        col = np.empty(ne.value, dtype=np.int32)
+        val = np.empty(ne.value)
+        _check(lib().ras_plan_sparse_schedule(self._p, p, pass_, None, None, None, None, None, step.ctypes.data,
+                                              meta.ctypes.data, col.ctypes.data, val.ctypes.data))
+        return {"step_ptr": step, "meta": meta, "col": col, "val": val, "slots": sl.value, "min_block": mb.value}
 
     def factor_fp16(self, p: int) -> tuple[np.ndarray, np.ndarray]:
         band, w = self.factor(p)

@@ -113,6 +113,7 @@ struct ras_handle {
     int max_w_rowmajor = -1;  // widest band kept row-major (w > kSlabMaxW), -1 if none
     bool any_slab = false;
     bool sparse = false;      // sparse Cholesky solver: device local order = elimination order
+    int64_t max_sparse_values = 0;  // sparse Cholesky: largest vector plus block slots kept in LDS
     int64_t sum_n = 0;
     int64_t sum_snap = 0;  // sum over subdomains of n + n_ext (asynchronous snapshot size per right-hand side)
     ras_plan_stats stats{};
@@ -207,7 +208,7 @@ void build_plan(const ras_csr* A, const ras_partition* part, int32_t overlap, co
                                                    std::to_string(plan.subs[p].omega.size()) +
                                                    " local rows; the sparse solver keeps at most " +
                                                    std::to_string(lim) + " in LDS"};
-        sparse_factor_local(plan);
+        sparse_factor_local(plan, kLdsLimit, local->storage == RAS_STORAGE_FP64 ? sizeof(double) : sizeof(float));
     }
 }
 
@@ -240,51 +241,8 @@ int64_t band_elems(int64_t n, int w) {
 constexpr int64_t kSlabTailBytes = 4096;
 
 // Upload the plan: ELL rows of A on every overlapping set, local column map,
-// factors in the storage type (forward L and reversed transpose), global CSR.
-// Level-scheduled form of one triangular pass of a sparse factor: rows are
-// solved first to last (L, `ascending`) or last to first (L^T); (ptr, idx, x)
-// lists the off-diagonal dependencies (j, L_kj) of each row k, d the diagonal.
-// Stored per level-order position: {row, first entry, end, 0}; entries
-// (k, 1 / d_k) and then (j, -L_kj / d_k), so a row's update is one dot product.
-struct SparsePass {
-    std::vector<int32_t> lev, meta, col;
-    std::vector<double> val;
-};
-
-SparsePass sparse_pass(int32_t n, const std::vector<int64_t>& ptr, const std::vector<int32_t>& idx,
-                       const std::vector<double>& x, const std::vector<double>& d, bool ascending) {
-    std::vector<int32_t> level(n, 0);
-    int32_t nlev = 0;
-    for (int32_t s = 0; s < n; ++s) {
-        const int32_t k = ascending ? s : n - 1 - s;
-        int32_t l = 0;
-        for (int64_t e = ptr[k]; e < ptr[k + 1]; ++e) l = std::max(l, level[idx[e]] + 1);
-        level[k] = l;
-        nlev = std::max(nlev, l + 1);
-    }
-    SparsePass sp;
-    sp.lev.assign(nlev + 1, 0);
-    for (int32_t k = 0; k < n; ++k) ++sp.lev[level[k] + 1];
-    for (int32_t l = 0; l < nlev; ++l) sp.lev[l + 1] += sp.lev[l];
-    std::vector<int32_t> pos(sp.lev.begin(), sp.lev.end() - 1), rows(n);
-    for (int32_t k = 0; k < n; ++k) rows[pos[level[k]]++] = k;
-    sp.meta.assign(4 * static_cast<size_t>(n), 0);
-    for (int32_t t = 0; t < n; ++t) {
-        const int32_t k = rows[t];
-        const double inv = 1.0 / d[k];
-        sp.meta[4 * t] = k;
-        sp.meta[4 * t + 1] = static_cast<int32_t>(sp.col.size());
-        sp.col.push_back(k);
-        sp.val.push_back(inv);
-        for (int64_t e = ptr[k]; e < ptr[k + 1]; ++e) {
-            sp.col.push_back(idx[e]);
-            sp.val.push_back(-x[e] * inv);
-        }
-        sp.meta[4 * t + 2] = static_cast<int32_t>(sp.col.size());
-    }
-    return sp;
-}
-
+// factors in the storage type (forward L and reversed transpose) or the sparse
+// solve schedules, global CSR.
 // Banded Cholesky factors of the listed subdomains computed on the device
 // (float64, in a temporary band buffer), then laid out in the storage type the
 // solves read (band_f, band_b, invd, FP16 scales) by device kernels.
@@ -424,12 +382,15 @@ void upload(ras_handle& h, const Plan& plan) {
         // per subdomain and pass: levels, position records and columns, each padded to
         // 4 int32, and the values padded to 16 bytes
         int64_t ni = 0, nv = 0;
-        for (int p = 0; p < P; ++p) {
-            const int64_t n = static_cast<int64_t>(plan.subs[p].omega.size());
-            const int64_t nnz = static_cast<int64_t>(plan.subs[p].sf.lj.size());
-            ni += 2 * ((n + 2 + 3) / 4 * 4 + 4 * n + (nnz + n + 3) / 4 * 4);
-            nv += 2 * (((nnz + n) * static_cast<int64_t>(sts) + 15) / 16 * 16);
-        }
+        for (int p = 0; p < P; ++p)
+            for (const SparseSchedule& q : plan.subs[p].sched) {
+                const int64_t ne = static_cast<int64_t>(q.col.size());
+                ni += (static_cast<int64_t>(q.step.size()) + 3) / 4 * 4 + static_cast<int64_t>(q.meta.size()) +
+                      (ne + 3) / 4 * 4;
+                nv += (ne * static_cast<int64_t>(sts) + 15) / 16 * 16;
+                h.max_sparse_values = std::max<int64_t>(
+                    h.max_sparse_values, static_cast<int64_t>(plan.subs[p].omega.size()) + q.slots);
+            }
         h.sp_idx.alloc(std::max<int64_t>(ni, 1) * sizeof(int32_t));
         h.sp_val.alloc(std::max<int64_t>(nv, 16));
     }
@@ -657,15 +618,13 @@ void upload(ras_handle& h, const Plan& plan) {
         }
         if (sparse) {
             const SparseFactor& F = s.sf;
-            const SparsePass fw = sparse_pass(static_cast<int32_t>(n), F.lp, F.lj, F.lx, F.d, true);
-            const SparsePass bw = sparse_pass(static_cast<int32_t>(n), F.cp, F.ci, F.cx, F.d, false);
-            const SparsePass* ps[2] = {&fw, &bw};
+            const SparseSchedule* ps[2] = {&s.sched[0], &s.sched[1]};
             std::vector<int32_t> idx;
             std::vector<unsigned char> vals;
             int64_t ioff[2][3], voff[2];
             for (int k = 0; k < 2; ++k) {
-                const SparsePass& q = *ps[k];
-                const std::vector<int32_t>* parts[3] = {&q.lev, &q.meta, &q.col};
+                const SparseSchedule& q = *ps[k];
+                const std::vector<int32_t>* parts[3] = {&q.step, &q.meta, &q.col};
                 for (int a = 0; a < 3; ++a) {
                     ioff[k][a] = sp_idx_used + static_cast<int64_t>(idx.size());
                     idx.insert(idx.end(), parts[a]->begin(), parts[a]->end());
@@ -683,7 +642,7 @@ void upload(ras_handle& h, const Plan& plan) {
                     }
                 }
                 while (vals.size() % 16) vals.push_back(0);
-                d.sp_nlev[k] = static_cast<int32_t>(q.lev.size()) - 1;
+                d.sp_nlev[k] = static_cast<int32_t>(q.step.size()) - 1;
             }
             hip_check(hipMemcpy(h.sp_idx.as<int32_t>() + sp_idx_used, idx.data(), idx.size() * sizeof(int32_t),
                                 hipMemcpyHostToDevice),
@@ -767,6 +726,7 @@ void drop_factors(Plan& plan) {
         std::vector<double>().swap(s.L);
         std::vector<uint16_t>().swap(s.Lh);
         std::vector<float>().swap(s.scale);
+        for (SparseSchedule& q : s.sched) q = SparseSchedule{};
     }
 }
 
@@ -851,7 +811,8 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
             for (ras_handle* h : hs) {
                 wrm = std::max(wrm, h->max_w_rowmajor);
                 if (h->any_slab) wslab = std::max(wslab, std::min(h->max_w, kSlabMaxW));
-                if (h->sparse) wsparse = std::max(wsparse, static_cast<size_t>(h->max_n) * cts);  // y in LDS
+                // y and the dense blocks' slots in LDS
+                if (h->sparse) wsparse = std::max(wsparse, static_cast<size_t>(h->max_sparse_values) * cts);
             }
             const int win = next_pow2(2 * max_w + 2 * kBandRows);
             size_t bytes = 0;
@@ -1378,8 +1339,10 @@ int64_t estimate_device_bytes(const Plan& plan, int nrhs) {
         // the float64 band of the device factorisation, held while the system is set up
         if (chol && sd.L.empty()) bytes += 8 * n * (sd.w + 1);
         if (plan.local.kind == RAS_LOCAL_CHOL_SPARSE) {
-            const int64_t nnz = static_cast<int64_t>(sd.sf.lj.size());
-            bytes += 2 * (4 * (5 * n + 16) + (nnz + n) * (4 + sts) + 32) + n * cts;
+            for (const SparseSchedule& q : sd.sched)
+                bytes += 4 * static_cast<int64_t>(q.step.size() + q.meta.size()) +
+                         static_cast<int64_t>(q.col.size()) * (4 + sts) + 48;
+            bytes += n * cts;
         }
     }
     if (chol) bytes += 2 * kSlabTailBytes;
@@ -1748,6 +1711,30 @@ ras_status ras_plan_sparse_factor(const ras_plan* plan, int32_t p, int32_t* perm
         if (col) std::copy(F.lj.begin(), F.lj.end(), col);
         if (val) std::copy(F.lx.begin(), F.lx.end(), val);
         if (diag) std::copy(F.d.begin(), F.d.end(), diag);
+        return RAS_OK;
+    });
+}
+
+ras_status ras_plan_sparse_schedule(const ras_plan* plan, int32_t p, int32_t pass, int32_t* nsteps, int64_t* nrec,
+                                    int64_t* nent, int32_t* slots, int32_t* min_block, int32_t* step_ptr,
+                                    int32_t* meta, int32_t* col, double* val) {
+    return guarded([&] {
+        if (!plan) throw Error{RAS_E_ARG, "null plan"};
+        if (p < 0 || p >= plan->P) throw Error{RAS_E_ARG, "subdomain out of range"};
+        if (pass != 0 && pass != 1) throw Error{RAS_E_ARG, "pass must be 0 (forward) or 1 (backward)"};
+        if (plan->local.kind != RAS_LOCAL_CHOL_SPARSE) throw Error{RAS_E_STATE, "plan has no sparse factors"};
+        const Subdomain& sd = plan->subs[p];
+        const SparseSchedule& q = sd.sched[pass];
+        if (q.step.empty()) throw Error{RAS_E_STATE, "schedule released"};
+        if (nsteps) *nsteps = static_cast<int32_t>(q.step.size()) - 1;
+        if (nrec) *nrec = static_cast<int64_t>(q.meta.size() / 4);
+        if (nent) *nent = static_cast<int64_t>(q.col.size());
+        if (slots) *slots = q.slots;
+        if (min_block) *min_block = sd.min_block;
+        if (step_ptr) std::copy(q.step.begin(), q.step.end(), step_ptr);
+        if (meta) std::copy(q.meta.begin(), q.meta.end(), meta);
+        if (col) std::copy(q.col.begin(), q.col.end(), col);
+        if (val) std::copy(q.val.begin(), q.val.end(), val);
         return RAS_OK;
     });
 }

@@ -30,6 +30,20 @@ struct SparseFactor {
     std::vector<double> d;       // diagonal of L
 };
 
+// One triangular pass of a sparse factor as a sequence of parallel steps: the
+// records of a step read only values written in earlier steps, and each writes
+// one value, the dot product of its entries with the vector (kept in LDS).
+// Value slots [0, n) are the rows of the local vector in elimination order;
+// slots n.. hold the partial results of dense diagonal blocks between their
+// two steps.
+struct SparseSchedule {
+    std::vector<int32_t> step;   // [nsteps + 1] record ranges of the steps
+    std::vector<int32_t> meta;   // 4 per record: slot written, first entry, end of entries, 0
+    std::vector<int32_t> col;    // slot read by each entry
+    std::vector<double> val;
+    int32_t slots = 0;           // value slots beyond n
+};
+
 struct Subdomain {
     std::vector<int32_t> omega;  // overlapping set, ascending global ids
     std::vector<uint8_t> owned;  // owned[i] != 0 iff omega[i] is owned by this subdomain
@@ -40,6 +54,8 @@ struct Subdomain {
     std::vector<uint16_t> Lh;    // FP16_ROWSCALED: float16 bits of L / scale(row)
     std::vector<float> scale;    // FP16_ROWSCALED: per-row scale
     SparseFactor sf;             // sparse Cholesky solver only
+    SparseSchedule sched[2];     // sparse Cholesky: forward (L) and backward (L^T) passes
+    int32_t min_block = 0;       // sparse Cholesky: smallest dense block solved by its inverse (0: none)
 };
 
 struct Plan {
@@ -76,7 +92,16 @@ inline double robin_shift_factor(const ras_local& l) {
 }
 // float64 banded Cholesky factor of one subdomain's local matrix on the host (sd.L)
 void factor_one(const Plan& plan, Subdomain& sd, int32_t p);
-void sparse_factor_local(Plan& plan);
+// Sparse factors and their solve schedules; lds_bytes bounds each subdomain's
+// vector plus block slots, value_bytes is the size of one value in LDS
+void sparse_factor_local(Plan& plan, size_t lds_bytes, size_t value_bytes);
+// Dense diagonal blocks of a sparse factor: maximal runs [s_i, s_{i+1}) of
+// consecutive rows whose diagonal block of L is a full triangle
+std::vector<int32_t> dense_runs(const SparseFactor& F);
+// Schedule of one pass; blocks of at least min_block rows (0: none) are solved by
+// the explicit inverse of their diagonal triangle
+void sparse_schedule(const SparseFactor& F, const std::vector<int32_t>& runs, int32_t min_block, bool forward,
+                     SparseSchedule* out);
 uint16_t f64_to_f16_rne(double d);
 
 uint64_t splitmix64_next(uint64_t& state);

@@ -74,7 +74,7 @@ public:
     }
 
 private:
-    static constexpr size_t kLeaf = 48;
+    static constexpr size_t kLeaf = 8;
 
     // breadth-first levels from s inside the current subset (member_ == id);
     // returns the vertices in visiting order, level_ holds their depth
@@ -266,8 +266,252 @@ void sparse_factor_one(const Plan& plan, Subdomain& sd, int32_t p) {
     }
 }
 
-void sparse_factor_local(Plan& plan) {
-    parallel_for(plan.P, [&](int64_t p, int) { sparse_factor_one(plan, plan.subs[p], static_cast<int32_t>(p)); });
+// ---------------------------------------------------------------------------
+// Triangular-solve schedules.  A level-scheduled pass takes one parallel step
+// per level of the dependency graph, and a dense diagonal block of s rows
+// (a separator of the dissection, eliminated last among its subtree) is a
+// chain of s levels.  A block of at least min_block rows is solved in two
+// steps instead (the partitioned-inverse form of Alvarado and Schreiber):
+// first every row of the block subtracts its products with rows outside the
+// block (one dot product per row, results into block slots), then every row
+// takes its dot product with the explicit inverse of the block's triangle,
+// computed here in float64 (forward: row k of T^{-1}; backward: column k).
+// Singleton rows keep their one-step form y_k = (v_k - sum_j L_kj y_j) / L_kk.
+
+std::vector<int32_t> dense_runs(const SparseFactor& F) {
+    const int32_t n = static_cast<int32_t>(F.d.size());
+    std::vector<int32_t> starts;
+    int32_t s0 = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        // row k continues the run iff its k - s0 largest columns are s0 .. k-1
+        const int64_t need = k - s0;
+        const bool cont = need > 0 && F.lp[k + 1] - F.lp[k] >= need && F.lj[F.lp[k + 1] - need] == s0;
+        if (!cont) {
+            starts.push_back(k);
+            s0 = k;
+        }
+    }
+    starts.push_back(n);
+    return starts;
+}
+
+namespace {
+
+struct PassShape {
+    int32_t nsteps = 0;
+    int32_t slots = 0;
+};
+
+// Steps of every row (singletons) and block (first step), and the slot
+// capacities; a block's slots are live from its first step to its second, so
+// blocks starting at even and at odd steps use two separate slot ranges.
+PassShape schedule_steps(const SparseFactor& F, const std::vector<int32_t>& runs, int32_t min_block, bool forward,
+                         std::vector<int32_t>& ready, std::vector<int32_t>& block_step) {
+    const int32_t n = static_cast<int32_t>(F.d.size());
+    const int32_t nruns = static_cast<int32_t>(runs.size()) - 1;
+    ready.assign(n, -1);
+    block_step.assign(nruns, -1);
+    std::vector<int64_t> at_step;
+    for (int32_t r = 0; r < nruns; ++r) {
+        const int32_t ri = forward ? r : nruns - 1 - r;
+        const int32_t a = runs[ri], b = runs[ri + 1];
+        const bool block = min_block > 0 && b - a >= min_block;
+        if (!block) {
+            for (int32_t q = 0; q < b - a; ++q) {
+                const int32_t k = forward ? a + q : b - 1 - q;
+                int32_t st = 0;
+                if (forward)
+                    for (int64_t e = F.lp[k]; e < F.lp[k + 1]; ++e) st = std::max(st, ready[F.lj[e]] + 1);
+                else
+                    for (int64_t e = F.cp[k]; e < F.cp[k + 1]; ++e) st = std::max(st, ready[F.ci[e]] + 1);
+                ready[k] = st;
+            }
+            continue;
+        }
+        int32_t st = 0;
+        for (int32_t k = a; k < b; ++k) {
+            if (forward)  // columns below a: all but the last k - a entries
+                for (int64_t e = F.lp[k]; e < F.lp[k + 1] - (k - a); ++e) st = std::max(st, ready[F.lj[e]] + 1);
+            else  // rows at or past b: all but the first b - 1 - k entries
+                for (int64_t e = F.cp[k] + (b - 1 - k); e < F.cp[k + 1]; ++e) st = std::max(st, ready[F.ci[e]] + 1);
+        }
+        block_step[ri] = st;
+        for (int32_t k = a; k < b; ++k) ready[k] = st + 1;
+        if (static_cast<int32_t>(at_step.size()) <= st) at_step.resize(st + 1, 0);
+        at_step[st] += b - a;
+    }
+    PassShape sh;
+    for (int32_t k = 0; k < n; ++k) sh.nsteps = std::max(sh.nsteps, ready[k] + 1);
+    int64_t cap[2] = {0, 0};
+    for (size_t s = 0; s < at_step.size(); ++s) cap[s & 1] = std::max(cap[s & 1], at_step[s]);
+    sh.slots = static_cast<int32_t>(cap[0] + cap[1]);
+    return sh;
+}
+
+// inverse of the dense lower triangle T = L[a:b, a:b] (row-major s x s, lower part)
+std::vector<double> block_inverse(const SparseFactor& F, int32_t a, int32_t b) {
+    const int32_t s = b - a;
+    std::vector<double> T(static_cast<size_t>(s) * s, 0.0), G(static_cast<size_t>(s) * s, 0.0);
+    for (int32_t r = 0; r < s; ++r) {
+        const int32_t k = a + r;
+        for (int32_t c = 0; c < r; ++c) T[static_cast<size_t>(r) * s + c] = F.lx[F.lp[k + 1] - r + c];
+        T[static_cast<size_t>(r) * s + r] = F.d[k];
+    }
+    for (int32_t c = 0; c < s; ++c) {
+        G[static_cast<size_t>(c) * s + c] = 1.0 / T[static_cast<size_t>(c) * s + c];
+        for (int32_t r = c + 1; r < s; ++r) {
+            double acc = 0.0;
+            for (int32_t m = c; m < r; ++m) acc += T[static_cast<size_t>(r) * s + m] * G[static_cast<size_t>(m) * s + c];
+            G[static_cast<size_t>(r) * s + c] = -acc / T[static_cast<size_t>(r) * s + r];
+        }
+    }
+    return G;
+}
+
+}  // namespace
+
+void sparse_schedule(const SparseFactor& F, const std::vector<int32_t>& runs, int32_t min_block, bool forward,
+                     SparseSchedule* out) {
+    const int32_t n = static_cast<int32_t>(F.d.size());
+    const int32_t nruns = static_cast<int32_t>(runs.size()) - 1;
+    std::vector<int32_t> ready, block_step;
+    const PassShape sh = schedule_steps(F, runs, min_block, forward, ready, block_step);
+    // slot base of every block: n, then the even-step range, then the odd-step range
+    std::vector<int64_t> at_step(sh.nsteps + 1, 0);
+    int64_t cap_even = 0;
+    for (int32_t r = 0; r < nruns; ++r)
+        if (block_step[r] >= 0) at_step[block_step[r]] += runs[r + 1] - runs[r];
+    for (int32_t s = 0; s < sh.nsteps; s += 2) cap_even = std::max(cap_even, at_step[s]);
+    std::fill(at_step.begin(), at_step.end(), 0);
+    std::vector<int32_t> base(nruns, -1);
+    for (int32_t q = 0; q < nruns; ++q) {
+        const int32_t r = forward ? q : nruns - 1 - q;
+        const int32_t st = block_step[r];
+        if (st < 0) continue;
+        base[r] = static_cast<int32_t>(n + (st & 1 ? cap_even : 0) + at_step[st]);
+        at_step[st] += runs[r + 1] - runs[r];
+    }
+    // records with their step, entries gathered per record, then emitted by step
+    struct Rec {
+        int32_t step, dest;
+        int64_t e0, e1;
+    };
+    std::vector<Rec> recs;
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    recs.reserve(n);
+    auto singleton = [&](int32_t k) {
+        const double inv = 1.0 / F.d[k];
+        Rec rc{ready[k], k, static_cast<int64_t>(col.size()), 0};
+        col.push_back(k);
+        val.push_back(inv);
+        if (forward)
+            for (int64_t e = F.lp[k]; e < F.lp[k + 1]; ++e) {
+                col.push_back(F.lj[e]);
+                val.push_back(-F.lx[e] * inv);
+            }
+        else
+            for (int64_t e = F.cp[k]; e < F.cp[k + 1]; ++e) {
+                col.push_back(F.ci[e]);
+                val.push_back(-F.cx[e] * inv);
+            }
+        rc.e1 = static_cast<int64_t>(col.size());
+        recs.push_back(rc);
+    };
+    for (int32_t q = 0; q < nruns; ++q) {
+        const int32_t r = forward ? q : nruns - 1 - q;
+        const int32_t a = runs[r], b = runs[r + 1];
+        if (block_step[r] < 0) {
+            for (int32_t i = 0; i < b - a; ++i) singleton(forward ? a + i : b - 1 - i);
+            continue;
+        }
+        const int32_t st = block_step[r], s = b - a;
+        // first step: v_k minus the products with rows outside the block
+        for (int32_t k = a; k < b; ++k) {
+            Rec rc{st, base[r] + (k - a), static_cast<int64_t>(col.size()), 0};
+            col.push_back(k);
+            val.push_back(1.0);
+            if (forward)
+                for (int64_t e = F.lp[k]; e < F.lp[k + 1] - (k - a); ++e) {
+                    col.push_back(F.lj[e]);
+                    val.push_back(-F.lx[e]);
+                }
+            else
+                for (int64_t e = F.cp[k] + (b - 1 - k); e < F.cp[k + 1]; ++e) {
+                    col.push_back(F.ci[e]);
+                    val.push_back(-F.cx[e]);
+                }
+            rc.e1 = static_cast<int64_t>(col.size());
+            recs.push_back(rc);
+        }
+        // second step: the inverse triangle (forward T^{-1}, backward T^{-T}) times the block slots
+        const std::vector<double> G = block_inverse(F, a, b);
+        for (int32_t i = 0; i < s; ++i) {
+            Rec rc{st + 1, a + i, static_cast<int64_t>(col.size()), 0};
+            if (forward)
+                for (int32_t j = 0; j <= i; ++j) {
+                    col.push_back(base[r] + j);
+                    val.push_back(G[static_cast<size_t>(i) * s + j]);
+                }
+            else
+                for (int32_t j = i; j < s; ++j) {
+                    col.push_back(base[r] + j);
+                    val.push_back(G[static_cast<size_t>(j) * s + i]);
+                }
+            rc.e1 = static_cast<int64_t>(col.size());
+            recs.push_back(rc);
+        }
+    }
+    std::stable_sort(recs.begin(), recs.end(), [](const Rec& x, const Rec& y) { return x.step < y.step; });
+    out->step.assign(sh.nsteps + 1, 0);
+    out->meta.assign(4 * recs.size(), 0);
+    out->col.clear();
+    out->val.clear();
+    out->col.reserve(col.size());
+    out->val.reserve(val.size());
+    for (size_t t = 0; t < recs.size(); ++t) {
+        const Rec& rc = recs[t];
+        ++out->step[rc.step + 1];
+        out->meta[4 * t] = rc.dest;
+        out->meta[4 * t + 1] = static_cast<int32_t>(out->col.size());
+        out->col.insert(out->col.end(), col.begin() + rc.e0, col.begin() + rc.e1);
+        out->val.insert(out->val.end(), val.begin() + rc.e0, val.begin() + rc.e1);
+        out->meta[4 * t + 2] = static_cast<int32_t>(out->col.size());
+    }
+    for (int32_t s = 0; s < sh.nsteps; ++s) out->step[s + 1] += out->step[s];
+    out->slots = sh.slots;
+}
+
+// The block threshold of one subdomain: the fewest steps over both passes whose
+// block slots fit beside the vector in LDS (ties: the larger threshold, fewer
+// inverse entries).
+int32_t choose_min_block(const SparseFactor& F, const std::vector<int32_t>& runs, int64_t slots_avail) {
+    int32_t best = 0;
+    int64_t best_steps = -1;
+    std::vector<int32_t> ready, bstep;
+    for (int32_t mb : {0, 64, 32, 16, 8, 4, 2}) {
+        const PassShape f = schedule_steps(F, runs, mb, true, ready, bstep);
+        const PassShape b = schedule_steps(F, runs, mb, false, ready, bstep);
+        if (std::max(f.slots, b.slots) > slots_avail) continue;
+        const int64_t steps = static_cast<int64_t>(f.nsteps) + b.nsteps;
+        if (best_steps < 0 || steps < best_steps) {
+            best_steps = steps;
+            best = mb;
+        }
+    }
+    return best;
+}
+
+void sparse_factor_local(Plan& plan, size_t lds_bytes, size_t value_bytes) {
+    parallel_for(plan.P, [&](int64_t p, int) {
+        Subdomain& sd = plan.subs[p];
+        sparse_factor_one(plan, sd, static_cast<int32_t>(p));
+        const std::vector<int32_t> runs = dense_runs(sd.sf);
+        const int64_t avail = static_cast<int64_t>(lds_bytes / value_bytes) - static_cast<int64_t>(sd.omega.size());
+        sd.min_block = choose_min_block(sd.sf, runs, avail);
+        sparse_schedule(sd.sf, runs, sd.min_block, true, &sd.sched[0]);
+        sparse_schedule(sd.sf, runs, sd.min_block, false, &sd.sched[1]);
+    });
 }
 
 }  // namespace ras
