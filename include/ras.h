@@ -237,6 +237,16 @@ ras_status ras_plan_sparse_factor(const ras_plan* plan, int32_t p, int32_t* perm
 ras_status ras_plan_sparse_schedule(const ras_plan* plan, int32_t p, int32_t pass, int32_t* nsteps, int64_t* nrec,
                                     int64_t* nent, int32_t* slots, int32_t* min_block, int32_t* step_ptr,
                                     int32_t* meta, int32_t* col, double* val);
+/* The same pass in the device's layout: the records of each step dealt out to
+ * the 64 lanes of each of *waves waves (one workgroup).  Wave w streams rounds
+ * wave[2w] .. wave[2w] + wave[2w+1] - 1, round r holding one item per lane,
+ * (col[64r + lane], val[64r + lane]).  An item with 0 <= col < 2^30 adds
+ * val * slot[col] to the lane's sum; col = INT32_MIN | s writes the sum to
+ * slot s and clears it; a round with col = 2^30 in every lane ends the wave's
+ * part of a step (the workgroup synchronises; sums are cleared).  *nitems
+ * receives the item count (a multiple of 64); the arrays may be NULL (query).  */
+ras_status ras_plan_sparse_lanes(const ras_plan* plan, int32_t p, int32_t pass, int32_t* waves, int64_t* nitems,
+                                 int32_t* wave, int32_t* col, double* val);
 /* Largest subdomain (local rows) the sparse Cholesky solver accepts for a
  * storage kind (FP64 or FP32), or 0 for a storage it does not support.  */
 int64_t ras_sparse_max_rows(int32_t storage);

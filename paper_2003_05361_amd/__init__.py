@@ -95,6 +95,8 @@ SIGNATURES = {
     "ras_plan_sparse_schedule": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                            C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P, _P,
                                            _P, _P]),
+    "ras_plan_sparse_lanes": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64), _P, _P,
+                                        _P]),
     "ras_sparse_max_rows": (C.c_int64, [C.c_int32]),
     "ras_plan_destroy": (None, [_P]),
     "ras_setup": (C.c_int, [C.POINTER(CSRStruct), C.POINTER(PartitionStruct), C.c_int32, C.POINTER(LocalStruct),
@@ -305,6 +307,18 @@ class Plan:
         _check(lib().ras_plan_sparse_schedule(self._p, p, pass_, None, None, None, None, None, step.ctypes.data,
                                               meta.ctypes.data, col.ctypes.data, val.ctypes.data))
         return {"step_ptr": step, "meta": meta, "col": col, "val": val, "slots": sl.value, "min_block": mb.value}
+
+    def sparse_lanes(self, p: int, pass_: int) -> dict:
+        """The same pass in the device's lane layout: wave (waves x 2: first round,
+        rounds), col and val (rounds x 64 items)."""
+        nw, ni = C.c_int32(), C.c_int64()
+        _check(lib().ras_plan_sparse_lanes(self._p, p, pass_, C.byref(nw), C.byref(ni), None, None, None))
+        wave = np.empty((nw.value, 2), dtype=np.int32)
+        col = np.empty(ni.value, dtype=np.int32)
+        val = np.empty(ni.value)
+        _check(lib().ras_plan_sparse_lanes(self._p, p, pass_, None, None, wave.ctypes.data, col.ctypes.data,
+                                           val.ctypes.data))
+        return {"wave": wave, "col": col.reshape(-1, 64), "val": val.reshape(-1, 64)}
 
     def factor_fp16(self, p: int) -> tuple[np.ndarray, np.ndarray]:
         band, w = self.factor(p)

@@ -381,18 +381,24 @@ void upload(ras_handle& h, const Plan& plan) {
     if (sparse) {
         // per subdomain and pass: levels, position records and columns, each padded to
         // 4 int32, and the values padded to 16 bytes
+        // (lane layout: per pass the wave table and the items; loads run ahead of use, so
+        // both arrays end with 2 * kSparseLead rounds of slack)
         int64_t ni = 0, nv = 0;
         for (int p = 0; p < P; ++p)
-            for (const SparseSchedule& q : plan.subs[p].sched) {
+            for (int k = 0; k < 2; ++k) {
+                const SparseLanes& q = plan.subs[p].lanes[k];
                 const int64_t ne = static_cast<int64_t>(q.col.size());
-                ni += (static_cast<int64_t>(q.step.size()) + 3) / 4 * 4 + static_cast<int64_t>(q.meta.size()) +
-                      (ne + 3) / 4 * 4;
+                ni += (static_cast<int64_t>(q.wave.size()) + 3) / 4 * 4 + (ne + 3) / 4 * 4;
                 nv += (ne * static_cast<int64_t>(sts) + 15) / 16 * 16;
                 h.max_sparse_values = std::max<int64_t>(
-                    h.max_sparse_values, static_cast<int64_t>(plan.subs[p].omega.size()) + q.slots);
+                    h.max_sparse_values, static_cast<int64_t>(plan.subs[p].omega.size()) + plan.subs[p].sched[k].slots);
             }
+        ni += 2 * kSparseLead * 64;
+        nv += 2 * kSparseLead * 64 * static_cast<int64_t>(sts);
         h.sp_idx.alloc(std::max<int64_t>(ni, 1) * sizeof(int32_t));
         h.sp_val.alloc(std::max<int64_t>(nv, 16));
+        hip_check(hipMemset(h.sp_idx.p, 0, h.sp_idx.bytes), "clear sparse index");
+        hip_check(hipMemset(h.sp_val.p, 0, h.sp_val.bytes), "clear sparse values");
     }
     h.omega.alloc(row_off[P] * sizeof(int32_t));
     h.ell_val.alloc(ell_off[P] * sizeof(double));
@@ -618,14 +624,13 @@ void upload(ras_handle& h, const Plan& plan) {
         }
         if (sparse) {
             const SparseFactor& F = s.sf;
-            const SparseSchedule* ps[2] = {&s.sched[0], &s.sched[1]};
             std::vector<int32_t> idx;
             std::vector<unsigned char> vals;
-            int64_t ioff[2][3], voff[2];
+            int64_t ioff[2][2], voff[2];
             for (int k = 0; k < 2; ++k) {
-                const SparseSchedule& q = *ps[k];
-                const std::vector<int32_t>* parts[3] = {&q.step, &q.meta, &q.col};
-                for (int a = 0; a < 3; ++a) {
+                const SparseLanes& q = s.lanes[k];
+                const std::vector<int32_t>* parts[2] = {&q.wave, &q.col};
+                for (int a = 0; a < 2; ++a) {
                     ioff[k][a] = sp_idx_used + static_cast<int64_t>(idx.size());
                     idx.insert(idx.end(), parts[a]->begin(), parts[a]->end());
                     while (idx.size() % 4) idx.push_back(0);  // 16-byte aligned arrays
@@ -642,7 +647,7 @@ void upload(ras_handle& h, const Plan& plan) {
                     }
                 }
                 while (vals.size() % 16) vals.push_back(0);
-                d.sp_nlev[k] = static_cast<int32_t>(q.step.size()) - 1;
+                d.sp_nlev[k] = static_cast<int32_t>(s.sched[k].step.size()) - 1;
             }
             hip_check(hipMemcpy(h.sp_idx.as<int32_t>() + sp_idx_used, idx.data(), idx.size() * sizeof(int32_t),
                                 hipMemcpyHostToDevice),
@@ -651,9 +656,8 @@ void upload(ras_handle& h, const Plan& plan) {
                                 hipMemcpyHostToDevice),
                       "copy sparse values");
             for (int k = 0; k < 2; ++k) {
-                d.sp_lev[k] = h.sp_idx.as<int32_t>() + ioff[k][0];
-                d.sp_meta[k] = h.sp_idx.as<int32_t>() + ioff[k][1];
-                d.sp_col[k] = h.sp_idx.as<int32_t>() + ioff[k][2];
+                d.sp_wave[k] = h.sp_idx.as<int32_t>() + ioff[k][0];
+                d.sp_col[k] = h.sp_idx.as<int32_t>() + ioff[k][1];
                 d.sp_val[k] = static_cast<char*>(h.sp_val.p) + voff[k];
             }
             sp_idx_used += static_cast<int64_t>(idx.size());
@@ -727,6 +731,7 @@ void drop_factors(Plan& plan) {
         std::vector<uint16_t>().swap(s.Lh);
         std::vector<float>().swap(s.scale);
         for (SparseSchedule& q : s.sched) q = SparseSchedule{};
+        for (SparseLanes& q : s.lanes) q = SparseLanes{};
     }
 }
 
@@ -1339,10 +1344,9 @@ int64_t estimate_device_bytes(const Plan& plan, int nrhs) {
         // the float64 band of the device factorisation, held while the system is set up
         if (chol && sd.L.empty()) bytes += 8 * n * (sd.w + 1);
         if (plan.local.kind == RAS_LOCAL_CHOL_SPARSE) {
-            for (const SparseSchedule& q : sd.sched)
-                bytes += 4 * static_cast<int64_t>(q.step.size() + q.meta.size()) +
-                         static_cast<int64_t>(q.col.size()) * (4 + sts) + 48;
-            bytes += n * cts;
+            for (const SparseLanes& q : sd.lanes)
+                bytes += 4 * static_cast<int64_t>(q.wave.size()) + static_cast<int64_t>(q.col.size()) * (4 + sts) + 48;
+            bytes += n * cts + 2 * kSparseLead * 64 * (4 + sts);
         }
     }
     if (chol) bytes += 2 * kSlabTailBytes;
@@ -1733,6 +1737,24 @@ ras_status ras_plan_sparse_schedule(const ras_plan* plan, int32_t p, int32_t pas
         if (min_block) *min_block = sd.min_block;
         if (step_ptr) std::copy(q.step.begin(), q.step.end(), step_ptr);
         if (meta) std::copy(q.meta.begin(), q.meta.end(), meta);
+        if (col) std::copy(q.col.begin(), q.col.end(), col);
+        if (val) std::copy(q.val.begin(), q.val.end(), val);
+        return RAS_OK;
+    });
+}
+
+ras_status ras_plan_sparse_lanes(const ras_plan* plan, int32_t p, int32_t pass, int32_t* waves, int64_t* nitems,
+                                 int32_t* wave, int32_t* col, double* val) {
+    return guarded([&] {
+        if (!plan) throw Error{RAS_E_ARG, "null plan"};
+        if (p < 0 || p >= plan->P) throw Error{RAS_E_ARG, "subdomain out of range"};
+        if (pass != 0 && pass != 1) throw Error{RAS_E_ARG, "pass must be 0 (forward) or 1 (backward)"};
+        if (plan->local.kind != RAS_LOCAL_CHOL_SPARSE) throw Error{RAS_E_STATE, "plan has no sparse factors"};
+        const SparseLanes& q = plan->subs[p].lanes[pass];
+        if (q.wave.empty()) throw Error{RAS_E_STATE, "schedule released"};
+        if (waves) *waves = kSparseWaves;
+        if (nitems) *nitems = static_cast<int64_t>(q.col.size());
+        if (wave) std::copy(q.wave.begin(), q.wave.end(), wave);
         if (col) std::copy(q.col.begin(), q.col.end(), col);
         if (val) std::copy(q.val.begin(), q.val.end(), val);
         return RAS_OK;

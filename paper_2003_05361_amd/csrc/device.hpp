@@ -31,6 +31,26 @@ constexpr int kSlabParts = 2 * kSlabFarWaves;  // far partial sums per row (one 
 constexpr int kSlabLead[3] = {2, 3, 4};  // blocks in flight: FP64, FP32, FP16 storage
 constexpr int kSlabWinTail = 16;    // mirrored slots after the solution window
 constexpr int kMaxFactorW = 1024;  // widest band the device factorisation takes
+// Sparse triangular passes as lane streams: a pass is a sequence of steps whose
+// records (one dot product each, writing one value of the vector in LDS) read
+// only values of earlier steps.  In each step the records are dealt out to
+// groups of G = 2^g consecutive lanes (g chosen per step; G > 1 for steps with
+// few, long records), and each wave then streams its own rounds, one item
+// (column, value) per lane and round: a record's entries go round-robin over
+// its group's lanes, which add val * y[slot] to their sums; a terminator item
+// in every lane of the group, in the same round, has the group sum its lanes
+// and the first lane write the total to the record's slot; padding items
+// (0, 0) fill a lane's rounds; every step of every wave ends with a marker
+// round (kSparseStep in every lane) at which the workgroup synchronises.
+// Item column: bits 0-23 the slot, bits 24-26 g, bit 31 terminator.  Loads run
+// kSparseLead rounds ahead of use, so the item arrays carry 2 * kSparseLead
+// rounds of slack after their last wave.
+constexpr int kSparseWaves = kBandThreads / 64;
+constexpr int32_t kSparseEnd = INT32_MIN;
+constexpr int32_t kSparseStep = 0x40000000;
+constexpr int32_t kSparseSlotMask = 0x00ffffff;
+constexpr int kSparseGroupShift = 24;
+constexpr int kSparseLead = 8;
 // The slab layout stores, per 32-row block, the strictly lower triangle of the
 // block's diagonal triangle at offsets o >= w - r (row r); its inverse has no
 // more nonzeros only if every such position has a slot, i.e. w >= kBandRows - 1.
@@ -86,17 +106,15 @@ struct SubDev {
     int32_t tri_inv;          // slab: the solver applies each block's triangle as its inverse, read from
                               // the triangle slots (FP64/FP32) or from tri_g (FP16), see tri_inverse_ok
     int64_t snap_off;         // offset of this subdomain's x snapshot (n + n_ext values) per right-hand side
-    // sparse Cholesky (local rows in elimination order); pass 0 = L (forward), 1 = L^T (backward).
-    // Level l holds the level-order positions [sp_lev[pass][l], sp_lev[pass][l + 1]); position t
-    // has sp_meta[pass][4 t .. 4 t + 3] = {row i, first entry, end of entries, 0}.  Row i's entries
-    // (sp_col, sp_val) are (i, 1 / L_ii) followed by (j, -L_ij / L_ii), so that the new y_i is
-    // the dot product of the entries with the current y.
     const float* tri_g[2];    // FP16 slab: packed float32 block-triangle inverses of L and of J L^T J
-    const int32_t* sp_lev[2];
-    const int32_t* sp_meta[2];
+    // sparse Cholesky (local rows in elimination order); pass 0 = L (forward), 1 = L^T (backward),
+    // as a lane stream (see kSparseWaves): wave w of the workgroup streams rounds
+    // sp_wave[pass][2w] .. + sp_wave[pass][2w + 1] - 1, round r being the items
+    // sp_col / sp_val[pass][r * 64 + lane]
+    const int32_t* sp_wave[2];
     const int32_t* sp_col[2];
     const void* sp_val[2];    // storage type
-    int32_t sp_nlev[2];
+    int32_t sp_nlev[2];       // steps of the pass
     int32_t sparse;           // 1: sparse Cholesky factor (sp_* valid)
     int32_t pad3_;
 };

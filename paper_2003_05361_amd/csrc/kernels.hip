@@ -1240,137 +1240,75 @@ __device__ __forceinline__ void slab_solve(const SubU& s, RAS_GLOBAL typename St
                  winm, true, tri_inv);
 }
 
-// One level-scheduled triangular pass over a sparse factor (Sec. 3.3.1's
-// sparse direct solve): the rows of a level depend only on rows of earlier
-// levels, so each level is one parallel step.  Each row's stored entries carry
-// the diagonal scaling (first entry (i, 1 / L_ii), then (j, -L_ij / L_ii)), so
-// the new y_i is one dot product of the entries with y; y stays in LDS and the
-// entries stream once from HBM.  A level with few rows gets more lanes per row
-// (up to a wave), a wide level one short group per row; each group sums its
-// row's entries and reduces across its lanes.
-typedef int i32x4 __attribute__((ext_vector_type(4)));
-
-// lanes per row for a level of R rows: up to a wave for a few rows, fewer as
-// rows grow, at least 4
-__device__ __forceinline__ int sparse_group(int R) {
-    int G = 64;
-    while (G > 4 && R * G > 2 * kBandThreads) G >>= 1;
-    return G;
-}
-
-// Loads of one level that do not depend on y: this thread's first row record
-// and its first U entries, issued a level (entries) or two (record) ahead.
+// One triangular pass over a sparse factor (Sec. 3.3.1's sparse direct
+// solve) as a sequence of steps whose records read only values written in
+// earlier steps: a record is one dot product of its entries with the vector y
+// (in LDS) and writes one slot (a row of y, or a partial result of a dense
+// block kept beyond the rows until the block's second step).  The host deals
+// each step's records out to groups of lanes and lays each wave's share out
+// as a stream of rounds (one item per lane, see kSparseWaves): entries
+// accumulate into the lane's sum, a terminator round has each terminating
+// group add its lanes' sums and write the total, and a marker round ends the
+// wave's part of a step with a workgroup barrier.  No load of the stream
+// depends on y, so each wave keeps kSparseLead rounds of loads in flight
+// across steps; the barrier drains only the LDS counter.
 template <class ST>
-struct SparseStage {
-    static constexpr int U = 8;
-    using CT = typename StorageTraits<ST>::CT;
-    int ta, tb, G;
-    i32x4 m;
-    CT v[U];
-    int c[U];
-
-    __device__ __forceinline__ void set(int a, int b) {
-        ta = a;
-        tb = b;
-        G = sparse_group(b - a);
-    }
-    __device__ __forceinline__ bool mine() const { return ta + static_cast<int>(threadIdx.x) / G < tb; }
-    __device__ __forceinline__ void load_record(RAS_GLOBAL const int32_t* meta) {
-        if (mine()) m = *reinterpret_cast<const RAS_GLOBAL i32x4*>(meta + 4 * (ta + static_cast<int>(threadIdx.x) / G));
-    }
-    __device__ __forceinline__ void load_entries(RAS_GLOBAL const int32_t* col, RAS_GLOBAL const ST* val) {
-        const bool ok = mine();
-        const int gl = static_cast<int>(threadIdx.x) & (G - 1);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            v[u] = CT(0);
-            c[u] = 0;
-            if (ok) {
-                const int e = m[1] + gl + u * G;
-                if (e < m[2]) {
-                    v[u] = static_cast<CT>(val[e]);
-                    c[u] = col[e];
-                }
-            }
-        }
-    }
-};
-
-// One level-scheduled triangular pass over a sparse factor (Sec. 3.3.1's
-// sparse direct solve): the rows of a level depend only on rows of earlier
-// levels, so each level is one parallel step.  Each row's stored entries carry
-// the diagonal scaling (first entry (i, 1 / L_ii), then (j, -L_ij / L_ii)), so
-// the new y_i is one dot product of the entries with y; y stays in LDS and the
-// entries stream once from HBM.  A level with few rows gets more lanes per row
-// (up to a wave), a wide level one short group per row; each group sums its
-// row's entries and reduces across its lanes.  The loads that do not depend
-// on y are pipelined across levels: the row record of level l + 2 and the
-// first entries of level l + 1 are in flight while level l computes.
-template <class ST>
-__device__ __attribute__((noinline)) void sparse_run(RAS_GLOBAL const int32_t* lev, RAS_GLOBAL const int32_t* meta,
-                                                     RAS_GLOBAL const int32_t* col, RAS_GLOBAL const ST* val, int nlev,
+__device__ __attribute__((noinline)) void sparse_run(RAS_GLOBAL const int32_t* wave_tab, RAS_GLOBAL const int32_t* col,
+                                                     RAS_GLOBAL const ST* val,
                                                      RAS_LDS typename StorageTraits<ST>::CT* y) {
     using CT = typename StorageTraits<ST>::CT;
-    using S = SparseStage<ST>;
-    constexpr int B = kBandThreads;
-    const int tid = threadIdx.x;
-    if (nlev <= 0) return;
-    S cur, nxt, nn;
-    cur.set(uni(lev[0]), uni(lev[1]));
-    cur.load_record(meta);
-    cur.load_entries(col, val);
-    nxt.set(cur.tb, nlev > 1 ? uni(lev[2]) : cur.tb);
-    nxt.load_record(meta);
-    for (int l = 0; l < nlev; ++l) {
-        if (l + 1 < nlev) nxt.load_entries(col, val);
-        nn.set(nxt.tb, l + 2 < nlev ? uni(lev[l + 3]) : nxt.tb);
-        nn.load_record(meta);
-        const int G = cur.G;
-        const int gi = tid / G, gl = tid & (G - 1), ng = B / G;
-        int t = cur.ta + gi;
-        if (t < cur.tb) {
-            CT acc = CT(0);
+    constexpr int D = kSparseLead;
+    static_assert(kBandThreads == 64 * kSparseWaves, "one wave stream per wave of the workgroup");
+    const int wave = uni(static_cast<int>(threadIdx.x) >> 6);
+    const int lane = static_cast<int>(threadIdx.x) & 63;
+    const int64_t base = uni(wave_tab[2 * wave]);
+    const int R = uni(wave_tab[2 * wave + 1]);
+    // the LDS address of y as an opaque scalar, so that it is not looked up again
+    // after every barrier
+    uint32_t yb = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(y));
+    asm volatile("" : "+s"(yb));
+    RAS_LDS CT* yy = reinterpret_cast<RAS_LDS CT*>(static_cast<uintptr_t>(yb));
+    RAS_GLOBAL const int32_t* pc = col + base * 64 + lane;
+    RAS_GLOBAL const ST* pv = val + base * 64 + lane;
+    int32_t rc[D];
+    CT rv[D];
+    // first rounds in the loop's own order (column, then value, round by round),
+    // so that the memory waits of the loop hold on entry as in steady state
 #pragma unroll
-            for (int u = 0; u < S::U; ++u) acc += cur.v[u] * y[cur.c[u]];
-            for (int e = cur.m[1] + gl + S::U * G; e < cur.m[2]; e += G) acc += static_cast<CT>(val[e]) * y[col[e]];
-            for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
-            if (gl == 0) y[cur.m[0]] = acc;
-        }
-        // further rows of a wide level, four per group at a time: all their records,
-        // then their first two entries per lane, are in flight together
-        for (t += ng; t < cur.tb; t += 4 * ng) {
-            i32x4 mm[4];
+    for (int i = 0; i < D; ++i) {
+        rc[i] = pc[i * 64];
+        rv[i] = static_cast<CT>(pv[i * 64]);
+        asm volatile("" ::: "memory");
+    }
+    CT acc = CT(0);
+    for (int r0 = 0; r0 < R; r0 += D) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int tq = t + q * ng;
-                mm[q] = i32x4{0, 0, 0, 0};
-                if (tq < cur.tb) mm[q] = *reinterpret_cast<const RAS_GLOBAL i32x4*>(meta + 4 * tq);
+        for (int i = 0; i < D; ++i) {
+            const int c = rc[i];
+            const CT v = rv[i];
+            const int cu = uni(c);
+            const bool live = r0 + i < R && !(cu & kSparseStep);  // uniform
+            if (r0 + i < R && (cu & kSparseStep)) {
+                lds_barrier();
+                acc = CT(0);
             }
-            CT vv[4][2];
-            int cc[4][2];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    const int e = mm[q][1] + gl + k * G;
-                    vv[q][k] = CT(0);
-                    cc[q][k] = 0;
-                    if (e < mm[q][2]) {
-                        vv[q][k] = static_cast<CT>(val[e]);
-                        cc[q][k] = col[e];
-                    }
-                }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                CT acc = vv[q][0] * y[cc[q][0]] + vv[q][1] * y[cc[q][1]];
-                for (int e = mm[q][1] + gl + 2 * G; e < mm[q][2]; e += G) acc += static_cast<CT>(val[e]) * y[col[e]];
-                for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
-                if (gl == 0 && t + q * ng < cur.tb) y[mm[q][0]] = acc;
+            const bool term = live && c < 0;
+            const bool add = live && c >= 0;
+            const int slot = live ? (c & kSparseSlotMask) : 0;
+            // a terminator's slot may hold anything (it is written, not read): select, do not scale
+            const CT yv = yy[add ? slot : 0];
+            acc = add ? acc + v * yv : acc;
+            if (__ballot(term)) {
+                // groups of 2^g lanes end records together: sum over the group
+                const int g = (cu >> kSparseGroupShift) & 7;
+                CT t = acc;
+                for (int k = 0; k < g; ++k) t += __shfl_xor(t, 1 << k);
+                if (term && (lane & ((1 << g) - 1)) == 0) yy[slot] = t;
+                acc = term ? CT(0) : acc;
             }
+            rc[i] = pc[(r0 + i + D) * 64];
+            rv[i] = static_cast<CT>(pv[(r0 + i + D) * 64]);
         }
-        __syncthreads();
-        cur = nxt;
-        nxt = nn;
     }
 }
 
@@ -1383,8 +1321,8 @@ __device__ __forceinline__ void sparse_solve(const SubDev* sd, int n, RAS_GLOBAL
     __syncthreads();
 #pragma unroll 1
     for (int pass = 0; pass < 2; ++pass)
-        sparse_run<ST>(gptr(sd->sp_lev[pass]), gptr(sd->sp_meta[pass]), gptr(sd->sp_col[pass]),
-                       gptr(static_cast<const ST*>(sd->sp_val[pass])), uni(sd->sp_nlev[pass]), y);
+        sparse_run<ST>(gptr(sd->sp_wave[pass]), gptr(sd->sp_col[pass]), gptr(static_cast<const ST*>(sd->sp_val[pass])),
+                       y);
     for (int i = threadIdx.x; i < n; i += kBandThreads) v[i] = y[i];
     __syncthreads();
 }

@@ -44,6 +44,15 @@ struct SparseSchedule {
     int32_t slots = 0;           // value slots beyond n
 };
 
+// A schedule dealt out to the lanes of one workgroup (the device layout of a
+// pass): wave w's rounds are wave[2w] .. wave[2w] + wave[2w+1] - 1, round r's
+// items col / val[r * 64 + lane]; see kSparseWaves for the item semantics.
+struct SparseLanes {
+    std::vector<int32_t> wave;
+    std::vector<int32_t> col;
+    std::vector<double> val;
+};
+
 struct Subdomain {
     std::vector<int32_t> omega;  // overlapping set, ascending global ids
     std::vector<uint8_t> owned;  // owned[i] != 0 iff omega[i] is owned by this subdomain
@@ -55,6 +64,7 @@ struct Subdomain {
     std::vector<float> scale;    // FP16_ROWSCALED: per-row scale
     SparseFactor sf;             // sparse Cholesky solver only
     SparseSchedule sched[2];     // sparse Cholesky: forward (L) and backward (L^T) passes
+    SparseLanes lanes[2];        // the same passes in the device's lane layout
     int32_t min_block = 0;       // sparse Cholesky: smallest dense block solved by its inverse (0: none)
 };
 
@@ -102,6 +112,10 @@ std::vector<int32_t> dense_runs(const SparseFactor& F);
 // the explicit inverse of their diagonal triangle
 void sparse_schedule(const SparseFactor& F, const std::vector<int32_t>& runs, int32_t min_block, bool forward,
                      SparseSchedule* out);
+// Lane layout of a schedule: the records of each step dealt out to the lanes
+// longest first, each to the least loaded lane, and the lanes grouped into
+// waves by load
+void pack_schedule(const SparseSchedule& q, SparseLanes* out);
 uint16_t f64_to_f16_rne(double d);
 
 uint64_t splitmix64_next(uint64_t& state);

@@ -15,9 +15,14 @@
 // scattering each finished entry along its column.
 #include <algorithm>
 #include <cmath>
+#include <functional>
+#include <numeric>
+#include <queue>
 #include <string>
+#include <utility>
 #include <vector>
 
+#include "device.hpp"
 #include "plan.hpp"
 
 namespace ras {
@@ -482,6 +487,98 @@ void sparse_schedule(const SparseFactor& F, const std::vector<int32_t>& runs, in
     out->slots = sh.slots;
 }
 
+namespace {
+
+// Records dealt to ng groups, longest first, each to the least loaded group
+// (ties: the lowest group); returns the largest group load in rounds.
+int64_t deal(const std::vector<int32_t>& order, const std::vector<int64_t>& rounds, int32_t ng,
+             std::vector<std::vector<int32_t>>* groups, std::vector<int64_t>* load) {
+    using Slot = std::pair<int64_t, int32_t>;
+    std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
+    for (int32_t g = 0; g < ng; ++g) heap.push({0, g});
+    if (groups) groups->assign(ng, {});
+    if (load) load->assign(ng, 0);
+    int64_t most = 0;
+    for (size_t k = 0; k < order.size(); ++k) {
+        const Slot t = heap.top();
+        heap.pop();
+        const int64_t l = t.first + rounds[k];
+        if (groups) (*groups)[t.second].push_back(order[k]);
+        if (load) (*load)[t.second] = l;
+        most = std::max(most, l);
+        heap.push({l, t.second});
+    }
+    return most;
+}
+
+}  // namespace
+
+void pack_schedule(const SparseSchedule& q, SparseLanes* out) {
+    constexpr int W = kSparseWaves, NL = 64 * kSparseWaves;
+    const int32_t nsteps = static_cast<int32_t>(q.step.size()) - 1;
+    std::vector<std::vector<int32_t>> wc(W);
+    std::vector<std::vector<double>> wv(W);
+    std::vector<std::vector<int32_t>> groups;
+    std::vector<int64_t> load, rounds;
+    std::vector<int32_t> order, gorder;
+    auto len = [&](int32_t r) { return static_cast<int64_t>(q.meta[4 * r + 2] - q.meta[4 * r + 1]); };
+    for (int32_t s = 0; s < nsteps; ++s) {
+        order.resize(q.step[s + 1] - q.step[s]);
+        std::iota(order.begin(), order.end(), q.step[s]);
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return len(a) > len(b); });
+        // group width: the fewest rounds for the step (ties: the narrower group)
+        int lg = 0;
+        int64_t best = -1;
+        for (int g = 0; g <= 6; ++g) {
+            rounds.resize(order.size());
+            for (size_t k = 0; k < order.size(); ++k) rounds[k] = (len(order[k]) + (1 << g) - 1) / (1 << g) + 1;
+            const int64_t m = deal(order, rounds, NL >> g, nullptr, nullptr);
+            if (best < 0 || m < best) {
+                best = m;
+                lg = g;
+            }
+        }
+        const int G = 1 << lg, ng = NL >> lg, gpw = 64 >> lg;  // groups per wave
+        for (size_t k = 0; k < order.size(); ++k) rounds[k] = (len(order[k]) + G - 1) / G + 1;
+        deal(order, rounds, ng, &groups, &load);
+        gorder.resize(ng);
+        std::iota(gorder.begin(), gorder.end(), 0);
+        std::stable_sort(gorder.begin(), gorder.end(), [&](int32_t a, int32_t b) { return load[a] > load[b]; });
+        const int32_t tag = lg << kSparseGroupShift;
+        for (int w = 0; w < W; ++w) {
+            int64_t U = 0;
+            for (int i = 0; i < gpw; ++i) U = std::max(U, load[gorder[gpw * w + i]]);
+            const size_t base = wc[w].size();
+            wc[w].resize(base + static_cast<size_t>(U + 1) * 64, tag);
+            wv[w].resize(base + static_cast<size_t>(U + 1) * 64, 0.0);
+            for (int i = 0; i < gpw; ++i) {
+                int64_t u = 0;  // next round of this group
+                for (int32_t r : groups[gorder[gpw * w + i]]) {
+                    const int32_t e0 = q.meta[4 * r + 1], e1 = q.meta[4 * r + 2];
+                    for (int32_t e = e0; e < e1; ++e) {
+                        const size_t at = base + static_cast<size_t>(u + (e - e0) / G) * 64 + i * G + (e - e0) % G;
+                        wc[w][at] = q.col[e] | tag;
+                        wv[w][at] = q.val[e];
+                    }
+                    u += (e1 - e0 + G - 1) / G;
+                    for (int l = 0; l < G; ++l) wc[w][base + static_cast<size_t>(u) * 64 + i * G + l] = q.meta[4 * r] | tag | kSparseEnd;
+                    ++u;
+                }
+            }
+            for (int l = 0; l < 64; ++l) wc[w][base + static_cast<size_t>(U) * 64 + l] = kSparseStep;
+        }
+    }
+    out->wave.assign(2 * W, 0);
+    out->col.clear();
+    out->val.clear();
+    for (int w = 0; w < W; ++w) {
+        out->wave[2 * w] = static_cast<int32_t>(out->col.size() / 64);
+        out->wave[2 * w + 1] = static_cast<int32_t>(wc[w].size() / 64);
+        out->col.insert(out->col.end(), wc[w].begin(), wc[w].end());
+        out->val.insert(out->val.end(), wv[w].begin(), wv[w].end());
+    }
+}
+
 // The block threshold of one subdomain: the fewest steps over both passes whose
 // block slots fit beside the vector in LDS (ties: the larger threshold, fewer
 // inverse entries).
@@ -511,6 +608,7 @@ void sparse_factor_local(Plan& plan, size_t lds_bytes, size_t value_bytes) {
         sd.min_block = choose_min_block(sd.sf, runs, avail);
         sparse_schedule(sd.sf, runs, sd.min_block, true, &sd.sched[0]);
         sparse_schedule(sd.sf, runs, sd.min_block, false, &sd.sched[1]);
+        for (int k = 0; k < 2; ++k) pack_schedule(sd.sched[k], &sd.lanes[k]);
     });
 }
 

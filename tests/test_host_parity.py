@@ -407,11 +407,98 @@ def test_sparse_schedule_solves_the_triangular_systems(name, A, part, gamma, sto
             assert len(sch["step_ptr"]) - 1 <= _levels(rp, col, n, pass_ == 0)
 
 
+def _run_lanes(lay, v, nslots):
+    """Applies a pass in the device's lane layout with the kernel's semantics:
+    every wave streams its rounds, a lane adds val * y[slot] to its sum, a
+    terminator in every lane of a group of 2^g lanes (g in bits 24-26 of the
+    column) has the group add its sums and write the total to the slot, a
+    marker round ends the wave's part of a step and all waves meet there.
+    Within a step the waves and lanes run in any order; here each step is
+    applied wave by wave with the values of the step's start for reads, and a
+    read of a slot written in the same step fails.  Padding items (slot 0,
+    value 0) add nothing and are exempt."""
+    n = v.size
+    y = np.concatenate([v, np.full(nslots, np.nan)])
+    wave, col, val = lay["wave"], lay["col"], lay["val"]
+    STEP, MASK = 2**30, 2**24 - 1
+    streams = []
+    for w0, nr in wave:
+        c = col[w0:w0 + nr]
+        marks = np.flatnonzero(np.all(c == STEP, axis=1))
+        assert not np.any(c[np.setdiff1d(np.arange(nr), marks)] == STEP)
+        streams.append((c, val[w0:w0 + nr], np.concatenate([[-1], marks])))
+    nsteps = {len(m) - 1 for _, _, m in streams}
+    assert len(nsteps) == 1  # every wave meets every barrier
+    lanes = np.arange(64)
+    for s in range(nsteps.pop()):
+        start = y.copy()
+        wrote = np.zeros(y.size, dtype=bool)
+        for c, vv, marks in streams:
+            acc = np.zeros(64)
+            g = None
+            for r in range(marks[s] + 1, marks[s + 1]):
+                cr, vr = c[r], vv[r]
+                gr = (cr >> 24) & 7
+                g = gr[0] if g is None else g
+                assert np.all(gr == g)  # one group width per wave and step
+                G = 1 << int(g)
+                term = cr < 0
+                slot = cr & MASK
+                pad = (slot == 0) & (vr == 0) & ~term
+                rd = ~term & ~pad
+                assert not np.any(wrote[slot[rd]]), s
+                acc[rd] += vr[rd] * start[slot[rd]]
+                if term.any():
+                    tg = term.reshape(-1, G)
+                    assert np.all(tg.all(axis=1) | ~tg.any(axis=1))  # whole groups end together
+                    sums = acc.reshape(-1, G).sum(axis=1)
+                    lead = term & (lanes % G == 0)
+                    assert np.all(slot.reshape(-1, G)[tg.any(axis=1)].min(axis=1) ==
+                                  slot.reshape(-1, G)[tg.any(axis=1)].max(axis=1))
+                    assert not np.any(wrote[slot[lead]])
+                    y[slot[lead]] = sums[lanes[lead] // G]
+                    wrote[slot[lead]] = True
+                    acc[term] = 0.0
+    return y[:n]
+
+
+@pytest.mark.parametrize("name,A,part,gamma", SPARSE_CASES, ids=[c[0] for c in SPARSE_CASES])
+def test_sparse_lane_layout_applies_the_schedule(name, A, part, gamma):
+    """The device layout of both passes, run with the kernel's semantics, gives
+    the triangular solves, every slot written once per step, no read of a value
+    written in the same step, and bounded padding."""
+    _lib_or_skip()
+    kind, arg = part
+    spec = (ras.partition("rcb", arg[0], grid=A.grid, seed=arg[1], jitter=arg[2]) if kind == "rcb"
+            else ras.partition(kind, arg, grid=A.grid))
+    plan = ras.Plan(A, spec, gamma, ras.local("chol_sparse", "fp64"))
+    _, ptr, _ = plan.sets()
+    rng = np.random.default_rng(12)
+    import scipy.sparse.linalg as spla
+    for p in range(len(ptr) - 1):
+        n = int(ptr[p + 1] - ptr[p])
+        perm, rp, col, val, diag = plan.sparse_factor(p)
+        L = (sp.csr_matrix((val, col, rp), shape=(n, n)) + sp.diags(diag)).tocsr()
+        v = rng.standard_normal(n)
+        for pass_, M, lower in ((0, L, True), (1, L.T.tocsr(), False)):
+            sch = plan.sparse_schedule(p, pass_)
+            lay = plan.sparse_lanes(p, pass_)
+            y = _run_lanes(lay, v, sch["slots"])
+            ref = spla.spsolve_triangular(M, v, lower=lower)
+            assert np.max(np.abs(y - ref)) <= 1e-12 * np.max(np.abs(ref)), (p, pass_)
+            # the longest wave is no longer than one record per lane would make it
+            meta = sch["meta"]
+            longest = sum(int((meta[a:b, 2] - meta[a:b, 1]).max()) + 2
+                          for a, b in zip(sch["step_ptr"][:-1], sch["step_ptr"][1:]))
+            assert lay["wave"][:, 1].max() <= longest, p
+
+
 def test_sparse_schedule_cuts_the_steps_of_a_grid_box():
     """An interior 136^2 box (128^2 owned, overlap 4) of a 2-D grid: the plain
     level schedule has hundreds of levels per pass (the separators are dense
     chains); with the separators' blocks solved through their inverses the
-    passes take at least 4x fewer steps, in both storages."""
+    passes take at least 4x fewer steps, in both storages, and the device
+    layout spreads them evenly over the workgroup's lanes."""
     _lib_or_skip()
     A = R.laplace2d(384)
     for storage, most in (("fp64", 60), ("fp32", 45)):
@@ -425,6 +512,13 @@ def test_sparse_schedule_cuts_the_steps_of_a_grid_box():
             steps = len(sch["step_ptr"]) - 1
             assert steps <= most and 4 * steps <= _levels(rp, col, n, pass_ == 0), (storage, pass_, steps)
             assert sch["min_block"] > 0 and (n + sch["slots"]) * (8 if storage == "fp64" else 4) <= 160 * 1024 - 4096
+            # device layout: padding under 25 % of the items, the longest wave within
+            # 1.4x of the items spread evenly over the workgroup's lanes
+            lay = plan.sparse_lanes(p, pass_)
+            items = len(sch["col"]) + len(sch["meta"])
+            rounds = lay["wave"][:, 1]
+            assert rounds.sum() * 64 <= 1.25 * items
+            assert rounds.max() <= 1.4 * items / (64 * len(rounds))
 
 
 def test_nested_dissection_reduces_fill_of_wide_bands():
