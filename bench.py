@@ -36,6 +36,7 @@ WORKLOADS = {
     "diffusion2d_2048_16x16_fp32": ("diffusion2d_2048_16x16", "chol", "fp32", 0),
     "diffusion2d_2048_16x16_fp16": ("diffusion2d_2048_16x16", "chol", "fp16", 0),
     "diffusion2d_2048_16x16_sparse_fp64": ("diffusion2d_2048_16x16", "chol_sparse", "fp64", 0),
+    "diffusion2d_2048_16x16_sparse_fp32": ("diffusion2d_2048_16x16", "chol_sparse", "fp32", 0),
     "poisson2d_512_strips64_sparse_fp64": ("poisson2d_512_strips64", "chol_sparse", "fp64", 0),
     "poisson2d_512_strips64_fp64": ("poisson2d_512_strips64", "chol", "fp64", 0),
     "poisson2d_64_strips4": ("poisson2d_64_strips4", "chol", "fp64", 0),

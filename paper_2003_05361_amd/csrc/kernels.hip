@@ -380,15 +380,26 @@ __device__ __forceinline__ double row_residual(const SubU& s, RAS_GLOBAL double*
 // stores; everything reads the snapshot with device-scope loads.
 __device__ __forceinline__ void take_snapshot(const SubU& s, RAS_GLOBAL double* x, RAS_GLOBAL double* xs, int lo,
                                               int hi, int nthreads) {
-    for (int k = lo + static_cast<int>(threadIdx.x); k < hi; k += nthreads) {
-        int32_t g;
-        if (k < s.n) {
-            const int32_t e = s.omega[k];
-            g = e >= 0 ? e : ~e;
-        } else {
-            g = s.ext[k - s.n];
+    // four slots per thread at a time: the index loads, then the x loads, in flight together
+    constexpr int U = 4;
+    for (int k0 = lo + static_cast<int>(threadIdx.x); k0 < hi; k0 += U * nthreads) {
+        int32_t g[U];
+        double xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = min(k0 + u * nthreads, hi - 1);
+            if (k < s.n) {
+                const int32_t e = s.omega[k];
+                g[u] = e >= 0 ? e : ~e;
+            } else {
+                g[u] = s.ext[k - s.n];
+            }
         }
-        stg_dev(xs + k, ldx<true>(x + g));
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = ldx<true>(x + g[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u * nthreads < hi) stg_dev(xs + k0 + u * nthreads, xv[u]);
     }
 }
 
@@ -418,6 +429,52 @@ __device__ __forceinline__ double row_residual_snap(const SubU& s, RAS_GLOBAL do
         }
     }
     return comp_value(acc);
+}
+
+// Residual of every local row of one workgroup's subdomain into v (the local
+// solves' right-hand side) with the three squared norms, U rows per thread at
+// a time: the independent loads of the U rows (omega, the ELL row, then b and
+// the x values) are issued together, so a thread waits for two memory round
+// trips per U rows instead of per row.  x is the shared vector (global
+// columns) or, asynchronously, the update's snapshot (local columns).
+template <int KT, int U, bool SNAP, class CT>
+__device__ __forceinline__ void residual_rows(const SubU& s, RAS_GLOBAL double* b, RAS_GLOBAL double* x,
+                                              RAS_GLOBAL CT* v, int n, int nthreads, double& own2, double& loc2,
+                                              double& b2) {
+    RAS_GLOBAL const int32_t* cols = SNAP ? s.ell_lcol : s.ell_gcol;
+    for (int i0 = static_cast<int>(threadIdx.x); i0 < n; i0 += U * nthreads) {
+        int32_t e[U], c[U][KT];
+        double a[U][KT], bg[U], xv[U][KT];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = min(i0 + u * nthreads, n - 1);
+            e[u] = s.omega[i];
+#pragma unroll
+            for (int k = 0; k < KT; ++k) {
+                c[u][k] = (cols + static_cast<uint32_t>(k * s.n_pad))[static_cast<uint32_t>(i)];
+                a[u][k] = (s.ell_val + static_cast<uint32_t>(k * s.n_pad))[static_cast<uint32_t>(i)];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            bg[u] = b[e[u] >= 0 ? e[u] : ~e[u]];
+#pragma unroll
+            for (int k = 0; k < KT; ++k) xv[u][k] = SNAP ? ldg_dev(x + c[u][k]) : x[c[u][k]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * nthreads;
+            if (i >= n) break;
+            CompAcc acc{bg[u], 0.0};
+#pragma unroll
+            for (int k = 0; k < KT; ++k) comp_sub(acc, a[u][k], xv[u][k]);
+            const double ri = comp_value(acc);
+            loc2 += ri * ri;
+            b2 += bg[u] * bg[u];
+            if (e[u] >= 0) own2 += ri * ri;
+            v[i] = static_cast<CT>(ri);
+        }
+    }
 }
 
 // ------------------------------------------------------------------------------ CG update
@@ -1360,18 +1417,25 @@ struct BandUpdate {
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
         }
-        for (int i = tid; i < n; i += B) {
-            bool owned;
-            double bg;
-            double ri;
-            if constexpr (ASYNC)
-                ri = row_residual_snap<0>(s, in.b, xs, i, owned, bg);
-            else
-                ri = row_residual<0, false>(s, in.b, xin, i, owned, bg);
-            loc2 += ri * ri;
-            b2 += bg * bg;
-            if (owned) own2 += ri * ri;
-            v[i] = static_cast<CT>(ri);
+        RAS_GLOBAL double* xr = ASYNC ? xs : xin;
+        if (s.K == 5) {
+            residual_rows<5, 4, ASYNC>(s, in.b, xr, v, n, B, own2, loc2, b2);
+        } else if (s.K == 7) {
+            residual_rows<7, 4, ASYNC>(s, in.b, xr, v, n, B, own2, loc2, b2);
+        } else {
+            for (int i = tid; i < n; i += B) {
+                bool owned;
+                double bg;
+                double ri;
+                if constexpr (ASYNC)
+                    ri = row_residual_snap<0>(s, in.b, xs, i, owned, bg);
+                else
+                    ri = row_residual<0, false>(s, in.b, xin, i, owned, bg);
+                loc2 += ri * ri;
+                b2 += bg * bg;
+                if (owned) own2 += ri * ri;
+                v[i] = static_cast<CT>(ri);
+            }
         }
         // the loaders read v back through global-to-LDS loads
         __builtin_amdgcn_s_waitcnt(0);
@@ -1393,14 +1457,26 @@ struct BandUpdate {
             band_pass<ST>(Lr, s.scale, true, iv, n, s.w, v, stage, win, winm, gsum);
         }
         if (tid == 0) tc.st_solve = wall_clock64();
-        for (int i = tid; i < n; i += B) {
-            const int32_t e = s.omega[i];
-            if (e >= 0) {
-                if constexpr (ASYNC)
-                    stx<true>(xout + e, ldg_dev(xs + i) + static_cast<double>(v[i]));
-                else
-                    stx<false>(xout + e, xin[e] + static_cast<double>(v[i]));
+        // restricted prolongation, four rows per thread at a time (loads first)
+        constexpr int UP = 4;
+        for (int i0 = tid; i0 < n; i0 += UP * B) {
+            int32_t e[UP];
+            double xo[UP];
+            CT dv[UP];
+#pragma unroll
+            for (int u = 0; u < UP; ++u) {
+                const int i = min(i0 + u * B, n - 1);
+                e[u] = i0 + u * B < n ? s.omega[i] : -1;
+                dv[u] = v[i];
+                if constexpr (ASYNC) xo[u] = ldg_dev(xs + i);
             }
+            if constexpr (!ASYNC) {
+#pragma unroll
+                for (int u = 0; u < UP; ++u) xo[u] = e[u] >= 0 ? xin[e[u]] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < UP; ++u)
+                if (e[u] >= 0) stx<ASYNC>(xout + e[u], xo[u] + static_cast<double>(dv[u]));
         }
     }
 };
