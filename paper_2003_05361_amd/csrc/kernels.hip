@@ -432,15 +432,16 @@ __device__ __forceinline__ double row_residual_snap(const SubU& s, RAS_GLOBAL do
 }
 
 // Residual of every local row of one workgroup's subdomain into v (the local
-// solves' right-hand side) with the three squared norms, U rows per thread at
-// a time: the independent loads of the U rows (omega, the ELL row, then b and
-// the x values) are issued together, so a thread waits for two memory round
-// trips per U rows instead of per row.  x is the shared vector (global
-// columns) or, asynchronously, the update's snapshot (local columns).
-template <int KT, int U, bool SNAP, class CT>
-__device__ __forceinline__ void residual_rows(const SubU& s, RAS_GLOBAL double* b, RAS_GLOBAL double* x,
-                                              RAS_GLOBAL CT* v, int n, int nthreads, double& own2, double& loc2,
-                                              double& b2) {
+// solves' right-hand side; LDS when the solve keeps its vector there) with the
+// three squared norms, U rows per thread at a time: the independent loads of
+// the U rows (omega, the ELL row, then b and the x values) are issued
+// together, so a thread waits for two memory round trips per U rows instead of
+// per row.  x is the shared vector (global columns) or, asynchronously, the
+// update's snapshot (local columns).
+template <int KT, int U, bool SNAP, class VP>
+__device__ __forceinline__ void residual_rows(const SubU& s, RAS_GLOBAL double* b, RAS_GLOBAL double* x, VP v, int n,
+                                              int nthreads, double& own2, double& loc2, double& b2) {
+    using CT = typename std::remove_reference<decltype(*v)>::type;
     RAS_GLOBAL const int32_t* cols = SNAP ? s.ell_lcol : s.ell_gcol;
     for (int i0 = static_cast<int>(threadIdx.x); i0 < n; i0 += U * nthreads) {
         int32_t e[U], c[U][KT];
@@ -1369,19 +1370,16 @@ __device__ __attribute__((noinline)) void sparse_run(RAS_GLOBAL const int32_t* w
     }
 }
 
+// Both passes on the vector y in LDS (its first n slots hold the right-hand
+// side on entry and the solution on return; every pass ends with a workgroup
+// barrier, so the solution is visible to all threads on return).
 template <class ST>
-__device__ __forceinline__ void sparse_solve(const SubDev* sd, int n, RAS_GLOBAL typename StorageTraits<ST>::CT* v,
-                                             unsigned char* lds) {
-    using CT = typename StorageTraits<ST>::CT;
-    RAS_LDS CT* y = (RAS_LDS CT*)(lds);
-    for (int i = threadIdx.x; i < n; i += kBandThreads) y[i] = v[i];
+__device__ __forceinline__ void sparse_solve(const SubDev* sd, RAS_LDS typename StorageTraits<ST>::CT* y) {
     __syncthreads();
 #pragma unroll 1
     for (int pass = 0; pass < 2; ++pass)
         sparse_run<ST>(gptr(sd->sp_wave[pass]), gptr(sd->sp_col[pass]), gptr(static_cast<const ST*>(sd->sp_val[pass])),
                        y);
-    for (int i = threadIdx.x; i < n; i += kBandThreads) v[i] = y[i];
-    __syncthreads();
 }
 
 template <class ST, bool ASYNC>
@@ -1418,7 +1416,14 @@ struct BandUpdate {
             __syncthreads();
         }
         RAS_GLOBAL double* xr = ASYNC ? xs : xin;
-        if (s.K == 5) {
+        // the sparse solve keeps its vector in LDS: the residual goes there directly
+        RAS_LDS CT* yl = (RAS_LDS CT*)(smem);
+        const bool to_lds = sparse && sizeof(ST) != 2;
+        if (s.K == 5 && to_lds) {
+            residual_rows<5, 4, ASYNC>(s, in.b, xr, yl, n, B, own2, loc2, b2);
+        } else if (s.K == 7 && to_lds) {
+            residual_rows<7, 4, ASYNC>(s, in.b, xr, yl, n, B, own2, loc2, b2);
+        } else if (s.K == 5) {
             residual_rows<5, 4, ASYNC>(s, in.b, xr, v, n, B, own2, loc2, b2);
         } else if (s.K == 7) {
             residual_rows<7, 4, ASYNC>(s, in.b, xr, v, n, B, own2, loc2, b2);
@@ -1434,7 +1439,10 @@ struct BandUpdate {
                 loc2 += ri * ri;
                 b2 += bg * bg;
                 if (owned) own2 += ri * ri;
-                v[i] = static_cast<CT>(ri);
+                if (to_lds)
+                    yl[i] = static_cast<CT>(ri);
+                else
+                    v[i] = static_cast<CT>(ri);
             }
         }
         // the loaders read v back through global-to-LDS loads
@@ -1442,8 +1450,7 @@ struct BandUpdate {
         block_sum3<B>(own2, loc2, b2, red3);
         if (tid == 0) tc.st_res = wall_clock64();
         if (sparse) {
-            if constexpr (sizeof(ST) != 2)
-                sparse_solve<ST>(P.subs + item.sub, n, v, smem);
+            if constexpr (sizeof(ST) != 2) sparse_solve<ST>(P.subs + item.sub, yl);
         } else if (slab) {
             slab_solve<ST>(s, v, smem, winm, stage_bytes, tri_inv != 0, P.subs[item.sub].tri_g[0],
                            P.subs[item.sub].tri_g[1]);
@@ -1467,7 +1474,7 @@ struct BandUpdate {
             for (int u = 0; u < UP; ++u) {
                 const int i = min(i0 + u * B, n - 1);
                 e[u] = i0 + u * B < n ? s.omega[i] : -1;
-                dv[u] = v[i];
+                dv[u] = to_lds ? yl[i] : v[i];
                 if constexpr (ASYNC) xo[u] = ldg_dev(xs + i);
             }
             if constexpr (!ASYNC) {
