@@ -340,10 +340,12 @@ def fixed_sweep_leg(h, bt, bps, N, reps, warmup, label_workload, kind, storage, 
     return leg
 
 
-def slab_legs(storages, N=200, reps=3):
-    """The 2048^2 log-normal diffusion workload (16 x 16 boxes, overlap 4, banded
-    Cholesky): factors of 1.3-5.1 GB per triangular pass, far beyond the 256 MB
-    Infinity Cache, so the sweep streams from HBM -- the honest roofline test."""
+def slab_legs(locals_, N=200, reps=3):
+    """The 2048^2 log-normal diffusion workload (16 x 16 boxes, overlap 4, exact
+    local solves: banded Cholesky, or sparse Cholesky with suffix _sparse):
+    factors of 1.3-5.1 GB (band) or 2.9 GB (sparse FP64) per triangular pass, far
+    beyond the 256 MB Infinity Cache, so the sweep streams from HBM -- the honest
+    roofline test.  locals_: (kind, storage) pairs."""
     import numpy as np
     import torch
 
@@ -352,19 +354,20 @@ def slab_legs(storages, N=200, reps=3):
     from paper_2003_05361_amd.perfmodel import bytes_per_local_solve
 
     A, b, cfg = R.config_problem("diffusion2d_2048_16x16")
-    shapes = subdomain_shapes(A, "regular_2d", (16, 16), 4, "chol")
     bt = torch.tensor(b, dtype=torch.float64, device="cuda")
     legs = []
-    for st in storages:
+    for kind, st in locals_:
+        shapes = subdomain_shapes(A, "regular_2d", (16, 16), 4, kind)
         t0 = time.perf_counter()
-        h = ras.setup(A, ras.partition("regular_2d", (16, 16), grid=A.grid), 4, ras.local("chol", st))
+        h = ras.setup(A, ras.partition("regular_2d", (16, 16), grid=A.grid), 4, ras.local(kind, st))
         setup_s = time.perf_counter() - t0
-        bps = np.array(bytes_per_local_solve(shapes, "chol", st, 0), dtype=np.float64)
-        leg = fixed_sweep_leg(h, bt, bps, N, reps, 1, f"diffusion2d_2048_16x16_{st}", "chol", st, 0)
+        bps = np.array(bytes_per_local_solve(shapes, kind, st, 0), dtype=np.float64)
+        name = f"diffusion2d_2048_16x16_{'sparse_' if kind == 'chol_sparse' else ''}{st}"
+        leg = fixed_sweep_leg(h, bt, bps, N, reps, 1, name, kind, st, 0)
         leg["setup_s"] = setup_s
         h.close()
         torch.cuda.empty_cache()
-        print(f"slab leg {st}: {leg['async']['GBps']:.0f} GB/s async, {leg['sync']['GBps']:.0f} GB/s sync",
+        print(f"leg {name}: {leg['async']['GBps']:.0f} GB/s async, {leg['sync']['GBps']:.0f} GB/s sync",
               file=sys.stderr, flush=True)
         legs.append(leg)
     return legs
@@ -531,7 +534,7 @@ def main():
                             "HBM rate and may exceed the HBM peak; counter_GBps is the measured fabric rate")
     legs = []
     if args.workload == "poisson2d_1024_8x8" and not args.no_slab_legs:
-        legs = slab_legs(("fp64", "fp16"))
+        legs = slab_legs((("chol", "fp64"), ("chol", "fp16"), ("chol_sparse", "fp64")))
     # the roofline row: the streamed (beyond-cache) sweep of the 2048^2 diffusion
     # workload when it ran, else this workload's own kernel
     roof = dict(legs[0]["roofline"]) if legs else own_roof

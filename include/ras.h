@@ -240,11 +240,14 @@ ras_status ras_plan_sparse_schedule(const ras_plan* plan, int32_t p, int32_t pas
 /* The same pass in the device's layout: the records of each step dealt out to
  * the 64 lanes of each of *waves waves (one workgroup).  Wave w streams rounds
  * wave[2w] .. wave[2w] + wave[2w+1] - 1, round r holding one item per lane,
- * (col[64r + lane], val[64r + lane]).  An item with 0 <= col < 2^30 adds
- * val * slot[col] to the lane's sum; col = INT32_MIN | s writes the sum to
- * slot s and clears it; a round with col = 2^30 in every lane ends the wave's
- * part of a step (the workgroup synchronises; sums are cleared).  *nitems
- * receives the item count (a multiple of 64); the arrays may be NULL (query).  */
+ * (col[64r + lane], val[64r + lane]); the device stores col in 16 bits.  An
+ * item with col < 0xfffe adds val * slot[col] to the lane's sum; col = 0xfffe
+ * is a terminator, present in every lane of a group of 2^g consecutive lanes
+ * in the same round, whose value's low 32 bits hold s | g << 24: the group's
+ * sums are added, the total written to slot s and the sums cleared; a round
+ * with col = 0xffff in every lane ends the wave's part of a step (the
+ * workgroup synchronises; sums are cleared).  *nitems receives the item count
+ * (a multiple of 64); the arrays may be NULL (query).  */
 ras_status ras_plan_sparse_lanes(const ras_plan* plan, int32_t p, int32_t pass, int32_t* waves, int64_t* nitems,
                                  int32_t* wave, int32_t* col, double* val);
 /* Largest subdomain (local rows) the sparse Cholesky solver accepts for a

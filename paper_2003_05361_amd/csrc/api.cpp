@@ -379,23 +379,23 @@ void upload(ras_handle& h, const Plan& plan) {
     const size_t sts = st == RAS_STORAGE_FP64 ? 8 : st == RAS_STORAGE_FP32 ? 4 : 2;
     int64_t sp_idx_used = 0, sp_val_used = 0;
     if (sparse) {
-        // per subdomain and pass: levels, position records and columns, each padded to
-        // 4 int32, and the values padded to 16 bytes
-        // (lane layout: per pass the wave table and the items; loads run ahead of use, so
-        // both arrays end with 2 * kSparseLead rounds of slack)
-        int64_t ni = 0, nv = 0;
+        // per subdomain and pass (lane layout): the wave table (int32) and the items'
+        // 16-bit columns in the index buffer, the items' values in the value buffer,
+        // every array 16-byte aligned; loads run ahead of use, so both buffers end
+        // with 2 * kSparseLead rounds of slack
+        int64_t ni = 0, nv = 0;  // bytes
         for (int p = 0; p < P; ++p)
             for (int k = 0; k < 2; ++k) {
                 const SparseLanes& q = plan.subs[p].lanes[k];
                 const int64_t ne = static_cast<int64_t>(q.col.size());
-                ni += (static_cast<int64_t>(q.wave.size()) + 3) / 4 * 4 + (ne + 3) / 4 * 4;
+                ni += (4 * static_cast<int64_t>(q.wave.size()) + 15) / 16 * 16 + (2 * ne + 15) / 16 * 16;
                 nv += (ne * static_cast<int64_t>(sts) + 15) / 16 * 16;
                 h.max_sparse_values = std::max<int64_t>(
                     h.max_sparse_values, static_cast<int64_t>(plan.subs[p].omega.size()) + plan.subs[p].sched[k].slots);
             }
-        ni += 2 * kSparseLead * 64;
+        ni += 2 * kSparseLead * 64 * 2;
         nv += 2 * kSparseLead * 64 * static_cast<int64_t>(sts);
-        h.sp_idx.alloc(std::max<int64_t>(ni, 1) * sizeof(int32_t));
+        h.sp_idx.alloc(std::max<int64_t>(ni, 16));
         h.sp_val.alloc(std::max<int64_t>(nv, 16));
         hip_check(hipMemset(h.sp_idx.p, 0, h.sp_idx.bytes), "clear sparse index");
         hip_check(hipMemset(h.sp_val.p, 0, h.sp_val.bytes), "clear sparse values");
@@ -624,24 +624,42 @@ void upload(ras_handle& h, const Plan& plan) {
         }
         if (sparse) {
             const SparseFactor& F = s.sf;
-            std::vector<int32_t> idx;
-            std::vector<unsigned char> vals;
+            std::vector<unsigned char> idx, vals;
             int64_t ioff[2][2], voff[2];
+            auto put = [](std::vector<unsigned char>& to, const void* from, size_t bytes) {
+                const unsigned char* c = static_cast<const unsigned char*>(from);
+                to.insert(to.end(), c, c + bytes);
+                while (to.size() % 16) to.push_back(0);  // 16-byte aligned arrays
+            };
             for (int k = 0; k < 2; ++k) {
                 const SparseLanes& q = s.lanes[k];
-                const std::vector<int32_t>* parts[2] = {&q.wave, &q.col};
-                for (int a = 0; a < 2; ++a) {
-                    ioff[k][a] = sp_idx_used + static_cast<int64_t>(idx.size());
-                    idx.insert(idx.end(), parts[a]->begin(), parts[a]->end());
-                    while (idx.size() % 4) idx.push_back(0);  // 16-byte aligned arrays
+                ioff[k][0] = sp_idx_used + static_cast<int64_t>(idx.size());
+                put(idx, q.wave.data(), q.wave.size() * sizeof(int32_t));
+                ioff[k][1] = sp_idx_used + static_cast<int64_t>(idx.size());
+                {
+                    // the columns of rounds 2m and 2m + 1 in one word per lane
+                    std::vector<uint32_t> words(q.col.size() / 2);
+                    for (size_t m = 0; m < words.size() / 64; ++m)
+                        for (size_t l = 0; l < 64; ++l)
+                            words[m * 64 + l] = static_cast<uint32_t>(q.col[(2 * m) * 64 + l]) |
+                                                static_cast<uint32_t>(q.col[(2 * m + 1) * 64 + l]) << 16;
+                    put(idx, words.data(), words.size() * sizeof(uint32_t));
                 }
                 voff[k] = sp_val_used + static_cast<int64_t>(vals.size());
-                for (double x : q.val) {
+                for (size_t e = 0; e < q.val.size(); ++e) {
+                    const double x = q.val[e];
                     if (st == RAS_STORAGE_FP64) {
                         const unsigned char* b = reinterpret_cast<const unsigned char*>(&x);
                         vals.insert(vals.end(), b, b + 8);
                     } else {
-                        const float f = static_cast<float>(x);
+                        // a terminator's payload is an integer in the value's bits: keep its low 32 bits
+                        float f = static_cast<float>(x);
+                        if (q.col[e] == kSparseTerm) {
+                            uint64_t bits;
+                            std::memcpy(&bits, &x, sizeof bits);
+                            const uint32_t lo = static_cast<uint32_t>(bits);
+                            std::memcpy(&f, &lo, sizeof f);
+                        }
                         const unsigned char* b = reinterpret_cast<const unsigned char*>(&f);
                         vals.insert(vals.end(), b, b + 4);
                     }
@@ -649,15 +667,15 @@ void upload(ras_handle& h, const Plan& plan) {
                 while (vals.size() % 16) vals.push_back(0);
                 d.sp_nlev[k] = static_cast<int32_t>(s.sched[k].step.size()) - 1;
             }
-            hip_check(hipMemcpy(h.sp_idx.as<int32_t>() + sp_idx_used, idx.data(), idx.size() * sizeof(int32_t),
+            hip_check(hipMemcpy(static_cast<char*>(h.sp_idx.p) + sp_idx_used, idx.data(), idx.size(),
                                 hipMemcpyHostToDevice),
                       "copy sparse index");
             hip_check(hipMemcpy(static_cast<char*>(h.sp_val.p) + sp_val_used, vals.data(), vals.size(),
                                 hipMemcpyHostToDevice),
                       "copy sparse values");
             for (int k = 0; k < 2; ++k) {
-                d.sp_wave[k] = h.sp_idx.as<int32_t>() + ioff[k][0];
-                d.sp_col[k] = h.sp_idx.as<int32_t>() + ioff[k][1];
+                d.sp_wave[k] = reinterpret_cast<const int32_t*>(static_cast<char*>(h.sp_idx.p) + ioff[k][0]);
+                d.sp_col[k] = reinterpret_cast<const uint32_t*>(static_cast<char*>(h.sp_idx.p) + ioff[k][1]);
                 d.sp_val[k] = static_cast<char*>(h.sp_val.p) + voff[k];
             }
             sp_idx_used += static_cast<int64_t>(idx.size());
@@ -1345,8 +1363,8 @@ int64_t estimate_device_bytes(const Plan& plan, int nrhs) {
         if (chol && sd.L.empty()) bytes += 8 * n * (sd.w + 1);
         if (plan.local.kind == RAS_LOCAL_CHOL_SPARSE) {
             for (const SparseLanes& q : sd.lanes)
-                bytes += 4 * static_cast<int64_t>(q.wave.size()) + static_cast<int64_t>(q.col.size()) * (4 + sts) + 48;
-            bytes += n * cts + 2 * kSparseLead * 64 * (4 + sts);
+                bytes += 4 * static_cast<int64_t>(q.wave.size()) + static_cast<int64_t>(q.col.size()) * (2 + sts) + 48;
+            bytes += n * cts + 2 * kSparseLead * 64 * (2 + sts);
         }
     }
     if (chol) bytes += 2 * kSlabTailBytes;

@@ -35,20 +35,22 @@ constexpr int kMaxFactorW = 1024;  // widest band the device factorisation takes
 // records (one dot product each, writing one value of the vector in LDS) read
 // only values of earlier steps.  In each step the records are dealt out to
 // groups of G = 2^g consecutive lanes (g chosen per step; G > 1 for steps with
-// few, long records), and each wave then streams its own rounds, one item
-// (column, value) per lane and round: a record's entries go round-robin over
-// its group's lanes, which add val * y[slot] to their sums; a terminator item
-// in every lane of the group, in the same round, has the group sum its lanes
-// and the first lane write the total to the record's slot; padding items
-// (0, 0) fill a lane's rounds; every step of every wave ends with a marker
-// round (kSparseStep in every lane) at which the workgroup synchronises.
-// Item column: bits 0-23 the slot, bits 24-26 g, bit 31 terminator.  Loads run
-// kSparseLead rounds ahead of use, so the item arrays carry 2 * kSparseLead
-// rounds of slack after their last wave.
+// few, long records), and each wave then streams its own rounds, one item per
+// lane and round: a 16-bit column and a value in the storage type.  A record's
+// entries go round-robin over its group's lanes, which add val * y[col] to their
+// sums; a terminator item (column kSparseTerm, value bits dest | g << 24 in the
+// low 32 bits) in every lane of the group, in the same round, has the group sum
+// its lanes and the first lane write the total to slot dest; padding items
+// (0, 0) fill a lane's rounds; every step of every wave ends with a marker round
+// (column kSparseMark in every lane) at which the workgroup synchronises.  A
+// wave has an even number of rounds, and the columns of rounds 2m and 2m + 1
+// share one 32-bit word per lane (low half, high half): word m * 64 + lane.
+// Loads run kSparseLead rounds ahead of use, so the item arrays carry
+// 2 * kSparseLead rounds of slack after their last wave.
 constexpr int kSparseWaves = kBandThreads / 64;
-constexpr int32_t kSparseEnd = INT32_MIN;
-constexpr int32_t kSparseStep = 0x40000000;
-constexpr int32_t kSparseSlotMask = 0x00ffffff;
+constexpr int32_t kSparseTerm = 0xfffe;
+constexpr int32_t kSparseMark = 0xffff;
+constexpr int32_t kSparseMaxSlots = 0xfffe;  // vector rows plus block slots
 constexpr int kSparseGroupShift = 24;
 constexpr int kSparseLead = 8;
 // The slab layout stores, per 32-row block, the strictly lower triangle of the
@@ -110,9 +112,9 @@ struct SubDev {
     // sparse Cholesky (local rows in elimination order); pass 0 = L (forward), 1 = L^T (backward),
     // as a lane stream (see kSparseWaves): wave w of the workgroup streams rounds
     // sp_wave[pass][2w] .. + sp_wave[pass][2w + 1] - 1, round r being the items
-    // sp_col / sp_val[pass][r * 64 + lane]
+    // (half r % 2 of sp_col[pass][(r / 2) * 64 + lane], sp_val[pass][r * 64 + lane])
     const int32_t* sp_wave[2];
-    const int32_t* sp_col[2];
+    const uint32_t* sp_col[2];
     const void* sp_val[2];    // storage type
     int32_t sp_nlev[2];       // steps of the pass
     int32_t sparse;           // 1: sparse Cholesky factor (sp_* valid)

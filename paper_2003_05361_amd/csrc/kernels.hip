@@ -1310,13 +1310,19 @@ __device__ __forceinline__ void slab_solve(const SubU& s, RAS_GLOBAL typename St
 // wave's part of a step with a workgroup barrier.  No load of the stream
 // depends on y, so each wave keeps kSparseLead rounds of loads in flight
 // across steps; the barrier drains only the LDS counter.
+__device__ __forceinline__ uint32_t low_bits(double v) {
+    return static_cast<uint32_t>(__builtin_bit_cast(uint64_t, v));
+}
+__device__ __forceinline__ uint32_t low_bits(float v) { return __builtin_bit_cast(uint32_t, v); }
+
 template <class ST>
-__device__ __attribute__((noinline)) void sparse_run(RAS_GLOBAL const int32_t* wave_tab, RAS_GLOBAL const int32_t* col,
+__device__ __attribute__((noinline)) void sparse_run(RAS_GLOBAL const int32_t* wave_tab, RAS_GLOBAL const uint32_t* col,
                                                      RAS_GLOBAL const ST* val,
                                                      RAS_LDS typename StorageTraits<ST>::CT* y) {
     using CT = typename StorageTraits<ST>::CT;
     constexpr int D = kSparseLead;
     static_assert(kBandThreads == 64 * kSparseWaves, "one wave stream per wave of the workgroup");
+    static_assert(D % 2 == 0, "column words hold two rounds");
     const int wave = uni(static_cast<int>(threadIdx.x) >> 6);
     const int lane = static_cast<int>(threadIdx.x) & 63;
     const int64_t base = uni(wave_tab[2 * wave]);
@@ -1326,45 +1332,49 @@ __device__ __attribute__((noinline)) void sparse_run(RAS_GLOBAL const int32_t* w
     uint32_t yb = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(y));
     asm volatile("" : "+s"(yb));
     RAS_LDS CT* yy = reinterpret_cast<RAS_LDS CT*>(static_cast<uintptr_t>(yb));
-    RAS_GLOBAL const int32_t* pc = col + base * 64 + lane;
+    // base is even: the wave's column words start at base / 2
+    RAS_GLOBAL const uint32_t* pc = col + (base / 2) * 64 + lane;
     RAS_GLOBAL const ST* pv = val + base * 64 + lane;
-    int32_t rc[D];
+    uint32_t rc[D / 2];
     CT rv[D];
-    // first rounds in the loop's own order (column, then value, round by round),
+    // first rounds in the loop's own order (column word, then the two values),
     // so that the memory waits of the loop hold on entry as in steady state
 #pragma unroll
-    for (int i = 0; i < D; ++i) {
-        rc[i] = pc[i * 64];
-        rv[i] = static_cast<CT>(pv[i * 64]);
+    for (int j = 0; j < D / 2; ++j) {
+        rc[j] = pc[j * 64];
+        rv[2 * j] = static_cast<CT>(pv[(2 * j) * 64]);
+        rv[2 * j + 1] = static_cast<CT>(pv[(2 * j + 1) * 64]);
         asm volatile("" ::: "memory");
     }
     CT acc = CT(0);
     for (int r0 = 0; r0 < R; r0 += D) {
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            const int c = rc[i];
+            const int c = static_cast<int>(i & 1 ? rc[i / 2] >> 16 : rc[i / 2] & 0xffffu);
             const CT v = rv[i];
             const int cu = uni(c);
-            const bool live = r0 + i < R && !(cu & kSparseStep);  // uniform
-            if (r0 + i < R && (cu & kSparseStep)) {
+            const bool live = r0 + i < R && cu != kSparseMark;  // uniform
+            if (r0 + i < R && cu == kSparseMark) {
                 lds_barrier();
                 acc = CT(0);
             }
-            const bool term = live && c < 0;
-            const bool add = live && c >= 0;
-            const int slot = live ? (c & kSparseSlotMask) : 0;
-            // a terminator's slot may hold anything (it is written, not read): select, do not scale
-            const CT yv = yy[add ? slot : 0];
+            const bool term = live && c == kSparseTerm;
+            const bool add = live && c < kSparseTerm;
+            const CT yv = yy[add ? c : 0];
             acc = add ? acc + v * yv : acc;
-            if (__ballot(term)) {
-                // groups of 2^g lanes end records together: sum over the group
-                const int g = (cu >> kSparseGroupShift) & 7;
+            const uint64_t tm = __ballot(term);
+            if (tm) {
+                // groups of 2^g lanes end records together: sum over the group; the
+                // terminator's value carries the slot and g
+                const uint32_t pay = low_bits(v);
+                const int g = (__builtin_amdgcn_readlane(static_cast<int>(pay), __builtin_ctzll(tm)) >>
+                               kSparseGroupShift) & 7;
                 CT t = acc;
                 for (int k = 0; k < g; ++k) t += __shfl_xor(t, 1 << k);
-                if (term && (lane & ((1 << g) - 1)) == 0) yy[slot] = t;
+                if (term && (lane & ((1 << g) - 1)) == 0) yy[pay & 0xffffffu] = t;
                 acc = term ? CT(0) : acc;
             }
-            rc[i] = pc[(r0 + i + D) * 64];
+            if (i & 1) rc[i / 2] = pc[((r0 + D) / 2 + i / 2) * 64];
             rv[i] = static_cast<CT>(pv[(r0 + i + D) * 64]);
         }
     }

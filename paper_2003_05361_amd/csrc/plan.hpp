@@ -49,8 +49,8 @@ struct SparseSchedule {
 // items col / val[r * 64 + lane]; see kSparseWaves for the item semantics.
 struct SparseLanes {
     std::vector<int32_t> wave;
-    std::vector<int32_t> col;
-    std::vector<double> val;
+    std::vector<uint16_t> col;
+    std::vector<double> val;  // a terminator's value holds dest | g << 24 in its low 32 bits
 };
 
 struct Subdomain {

@@ -15,6 +15,7 @@
 // scattering each finished entry along its column.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <functional>
 #include <numeric>
 #include <queue>
@@ -516,7 +517,7 @@ int64_t deal(const std::vector<int32_t>& order, const std::vector<int64_t>& roun
 void pack_schedule(const SparseSchedule& q, SparseLanes* out) {
     constexpr int W = kSparseWaves, NL = 64 * kSparseWaves;
     const int32_t nsteps = static_cast<int32_t>(q.step.size()) - 1;
-    std::vector<std::vector<int32_t>> wc(W);
+    std::vector<std::vector<uint16_t>> wc(W);
     std::vector<std::vector<double>> wv(W);
     std::vector<std::vector<int32_t>> groups;
     std::vector<int64_t> load, rounds;
@@ -544,12 +545,12 @@ void pack_schedule(const SparseSchedule& q, SparseLanes* out) {
         gorder.resize(ng);
         std::iota(gorder.begin(), gorder.end(), 0);
         std::stable_sort(gorder.begin(), gorder.end(), [&](int32_t a, int32_t b) { return load[a] > load[b]; });
-        const int32_t tag = lg << kSparseGroupShift;
+        const uint32_t tag = static_cast<uint32_t>(lg) << kSparseGroupShift;
         for (int w = 0; w < W; ++w) {
             int64_t U = 0;
             for (int i = 0; i < gpw; ++i) U = std::max(U, load[gorder[gpw * w + i]]);
             const size_t base = wc[w].size();
-            wc[w].resize(base + static_cast<size_t>(U + 1) * 64, tag);
+            wc[w].resize(base + static_cast<size_t>(U + 1) * 64, 0);
             wv[w].resize(base + static_cast<size_t>(U + 1) * 64, 0.0);
             for (int i = 0; i < gpw; ++i) {
                 int64_t u = 0;  // next round of this group
@@ -557,17 +558,30 @@ void pack_schedule(const SparseSchedule& q, SparseLanes* out) {
                     const int32_t e0 = q.meta[4 * r + 1], e1 = q.meta[4 * r + 2];
                     for (int32_t e = e0; e < e1; ++e) {
                         const size_t at = base + static_cast<size_t>(u + (e - e0) / G) * 64 + i * G + (e - e0) % G;
-                        wc[w][at] = q.col[e] | tag;
+                        wc[w][at] = static_cast<uint16_t>(q.col[e]);
                         wv[w][at] = q.val[e];
                     }
                     u += (e1 - e0 + G - 1) / G;
-                    for (int l = 0; l < G; ++l) wc[w][base + static_cast<size_t>(u) * 64 + i * G + l] = q.meta[4 * r] | tag | kSparseEnd;
+                    // terminator: the destination and the group width in the value's low 32 bits
+                    const uint64_t pay = static_cast<uint32_t>(q.meta[4 * r]) | tag;
+                    double pv;
+                    std::memcpy(&pv, &pay, sizeof pv);
+                    for (int l = 0; l < G; ++l) {
+                        wc[w][base + static_cast<size_t>(u) * 64 + i * G + l] = static_cast<uint16_t>(kSparseTerm);
+                        wv[w][base + static_cast<size_t>(u) * 64 + i * G + l] = pv;
+                    }
                     ++u;
                 }
             }
-            for (int l = 0; l < 64; ++l) wc[w][base + static_cast<size_t>(U) * 64 + l] = kSparseStep;
+            for (int l = 0; l < 64; ++l) wc[w][base + static_cast<size_t>(U) * 64 + l] = static_cast<uint16_t>(kSparseMark);
         }
     }
+    // an even round count per wave (the device loads the columns of two rounds in one word)
+    for (int w = 0; w < W; ++w)
+        if ((wc[w].size() / 64) % 2) {
+            wc[w].resize(wc[w].size() + 64, 0);
+            wv[w].resize(wv[w].size() + 64, 0.0);
+        }
     out->wave.assign(2 * W, 0);
     out->col.clear();
     out->val.clear();
@@ -604,7 +618,9 @@ void sparse_factor_local(Plan& plan, size_t lds_bytes, size_t value_bytes) {
         Subdomain& sd = plan.subs[p];
         sparse_factor_one(plan, sd, static_cast<int32_t>(p));
         const std::vector<int32_t> runs = dense_runs(sd.sf);
-        const int64_t avail = static_cast<int64_t>(lds_bytes / value_bytes) - static_cast<int64_t>(sd.omega.size());
+        // slots fit in LDS beside the vector, and in the items' 16-bit columns
+        const int64_t avail = std::min<int64_t>(static_cast<int64_t>(lds_bytes / value_bytes), kSparseMaxSlots) -
+                              static_cast<int64_t>(sd.omega.size());
         sd.min_block = choose_min_block(sd.sf, runs, avail);
         sparse_schedule(sd.sf, runs, sd.min_block, true, &sd.sched[0]);
         sparse_schedule(sd.sf, runs, sd.min_block, false, &sd.sched[1]);

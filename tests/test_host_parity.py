@@ -409,55 +409,58 @@ def test_sparse_schedule_solves_the_triangular_systems(name, A, part, gamma, sto
 
 def _run_lanes(lay, v, nslots):
     """Applies a pass in the device's lane layout with the kernel's semantics:
-    every wave streams its rounds, a lane adds val * y[slot] to its sum, a
-    terminator in every lane of a group of 2^g lanes (g in bits 24-26 of the
-    column) has the group add its sums and write the total to the slot, a
-    marker round ends the wave's part of a step and all waves meet there.
-    Within a step the waves and lanes run in any order; here each step is
-    applied wave by wave with the values of the step's start for reads, and a
-    read of a slot written in the same step fails.  Padding items (slot 0,
-    value 0) add nothing and are exempt."""
+    every wave streams its rounds, a lane adds val * y[col] to its sum, a
+    terminator (column 0xfffe) in every lane of a group of 2^g lanes has the
+    group add its sums and write the total to the slot held with g in the low
+    32 bits of the value, a marker round (column 0xffff) ends the wave's part
+    of a step and all waves meet there.  Within a step the waves and lanes run
+    in any order; here each step is applied wave by wave with the values of
+    the step's start for reads, and a read of a slot written in the same step
+    fails.  Padding items (0, 0) add nothing and are exempt."""
     n = v.size
     y = np.concatenate([v, np.full(nslots, np.nan)])
     wave, col, val = lay["wave"], lay["col"], lay["val"]
-    STEP, MASK = 2**30, 2**24 - 1
+    TERM, MARK = 0xFFFE, 0xFFFF
+    pay_all = val.view(np.uint64) & np.uint64(0xFFFFFFFF)
     streams = []
     for w0, nr in wave:
         c = col[w0:w0 + nr]
-        marks = np.flatnonzero(np.all(c == STEP, axis=1))
-        assert not np.any(c[np.setdiff1d(np.arange(nr), marks)] == STEP)
-        streams.append((c, val[w0:w0 + nr], np.concatenate([[-1], marks])))
-    nsteps = {len(m) - 1 for _, _, m in streams}
+        marks = np.flatnonzero(np.all(c == MARK, axis=1))
+        assert not np.any(c[np.setdiff1d(np.arange(nr), marks)] == MARK)
+        streams.append((c, val[w0:w0 + nr], pay_all[w0:w0 + nr], np.concatenate([[-1], marks])))
+    nsteps = {len(m) - 1 for _, _, _, m in streams}
     assert len(nsteps) == 1  # every wave meets every barrier
     lanes = np.arange(64)
     for s in range(nsteps.pop()):
         start = y.copy()
         wrote = np.zeros(y.size, dtype=bool)
-        for c, vv, marks in streams:
+        for c, vv, pay, marks in streams:
             acc = np.zeros(64)
             g = None
             for r in range(marks[s] + 1, marks[s + 1]):
                 cr, vr = c[r], vv[r]
-                gr = (cr >> 24) & 7
-                g = gr[0] if g is None else g
-                assert np.all(gr == g)  # one group width per wave and step
-                G = 1 << int(g)
-                term = cr < 0
-                slot = cr & MASK
-                pad = (slot == 0) & (vr == 0) & ~term
+                term = cr == TERM
+                pad = (cr == 0) & (vr == 0)
                 rd = ~term & ~pad
-                assert not np.any(wrote[slot[rd]]), s
-                acc[rd] += vr[rd] * start[slot[rd]]
+                assert not np.any(wrote[cr[rd]]), s
+                acc[rd] += vr[rd] * start[cr[rd]]
                 if term.any():
+                    pr = pay[r][term].astype(np.int64)
+                    gr = (pr >> 24) & 7
+                    g = gr[0] if g is None else g
+                    assert np.all(gr == g)  # one group width per wave and step
+                    G = 1 << int(g)
+                    dest = np.zeros(64, dtype=np.int64)
+                    dest[term] = pr & 0xFFFFFF
                     tg = term.reshape(-1, G)
                     assert np.all(tg.all(axis=1) | ~tg.any(axis=1))  # whole groups end together
+                    dg = dest.reshape(-1, G)[tg.any(axis=1)]
+                    assert np.all(dg.min(axis=1) == dg.max(axis=1))
                     sums = acc.reshape(-1, G).sum(axis=1)
                     lead = term & (lanes % G == 0)
-                    assert np.all(slot.reshape(-1, G)[tg.any(axis=1)].min(axis=1) ==
-                                  slot.reshape(-1, G)[tg.any(axis=1)].max(axis=1))
-                    assert not np.any(wrote[slot[lead]])
-                    y[slot[lead]] = sums[lanes[lead] // G]
-                    wrote[slot[lead]] = True
+                    assert not np.any(wrote[dest[lead]])
+                    y[dest[lead]] = sums[lanes[lead] // G]
+                    wrote[dest[lead]] = True
                     acc[term] = 0.0
     return y[:n]
 
