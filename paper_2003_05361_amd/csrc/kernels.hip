@@ -1346,11 +1346,21 @@ __device__ __attribute__((noinline)) void sparse_run(RAS_GLOBAL const int32_t* w
         rv[2 * j + 1] = static_cast<CT>(pv[(2 * j + 1) * 64]);
         asm volatile("" ::: "memory");
     }
+    // column of ring slot j (two rounds per word)
+    auto col_at = [&](int j) { return static_cast<int>(j & 1 ? rc[j / 2] >> 16 : rc[j / 2] & 0xffffu); };
     CT acc = CT(0);
+    // y of the next round is read one round ahead of its use: after this round's
+    // barrier and before this round's write, which is legal because no record
+    // reads a slot written in its own step
+    CT ynext;
+    {
+        const int c0 = col_at(0);
+        ynext = yy[R > 0 && c0 < kSparseTerm ? c0 : 0];
+    }
     for (int r0 = 0; r0 < R; r0 += D) {
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            const int c = static_cast<int>(i & 1 ? rc[i / 2] >> 16 : rc[i / 2] & 0xffffu);
+            const int c = col_at(i);
             const CT v = rv[i];
             const int cu = uni(c);
             const bool live = r0 + i < R && cu != kSparseMark;  // uniform
@@ -1358,9 +1368,13 @@ __device__ __attribute__((noinline)) void sparse_run(RAS_GLOBAL const int32_t* w
                 lds_barrier();
                 acc = CT(0);
             }
+            const CT yv = ynext;
+            {
+                const int cn = col_at((i + 1) % D);
+                ynext = yy[r0 + i + 1 < R && cn < kSparseTerm ? cn : 0];
+            }
             const bool term = live && c == kSparseTerm;
             const bool add = live && c < kSparseTerm;
-            const CT yv = yy[add ? c : 0];
             acc = add ? acc + v * yv : acc;
             const uint64_t tm = __ballot(term);
             if (tm) {
