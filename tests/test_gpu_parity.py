@@ -643,3 +643,35 @@ def test_config3_full_size_first_sweep_sampled():
     for p in (0, 77, 160, 255):
         own, d = _oracle_subdomain_update(A, owner, p, 1, b, ("cg", "fp32", 8))
         _agree(x[own], d, 2e-5, (p, team, _rel(x[own], d)))
+
+
+@pytest.mark.gpu
+def test_exact_local_autotune_picks_the_faster_and_it_converges():
+    """The exact-local-solver tuner times both Cholesky solvers on the system,
+    returns the faster one (the report holds both), caches the choice per
+    shape, and the chosen solver reaches the tolerance with the same sweep
+    count as the other (same iteration up to rounding, Sec. 3.3.1)."""
+    ras = _ras()
+    from paper_2003_05361_amd import autotune
+
+    _say("case: exact local autotune 96^2 4x4")
+    A = R.laplace2d(96)
+    b = _cuda(R.uniform_rhs(A.n, 31))
+    part = _spec(ras, A, "regular_2d", (4, 4))
+    loc, rep = autotune.exact_local(A, part, 3, b, "fp64", sweeps=10)
+    ms = rep["ms_per_sweep"]
+    assert ms["chol"] > 0 and ms["chol_sparse"] > 0
+    assert rep["choice"] == min(ms, key=ms.get) and loc["kind"] == rep["choice"]
+    loc2, rep2 = autotune.exact_local(A, part, 3, b, "fp64")
+    assert rep2["cached"] and loc2 == loc
+    sweeps = {}
+    for kind in ("chol", "chol_sparse"):
+        h = ras.setup(A, part, 3, ras.local(kind, "fp64"))
+        _, info = h.solve(b, tol=1e-9, mode="sync", max_sweeps=100000)
+        assert info[0]["converged"]
+        sweeps[kind] = info[0]["sweeps"]
+        h.close()
+    assert sweeps["chol"] == sweeps["chol_sparse"]
+    # FP16 storage: the band is the only candidate
+    _, rep16 = autotune.exact_local(A, part, 3, b, "fp16", sweeps=5)
+    assert rep16["choice"] == "chol" and rep16["ms_per_sweep"]["chol_sparse"] is None
