@@ -43,3 +43,17 @@ def test_more_than_one_gpu_is_refused():
     p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert p.returncode != 0 and "one GPU" in p.stderr
+
+
+def test_resident_roofline_reports_the_counter_rate():
+    """A cache-resident workload's roofline never reports the streaming-model rate
+    as an HBM rate: achieved and frac come from the counters, or are null."""
+    import bench
+
+    roof = {"bound": "hbm", "achieved": 8740.0, "frac": 1.0925, "peak": 8000.0}
+    bench.resident_roofline(roof, 4500.04)
+    assert roof["achieved"] == 4500.0 and roof["frac"] == round(4500.04 / 8000.0, 4)
+    assert roof["model_GBps"] == 8740.0
+    roof = {"bound": "hbm", "achieved": 8740.0, "frac": 1.0925, "peak": 8000.0}
+    bench.resident_roofline(roof, None)
+    assert roof["achieved"] is None and roof["frac"] is None and roof["model_GBps"] == 8740.0
