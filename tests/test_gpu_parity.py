@@ -610,15 +610,19 @@ def _oracle_subdomain_update(A, owner, p, gamma, r, local):
     return own, d[pos]
 
 
-@pytest.mark.parametrize("storage,tol", [("fp64", 1e-9), ("fp32", 2e-5), ("fp16", 2e-5)])
-def test_config4_full_size_first_sweep_sampled(storage, tol):
-    """2048^2 diffusion, 16x16 subdomains, overlap 4, banded Cholesky in the bench's
-    launch shape (256 workgroups, slab layout): one synchronous sweep from x = 0
-    against the oracle's update of sampled subdomains (corners, edge, interior)."""
+@pytest.mark.parametrize("kind,storage,tol", [("chol", "fp64", 1e-9), ("chol", "fp32", 2e-5), ("chol", "fp16", 2e-5),
+                                              ("chol_sparse", "fp64", 1e-9)])
+def test_config4_full_size_first_sweep_sampled(kind, storage, tol):
+    """2048^2 diffusion, 16x16 subdomains, overlap 4, banded Cholesky (slab layout)
+    or sparse Cholesky (lane streams) in the bench's launch shape (256
+    workgroups): one synchronous sweep from x = 0 against the oracle's update of
+    sampled subdomains (corners, edge, interior); the sparse factor solves the
+    same local systems exactly (another elimination order, the same solution up to
+    rounding), so the oracle's exact solve is its reference."""
     ras = _ras()
-    _say(f"case: diffusion2d_2048_16x16 first sweep sampled {storage}")
+    _say(f"case: diffusion2d_2048_16x16 first sweep sampled {kind} {storage}")
     A, b, cfg = R.config_problem("diffusion2d_2048_16x16")
-    h = ras.setup(A, ras.partition("regular_2d", (16, 16), grid=A.grid), 4, ras.local("chol", storage))
+    h = ras.setup(A, ras.partition("regular_2d", (16, 16), grid=A.grid), 4, ras.local(kind, storage))
     x, _ = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=1)
     x = x.cpu().numpy()
     owner = opart.regular_grid(A.grid, (16, 16))
