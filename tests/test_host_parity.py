@@ -552,6 +552,37 @@ def test_sparse_solver_arguments():
     assert e.value.status == -6
 
 
+def test_sparse_schedule_arguments():
+    """The schedule queries reject a pass other than 0 / 1, a subdomain out of
+    range and a plan without sparse factors; the lane layout keeps every slot
+    of the vector and the block slots below the 16-bit item columns' markers."""
+    _lib_or_skip()
+    A = R.laplace2d(24)
+    plan = ras.Plan(A, ras.partition("regular_2d", (2, 2), grid=A.grid), 1, ras.local("chol_sparse", "fp32"))
+    for bad in ((0, 2), (0, -1), (4, 0), (-1, 0)):
+        with pytest.raises(ras.RasError) as e:
+            plan.sparse_schedule(*bad)
+        assert e.value.status == -1
+        with pytest.raises(ras.RasError) as e:
+            plan.sparse_lanes(*bad)
+        assert e.value.status == -1
+    band = ras.Plan(A, ras.partition("regular_2d", (2, 2), grid=A.grid), 1, ras.local("chol", "fp32"))
+    for call in (band.sparse_schedule, band.sparse_lanes):
+        with pytest.raises(ras.RasError) as e:
+            call(0, 0)
+        assert e.value.status == -6
+    _, ptr, _ = plan.sets()
+    for p in range(4):
+        n = int(ptr[p + 1] - ptr[p])
+        for pass_ in (0, 1):
+            sch = plan.sparse_schedule(p, pass_)
+            lay = plan.sparse_lanes(p, pass_)
+            assert n + sch["slots"] < 0xFFFE
+            cols = lay["col"]
+            assert np.all((cols < n + sch["slots"]) | (cols >= 0xFFFE))
+            assert np.all(lay["wave"][:, 1] % 2 == 0)  # two rounds per column word on the device
+
+
 def test_sparse_factor_of_disconnected_local_matrices():
     """Subdomains whose local matrix falls apart (a block-diagonal A: many small
     independent systems) are ordered component by component."""
