@@ -13,6 +13,12 @@
 // then an up-looking numeric factorisation: row k of L solves the triangular
 // system with the rows above it, visiting its pattern in ascending order and
 // scattering each finished entry along its column.
+//
+// Solve schedules: each triangular pass becomes a short sequence of parallel
+// steps, dense separator blocks solved through the explicit inverses of their
+// triangles (Alvarado and Schreiber, SIAM J. Sci. Comput. 14, 1993), and each
+// step's records are dealt out to the lanes of one workgroup (the device's
+// lane-stream layout).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
