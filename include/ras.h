@@ -140,7 +140,14 @@ typedef struct ras_local {
  *     rather than the one before it.  Negative: library choice (0.25 for the
  *     Cholesky solvers, 0 for CG).  Ignored by SYNC and ORDERED.  */
 enum { RAS_MODE_SYNC = 0, RAS_MODE_ASYNC = 1, RAS_MODE_ORDERED = 2 };
-enum { RAS_DETECT_CENTRAL = 0, RAS_DETECT_DECENTRAL = 1 };
+/* Detectors of the asynchronous mode.  CENTRAL (Sec. 2.2): every subdomain's
+ * latest local criterion holds and the sum of the latest owned residuals is
+ * below tol^2 ||b||^2.  DECENTRAL (Sec. 2.2, Sec. 3.3.2): neighbour flags and
+ * flooding.  ESTIMATE (a library option, not the paper's): every subdomain has
+ * updated since the launch and the sum of the latest owned residuals is below
+ * tol^2 ||b||^2; it does not wait for the slowest local criterion.  Every
+ * detector's stop is verified exactly and the iteration resumes if it fails.  */
+enum { RAS_DETECT_CENTRAL = 0, RAS_DETECT_DECENTRAL = 1, RAS_DETECT_ESTIMATE = 2 };
 typedef struct ras_solve_opts {
     int32_t mode;
     int32_t detect;

@@ -148,7 +148,11 @@ class RAS:
         raises its global flag when it and all its neighbours report local
         convergence, or when a neighbour's flag is up (flooding), and then stops
         updating; once every flag is up the global criterion is verified, and on
-        failure all flags are cleared and the iteration resumes.  Subdomains in
+        failure all flags are cleared and the iteration resumes.  Estimate
+        detection (the library's option, not the paper's): once every subdomain
+        has updated since the last reset and the sum of the owned residuals each
+        computed at its latest update is below tol^2 ||b||^2, the global
+        criterion is verified; on failure the update marks are cleared.  Subdomains in
         `paused` take no events before event `pause_until` (forced staleness).
         Returns (x, info dict)."""
         rng = np.random.default_rng(seed)
@@ -158,6 +162,7 @@ class RAS:
         versions = [[x[s.owned].copy()] for s in self.subs]
         conv = np.zeros(P, dtype=bool)
         gflag = np.zeros(P, dtype=bool)
+        own2 = np.full(P, np.inf)  # owned residual^2 of each subdomain's latest update
         nbrs = self.neighbours() if detect == "decentral" else None
         counts = np.zeros(P, dtype=np.int64)
         verifications = 0
@@ -177,6 +182,9 @@ class RAS:
             s = self.subs[p]
             rp = ores.residual(self.M, view, b, s.omega)
             conv[p] = float(rp @ rp) < tol * tol * float(b[s.omega] @ b[s.omega])
+            own2[p] = float(rp[s.pos] @ rp[s.pos])
+            if detect == "estimate":
+                conv[p] = True  # the mark: updated since the last reset
             delta = s.solver(rp)
             x[s.owned] += delta[s.pos]
             versions[p].append(x[s.owned].copy())
@@ -197,7 +205,7 @@ class RAS:
                 gflag[:] = False
                 conv[:] = False
                 continue
-            if conv.all():
+            if conv.all() and (detect != "estimate" or own2.sum() < tol * tol * bn2):
                 verifications += 1
                 r = self.residual(x, b)
                 if float(r @ r) < tol * tol * bn2:

@@ -33,7 +33,7 @@ PART_KINDS = {"regular_1d": 0, "regular_2d": 1, "regular_3d": 2, "rcb": 3, "expl
 LOCAL_KINDS = {"chol": 0, "cg": 1, "chol_sparse": 2}
 STORAGES = {"fp64": 0, "fp32": 1, "fp16": 2}
 MODES = {"sync": 0, "async": 1, "ordered": 2}
-DETECT = {"central": 0, "decentral": 1}
+DETECT = {"central": 0, "decentral": 1, "estimate": 2}
 # size of the library's fixed device workspace of ras_solve_noalloc (per device)
 NOALLOC_SCRATCH_BYTES = 32 * 1024 * 1024
 # asynchronous mode: neighbour wait budget before a read, in units of the previous update's time
@@ -396,7 +396,9 @@ class Handle:
               max_seconds: float = 0.0, detect: str = "central", workgroups: int = 0, team: int = 0,
               allow_unconverged=True, pace=None, noalloc: bool = False):
         """Solve A x = b on the device.  b: float64 CUDA tensor [n] or [nrhs, n].
-        mode: "sync", "async" or "ordered"; detect: "central" or "decentral";
+        mode: "sync", "async" or "ordered"; detect: "central", "decentral" or
+        "estimate" (a library option: stop on the owned-residual estimate once every
+        subdomain has updated, verified exactly like the others);
         pace (async): neighbour wait budget before a read, in units of the
         previous update's time (None: the library's choice per local solver).
         noalloc: run through ras_solve_noalloc (workspace in the library's fixed

@@ -784,7 +784,8 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     if (o.mode != RAS_MODE_SYNC && o.mode != RAS_MODE_ASYNC && o.mode != RAS_MODE_ORDERED)
         throw Error{RAS_E_ARG, "unknown mode"};
     if (!(o.tol >= 0.0) || o.max_sweeps < 1) throw Error{RAS_E_ARG, "tol must be >= 0 and max_sweeps >= 1"};
-    if (o.detect != RAS_DETECT_CENTRAL && o.detect != RAS_DETECT_DECENTRAL) throw Error{RAS_E_ARG, "unknown detector"};
+    if (o.detect != RAS_DETECT_CENTRAL && o.detect != RAS_DETECT_DECENTRAL && o.detect != RAS_DETECT_ESTIMATE)
+        throw Error{RAS_E_ARG, "unknown detector"};
     if (!(o.pace <= 16.0)) throw Error{RAS_E_ARG, "pace must be at most 16 (negative: library choice)"};
     // distinct handles, in first-use order
     std::vector<ras_handle*> hs;

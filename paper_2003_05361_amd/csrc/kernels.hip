@@ -1678,7 +1678,9 @@ __device__ __forceinline__ void run_async(const Params& P, U& upd, TeamCtx& tc, 
             team_barrier(tc);  // every member's part of x is written (and fenced) before the publish
             if (tid == 0 && tc.member == 0) {
                 st_rlx(P.res2_own + it, own2);
-                st_rlx(P.conv + it, static_cast<int32_t>(loc2 < in.tol2 * b2));
+                // the local criterion (eq. local_conv); the estimate detector only needs to
+                // know that the subdomain has updated since the launch
+                st_rlx(P.conv + it, static_cast<int32_t>(P.detect == 2 || loc2 < in.tol2 * b2));
                 P.solves[it] += 1;
                 __hip_atomic_fetch_add(P.version + it, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
@@ -1704,6 +1706,7 @@ __device__ __forceinline__ void run_async(const Params& P, U& upd, TeamCtx& tc, 
             }
             if (wg == in.leader && it == in.item_begin) {
                 // centralized detector (Sec. 2.2): all local criteria + owned-residual estimate
+                // (estimate detector: every subdomain updated + owned-residual estimate)
                 int allc = 1;
                 double sum = 0.0;
                 for (int k = tid; k < in.item_count; k += B) {
@@ -1723,7 +1726,7 @@ __device__ __forceinline__ void run_async(const Params& P, U& upd, TeamCtx& tc, 
                     st->sweeps += 1;
                     int32_t stop = 0;
                     if (!(sum == sum) || sum > 1e300) stop = 4;
-                    else if (P.detect == 0 && allc && sum < in.tol2 * in.bnorm2) stop = 1;
+                    else if (P.detect != 1 && allc && sum < in.tol2 * in.bnorm2) stop = 1;
                     else if (P.max_ticks > 0 && now - st->t0 > P.max_ticks) stop = 2;
                     if (stop) st_rlx(&st->stop, stop);
                 }

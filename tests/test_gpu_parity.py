@@ -367,6 +367,27 @@ def test_async_decentralized_detection(loc, st, k, team):
         assert _rel(xx, xd) <= 1e-6
 
 
+@pytest.mark.parametrize("loc,st,k,team", [("chol", "fp64", 0, 0), ("chol_sparse", "fp32", 0, 0),
+                                          ("cg", "fp64", 10, 4)])
+def test_async_estimate_detection(loc, st, k, team):
+    """The estimate detector (the library's option: stop on the owned-residual
+    estimate once every subdomain has updated) still returns only verified
+    solutions."""
+    ras = _ras()
+    _say(f"case: async estimate {loc} {st} team={team}")
+    A = R.laplace2d(96)
+    b = R.uniform_rhs(A.n, 17)
+    xd = schwarz.direct_solve(A, b)
+    h = ras.setup(A, ras.partition("regular_2d", (4, 4), grid=A.grid), 3, ras.local(loc, st, k))
+    for run in range(2):
+        x, info = h.solve(_cuda(b), tol=1e-8, mode="async", detect="estimate", max_sweeps=200000, max_seconds=60,
+                          team=team)
+        xx = x.cpu().numpy()
+        assert info[0]["converged"], info
+        assert schwarz.relative_residual(A, xx, b) < 1e-8
+        assert _rel(xx, xd) <= 1e-6
+
+
 @pytest.mark.parametrize("pace", [0.0, 0.25, 16.0])
 def test_async_paced_reads(pace):
     """Paced reads wait for slower neighbours before reading (bounded by pace times

@@ -589,6 +589,23 @@ def test_async_simulator_decentralized_detection():
     assert np.linalg.norm(x - xd) <= 1e-6 * np.linalg.norm(xd)
 
 
+def test_async_simulator_estimate_detection():
+    """The estimate detector stops on the sum of the owned residuals of every
+    subdomain's latest update once all have updated; its stop is verified
+    exactly, so the result meets the global criterion, and with a subdomain
+    paused it cannot stop before that subdomain has updated."""
+    A = R.laplace2d(24)
+    b = R.uniform_rhs(A.n, 10)
+    xd = schwarz.direct_solve(A, b)
+    ras = schwarz.RAS(A, partition.regular_grid(A.grid, (3, 3)), 2, "chol")
+    x, info = ras.async_sim(b, 1e-8, seed=3, staleness=2, max_updates=200000, detect="estimate")
+    assert info["converged"] and schwarz.relative_residual(A, x, b) < 1e-8
+    assert np.linalg.norm(x - xd) <= 1e-6 * np.linalg.norm(xd)
+    x, info = ras.async_sim(b, 1e-8, seed=3, staleness=2, max_updates=200000, detect="estimate",
+                            paused={4}, pause_until=3000)
+    assert info["converged"] and info["events"] > 3000 and schwarz.relative_residual(A, x, b) < 1e-8
+
+
 def test_async_simulator_waits_for_paused_subdomain():
     A = R.laplace2d(16)
     b = R.uniform_rhs(A.n, 9)
