@@ -267,6 +267,22 @@ void ras_plan_destroy(ras_plan* plan);
  * allocates.  hip_stream may be NULL (default stream).  */
 ras_status ras_setup(const ras_csr* A, const ras_partition* part, int32_t overlap, const ras_local* local,
                      void* hip_stream, ras_handle** out);
+/* Host-forced stall and cancel of asynchronous solves (fault injection and
+ * control, callable from another thread while ras_solve runs; the words are
+ * pinned, coherent host memory that the running kernel polls).
+ * ras_pause: while paused != 0, subdomain p takes no updates in ASYNC mode
+ * (its neighbours keep reading its last values; a detector's stop is still
+ * verified exactly, so a stall cannot end the solve as converged unless the
+ * iterate meets the tolerance); the setting persists across solves until
+ * cleared.  Such a solve ends only once the subdomain is
+ * resumed, at max_seconds, or when cancelled, so give it a time limit.  SYNC
+ * and ORDERED modes ignore pauses.
+ * ras_cancel: the ASYNC solve running on the handle stops at its workgroups'
+ * next check and returns like a time limit (RAS_NOT_CONVERGED with the
+ * current iterate); every solve clears the request when it starts.
+ * RAS_E_ARG for a null handle or p out of range.  */
+ras_status ras_pause(ras_handle* h, int32_t p, int32_t paused);
+ras_status ras_cancel(ras_handle* h);
 /* Uploads a plan; the plan stays owned by the caller.  */
 ras_status ras_setup_from_plan(const ras_plan* plan, void* hip_stream, ras_handle** out);
 ras_status ras_handle_get_stats(const ras_handle* h, ras_plan_stats* out);

@@ -115,6 +115,8 @@ SIGNATURES = {
     "ras_phase_seconds": (C.c_int, [_P, C.c_int32, _P]),
     "ras_autotune": (C.c_int, [_P, _P, _P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "ras_destroy": (None, [_P]),
+    "ras_pause": (C.c_int, [_P, C.c_int32, C.c_int32]),
+    "ras_cancel": (C.c_int, [_P]),
     "ras_server_create": (C.c_int, [C.c_int64, C.c_double, _P, C.POINTER(_P)]),
     "ras_server_submit": (C.c_int, [_P, C.POINTER(CSRStruct), C.POINTER(PartitionStruct), C.c_int32,
                                     C.POINTER(LocalStruct), _P, C.c_int32, C.c_double, C.POINTER(C.c_uint64)]),
@@ -463,6 +465,16 @@ class Handle:
         _check(lib().ras_autotune(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), int(sweeps),
                                   C.byref(t), C.byref(ms)))
         return t.value, ms.value
+
+    def pause(self, p: int, paused: bool = True) -> None:
+        """Stall (or resume) subdomain p of asynchronous solves; may be called from
+        another thread while a solve runs.  Give paused solves a time limit."""
+        _check(lib().ras_pause(self._h, int(p), 1 if paused else 0))
+
+    def cancel(self) -> None:
+        """Stop the asynchronous solve running on this handle (from another thread);
+        it returns not converged with the current iterate."""
+        _check(lib().ras_cancel(self._h))
 
     def factor(self, p: int) -> tuple[np.ndarray, int]:
         """Subdomain p's banded Cholesky factor as the solves use it (read back from

@@ -120,6 +120,15 @@ struct ras_handle {
     DevBuf omega, ell_val, ell_valf, ell_gcol, ell_lcol, band_f, band_b, scale, invd, ext, sp_idx, sp_val;
     DevBuf csr_rp, csr_ci, csr_va, nbr;
     DevBuf tri_g;  // FP16 slab: packed float32 inverses of the block triangles (both passes)
+    // host-written control words (cancel, per-subdomain pause), pinned and coherent so
+    // that a running asynchronous kernel sees the host's writes
+    struct Control {
+        int32_t* host = nullptr;
+        int32_t* dev = nullptr;
+        ~Control() {
+            if (host) (void)hipHostFree(host);
+        }
+    } ctl;
     std::vector<SubDev> subs;  // host copy with device pointers
     // CG team windows: for team size kTeamSizes[t], per subdomain and member the
     // LDS window [lo, hi) of local rows its rows reference
@@ -697,6 +706,18 @@ void upload(ras_handle& h, const Plan& plan) {
         h.subs[p] = d;
     }
     if (!dev_factor.empty()) device_factor(h, plan, dev_factor);
+    // control words: cancel, then one pause word per subdomain
+    {
+        void* hp = nullptr;
+        hip_check(hipHostMalloc(&hp, (1 + static_cast<size_t>(P)) * sizeof(int32_t),
+                                hipHostMallocMapped | hipHostMallocCoherent),
+                  "control words");
+        h.ctl.host = static_cast<int32_t*>(hp);
+        std::memset(h.ctl.host, 0, (1 + static_cast<size_t>(P)) * sizeof(int32_t));
+        void* dp = nullptr;
+        hip_check(hipHostGetDevicePointer(&dp, hp, 0), "control words (device address)");
+        h.ctl.dev = static_cast<int32_t*>(dp);
+    }
     // neighbours: subdomains owning a column read by a row of Omega_p (the
     // residual's interface columns included); used by decentralized detection
     {
@@ -1049,6 +1070,8 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
         in.max_sweeps = o.max_sweeps;
         in.tol2 = tol_v[i] * tol_v[i];
         in.leader = owner_wg[in.item_begin];
+        in.ctl = ordered ? nullptr : specs[i].h->ctl.dev;  // ORDERED ignores pauses and cancels
+        if (specs[i].h->ctl.host) __atomic_store_n(specs[i].h->ctl.host, 0, __ATOMIC_SEQ_CST);  // a new solve: not cancelled
     }
     {
         // ||b||^2 of the right-hand sides not given one (deterministic two-pass
@@ -2044,6 +2067,23 @@ ras_status ras_relative_residual(ras_handle* h, const double* b_dev, const doubl
 }
 
 void ras_destroy(ras_handle* h) { delete h; }
+
+ras_status ras_pause(ras_handle* h, int32_t p, int32_t paused) {
+    return guarded([&] {
+        if (!h || !h->ctl.host) throw Error{RAS_E_ARG, "null handle"};
+        if (p < 0 || p >= h->plan->P) throw Error{RAS_E_ARG, "subdomain out of range"};
+        __atomic_store_n(h->ctl.host + 1 + p, paused ? 1 : 0, __ATOMIC_SEQ_CST);
+        return RAS_OK;
+    });
+}
+
+ras_status ras_cancel(ras_handle* h) {
+    return guarded([&] {
+        if (!h || !h->ctl.host) throw Error{RAS_E_ARG, "null handle"};
+        __atomic_store_n(h->ctl.host, 1, __ATOMIC_SEQ_CST);
+        return RAS_OK;
+    });
+}
 
 ras_status ras_autotune(ras_handle* h, const double* b_dev, double* x_dev, int32_t sweeps, int32_t* best_team,
                         double* best_ms_per_sweep) {

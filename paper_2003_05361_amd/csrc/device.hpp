@@ -167,6 +167,10 @@ struct InstDev {
     int32_t item_count;
     int32_t leader;           // workgroup owning item_begin (runs the detector / records history)
     int32_t pad_;
+    // host-written control words of the system's handle (pinned, coherent host
+    // memory; asynchronous mode): ctl[0] != 0 cancels the solve, ctl[1 + p] != 0
+    // pauses subdomain p (it takes no updates while set); null: none
+    const int32_t* ctl;
 };
 
 // Mutable per-instance state.

@@ -1654,13 +1654,29 @@ __device__ __forceinline__ void run_async(const Params& P, U& upd, TeamCtx& tc, 
             if (P.pace > 0.0 && tc.member == 0 && last_dur > 0)
                 paced_read_wait<B>(P, item, in, it, static_cast<int64_t>(P.pace * static_cast<double>(last_dur)));
             const int64_t t_upd = wall_clock64();
+            // 1: this item is finished; 2: the host has paused its subdomain
             int v0 = 0;
-            if (tc.member == 0 && tid == 0)
+            if (tc.member == 0 && tid == 0) {
+                if (in.ctl && __hip_atomic_load(in.ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
+                    st_rlx(&st->stop, 2);  // cancelled by the host: ends like a time limit
                 v0 = (ld_rlx(&st->stop) != 0) || (P.solves[it] >= in.max_sweeps) ||
                      (P.detect == 1 && ld_rlx(P.gflag + it) != 0);
-            const bool skip = team_bcast(tc, v0, &flag) != 0;
-            if (skip) {
+                if (!v0 && in.ctl &&
+                    __hip_atomic_load(in.ctl + 1 + (it - in.item_begin), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
+                    v0 = 2;
+            }
+            const int state = team_bcast(tc, v0, &flag);
+            if (state == 1) {
                 if (tid == 0) done[j - ib] = 1;
+                __syncthreads();
+                continue;
+            }
+            if (state == 2) {
+                // a stalled subdomain: no update; the time limit still applies
+                any = true;
+                if (wg == in.leader && it == in.item_begin && tid == 0 && P.max_ticks > 0 &&
+                    wall_clock64() - st->t0 > P.max_ticks)
+                    st_rlx(&st->stop, 2);
                 __syncthreads();
                 continue;
             }

@@ -700,3 +700,62 @@ def test_exact_local_autotune_picks_the_faster_and_it_converges():
     # FP16 storage: the band is the only candidate
     _, rep16 = autotune.exact_local(A, part, 3, b, "fp16", sweeps=5)
     assert rep16["choice"] == "chol" and rep16["ms_per_sweep"]["chol_sparse"] is None
+
+
+@pytest.mark.parametrize("p", [5, 0])
+def test_paused_subdomain_stalls_async_until_resumed(p):
+    """Host-forced stall (fault injection): a paused subdomain takes no updates,
+    so the solve cannot end converged while it is stalled -- with a 1 s limit it
+    returns not converged, the paused subdomain at zero local solves and every
+    other one updating; resumed from another thread during the next solve, the
+    iteration converges (verified).  p = 0 is the subdomain whose workgroup runs
+    the detector and the time limit."""
+    import threading
+    import time
+
+    ras = _ras()
+    _say(f"case: paused subdomain {p}")
+    A = R.laplace2d(96)
+    b = R.uniform_rhs(A.n, 41)
+    h = ras.setup(A, ras.partition("regular_2d", (4, 4), grid=A.grid), 3, ras.local("chol", "fp64"))
+    h.pause(p)
+    x, info = h.solve(_cuda(b), tol=1e-8, mode="async", max_sweeps=10**9, max_seconds=1.0)
+    counts = h.local_solve_counts()
+    assert not info[0]["converged"] and counts[p] == 0 and np.delete(counts, p).min() > 0
+    assert np.all(np.isfinite(x.cpu().numpy()))
+    t = threading.Timer(0.5, lambda: h.pause(p, False))
+    t.start()
+    t0 = time.perf_counter()
+    x, info = h.solve(_cuda(b), tol=1e-8, mode="async", max_sweeps=10**9, max_seconds=60)
+    t.join()
+    assert info[0]["converged"] and time.perf_counter() - t0 >= 0.5
+    assert h.local_solve_counts()[p] > 0
+    assert schwarz.relative_residual(A, x.cpu().numpy(), b) < 1e-8
+    h.close()
+
+
+def test_cancel_stops_a_running_async_solve():
+    """A cancel from another thread ends a running asynchronous solve that would
+    otherwise run to its limit (tol 0): it returns not converged with a finite
+    iterate well before the limit, and the next solve is not affected."""
+    import threading
+    import time
+
+    ras = _ras()
+    _say("case: cancel")
+    A = R.laplace2d(96)
+    b = R.uniform_rhs(A.n, 42)
+    h = ras.setup(A, ras.partition("regular_2d", (4, 4), grid=A.grid), 3, ras.local("cg", "fp64", 6))
+    t = threading.Timer(0.5, h.cancel)
+    t.start()
+    t0 = time.perf_counter()
+    x, info = h.solve(_cuda(b), tol=0.0, mode="async", max_sweeps=10**12, max_seconds=60)
+    dt = time.perf_counter() - t0
+    t.join()
+    assert not info[0]["converged"] and 0.4 <= dt < 20
+    assert np.all(np.isfinite(x.cpu().numpy()))
+    x, info = h.solve(_cuda(b), tol=1e-8, mode="async", max_sweeps=10**9, max_seconds=60)
+    assert info[0]["converged"] and schwarz.relative_residual(A, x.cpu().numpy(), b) < 1e-8
+    with pytest.raises(ras.RasError):
+        h.pause(16)
+    h.close()
