@@ -271,15 +271,18 @@ ras_status ras_setup(const ras_csr* A, const ras_partition* part, int32_t overla
  * control, callable from another thread while ras_solve runs; the words are
  * pinned, coherent host memory that the running kernel polls).
  * ras_pause: while paused != 0, subdomain p takes no updates in ASYNC mode
- * (its neighbours keep reading its last values; a detector's stop is still
+ * (a pause set before the solve holds from its start, one set during it
+ * within a few updates; the kernel polls the words on every 8th visit of a
+ * workgroup's subdomains and on every visit after a stall; its neighbours
+ * keep reading its last values; a detector's stop is still
  * verified exactly, so a stall cannot end the solve as converged unless the
  * iterate meets the tolerance); the setting persists across solves until
  * cleared.  Such a solve ends only once the subdomain is
  * resumed, at max_seconds, or when cancelled, so give it a time limit.  SYNC
  * and ORDERED modes ignore pauses.
- * ras_cancel: the ASYNC solve running on the handle stops at its workgroups'
- * next check and returns like a time limit (RAS_NOT_CONVERGED with the
- * current iterate); every solve clears the request when it starts.
+ * ras_cancel: the ASYNC solve running on the handle stops within a few
+ * updates and returns like a time limit (RAS_NOT_CONVERGED with the current
+ * iterate); every solve clears the request when it starts.
  * RAS_E_ARG for a null handle or p out of range.  */
 ras_status ras_pause(ras_handle* h, int32_t p, int32_t paused);
 ras_status ras_cancel(ras_handle* h);

@@ -1642,6 +1642,8 @@ __device__ __forceinline__ void run_async(const Params& P, U& upd, TeamCtx& tc, 
     for (int j = tid; j < ie - ib; j += B) done[j] = 0;
     __syncthreads();
     int64_t last_dur = 0;  // wall-clock ticks of this workgroup's previous update (0: none yet)
+    uint32_t ctl_visits = 0;  // item visits since the launch (host control words are polled on some)
+    bool stalled = false;     // the previous visit found its subdomain paused
     for (;;) {
         bool any = false;
         for (int j = ib; j < ie; ++j) {
@@ -1657,15 +1659,21 @@ __device__ __forceinline__ void run_async(const Params& P, U& upd, TeamCtx& tc, 
             // 1: this item is finished; 2: the host has paused its subdomain
             int v0 = 0;
             if (tc.member == 0 && tid == 0) {
-                if (in.ctl && __hip_atomic_load(in.ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
-                    st_rlx(&st->stop, 2);  // cancelled by the host: ends like a time limit
+                // both host words in one round trip over the host link, on every 8th
+                // visit and on every visit after a stall (a round trip costs about as
+                // much as 1 % of a typical update)
+                int32_t cz = 0, pz = 0;
+                if (in.ctl && ((ctl_visits++ & 7) == 0 || stalled)) {
+                    cz = __hip_atomic_load(in.ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    pz = __hip_atomic_load(in.ctl + 1 + (it - in.item_begin), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                }
+                if (cz != 0) st_rlx(&st->stop, 2);  // cancelled by the host: ends like a time limit
                 v0 = (ld_rlx(&st->stop) != 0) || (P.solves[it] >= in.max_sweeps) ||
                      (P.detect == 1 && ld_rlx(P.gflag + it) != 0);
-                if (!v0 && in.ctl &&
-                    __hip_atomic_load(in.ctl + 1 + (it - in.item_begin), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
-                    v0 = 2;
+                if (!v0 && pz != 0) v0 = 2;
             }
             const int state = team_bcast(tc, v0, &flag);
+            stalled = state == 2;
             if (state == 1) {
                 if (tid == 0) done[j - ib] = 1;
                 __syncthreads();
