@@ -61,6 +61,8 @@ def parse():
                     help="skip the fixed-sweep legs of the 2048^2 diffusion workload in the default run")
     ap.add_argument("--serve-count", type=int, default=200, help="systems in the serving stream")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-local2d", default="chol_sparse", choices=("chol", "chol_sparse"),
+                    help="exact local solver of the stream's 2-D systems (3-D systems use CG-8)")
     return ap.parse_args()
 
 
@@ -213,7 +215,7 @@ def serving_bench(args):
     for sp in specs:
         A, B, parts = R.serving_system(sp)
         if sp["dims"] == 2:
-            part, loc = ras.partition("regular_2d", parts, grid=A.grid), ras.local("chol", "fp32")
+            part, loc = ras.partition("regular_2d", parts, grid=A.grid), ras.local(args.serve_local2d, "fp32")
         else:
             part, loc = ras.partition("regular_3d", parts, grid=A.grid), ras.local("cg", "fp32", 8)
         systems.append((A, part, loc, B))
@@ -286,7 +288,8 @@ def serving_bench(args):
         "data": "synthetic",
         "config": {"workload": "serving", "systems": len(systems), "rhs": int(rhs),
                    "arrival_rate_per_s": rate, "saturated_rate_per_s": sat_rate,
-                   "budget_bytes": budget, "tol": 1e-8},
+                   "budget_bytes": budget, "tol": 1e-8,
+                   "local": {"2d": f"{args.serve_local2d}-fp32", "3d": "cg8-fp32"}},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "max": float(lat.max())},
         "occupancy": occupancy_summary(run.occupancy, budget),
