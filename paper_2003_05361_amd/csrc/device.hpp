@@ -43,8 +43,9 @@ constexpr int kMaxFactorW = 1024;  // widest band the device factorisation takes
 // its lanes and the first lane write the total to slot dest; padding items
 // (0, 0) fill a lane's rounds; every step of every wave ends with a marker round
 // (column kSparseMark in every lane) at which the workgroup synchronises.  A
-// wave has an even number of rounds, and the columns of rounds 2m and 2m + 1
-// share one 32-bit word per lane (low half, high half): word m * 64 + lane.
+// wave's round count is a multiple of kSparseLead (padding rounds after its
+// last marker), and the columns of rounds 2m and 2m + 1 share one 32-bit word
+// per lane (low half, high half): word m * 64 + lane.
 // Loads run kSparseLead rounds ahead of use, so the item arrays carry
 // 2 * kSparseLead rounds of slack after their last wave.
 constexpr int kSparseWaves = kBandThreads / 64;

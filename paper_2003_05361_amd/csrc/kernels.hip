@@ -1357,24 +1357,28 @@ __device__ __attribute__((noinline)) void sparse_run(RAS_GLOBAL const int32_t* w
         const int c0 = col_at(0);
         ynext = yy[R > 0 && c0 < kSparseTerm ? c0 : 0];
     }
+    // R is a multiple of D: no bound check inside a group of D rounds; the loads
+    // of the next group use immediate offsets from pointers advanced once per group
     for (int r0 = 0; r0 < R; r0 += D) {
+        RAS_GLOBAL const uint32_t* pcn = pc + (D / 2) * 64;
+        RAS_GLOBAL const ST* pvn = pv + D * 64;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
             const int c = col_at(i);
             const CT v = rv[i];
-            const int cu = uni(c);
-            const bool live = r0 + i < R && cu != kSparseMark;  // uniform
-            if (r0 + i < R && cu == kSparseMark) {
+            if (uni(c) == kSparseMark) {
                 lds_barrier();
                 acc = CT(0);
             }
             const CT yv = ynext;
             {
+                // the last round of the group reads ahead into the next group, which
+                // exists only below R (beyond it the arrays hold other waves' items)
                 const int cn = col_at((i + 1) % D);
-                ynext = yy[r0 + i + 1 < R && cn < kSparseTerm ? cn : 0];
+                ynext = yy[(i + 1 < D || r0 + D < R) && cn < kSparseTerm ? cn : 0];
             }
-            const bool term = live && c == kSparseTerm;
-            const bool add = live && c < kSparseTerm;
+            const bool term = c == kSparseTerm;
+            const bool add = c < kSparseTerm;
             acc = add ? acc + v * yv : acc;
             const uint64_t tm = __ballot(term);
             if (tm) {
@@ -1388,9 +1392,11 @@ __device__ __attribute__((noinline)) void sparse_run(RAS_GLOBAL const int32_t* w
                 if (term && (lane & ((1 << g) - 1)) == 0) yy[pay & 0xffffffu] = t;
                 acc = term ? CT(0) : acc;
             }
-            if (i & 1) rc[i / 2] = pc[((r0 + D) / 2 + i / 2) * 64];
-            rv[i] = static_cast<CT>(pv[(r0 + i + D) * 64]);
+            if (i & 1) rc[i / 2] = pcn[(i / 2) * 64];
+            rv[i] = static_cast<CT>(pvn[i * 64]);
         }
+        pc = pcn;
+        pv = pvn;
     }
 }
 

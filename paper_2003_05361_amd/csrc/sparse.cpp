@@ -582,12 +582,15 @@ void pack_schedule(const SparseSchedule& q, SparseLanes* out) {
             for (int l = 0; l < 64; ++l) wc[w][base + static_cast<size_t>(U) * 64 + l] = static_cast<uint16_t>(kSparseMark);
         }
     }
-    // an even round count per wave (the device loads the columns of two rounds in one word)
-    for (int w = 0; w < W; ++w)
-        if ((wc[w].size() / 64) % 2) {
-            wc[w].resize(wc[w].size() + 64, 0);
-            wv[w].resize(wv[w].size() + 64, 0.0);
-        }
+    // a round count per wave that is a multiple of the device's load lead (an even
+    // number: the columns of two rounds share a word; the kernel then needs no
+    // bound check inside a group of rounds); the padding rounds follow the last
+    // marker and add nothing
+    for (int w = 0; w < W; ++w) {
+        const size_t r = wc[w].size() / 64, rp = (r + kSparseLead - 1) / kSparseLead * kSparseLead;
+        wc[w].resize(rp * 64, 0);
+        wv[w].resize(rp * 64, 0.0);
+    }
     out->wave.assign(2 * W, 0);
     out->col.clear();
     out->val.clear();
