@@ -306,12 +306,40 @@ def test_tiny_and_ragged_subdomains():
     A = R.laplace2d(7, 5)
     b = R.uniform_rhs(A.n, 14)
     part = ("regular_1d", 6)
-    for loc, st, k in (("chol", "fp64", 0), ("cg", "fp64", 3)):
-        orc = _oracle(A, *part, 1, loc, st, k)
+    # the sparse solver's subdomains here (11 to 20 rows) are single leaves or
+    # nearly so: some keep no dense block at all, and one lane group covers a step
+    for loc, st, k, oloc, tol in (("chol", "fp64", 0, "chol", 1e-9), ("cg", "fp64", 3, "cg", 1e-9),
+                                  ("chol_sparse", "fp64", 0, "chol", 1e-9), ("chol_sparse", "fp32", 0, "chol", 2e-5)):
+        _say(f"case: tiny ragged {loc} {st}")
+        orc = _oracle(A, *part, 1, oloc, "fp64", k)
         h = ras.setup(A, _spec(ras, A, *part), 1, ras.local(loc, st, k))
         xo, _, _ = orc.sync(b, 0.0, 3)
         x, _ = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=3)
-        _agree(x.cpu().numpy(), xo, 1e-9)
+        _agree(x.cpu().numpy(), xo, tol, (loc, st))
+        h.close()
+
+
+@pytest.mark.parametrize("N,storage", [(27, "fp64"), (34, "fp32")])
+def test_sparse_cholesky_at_lds_capacity(N, storage):
+    """One 3-D box with nearly as many rows as the sparse solve keeps in LDS
+    (19,683 of 19,968 in FP64; 39,304 of 39,936 in FP32), overlap 0: one sweep
+    from zero is the direct solve (FP64), and in FP32 the sweeps are iterative
+    refinement with a single-precision factor, each gaining several digits.
+    The right-hand side comes from a known solution, so no reference solve is
+    needed."""
+    ras = _ras()
+    _say(f"case: sparse at LDS capacity {N}^3 {storage}")
+    A = R.laplace3d(N)
+    assert A.n <= ras.sparse_max_rows(storage) < A.n + 1024
+    xs = R.uniform_rhs(A.n, 31)
+    b = A.scipy() @ xs
+    h = ras.setup(A, ras.partition("rcb", 1, grid=A.grid, seed=5, jitter=0.3), 0, ras.local("chol_sparse", storage))
+    x, info = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=1)
+    _agree(x.cpu().numpy(), xs, 1e-11 if storage == "fp64" else 1e-4, "one sweep")
+    x, info = h.solve(_cuda(b), tol=1e-13, mode="sync", max_sweeps=8)
+    assert info[0]["converged"] and info[0]["sweeps"] <= (1 if storage == "fp64" else 5), info
+    _agree(x.cpu().numpy(), xs, 1e-10, "converged")
+    h.close()
 
 
 # ----------------------------------------------------------------------------- ordered = RMS

@@ -552,6 +552,33 @@ def test_sparse_solver_arguments():
     assert e.value.status == -6
 
 
+def test_sparse_solver_lds_capacity():
+    """The sparse solve keeps a subdomain's vector and its block slots in one
+    workgroup's LDS. A 3-D box with more rows than fit is rejected at set-up in
+    FP64 (E_UNSUPPORTED) and accepted in FP32 (half the bytes per value); at the
+    largest boxes that fit, no dense block has room and the schedule keeps plain
+    levels (min_block 0, no slots)."""
+    _lib_or_skip()
+    cap = {st: ras.sparse_max_rows(st) for st in ("fp64", "fp32")}
+    # (box side, storage, fits, no room left for a dense block)
+    for N, storage, fits, full in ((30, "fp64", False, False), (30, "fp32", True, False),
+                                   (27, "fp64", True, True), (34, "fp32", True, True)):
+        A = R.laplace3d(N)
+        spec = ras.partition("rcb", 1, grid=A.grid, seed=5, jitter=0.3)
+        assert (A.n <= cap[storage]) == fits, (N, storage, A.n, cap)
+        if not fits:
+            with pytest.raises(ras.RasError) as e:
+                ras.Plan(A, spec, 0, ras.local("chol_sparse", storage))
+            assert e.value.status == -8 and "LDS" in str(e.value)
+            continue
+        plan = ras.Plan(A, spec, 0, ras.local("chol_sparse", storage))
+        for pass_ in (0, 1):
+            sch = plan.sparse_schedule(0, pass_)
+            assert A.n + sch["slots"] <= cap[storage], (N, storage, sch["slots"])
+            if full:
+                assert sch["min_block"] == 0 and sch["slots"] == 0, (N, storage, sch["min_block"])
+
+
 def test_sparse_schedule_arguments():
     """The schedule queries reject a pass other than 0 / 1, a subdomain out of
     range and a plan without sparse factors; the lane layout keeps every slot
