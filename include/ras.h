@@ -180,7 +180,7 @@ typedef struct ras_plan_stats {
     int64_t sum_local_rows;    /* sum_p |Omega_p| */
     int64_t min_local_rows;
     int64_t max_local_rows;
-    int32_t max_band;          /* max lower half-bandwidth of the local matrices */
+    int32_t max_band;          /* max stored lower half-bandwidth (>= 1) of the local matrices */
     int32_t reserved;
     int64_t band_entries;      /* factor entries: sum_p |Omega_p| (w_p + 1); sparse solver: sum_p nnz(L_p) */
     int64_t device_bytes;      /* device memory the handle allocates for the matrix data */
@@ -208,7 +208,8 @@ ras_status ras_plan_sets(const ras_plan* plan, int32_t* owner, int64_t* omega_pt
  * The diagonal is 0.  RAS_E_ARG on a NULL argument.  */
 ras_status ras_plan_comm_volume(const ras_plan* plan, int64_t* volume);
 /* Float64 band factor of subdomain p: band[i*(w+1) + (j - i + w)] = L_ij for
- * i-w <= j <= i (zero outside the matrix); *w receives the half-bandwidth.
+ * i-w <= j <= i (zero outside the matrix); *w receives the stored half-bandwidth
+ * (the local matrix's, at least 1: a diagonal matrix keeps a zero sub-diagonal).
  * band may be NULL to query w (any local solver); with band non-NULL the
  * call returns RAS_E_STATE unless the solver is Cholesky.  */
 ras_status ras_plan_factor(const ras_plan* plan, int32_t p, double* band, int32_t* w);

@@ -240,7 +240,10 @@ void build_overlap(Plan& plan) {
         }
         sd.n_owned = no;
         sd.ell_width = width;
-        sd.w = w;
+        // the stored band keeps at least one sub-diagonal (zero for a diagonal
+        // local matrix): the device layout writes each row's diagonal reciprocal
+        // together with its first band entry, and sizes its stages by w
+        sd.w = std::max<int32_t>(w, 1);
     });
 }
 

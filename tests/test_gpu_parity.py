@@ -319,6 +319,50 @@ def test_tiny_and_ragged_subdomains():
         h.close()
 
 
+@pytest.mark.parametrize("mode", ["sync", "async"])
+def test_one_unknown_and_a_chain(mode):
+    """Degenerate systems: one unknown (each local solve is one division) and a
+    1-D chain of 16 unknowns in two overlapping halves; every local solver and
+    storage reaches the direct solution, in both modes."""
+    ras = _ras()
+    one = R.CSR(np.array([0, 1], np.int64), np.array([0], np.int32), np.array([4.0]), (1, 1, 1))
+    chain = R.laplace2d(16, 1)
+    for A, P, gamma in ((one, 1, 0), (chain, 2, 1)):
+        b = R.uniform_rhs(A.n, 41) + 0.5
+        xd = schwarz.direct_solve(A, b)
+        for loc, st, k in (("chol", "fp64", 0), ("chol", "fp32", 0), ("chol", "fp16", 0),
+                           ("chol_sparse", "fp64", 0), ("chol_sparse", "fp32", 0),
+                           ("cg", "fp64", 10), ("cg", "fp32", 10)):
+            _say(f"case: degenerate n={A.n} P={P} {loc} {st} {mode}")
+            h = ras.setup(A, ras.partition("regular_1d", P, grid=A.grid), gamma, ras.local(loc, st, k))
+            x, info = h.solve(_cuda(b), tol=1e-12, mode=mode, max_sweeps=500, max_seconds=30)
+            assert info[0]["converged"], (loc, st, info)
+            _agree(x.cpu().numpy(), xd, 1e-9, (A.n, loc, st))
+            h.close()
+
+
+def test_point_subdomains_are_jacobi():
+    """One grid point per subdomain and no overlap: every local matrix is the
+    point's diagonal entry, and a synchronous sweep is a Jacobi step,
+    x <- x + D^-1 (b - A x), for every local solver."""
+    ras = _ras()
+    A = R.laplace2d(5, 4)
+    S = A.scipy()
+    d = S.diagonal()
+    b = R.uniform_rhs(A.n, 43)
+    xs, x = [], np.zeros(A.n)
+    for _ in range(4):
+        x = x + (b - S @ x) / d
+        xs.append(x)
+    for loc, st, k in (("chol", "fp64", 0), ("chol", "fp32", 0), ("chol_sparse", "fp64", 0), ("cg", "fp64", 2)):
+        _say(f"case: point subdomains {loc} {st}")
+        h = ras.setup(A, ras.partition("regular_1d", A.n, grid=A.grid), 0, ras.local(loc, st, k))
+        for sweeps in (1, 4):
+            xg, _ = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=sweeps)
+            _agree(xg.cpu().numpy(), xs[sweeps - 1], 1e-13 if st == "fp64" else 5e-7, (loc, st, sweeps))
+        h.close()
+
+
 @pytest.mark.parametrize("N,storage", [(27, "fp64"), (34, "fp32")])
 def test_sparse_cholesky_at_lds_capacity(N, storage):
     """One 3-D box with nearly as many rows as the sparse solve keeps in LDS

@@ -210,9 +210,11 @@ def test_fp16_conversion_rounding_matches_numpy():
                     ras.local("chol", "fp16"))
     bits, scale = plan.factor_fp16(0)
     band, w = plan.factor(0)
-    assert w == 0
-    ref = (band[:, 0] / scale.astype(np.float64)).astype(np.float16).view(np.uint16)
-    assert np.array_equal(bits[:, 0], ref)
+    # a diagonal matrix is stored with one zero sub-diagonal
+    assert w == 1 and np.all(band[:, 0] == 0) and np.all(bits[:, 0] == 0)
+    assert np.array_equal(band[:, 1], vals)
+    ref = (band[:, 1] / scale.astype(np.float64)).astype(np.float16).view(np.uint16)
+    assert np.array_equal(bits[:, 1], ref)
     # direct conversion checks through a 2-entry row: L = [[a,0],[b,c]] -> row scale max(|b|,|c|)
     A2 = sp.csr_matrix(np.array([[1.0, 2.0**-12], [2.0**-12, 1.0]]))
     A2.indptr = A2.indptr.astype(np.int64)
@@ -298,6 +300,10 @@ def test_plan_stats_config2_shape():
 
 # ----------------------------------------------------------------------------- sparse Cholesky (host)
 SPARSE_CASES = [
+    # degenerate: one unknown, and a 1-D chain whose separators are single points
+    ("one_unknown", R.CSR(np.array([0, 1], np.int64), np.array([0], np.int32), np.array([4.0]), (1, 1, 1)),
+     ("regular_1d", 1), 0),
+    ("chain_16_halves_g1", R.laplace2d(16, 1), ("regular_1d", 2), 1),
     ("poisson2d_40_2x2_g3", R.laplace2d(40), ("regular_2d", (2, 2)), 3),
     ("laplace3d_12_rcb5_g1", R.laplace3d(12), ("rcb", (5, 2, 0.3)), 1),
     ("tpfa2d_24_strips3_g2", R.tpfa2d(np.exp(2 * R.gaussian_random_field_2d(24, 4.0, 3)), 10.0), ("regular_1d", 3), 2),
@@ -486,14 +492,20 @@ def test_sparse_lane_layout_applies_the_schedule(name, A, part, gamma):
         for pass_, M, lower in ((0, L, True), (1, L.T.tocsr(), False)):
             sch = plan.sparse_schedule(p, pass_)
             lay = plan.sparse_lanes(p, pass_)
+            # the waves tile the stream, each a whole number of 8-round load groups
+            # (the device loads a group ahead without checking a wave's end)
+            w0, nr = lay["wave"][:, 0], lay["wave"][:, 1]
+            assert np.all(nr > 0) and np.all(nr % 8 == 0), (p, pass_, nr)
+            assert w0[0] == 0 and np.array_equal(w0[1:], np.cumsum(nr)[:-1]) and nr.sum() == lay["col"].shape[0]
             y = _run_lanes(lay, v, sch["slots"])
             ref = spla.spsolve_triangular(M, v, lower=lower)
             assert np.max(np.abs(y - ref)) <= 1e-12 * np.max(np.abs(ref)), (p, pass_)
-            # the longest wave is no longer than one record per lane would make it
+            # the longest wave is no longer than one record per lane would make it,
+            # rounded up to a whole load group
             meta = sch["meta"]
             longest = sum(int((meta[a:b, 2] - meta[a:b, 1]).max()) + 2
                           for a, b in zip(sch["step_ptr"][:-1], sch["step_ptr"][1:]))
-            assert lay["wave"][:, 1].max() <= longest, p
+            assert lay["wave"][:, 1].max() <= -(-longest // 8) * 8, p
 
 
 def test_sparse_schedule_cuts_the_steps_of_a_grid_box():
