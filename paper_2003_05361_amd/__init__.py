@@ -370,6 +370,30 @@ def _order_before(stream_value: int):
         cur.synchronize()
 
 
+def _rhs(b, n: int, what: str = "b"):
+    """b as the C ABI takes it: a contiguous float64 CUDA tensor of shape [n] or
+    [nrhs, n] (nrhs >= 1).  The library reads nrhs * n values from its address,
+    so a wrong shape is refused here, before any launch."""
+    import torch
+
+    if not isinstance(b, torch.Tensor) or b.device.type != "cuda" or b.dtype != torch.float64:
+        raise TypeError(f"{what} must be a float64 CUDA tensor")
+    if b.dim() not in (1, 2) or b.shape[-1] != n or b.numel() == 0:
+        raise ValueError(f"{what} must have shape [{n}] or [nrhs >= 1, {n}], got {tuple(b.shape)}")
+    return b.contiguous()
+
+
+def _initial(x0, b, what: str = "x0"):
+    """A writable copy of the initial guess on b's device (zeros if x0 is None)."""
+    import torch
+
+    if x0 is None:
+        return torch.zeros_like(b)
+    if not isinstance(x0, torch.Tensor) or tuple(x0.shape) != tuple(b.shape):
+        raise ValueError(f"{what} must be a tensor of b's shape {tuple(b.shape)}")
+    return x0.to(device=b.device, dtype=torch.float64).contiguous().clone()
+
+
 def _opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team=0, pace=None) -> SolveOpts:
     return SolveOpts(MODES[mode], DETECT[detect], float(tol), int(max_sweeps), float(max_seconds), int(workgroups),
                      int(team), float(DEFAULT_PACE if pace is None else pace))
@@ -406,13 +430,9 @@ class Handle:
         noalloc: run through ras_solve_noalloc (workspace in the library's fixed
         device scratch of NOALLOC_SCRATCH_BYTES; x is still allocated here unless
         x0 is given).  Returns (x, infos) with x the same shape as b."""
-        import torch
-
-        if b.device.type != "cuda" or b.dtype != torch.float64:
-            raise TypeError("b must be a float64 CUDA tensor")
-        b = b.contiguous()
+        b = _rhs(b, self.n)
         nrhs = 1 if b.dim() == 1 else b.shape[0]
-        x = torch.zeros_like(b) if x0 is None else x0.to(torch.float64).contiguous().clone()
+        x = _initial(x0, b)
         infos = (SolveInfo * nrhs)()
         self._order_after_current_stream()
         fn = lib().ras_solve_noalloc if noalloc else lib().ras_solve
@@ -455,9 +475,12 @@ class Handle:
 
     def autotune(self, b, sweeps: int = 20) -> tuple[int, float]:
         """Time `sweeps` synchronous sweeps for every feasible team size; keep the best.
-        Returns (team, ms per sweep)."""
+        Returns (team, ms per sweep).  b: one right-hand side [n]."""
         import torch
 
+        b = _rhs(b, self.n)
+        if b.dim() != 1:
+            raise ValueError("autotune takes one right-hand side of shape [n]")
         x = torch.zeros_like(b)
         t = C.c_int32()
         ms = C.c_double()
@@ -488,6 +511,10 @@ class Handle:
         return band, w.value
 
     def relative_residual(self, b, x) -> float:
+        """||b - A x|| / ||b|| on the device (compensated); b and x of shape [n]."""
+        b, x = _rhs(b, self.n), _rhs(x, self.n, "x")
+        if b.dim() != 1 or x.dim() != 1 or x.device != b.device:
+            raise ValueError("relative_residual takes b and x of shape [n] on one device")
         r = C.c_double()
         self._order_after_current_stream()
         _check(lib().ras_relative_residual(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
@@ -525,8 +552,17 @@ def batch_solve(handles: Sequence[Handle], bs, xs=None, tol: float = 1e-8, mode:
     import torch
 
     m = len(handles)
-    bs = [b.contiguous() for b in bs]
-    xs = [torch.zeros_like(b) for b in bs] if xs is None else [x.contiguous() for x in xs]
+    if len(bs) != m or (xs is not None and len(xs) != m):
+        raise ValueError("one right-hand side (and one x, if given) per handle")
+    bs = [_rhs(b, h.n, f"bs[{i}]") for i, (h, b) in enumerate(zip(handles, bs))]
+    if xs is None:
+        xs = [torch.zeros_like(b) for b in bs]
+    else:
+        for i, (x, b) in enumerate(zip(xs, bs)):
+            if not isinstance(x, torch.Tensor) or tuple(x.shape) != tuple(b.shape) or x.device != b.device \
+                    or x.dtype != torch.float64:
+                raise ValueError(f"xs[{i}] must be a float64 tensor of bs[{i}]'s shape on its device")
+        xs = [x.contiguous() for x in xs]
     nr = [1 if b.dim() == 1 else b.shape[0] for b in bs]
     H = (_P * m)(*[h._h for h in handles])
     B = (_P * m)(*[b.data_ptr() for b in bs])
@@ -564,25 +600,35 @@ class Server:
         st = None if stream is None else _stream_ptr(stream)
         _check(lib().ras_server_create(int(hbm_budget_bytes), float(slice_seconds), st, C.byref(p)))
         self._s = p
+        self._shapes = {}  # ticket -> (n, nrhs): the size of the result poll receives
 
     def submit(self, A, part: dict, overlap: int, loc: dict, B, tol: float = 1e-8) -> int:
         """Queue a system; B is a host array [n] or [nrhs, n].  Returns a ticket."""
         keep = _Keep()
         Bh = keep.add(np.ascontiguousarray(B, dtype=np.float64))
+        n = len(A.indptr) - 1
+        if Bh.ndim not in (1, 2) or Bh.shape[-1] != n or Bh.size == 0:
+            raise ValueError(f"B must have shape [{n}] or [nrhs >= 1, {n}], got {Bh.shape}")
         nrhs = 1 if Bh.ndim == 1 else Bh.shape[0]
         t = C.c_uint64()
         _check(lib().ras_server_submit(self._s, C.byref(_csr(A, keep)), C.byref(_part(part, A, keep)), int(overlap),
                                        C.byref(_local(loc)), Bh.ctypes.data, nrhs, float(tol), C.byref(t)))
+        self._shapes[t.value] = (n, nrhs)
         return t.value
 
     def poll(self, ticket: int, n: int, nrhs: int = 1):
-        """(done, x[nrhs, n] or None, infos, latency_s); raises on a failed system."""
+        """(done, x[nrhs, n] or None, infos, latency_s); raises on a failed system.
+        n and nrhs must be those of the submitted system (the library writes its
+        whole solution into the array allocated here)."""
+        if self._shapes.get(int(ticket), (n, nrhs)) != (n, nrhs):
+            raise ValueError(f"ticket {ticket} is a system of (n, nrhs) = {self._shapes[int(ticket)]}")
         x = np.empty((nrhs, n))
         infos = (SolveInfo * nrhs)()
         lat = C.c_double()
         st = lib().ras_server_poll(self._s, int(ticket), x.ctypes.data, infos, C.byref(lat))
         if st == RAS_PENDING:
             return False, None, None, None
+        self._shapes.pop(int(ticket), None)
         _check(st)
         return True, x, [i.as_dict() for i in infos], lat.value
 

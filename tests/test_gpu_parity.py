@@ -658,6 +658,47 @@ def test_solve_under_a_side_stream():
     assert torch.equal(x, x_ref)
 
 
+def test_binding_refuses_wrong_shapes_before_any_launch():
+    """The C ABI reads nrhs * n values from the addresses it is given, so the
+    binding checks shapes first: a right-hand side of the wrong length or rank,
+    an initial guess of another shape, a batch with a missing vector and a
+    serving request of the wrong width are refused with ValueError; an initial
+    guess in host memory is copied to the device."""
+    ras = _ras()
+    torch = _torch()
+    _say("case: binding shape checks")
+    A = R.laplace2d(24)
+    b = R.uniform_rhs(A.n, 35)
+    h = ras.setup(A, ras.partition("regular_2d", (2, 2), grid=A.grid), 1, ras.local("chol", "fp64"))
+    bt = _cuda(b)
+    for bad in (bt[:-1], bt.reshape(1, 1, -1), bt[:0], torch.zeros(0, A.n, dtype=torch.float64, device="cuda")):
+        with pytest.raises(ValueError):
+            h.solve(bad, tol=1e-9, mode="sync")
+    with pytest.raises(TypeError):
+        h.solve(bt.float(), tol=1e-9, mode="sync")
+    with pytest.raises(ValueError):
+        h.solve(bt, x0=torch.zeros(A.n + 1, dtype=torch.float64), tol=1e-9, mode="sync")
+    with pytest.raises(ValueError):
+        h.relative_residual(bt, bt[:-1])
+    with pytest.raises(ValueError):
+        ras.batch_solve([h, h], [bt], mode="sync")
+    x_ref, _ = h.solve(bt, tol=0.0, mode="sync", max_sweeps=5)
+    x_host0, _ = h.solve(bt, x0=torch.zeros(A.n, dtype=torch.float64), tol=0.0, mode="sync", max_sweeps=5)
+    assert x_host0.device.type == "cuda" and torch.equal(x_host0, x_ref)
+    h.close()
+    srv = ras.Server(1 << 30, slice_seconds=0.01)
+    part = ras.partition("regular_2d", (2, 2), grid=A.grid)
+    with pytest.raises(ValueError):
+        srv.submit(A, part, 1, ras.local("chol", "fp64"), np.ones(A.n + 3), 1e-8)
+    t = srv.submit(A, part, 1, ras.local("chol", "fp64"), np.stack([b, b]), 1e-8)
+    assert srv.wait(t, 60.0)
+    with pytest.raises(ValueError):
+        srv.poll(t, A.n, 1)
+    done, x, infos, _ = srv.poll(t, A.n, 2)
+    assert done and x.shape == (2, A.n) and all(i["converged"] for i in infos)
+    srv.close()
+
+
 def test_autotune_picks_a_feasible_team_and_keeps_parity():
     ras = _ras()
     _say("case: autotune")
