@@ -387,14 +387,15 @@ def test_sparse_cholesky_at_lds_capacity(N, storage):
 
 
 # ----------------------------------------------------------------------------- ordered = RMS
-@pytest.mark.parametrize("loc,k", [("chol", 0), ("cg", 5)])
+@pytest.mark.parametrize("loc,k", [("chol", 0), ("cg", 5), ("chol_sparse", 0)])
 def test_ordered_mode_is_multiplicative_schwarz(loc, k):
     ras = _ras()
     _say(f"case: ordered {loc}")
     A = R.laplace2d(40)
     b = R.uniform_rhs(A.n, 15)
     part = ("regular_2d", (2, 3))
-    orc = _oracle(A, *part, 2, loc, "fp64", k)
+    # the sparse solver is exact like the band: the same multiplicative iterates
+    orc = _oracle(A, *part, 2, "chol" if loc == "chol_sparse" else loc, "fp64", k)
     h = ras.setup(A, _spec(ras, A, *part), 2, ras.local(loc, "fp64", k))
     for passes in (1, 3):
         xo, _ = orc.ordered(b, passes)
@@ -422,7 +423,8 @@ def test_async_converges_and_verifies(loc, st, k):
         assert counts.min() >= 1 and counts.sum() == info[0]["total_local_solves"]
 
 
-@pytest.mark.parametrize("loc,st,k,team", [("chol", "fp64", 0, 0), ("cg", "fp64", 10, 4), ("cg", "fp32", 6, 1)])
+@pytest.mark.parametrize("loc,st,k,team", [("chol", "fp64", 0, 0), ("cg", "fp64", 10, 4), ("cg", "fp32", 6, 1),
+                                            ("chol_sparse", "fp64", 0, 0)])
 def test_async_decentralized_detection(loc, st, k, team):
     ras = _ras()
     _say(f"case: async decentral {loc} {st} team={team}")
