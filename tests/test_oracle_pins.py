@@ -564,6 +564,35 @@ def test_ordered_zero_overlap_is_block_gauss_seidel():
         assert np.linalg.norm(xo - x) <= 1e-13 * np.linalg.norm(x)
 
 
+def test_point_subdomains_are_jacobi_and_gauss_seidel():
+    """One grid point per subdomain, no overlap: the synchronous sweep is the
+    textbook Jacobi step and the ordered pass the Gauss-Seidel sweep in
+    subdomain order, both written out component by component."""
+    A = R.laplace2d(5, 4)
+    S = A.scipy().tocsr()
+    b = R.uniform_rhs(A.n, 9)
+    owner = np.arange(A.n, dtype=np.int32)
+    for loc in ("chol", "cg"):
+        ras = schwarz.RAS(A, owner, 0, loc, "fp64", 2)
+        xj = np.zeros(A.n)
+        xg = np.zeros(A.n)
+        for k in range(1, 4):
+            new = np.empty(A.n)
+            for i in range(A.n):
+                cols, vals = S.indices[S.indptr[i]:S.indptr[i + 1]], S.data[S.indptr[i]:S.indptr[i + 1]]
+                off = sum(v * xj[c] for c, v in zip(cols, vals) if c != i)
+                new[i] = (b[i] - off) / S[i, i]
+            xj = new
+            for i in range(A.n):
+                cols, vals = S.indices[S.indptr[i]:S.indptr[i + 1]], S.data[S.indptr[i]:S.indptr[i + 1]]
+                off = sum(v * xg[c] for c, v in zip(cols, vals) if c != i)
+                xg[i] = (b[i] - off) / S[i, i]
+            xo, _, _ = ras.sync(b, 0.0, k)
+            assert np.max(np.abs(xo - xj)) <= 1e-14 * np.max(np.abs(xj)), (loc, k)
+            xs, _ = ras.ordered(b, k)
+            assert np.max(np.abs(xs - xg)) <= 1e-14 * np.max(np.abs(xg)), (loc, k)
+
+
 def test_async_simulator_converges_and_verifies():
     A = R.laplace2d(24)
     b = R.uniform_rhs(A.n, 8)
