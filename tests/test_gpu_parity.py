@@ -343,23 +343,32 @@ def test_one_unknown_and_a_chain(mode):
 
 def test_point_subdomains_are_jacobi():
     """One grid point per subdomain and no overlap: every local matrix is the
-    point's diagonal entry, and a synchronous sweep is a Jacobi step,
-    x <- x + D^-1 (b - A x), for every local solver."""
+    point's diagonal entry, a synchronous sweep is a Jacobi step,
+    x <- x + D^-1 (b - A x), and an ordered pass a Gauss-Seidel sweep in point
+    order, for every local solver."""
     ras = _ras()
     A = R.laplace2d(5, 4)
-    S = A.scipy()
+    S = A.scipy().tocsr()
     d = S.diagonal()
     b = R.uniform_rhs(A.n, 43)
     xs, x = [], np.zeros(A.n)
+    gs, y = [], np.zeros(A.n)
     for _ in range(4):
         x = x + (b - S @ x) / d
         xs.append(x)
+        y = y.copy()
+        for i in range(A.n):
+            y[i] += (b[i] - (S[i] @ y)[0]) / d[i]
+        gs.append(y)
     for loc, st, k in (("chol", "fp64", 0), ("chol", "fp32", 0), ("chol_sparse", "fp64", 0), ("cg", "fp64", 2)):
         _say(f"case: point subdomains {loc} {st}")
         h = ras.setup(A, ras.partition("regular_1d", A.n, grid=A.grid), 0, ras.local(loc, st, k))
+        tol = 1e-13 if st == "fp64" else 5e-7
         for sweeps in (1, 4):
             xg, _ = h.solve(_cuda(b), tol=0.0, mode="sync", max_sweeps=sweeps)
-            _agree(xg.cpu().numpy(), xs[sweeps - 1], 1e-13 if st == "fp64" else 5e-7, (loc, st, sweeps))
+            _agree(xg.cpu().numpy(), xs[sweeps - 1], tol, (loc, st, sweeps))
+            xo, _ = h.solve(_cuda(b), tol=0.0, mode="ordered", max_sweeps=sweeps)
+            _agree(xo.cpu().numpy(), gs[sweeps - 1], tol, ("ordered", loc, st, sweeps))
         h.close()
 
 
