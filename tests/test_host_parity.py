@@ -37,6 +37,50 @@ def test_header_symbols_exported():
     assert declared == set(ras.SIGNATURES), declared ^ set(ras.SIGNATURES)
 
 
+def test_null_arguments_are_argument_errors():
+    """Every entry point that takes a plan, handle or server, or output pointers,
+    answers NULL with RAS_E_ARG (-1) before touching a device; destroying NULL
+    is a no-op."""
+    lib = _lib_or_skip()
+    calls = {
+        "ras_plan_create": lambda: lib.ras_plan_create(None, None, 1, None, None),
+        "ras_plan_get_stats": lambda: lib.ras_plan_get_stats(None, None),
+        "ras_plan_sets": lambda: lib.ras_plan_sets(None, None, None, None),
+        "ras_plan_factor": lambda: lib.ras_plan_factor(None, 0, None, None),
+        "ras_plan_factor_fp16": lambda: lib.ras_plan_factor_fp16(None, 0, None, None),
+        "ras_plan_sparse_factor": lambda: lib.ras_plan_sparse_factor(None, 0, None, None, None, None, None, None),
+        "ras_plan_sparse_schedule": lambda: lib.ras_plan_sparse_schedule(None, 0, 0, None, None, None, None, None,
+                                                                         None, None, None, None),
+        "ras_plan_sparse_lanes": lambda: lib.ras_plan_sparse_lanes(None, 0, 0, None, None, None, None, None),
+        "ras_setup": lambda: lib.ras_setup(None, None, 1, None, None, None),
+        "ras_setup_from_plan": lambda: lib.ras_setup_from_plan(None, None, None),
+        "ras_pause": lambda: lib.ras_pause(None, 0, 1),
+        "ras_cancel": lambda: lib.ras_cancel(None),
+        "ras_handle_get_stats": lambda: lib.ras_handle_get_stats(None, None),
+        "ras_solve": lambda: lib.ras_solve(None, None, None, 1, None, None),
+        "ras_solve_noalloc": lambda: lib.ras_solve_noalloc(None, None, None, 1, None, None),
+        "ras_batch_solve": lambda: lib.ras_batch_solve(0, None, None, None, None, None, None),
+        "ras_residual_history": lambda: lib.ras_residual_history(None, 0, None, None, 0, None),
+        "ras_local_solve_counts": lambda: lib.ras_local_solve_counts(None, 0, None),
+        "ras_partition_sets": lambda: lib.ras_partition_sets(None, None, None, None),
+        "ras_phase_seconds": lambda: lib.ras_phase_seconds(None, 0, None),
+        "ras_autotune": lambda: lib.ras_autotune(None, None, None, 1, None, None),
+        "ras_handle_factor": lambda: lib.ras_handle_factor(None, 0, None, None),
+        "ras_relative_residual": lambda: lib.ras_relative_residual(None, None, None, None),
+        "ras_server_create": lambda: lib.ras_server_create(0, 0.01, None, None),
+        "ras_server_submit": lambda: lib.ras_server_submit(None, None, None, 1, None, None, 1, 1e-8, None),
+        "ras_server_poll": lambda: lib.ras_server_poll(None, 0, None, None, None),
+        "ras_server_wait": lambda: lib.ras_server_wait(None, 0, 0.0),
+        "ras_server_get_stats": lambda: lib.ras_server_get_stats(None, None),
+    }
+    for name, call in calls.items():
+        assert call() == -1, name
+        assert lib.ras_last_error(), name
+    assert lib.ras_server_destroy(None) == 0
+    lib.ras_destroy(None)
+    lib.ras_plan_destroy(None)
+
+
 def _oracle_sets(A, owner, gamma):
     sets = oover.subdomain_sets(A, owner, gamma)
     return oover.flatten_sets(sets)
