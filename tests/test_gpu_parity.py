@@ -504,9 +504,9 @@ def test_async_paced_cg_teams_converge():
     assert schwarz.relative_residual(A, x.cpu().numpy(), b) < 1e-8
 
 
-def test_pace_out_of_range_is_an_argument_error():
+def test_solve_options_out_of_range_are_argument_errors():
     ras = _ras()
-    _say("case: pace argument errors")
+    _say("case: solve option argument errors")
     A = R.laplace2d(16)
     b = _cuda(R.uniform_rhs(A.n, 1))
     h = ras.setup(A, ras.partition("regular_2d", (2, 2), grid=A.grid), 1, ras.local("chol", "fp64"))
@@ -514,6 +514,18 @@ def test_pace_out_of_range_is_an_argument_error():
         with pytest.raises(ras.RasError) as e:
             h.solve(b, tol=1e-8, mode="async", pace=bad)
         assert e.value.status == -1
+    for kw in (dict(tol=-1.0), dict(tol=float("nan")), dict(max_sweeps=0)):
+        with pytest.raises(ras.RasError) as e:
+            h.solve(b, **{"tol": 1e-8, "mode": "sync", **kw})
+        assert e.value.status == -1, kw
+    # mode and detector codes outside the enums, through the C ABI itself
+    import ctypes as C
+    x = b.clone()
+    info = (ras.SolveInfo * 1)()
+    for mode, det in ((7, 0), (0, 9)):
+        opts = ras.SolveOpts(mode, det, 1e-8, 100, 0.0, 0, 0, -1.0)
+        st = ras.lib().ras_solve(h._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), 1, C.byref(opts), info)
+        assert st == -1 and b"unknown" in ras.lib().ras_last_error(), (mode, det)
     _, info = h.solve(b, tol=1e-8, mode="async", max_seconds=30)
     assert info[0]["converged"]
 
