@@ -429,7 +429,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (every subdomain of a system "
+        print("bench.py measures one GPU: the library has no multi-GPU path (every subdomain of a system "
               "lives on one device). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
