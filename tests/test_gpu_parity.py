@@ -584,6 +584,26 @@ def test_batch_equals_alone(kind):
         assert _rel(yy, schwarz.direct_solve(A, b)) <= 1e-6
 
 
+def test_batch_of_different_local_solvers_is_refused():
+    """One launch runs one kernel: systems whose local solver, storage or CG
+    iteration count differ cannot share a batch (RAS_E_ARG); each still solves alone."""
+    ras = _ras()
+    _say("case: batch mixing refused")
+    A = R.laplace2d(24)
+    b = _cuda(R.uniform_rhs(A.n, 36))
+    part = ras.partition("regular_2d", (2, 2), grid=A.grid)
+    hs = [ras.setup(A, part, 1, ras.local(*loc)) for loc in
+          (("chol", "fp64"), ("cg", "fp64", 4), ("chol", "fp32"), ("cg", "fp64", 6))]
+    for other in hs[1:]:
+        with pytest.raises(ras.RasError) as e:
+            ras.batch_solve([hs[0] if other is not hs[3] else hs[1], other], [b, b], tol=1e-8, mode="sync")
+        assert e.value.status == -1
+    for h in hs:
+        _, info = h.solve(b, tol=1e-8, mode="sync", max_sweeps=100000)
+        assert info[0]["converged"]
+        h.close()
+
+
 # ----------------------------------------------------------------------------- optimized Schwarz
 @pytest.mark.parametrize("kind,storage,tol", [("chol", "fp64", 1e-9), ("chol_sparse", "fp64", 1e-9),
                                               ("chol", "fp32", 2e-5)])
