@@ -86,9 +86,10 @@ def laplace2d(N: int, M: int | None = None) -> CSR:
     return _stencil(N, N if M is None else M, 1, 4.0)
 
 
-def laplace3d(N: int) -> CSR:
-    """3-D 7-point Laplacian on an N^3 interior grid (diagonal 6, six -1's)."""
-    return _stencil(N, N, N, 6.0)
+def laplace3d(N: int, ny: int | None = None, nz: int | None = None) -> CSR:
+    """3-D 7-point Laplacian on an N x ny x nz interior grid (N^3 by default;
+    diagonal 6, six -1's)."""
+    return _stencil(N, N if ny is None else ny, N if nz is None else nz, 6.0)
 
 
 def _tpfa(k: np.ndarray, aniso: tuple) -> CSR:

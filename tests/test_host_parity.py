@@ -92,6 +92,10 @@ CASES = [
     ("laplace3d_20_rcb16", R.laplace3d(20), ("rcb", (16, 3, 0.4)), 1),
     ("laplace3d_18_2x3x2", R.laplace3d(18), ("regular_3d", (2, 3, 2)), 2),
     ("laplace2d_33_rcb7_g0", R.laplace2d(33, 17), ("rcb", (7, 11, 0.3)), 0),
+    # ragged: grid sides that the part counts do not divide
+    ("laplace2d_37x23_4x3_g2", R.laplace2d(37, 23), ("regular_2d", (4, 3)), 2),
+    ("laplace2d_37x23_strips7_g3", R.laplace2d(37, 23), ("regular_1d", 7), 3),
+    ("laplace3d_13x11x7_4x3x2_g2", R.laplace3d(13, 11, 7), ("regular_3d", (4, 3, 2)), 2),
 ]
 
 
