@@ -20,7 +20,9 @@ from typing import Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libras.so")
+# RAS_LIBRARY may name another build of the same library (the host-sanitizer
+# build of paper_2003_05361_amd.hostsan); by default the in-tree libras.so
+LIB_PATH = os.environ.get("RAS_LIBRARY") or os.path.join(_HERE, "_lib", "libras.so")
 
 # ----------------------------------------------------------------------------- C mirrors
 RAS_OK, RAS_NOT_CONVERGED, RAS_PENDING = 0, 1, 2
