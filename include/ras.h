@@ -138,7 +138,15 @@ typedef struct ras_local {
  *     read schedule is admissible); it only chooses when the read happens, so
  *     that evenly loaded subdomains read their neighbours' latest update
  *     rather than the one before it.  Negative: library choice (0.25 for the
- *     Cholesky solvers, 0 for CG).  Ignored by SYNC and ORDERED.  */
+ *     Cholesky solvers, 0 for CG).  Ignored by SYNC and ORDERED.
+ *   detect_factor (ASYNC and ORDERED): the detector tests the local and
+ *     global criteria against detect_factor * tol, while the verification
+ *     that follows every stop (Sec. 3.3.2) always uses tol.  A factor above 1
+ *     makes the detector fire before the tolerance is reached, so the
+ *     verification fails and the iteration resumes: it exercises the resume
+ *     path (info.launches > 1) and costs extra launches.  A factor below 1
+ *     delays the detector.  0 means 1; negative or NaN is RAS_E_ARG.  Ignored
+ *     by SYNC, whose stop is the exact residual of every sweep.  */
 enum { RAS_MODE_SYNC = 0, RAS_MODE_ASYNC = 1, RAS_MODE_ORDERED = 2 };
 /* Detectors of the asynchronous mode.  CENTRAL (Sec. 2.2): every subdomain's
  * latest local criterion holds and the sum of the latest owned residuals is
@@ -157,6 +165,7 @@ typedef struct ras_solve_opts {
     int32_t workgroups;
     int32_t team;
     double pace;
+    double detect_factor;
 } ras_solve_opts;
 
 typedef struct ras_solve_info {

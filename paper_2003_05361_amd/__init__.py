@@ -60,7 +60,8 @@ class LocalStruct(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("detect", C.c_int32), ("tol", C.c_double), ("max_sweeps", C.c_int64),
-                ("max_seconds", C.c_double), ("workgroups", C.c_int32), ("team", C.c_int32), ("pace", C.c_double)]
+                ("max_seconds", C.c_double), ("workgroups", C.c_int32), ("team", C.c_int32), ("pace", C.c_double),
+                ("detect_factor", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -396,9 +397,10 @@ def _initial(x0, b, what: str = "x0"):
     return x0.to(device=b.device, dtype=torch.float64).contiguous().clone()
 
 
-def _opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team=0, pace=None) -> SolveOpts:
+def _opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team=0, pace=None,
+          detect_factor=1.0) -> SolveOpts:
     return SolveOpts(MODES[mode], DETECT[detect], float(tol), int(max_sweeps), float(max_seconds), int(workgroups),
-                     int(team), float(DEFAULT_PACE if pace is None else pace))
+                     int(team), float(DEFAULT_PACE if pace is None else pace), float(detect_factor))
 
 
 class Handle:
@@ -422,13 +424,15 @@ class Handle:
 
     def solve(self, b, x0=None, tol: float = 1e-8, mode: str = "async", max_sweeps: int = 1_000_000,
               max_seconds: float = 0.0, detect: str = "central", workgroups: int = 0, team: int = 0,
-              allow_unconverged=True, pace=None, noalloc: bool = False):
+              allow_unconverged=True, pace=None, noalloc: bool = False, detect_factor: float = 1.0):
         """Solve A x = b on the device.  b: float64 CUDA tensor [n] or [nrhs, n].
         mode: "sync", "async" or "ordered"; detect: "central", "decentral" or
         "estimate" (a library option: stop on the owned-residual estimate once every
         subdomain has updated, verified exactly like the others);
         pace (async): neighbour wait budget before a read, in units of the
         previous update's time (None: the library's choice per local solver).
+        detect_factor (async, ordered): the detector tests detect_factor * tol, the
+        verification tol (> 1: stops that fail verification and resume).
         noalloc: run through ras_solve_noalloc (workspace in the library's fixed
         device scratch of NOALLOC_SCRATCH_BYTES; x is still allocated here unless
         x0 is given).  Returns (x, infos) with x the same shape as b."""
@@ -439,7 +443,8 @@ class Handle:
         self._order_after_current_stream()
         fn = lib().ras_solve_noalloc if noalloc else lib().ras_solve
         st = fn(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), nrhs,
-                C.byref(_opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team, pace)), infos)
+                C.byref(_opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team, pace, detect_factor)),
+                infos)
         _check(st, (RAS_OK, RAS_NOT_CONVERGED) if allow_unconverged else (RAS_OK,))
         self.last_nrhs = nrhs
         return x, [i.as_dict() for i in infos]
@@ -549,7 +554,7 @@ def setup(A, part: dict, overlap: int, loc: dict, stream=None) -> Handle:
 
 def batch_solve(handles: Sequence[Handle], bs, xs=None, tol: float = 1e-8, mode: str = "async",
                 max_sweeps: int = 1_000_000, max_seconds: float = 0.0, detect: str = "central", workgroups: int = 0,
-                team: int = 0, pace=None):
+                team: int = 0, pace=None, detect_factor: float = 1.0):
     """Solve several systems in one persistent launch (same local solver kind/storage)."""
     import torch
 
@@ -574,7 +579,8 @@ def batch_solve(handles: Sequence[Handle], bs, xs=None, tol: float = 1e-8, mode:
     for h in handles:
         h._order_after_current_stream()
     st = lib().ras_batch_solve(m, H, B, X, NR,
-                               C.byref(_opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team, pace)), infos)
+                               C.byref(_opts(tol, mode, max_sweeps, max_seconds, detect, workgroups, team, pace,
+                                             detect_factor)), infos)
     _check(st, (RAS_OK, RAS_NOT_CONVERGED))
     out, k = [], 0
     for r in nr:

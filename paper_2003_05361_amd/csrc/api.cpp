@@ -808,6 +808,9 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
     if (o.detect != RAS_DETECT_CENTRAL && o.detect != RAS_DETECT_DECENTRAL && o.detect != RAS_DETECT_ESTIMATE)
         throw Error{RAS_E_ARG, "unknown detector"};
     if (!(o.pace <= 16.0)) throw Error{RAS_E_ARG, "pace must be at most 16 (negative: library choice)"};
+    if (!(o.detect_factor >= 0.0)) throw Error{RAS_E_ARG, "detect_factor must be >= 0 (0: 1)"};
+    // the detector's threshold; SYNC stops on the exact residual of each sweep
+    const double detect_factor = (sync || o.detect_factor == 0.0) ? 1.0 : o.detect_factor;
     // distinct handles, in first-use order
     std::vector<ras_handle*> hs;
     for (auto& sp : specs)
@@ -1068,7 +1071,7 @@ ras_status run_solve(std::vector<InstSpec>& specs, const ras_solve_opts& o, ras_
         in.hist_t = reinterpret_cast<double*>(base + o_hist) + static_cast<size_t>(ninst + i) * hist_cap;
         in.hist_cap = hist_cap;
         in.max_sweeps = o.max_sweeps;
-        in.tol2 = tol_v[i] * tol_v[i];
+        in.tol2 = (tol_v[i] * detect_factor) * (tol_v[i] * detect_factor);
         in.leader = owner_wg[in.item_begin];
         in.ctl = ordered ? nullptr : specs[i].h->ctl.dev;  // ORDERED ignores pauses and cancels
         if (specs[i].h->ctl.host) __atomic_store_n(specs[i].h->ctl.host, 0, __ATOMIC_SEQ_CST);  // a new solve: not cancelled

@@ -432,6 +432,32 @@ def test_async_converges_and_verifies(loc, st, k):
         assert counts.min() >= 1 and counts.sum() == info[0]["total_local_solves"]
 
 
+@pytest.mark.parametrize("loc,k,detect", [("chol", 0, "central"), ("cg", 10, "decentral"),
+                                           ("chol_sparse", 0, "estimate")])
+def test_failed_verification_resumes(loc, k, detect):
+    """A detector that tests 100 tol fires before the tolerance is reached; the
+    exact verification that follows the stop fails, and the iteration resumes
+    from the current iterate (Sec. 3.3.2) until a stop passes it: more than one
+    launch, converged, verified residual below tol, the direct solution.  A
+    synchronous solve ignores the factor (its stop is the exact residual)."""
+    ras = _ras()
+    _say(f"case: resume after failed verification {loc} {detect}")
+    A = R.laplace2d(96)
+    b = R.uniform_rhs(A.n, 18)
+    xd = schwarz.direct_solve(A, b)
+    h = ras.setup(A, ras.partition("regular_2d", (4, 4), grid=A.grid), 3, ras.local(loc, "fp64", k))
+    x, info = h.solve(_cuda(b), tol=1e-8, mode="async", detect=detect, max_sweeps=200000, max_seconds=60,
+                      detect_factor=100.0)
+    xx = x.cpu().numpy()
+    assert info[0]["converged"] and info[0]["launches"] >= 2, info
+    assert schwarz.relative_residual(A, xx, b) < 1e-8
+    assert _rel(xx, xd) <= 1e-6
+    _, plain = h.solve(_cuda(b), tol=1e-8, mode="sync", max_sweeps=100000)
+    _, scaled = h.solve(_cuda(b), tol=1e-8, mode="sync", max_sweeps=100000, detect_factor=100.0)
+    assert scaled[0]["sweeps"] == plain[0]["sweeps"] and scaled[0]["converged"], (plain, scaled)
+    h.close()
+
+
 @pytest.mark.parametrize("loc,st,k,team", [("chol", "fp64", 0, 0), ("cg", "fp64", 10, 4), ("cg", "fp32", 6, 1),
                                             ("chol_sparse", "fp64", 0, 0)])
 def test_async_decentralized_detection(loc, st, k, team):
@@ -514,7 +540,8 @@ def test_solve_options_out_of_range_are_argument_errors():
         with pytest.raises(ras.RasError) as e:
             h.solve(b, tol=1e-8, mode="async", pace=bad)
         assert e.value.status == -1
-    for kw in (dict(tol=-1.0), dict(tol=float("nan")), dict(max_sweeps=0)):
+    for kw in (dict(tol=-1.0), dict(tol=float("nan")), dict(max_sweeps=0), dict(detect_factor=-1.0),
+               dict(detect_factor=float("nan"))):
         with pytest.raises(ras.RasError) as e:
             h.solve(b, **{"tol": 1e-8, "mode": "sync", **kw})
         assert e.value.status == -1, kw
