@@ -15,7 +15,9 @@
 #include <queue>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <unordered_map>
+#include <utility>
 #include <vector>
 
 #include "../../include/ras.h"
@@ -162,6 +164,22 @@ ras_status guarded(F&& f) {
         return fail(RAS_E_NOMEM, "host allocation failed");
     } catch (const std::exception& e) {
         return fail(RAS_E_ARG, e.what());
+    }
+}
+
+// Status and message of the exception being handled, mapped as guarded() maps
+// them; for the server's threads, where nothing may escape.
+std::pair<ras_status, std::string> current_error() {
+    try {
+        throw;
+    } catch (const Error& e) {
+        return {e.status, e.msg};
+    } catch (const std::bad_alloc&) {
+        return {RAS_E_NOMEM, "host allocation failed"};
+    } catch (const std::exception& e) {
+        return {RAS_E_ARG, e.what()};
+    } catch (...) {
+        return {RAS_E_STATE, "unknown exception"};
     }
 }
 
@@ -1492,12 +1510,8 @@ struct ras_server {
                 std::vector<int64_t>().swap(rq->rp);
                 std::vector<int32_t>().swap(rq->ci);
                 std::vector<double>().swap(rq->va);
-            } catch (const Error& e) {
-                err.status = e.status;
-                err.msg = e.msg;
-            } catch (const std::bad_alloc&) {
-                err.status = RAS_E_NOMEM;
-                err.msg = "host allocation failed";
+            } catch (...) {
+                std::tie(err.status, err.msg) = current_error();
             }
             std::lock_guard<std::mutex> lk(mu);
             if (err.status != RAS_OK) {
@@ -1576,7 +1590,8 @@ struct ras_server {
     }
 
     void drive_loop() {
-        if (hipSetDevice(device) != hipSuccess) return;
+        // without its device the thread still answers every request (RAS_E_HIP)
+        const bool device_ok = hipSetDevice(device) == hipSuccess;
         for (;;) {
             // admission by budget: the oldest planned systems that fit
             for (;;) {
@@ -1596,15 +1611,15 @@ struct ras_server {
                     state[rq->ticket] = 2;
                 }
                 try {
+                    if (!device_ok) throw Error{RAS_E_HIP, "hipSetDevice failed on the server's driver thread"};
                     auto sys = admit(*rq);
                     std::lock_guard<std::mutex> lk(mu);
                     active.push_back(std::move(sys));
-                } catch (const Error& e) {
+                } catch (...) {
+                    SrvResult r;
+                    std::tie(r.status, r.msg) = current_error();
                     std::lock_guard<std::mutex> lk(mu);
                     in_use -= rq->bytes;
-                    SrvResult r;
-                    r.status = e.status;
-                    r.msg = e.msg;
                     finish(rq->ticket, std::move(r));
                 }
             }
@@ -1633,9 +1648,8 @@ struct ras_server {
                     Workspace where;
                     where.reuse = &ws;
                     st = run_solve(specs, o, infos.data(), where);
-                } catch (const Error& e) {
-                    st = e.status;
-                    msg = e.msg;
+                } catch (...) {
+                    std::tie(st, msg) = current_error();
                 }
                 size_t k = 0;
                 for (SrvSystem* sy : kv.second) {
