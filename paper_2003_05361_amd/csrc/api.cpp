@@ -1573,7 +1573,9 @@ struct ras_server {
         return sys;
     }
 
-    void retire(SrvSystem& sys, ras_status st, const std::string& msg) {
+    // The result of a finished system: the solution copied to the host (no lock
+    // held, so submitters and pollers do not wait on the copy).
+    SrvResult collect(SrvSystem& sys, ras_status st, const std::string& msg) {
         SrvResult r;
         r.status = st;
         r.msg = msg;
@@ -1586,7 +1588,7 @@ struct ras_server {
         }
         r.info = sys.acc;
         r.latency = std::chrono::duration<double>(std::chrono::steady_clock::now() - sys.t_submit).count();
-        finish(sys.ticket, std::move(r));
+        return r;
     }
 
     void drive_loop() {
@@ -1683,11 +1685,23 @@ struct ras_server {
                 }
             }
             const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            std::vector<SrvResult> outs;
+            outs.reserve(done.size());
+            for (auto& d : done) {
+                try {
+                    outs.push_back(collect(*d.first, d.second.first, d.second.second));
+                } catch (...) {
+                    SrvResult r;
+                    std::tie(r.status, r.msg) = current_error();
+                    outs.push_back(std::move(r));
+                }
+            }
             std::lock_guard<std::mutex> lk(mu);
             ++slices;
             device_seconds += dt;
-            for (auto& d : done) {
-                retire(*d.first, d.second.first, d.second.second);
+            for (size_t j = 0; j < done.size(); ++j) {
+                const auto& d = done[j];
+                finish(d.first->ticket, std::move(outs[j]));
                 in_use -= d.first->bytes;
                 for (size_t i = 0; i < active.size(); ++i)
                     if (active[i].get() == d.first) {
