@@ -8,7 +8,7 @@
  *     grid graph the distance to a block is the Manhattan distance;
  *   - the communication volume (Sec. 3.2.1, Fig. 2) by counting;
  *   - the band factor by multiplying it out: L L^T = A[Omega_p, Omega_p]
- *     (Sec. 3.3.1);
+ *     (Sec. 3.3.1), and the sparse factor likewise in its elimination order;
  *   - the asynchronous stop rule's documented precedence (Sec. 3.3.2).
  * Exit status 0 when every check holds; each failure is printed.  */
 #include <math.h>
@@ -158,6 +158,55 @@ static void check_factors(ras_plan* plan) {
     free(oidx);
 }
 
+/* Sparse factor (nested-dissection order): perm is a permutation of the local
+ * rows, L is lower triangular with a positive diagonal and columns ascending,
+ * and L L^T = A_p[perm, perm] entry by entry (the dense product, small boxes).  */
+static void check_sparse_factors(ras_plan* plan) {
+    int64_t optr[P + 1];
+    CHECK(ras_plan_sets(plan, NULL, optr, NULL) == RAS_OK, "sets");
+    int32_t* oidx = malloc(sizeof(int32_t) * (size_t)optr[P]);
+    CHECK(ras_plan_sets(plan, NULL, optr, oidx) == RAS_OK, "sets");
+    for (int p = 0; p < P; ++p) {
+        const int m = (int)(optr[p + 1] - optr[p]);
+        const int32_t* om = oidx + optr[p];
+        int64_t nnz = -1;
+        CHECK(ras_plan_sparse_factor(plan, p, NULL, NULL, NULL, NULL, NULL, &nnz) == RAS_OK && nnz >= 0,
+              "sparse query %d: %s", p, ras_last_error());
+        int32_t* perm = malloc(sizeof(int32_t) * (size_t)m);
+        int64_t* lp = malloc(sizeof(int64_t) * (size_t)(m + 1));
+        int32_t* lc = malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+        double* lv = malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+        double* dg = malloc(sizeof(double) * (size_t)m);
+        double* L = calloc((size_t)m * (size_t)m, sizeof(double));
+        int* seen = calloc((size_t)m, sizeof(int));
+        CHECK(ras_plan_sparse_factor(plan, p, perm, lp, lc, lv, dg, &nnz) == RAS_OK, "sparse %d: %s", p,
+              ras_last_error());
+        for (int k = 0; k < m; ++k) {
+            CHECK(perm[k] >= 0 && perm[k] < m && !seen[perm[k]], "subdomain %d: perm is not a permutation", p);
+            if (perm[k] >= 0 && perm[k] < m) seen[perm[k]] = 1;
+            CHECK(dg[k] > 0.0, "subdomain %d: non-positive pivot at step %d", p, k);
+            L[(size_t)k * m + k] = dg[k];
+            for (int64_t e = lp[k]; e < lp[k + 1]; ++e) {
+                CHECK(lc[e] >= 0 && lc[e] < k, "subdomain %d: entry (%d, %d) not strictly lower", p, k, lc[e]);
+                CHECK(e == lp[k] || lc[e] > lc[e - 1], "subdomain %d: row %d columns not ascending", p, k);
+                if (lc[e] >= 0 && lc[e] < k) L[(size_t)k * m + lc[e]] = lv[e];
+            }
+        }
+        CHECK(lp[0] == 0 && lp[m] == nnz, "subdomain %d: row pointers", p);
+        double err = 0.0;
+        for (int r = 0; r < m; ++r)
+            for (int c = 0; c <= r; ++c) {
+                double sum = 0.0;
+                for (int k = 0; k <= c; ++k) sum += L[(size_t)r * m + k] * L[(size_t)c * m + k];
+                const double d = fabs(sum - a_entry(om[perm[r]], om[perm[c]]));
+                if (d > err) err = d;
+            }
+        CHECK(err <= 8e-12, "subdomain %d: max |L L^T - P A_p P^T| = %g", p, err);
+        free(perm); free(lp); free(lc); free(lv); free(dg); free(L); free(seen);
+    }
+    free(oidx);
+}
+
 static void check_stop_rule(void) {
     /* precedence: diverged, converged, limit, resume */
     CHECK(ras_async_next_step(RAS_KSTOP_DIVERGED, 1e-12, 1e-8, 5, 100, 0.0, 0.0, 0) == RAS_STEP_DIVERGED, "kstop diverged");
@@ -203,6 +252,18 @@ int main(void) {
         ras_plan_destroy(plan);
     }
     ras_plan_destroy(NULL);
+
+    const ras_local sparse = {RAS_LOCAL_CHOL_SPARSE, 0, RAS_STORAGE_FP64, RAS_TRANSMISSION_DIRICHLET, 1.0};
+    plan = NULL;
+    CHECK(ras_plan_create(&A, &part, GAMMA, &sparse, &plan) == RAS_OK && plan, "sparse plan: %s", ras_last_error());
+    if (plan) {
+        check_sparse_factors(plan);
+        /* a banded factor is not held by a sparse plan */
+        double one = 0.0;
+        int32_t w = 0;
+        CHECK(ras_plan_factor(plan, 0, &one, &w) == RAS_E_STATE, "band factor of a sparse plan");
+        ras_plan_destroy(plan);
+    }
 
     /* argument and pattern errors, each with a message */
     plan = NULL;
