@@ -5,7 +5,8 @@ library's owners, overlapping sets (Sec. 2.1, Fig. 1; Sec. 3.2.1) and
 communication volume (Fig. 2) equal the oracle's bit for bit; on random SPD
 matrices with the grid's pattern the local factors (Sec. 3.3.1) are the
 Cholesky factors of the local matrices: the band factor equals LAPACK's, the
-sparse factor gives L L^T = P A_p P^T."""
+sparse factor gives L L^T = P A_p P^T, and its solve schedules and device lane
+layout give the triangular solves."""
 import numpy as np
 import pytest
 from hypothesis import HealthCheck, given, settings
@@ -132,3 +133,39 @@ def test_local_factors_are_cholesky_factors(case, seed):
     finally:
         band_plan.close()
         sparse_plan.close()
+
+
+@settings(max_examples=100, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(problems(), st.integers(0, 2**32 - 1), st.sampled_from(["fp64", "fp32"]))
+def test_sparse_schedules_and_lanes_solve_the_triangular_systems(case, seed, storage):
+    """Both passes of every subdomain's solve schedule, and the lane layout the
+    device streams, run with parallel step semantics (race-free, checked by the
+    simulators), give L^{-1} v and L^{-T} v to rounding."""
+    import scipy.sparse.linalg as spla
+
+    from test_host_parity import _run_lanes, _run_schedule
+
+    A0, (kind, arg), gamma = case
+    A = _random_spd(A0, seed)
+    if kind == "rcb":
+        spec = ras.partition("rcb", arg[0], grid=A.grid, seed=arg[1], jitter=arg[2])
+    else:
+        spec = ras.partition(kind, arg, grid=A.grid)
+    plan = ras.Plan(A, spec, gamma, ras.local("chol_sparse", storage))
+    rng = np.random.default_rng(seed)
+    try:
+        _, ptr, _ = plan.sets()
+        for p in range(len(ptr) - 1):
+            n = int(ptr[p + 1] - ptr[p])
+            perm, rp, col, val, diag = plan.sparse_factor(p)
+            L = (sp.csr_matrix((val, col, rp), shape=(n, n)) + sp.diags(diag)).tocsr()
+            v = rng.standard_normal(n)
+            for pass_, M, lower in ((0, L, True), (1, L.T.tocsr(), False)):
+                ref = spla.spsolve_triangular(M, v, lower=lower)
+                scale = max(np.max(np.abs(ref)), 1e-300)
+                sch = plan.sparse_schedule(p, pass_)
+                assert np.max(np.abs(_run_schedule(sch, v) - ref)) <= 1e-11 * scale, (p, pass_)
+                lay = plan.sparse_lanes(p, pass_)
+                assert np.max(np.abs(_run_lanes(lay, v, sch["slots"]) - ref)) <= 1e-11 * scale, (p, pass_)
+    finally:
+        plan.close()
