@@ -6,7 +6,8 @@ communication volume (Fig. 2) equal the oracle's bit for bit; on random SPD
 matrices with the grid's pattern the local factors (Sec. 3.3.1) are the
 Cholesky factors of the local matrices: the band factor equals LAPACK's, the
 sparse factor gives L L^T = P A_p P^T, and its solve schedules and device lane
-layout give the triangular solves."""
+layout give the triangular solves; FP16 row-scaled storage and ORAS (Robin)
+factors follow their definitions on the same random cases."""
 import numpy as np
 import pytest
 from hypothesis import HealthCheck, given, settings
@@ -169,3 +170,72 @@ def test_sparse_schedules_and_lanes_solve_the_triangular_systems(case, seed, sto
                 assert np.max(np.abs(_run_lanes(lay, v, sch["slots"]) - ref)) <= 1e-11 * scale, (p, pass_)
     finally:
         plan.close()
+
+
+@settings(max_examples=60, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(problems(), st.integers(0, 2**32 - 1))
+def test_fp16_rowscaled_storage_quantises_the_band_factor(case, seed):
+    """FP16_ROWSCALED storage of every subdomain's factor: scale[i] =
+    float32(max_j |L_ij|) (1 for a zero row) and each stored slot the float16
+    (round to nearest even from float64) of L_ij / scale[i], bit for bit against
+    numpy's conversion of the library's own float64 factor."""
+    A0, (kind, arg), gamma = case
+    A = _random_spd(A0, seed)
+    if kind == "rcb":
+        spec = ras.partition("rcb", arg[0], grid=A.grid, seed=arg[1], jitter=arg[2])
+    else:
+        spec = ras.partition(kind, arg, grid=A.grid)
+    plan = ras.Plan(A, spec, gamma, ras.local("chol", "fp16"))
+    try:
+        _, ptr, _ = plan.sets()
+        for p in range(len(ptr) - 1):
+            band, w = plan.factor(p)
+            bits, scale = plan.factor_fp16(p)
+            mx = np.max(np.abs(band), axis=1)
+            ref_scale = np.where(mx > 0, mx, 1.0).astype(np.float32)
+            assert np.array_equal(scale, ref_scale), p
+            ref_bits = (band / scale.astype(np.float64)[:, None]).astype(np.float16).view(np.uint16)
+            assert np.array_equal(bits, ref_bits), p
+    finally:
+        plan.close()
+
+
+@settings(max_examples=60, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(problems(), st.integers(0, 2**32 - 1), st.floats(0.05, 1.0))
+def test_oras_factors_are_cholesky_of_the_robin_local_matrices(case, seed, q):
+    """ORAS plans (a Robin transmission condition in algebraic form): the band
+    and the sparse factor of every subdomain are Cholesky factors of the oracle's
+    Robin local matrix, A[Omega_p, Omega_p] with the diagonal lowered by
+    (1 - q) times the coupling to points outside Omega_p."""
+    A0, (kind, arg), gamma = case
+    A = _random_spd(A0, seed)
+    if kind == "rcb":
+        spec = ras.partition("rcb", arg[0], grid=A.grid, seed=arg[1], jitter=arg[2])
+    else:
+        spec = ras.partition(kind, arg, grid=A.grid)
+    band_plan = ras.Plan(A, spec, gamma, ras.local("chol", "fp64", robin_q=q))
+    sparse_plan = ras.Plan(A, spec, gamma, ras.local("chol_sparse", "fp64", robin_q=q))
+    try:
+        _, ptr, idx = band_plan.sets()
+        for p in range(len(ptr) - 1):
+            om = idx[ptr[p]:ptr[p + 1]]
+            n = om.size
+            Ar = olocal.robin_local_matrix(A, om, q).toarray()
+            band, w = band_plan.factor(p)
+            L = np.zeros((n, n))
+            for o in range(w + 1):
+                i = np.arange(n)
+                j = i - w + o
+                m = j >= 0
+                L[i[m], j[m]] = band[i[m], o]
+            assert np.max(np.abs(L @ L.T - Ar)) <= 1e-12 * np.max(np.abs(Ar)), p
+            perm, rp, col, val, diag = sparse_plan.sparse_factor(p)
+            Ls = np.zeros((n, n))
+            for k in range(n):
+                Ls[k, col[rp[k]:rp[k + 1]]] = val[rp[k]:rp[k + 1]]
+                Ls[k, k] = diag[k]
+            Ad = Ar[np.ix_(perm, perm)]
+            assert np.max(np.abs(Ls @ Ls.T - Ad)) <= 1e-12 * np.max(np.abs(Ad)), p
+    finally:
+        band_plan.close()
+        sparse_plan.close()
