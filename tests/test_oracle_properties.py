@@ -1,0 +1,109 @@
+"""Property-based pins of the oracle (CPU only): on random SPD systems with a
+grid pattern (graph Laplacians with edge weights over four decades plus a
+positive diagonal shift), random boxes and partitions, the oracle's RAS sweeps
+are checked against the mathematics, built here densely and independently of
+the oracle's own overlap and local-matrix code:
+  - one sweep of restricted additive Schwarz (Sec. 2.1) from x is
+    x + sum_p Rt_p^T A_p^{-1} R_p (b - A x), with Omega_p grown by gamma
+    applications of the pattern of A (matrix powers) and Rt_p the restriction
+    to the owned points;
+  - without overlap a sweep is block Jacobi and an ordered pass block
+    Gauss-Seidel over the owned blocks;
+  - one subdomain gives the direct solve in one sweep."""
+import numpy as np
+import scipy.sparse as sp
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
+
+import ras_inputs as R
+from oracle import partition as opart
+from oracle import schwarz
+
+
+@st.composite
+def systems(draw):
+    if draw(st.booleans()):
+        grid = (draw(st.integers(1, 14)), draw(st.integers(1, 14)), 1)
+        A = R.laplace2d(grid[0], grid[1])
+    else:
+        grid = (draw(st.integers(1, 6)), draw(st.integers(1, 6)), draw(st.integers(1, 6)))
+        A = R.laplace3d(*grid)
+    rng = np.random.default_rng(draw(st.integers(0, 2**32 - 1)))
+    M = sp.csr_matrix((A.data, A.indices, A.indptr), shape=(A.n, A.n))
+    U = sp.triu(M, k=1).tocoo()
+    W = sp.coo_matrix((-(10.0 ** rng.uniform(-2, 2, U.nnz)), (U.row, U.col)), shape=M.shape)
+    W = (W + W.T).tocsr()
+    S = (W + sp.diags(-np.asarray(W.sum(axis=1)).ravel() + 10.0 ** rng.uniform(-2, 0, A.n))).tocsr()
+    S.sort_indices()
+    A = R.CSR(S.indptr.astype(np.int64), S.indices.astype(np.int32), S.data, A.grid)
+    if draw(st.booleans()):
+        owner = opart.regular_1d(A.n, draw(st.integers(1, min(A.n, 8))))
+    else:
+        owner = opart.rcb(A.coords(), draw(st.integers(1, min(A.n, 8))), draw(st.integers(0, 2**63 - 1)),
+                          draw(st.floats(0.0, 0.9)))
+    b = rng.standard_normal(A.n)
+    x0 = rng.standard_normal(A.n)
+    return A, S.toarray(), owner, b, x0
+
+
+def _omega(D, owned, gamma):
+    """Omega_p: the owned points grown by gamma applications of A's pattern."""
+    reach = np.zeros(D.shape[0], dtype=bool)
+    reach[owned] = True
+    pattern = D != 0
+    for _ in range(gamma):
+        reach = reach | pattern[reach].any(axis=0)
+    return np.flatnonzero(reach)
+
+
+def _ras_sweep(D, owner, gamma, b, x):
+    r = b - D @ x
+    x1 = x.copy()
+    for p in range(int(owner.max()) + 1):
+        owned = np.flatnonzero(owner == p)
+        om = _omega(D, owned, gamma)
+        delta = np.linalg.solve(D[np.ix_(om, om)], r[om])
+        keep = np.isin(om, owned)
+        x1[om[keep]] += delta[keep]
+    return x1
+
+
+@settings(max_examples=80, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(systems(), st.integers(0, 3))
+def test_sync_sweep_is_the_ras_update(sysm, gamma):
+    A, D, owner, b, x0 = sysm
+    orc = schwarz.RAS(A, owner, gamma, "chol", "fp64", 0)
+    x1, _, sweeps = orc.sync(b, 0.0, 1, x0=x0)
+    assert sweeps == 1
+    ref = _ras_sweep(D, owner, gamma, b, x0)
+    assert np.max(np.abs(x1 - ref)) <= 1e-9 * max(np.max(np.abs(ref)), 1.0)
+
+
+@settings(max_examples=60, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(systems())
+def test_no_overlap_is_block_jacobi_and_block_gauss_seidel(sysm):
+    A, D, owner, b, x0 = sysm
+    P = int(owner.max()) + 1
+    blocks = [np.flatnonzero(owner == p) for p in range(P)]
+    jac = x0.copy()
+    for o in blocks:
+        jac[o] = np.linalg.solve(D[np.ix_(o, o)], b[o] - D[o] @ x0 + D[np.ix_(o, o)] @ x0[o])
+    gs = x0.copy()
+    for o in blocks:
+        gs[o] = np.linalg.solve(D[np.ix_(o, o)], b[o] - D[o] @ gs + D[np.ix_(o, o)] @ gs[o])
+    orc = schwarz.RAS(A, owner, 0, "chol", "fp64", 0)
+    xj, _, _ = orc.sync(b, 0.0, 1, x0=x0)
+    xg, _ = orc.ordered(b, 1, x0=x0)
+    scale = max(np.max(np.abs(jac)), np.max(np.abs(gs)), 1.0)
+    assert np.max(np.abs(xj - jac)) <= 1e-9 * scale
+    assert np.max(np.abs(xg - gs)) <= 1e-9 * scale
+
+
+@settings(max_examples=40, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(systems(), st.integers(0, 3))
+def test_one_subdomain_is_the_direct_solve(sysm, gamma):
+    A, D, _, b, x0 = sysm
+    orc = schwarz.RAS(A, np.zeros(A.n, dtype=np.int32), gamma, "chol", "fp64", 0)
+    x1, _, _ = orc.sync(b, 0.0, 1, x0=x0)
+    xd = np.linalg.solve(D, b)
+    assert np.max(np.abs(x1 - xd)) <= 1e-9 * max(np.max(np.abs(xd)), 1.0)
