@@ -141,3 +141,41 @@ def test_cg_steps_are_the_krylov_galerkin_projection(sysm, k, gamma):
     ref = V @ np.linalg.solve(V.T @ Dp @ V, V.T @ r)
     d = olocal.cg_fixed(sp.csr_matrix(Dp), r, k)
     assert np.linalg.norm(d - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+@settings(max_examples=150, deadline=None, derandomize=True, suppress_health_check=[HealthCheck.too_slow])
+@given(st.integers(1, 12), st.integers(1, 9), st.integers(0, 2**32 - 1), st.booleans())
+def test_compensated_residual_within_the_dot2_bound(rows, per_row, seed, cancel):
+    """The oracle's outer residual b - A x is Dot2 (Ogita, Rump, Oishi 2005): for
+    each row of m = per_row + 1 terms, |res - exact| <= eps |exact| +
+    gamma_m^2 (|b_i| + sum_j |a_ij x_j|) with eps = 2^-53 and gamma_m = m eps /
+    (1 - m eps); the exact value in rational arithmetic.  With `cancel`, b is
+    the float64 product A x plus a few ulps, so the residual cancels almost
+    completely (where plain float64 is off by about the size of r itself)."""
+    from fractions import Fraction
+
+    from oracle import residual as oresidual
+
+    rng = np.random.default_rng(seed)
+    n = 40
+    indptr = [0]
+    cols, vals = [], []
+    for _ in range(rows):
+        c = np.sort(rng.choice(n, size=per_row, replace=False))
+        cols.extend(c.tolist())
+        vals.extend((rng.standard_normal(per_row) * 2.0 ** rng.integers(-30, 30, per_row)).tolist())
+        indptr.append(len(cols))
+    M = sp.csr_matrix((np.array(vals), np.array(cols, dtype=np.int32), np.array(indptr, dtype=np.int64)),
+                      shape=(rows, n))
+    x = rng.standard_normal(n) * 2.0 ** rng.integers(-20, 20, n)
+    b = np.zeros(n)
+    b[:rows] = (M @ x) * (1.0 + rng.integers(-3, 4, rows) * 2.0 ** -52) if cancel else rng.standard_normal(rows)
+    r = oresidual.residual(M, x, b)
+    eps = 2.0 ** -53
+    gamma = (per_row + 1) * eps / (1 - (per_row + 1) * eps)
+    for i in range(rows):
+        lo_, hi_ = indptr[i], indptr[i + 1]
+        exact = Fraction(b[i]) - sum(Fraction(vals[k]) * Fraction(x[cols[k]]) for k in range(lo_, hi_))
+        size = abs(b[i]) + sum(abs(vals[k] * x[cols[k]]) for k in range(lo_, hi_))
+        err = abs(Fraction(r[i]) - exact)
+        assert err <= Fraction(eps) * abs(exact) + Fraction(gamma * gamma * size * 1.01), (i, float(err), float(exact))
