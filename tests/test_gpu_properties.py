@@ -67,3 +67,25 @@ def test_random_systems_sync_and_ordered_match_the_oracle(case):
         _agree(x.cpu().numpy(), xo, 1e-9, ("ordered", loc, sweeps))
     finally:
         h.close()
+
+
+@settings(max_examples=40, deadline=None, derandomize=True, suppress_health_check=[HealthCheck.too_slow])
+@given(cases(), st.sampled_from(["chol", "chol_sparse"]), st.sampled_from(["central", "decentral", "estimate"]))
+def test_random_systems_async_converge_and_verify(case, loc, detect):
+    """Asynchronous solves of the same random systems with exact local solves
+    (the matrices are M-matrices: graph Laplacians plus a positive shift, for
+    which asynchronous RAS converges, Sec. 2.1) reach tol 1e-8 under every
+    detector, and the returned iterate's relative residual, recomputed by the
+    oracle, is below tol."""
+    from oracle import schwarz
+
+    ras = _ras()
+    A, (kind, arg), gamma, _, _, b = case
+    _say(f"case: random async n={A.n} grid={A.grid} {kind} {arg} gamma={gamma} {loc} {detect}")
+    h = ras.setup(A, _spec(ras, A, kind, arg), gamma, ras.local(loc, "fp64", 0))
+    try:
+        x, info = h.solve(_cuda(b), tol=1e-8, mode="async", detect=detect, max_sweeps=10**7, max_seconds=5)
+        assert info[0]["converged"], info
+        assert schwarz.relative_residual(A, x.cpu().numpy(), b) < 1e-8
+    finally:
+        h.close()
